@@ -1,0 +1,266 @@
+"""Synthetic batches of linear time-varying centroidal MPC problems.
+
+Every problem is drawn from its own substream ``default_rng([seed, index])``, so
+any subset of a batch is reproducible on its own and independent of the batch
+size.  Values are generated in float64 and then rounded to float32; the rounded
+arrays are the problem as stored, and both the FP64 oracle and the GPU solver
+solve exactly that rounded problem (the oracle upcasts it).
+
+Model (single-rigid-body centroidal dynamics, forward Euler; the paper's
+discrete centroidal dynamics of Sec. II-A written in the 13-state form with
+gravity carried as a state):
+
+    x = (roll, pitch, yaw, p (3), omega (3), v (3), g_s)      13 states
+    u = per contact i in {0, 1}: (f_i (3), tau_i (3))          12 inputs
+    A_k = I + dt * A_c(yaw),   B_k = dt * B_c(yaw, r_{i,k}, m, I_body)
+    r_{i,k} = p_i - c_ref,k  (foot position minus reference CoM at stage k)
+
+The standard-form problem (Sec. III) that results is
+
+    min  sum_k 1/2 |x_{k+1} - x_ref[k]|_Q^2 + 1/2 |u_k - u_ref[k]|_R^2
+    s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,   x_0 given,
+         stance contact: |f_x|, |f_y| <= mu f_z, f_z <= fz_max, |tau_j| <= tau_max
+         swing contact:  f = 0, tau = 0.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NX = 13          # state dimension
+NU = 12          # input dimension: 2 contacts x (force 3 + moment 3)
+NC = 2           # contacts
+GRAVITY = 9.81
+COM_HEIGHT = 0.8
+GAIT_PERIOD = 0.4
+FOOT_HALF_WIDTH = 0.10
+
+# Workloads.  ``horizons`` is the set the per-problem horizon is drawn from
+# uniformly; ``duty`` None draws the stance fraction per problem from
+# U(0.35, 0.65) (flight, single and double support all occur).
+CONFIGS = {
+    "small_b64_n10": dict(batch=64, horizons=(10,), dt=0.04, duty=0.5,
+                          mu=(0.4, 0.8), push=0.0, payload=0.0, seed=1),
+    "plain_b4096_n20": dict(batch=4096, horizons=(20,), dt=0.03, duty=0.6,
+                            mu=(0.3, 0.9), push=0.5, payload=0.0, seed=2),
+    "uneven_b16384": dict(batch=16384, horizons=(10, 20, 30, 40, 60), dt=0.03,
+                          duty=None, mu=(0.3, 0.9), push=0.5, payload=0.0,
+                          seed=3),
+    "precision_b16384_n30": dict(batch=16384, horizons=(30,), dt=0.03,
+                                 duty=0.6, mu=(0.3, 0.9), push=0.5,
+                                 payload=0.0, seed=4),
+    "serving_tick": dict(batch=32768, horizons=tuple(range(10, 61)), dt=0.03,
+                         duty=None, mu=(0.3, 0.9), push=0.5, payload=10.0,
+                         seed=5),
+}
+
+
+def _cfg(config):
+    if isinstance(config, str):
+        return dict(CONFIGS[config])
+    return dict(config)
+
+
+def _draw(cfg, seed, idx):
+    """Per-problem scalar draws, in a fixed order from one substream."""
+    rng = np.random.default_rng([int(seed), int(idx)])
+    d = {}
+    d["mass"] = rng.uniform(30.0, 60.0)
+    d["inertia"] = rng.uniform(1.0, 4.0, 3)
+    d["yaw"] = rng.uniform(-math.pi, math.pi)
+    d["vx"] = rng.uniform(-1.0, 1.0)
+    lo, hi = cfg["mu"]
+    d["mu"] = lo + (hi - lo) * rng.uniform(0.0, 1.0)
+    d["phase"] = rng.uniform(0.0, 1.0)
+    d["q"] = rng.uniform(1.0, 100.0, NX)
+    d["foot_off"] = rng.normal(0.0, 0.1, (NC, 3))
+    d["push"] = cfg["push"] * rng.normal(0.0, 1.0, 3)
+    duty = rng.uniform(0.35, 0.65)
+    d["duty"] = duty if cfg["duty"] is None else cfg["duty"]
+    hz = cfg["horizons"]
+    d["N"] = int(hz[int(rng.integers(0, len(hz)))])
+    d["mass"] += cfg["payload"] * rng.uniform(0.0, 1.0)
+    return d
+
+
+def _rotz(psi):
+    c, s = np.cos(psi), np.sin(psi)
+    R = np.zeros(psi.shape + (3, 3))
+    R[..., 0, 0] = c
+    R[..., 0, 1] = -s
+    R[..., 1, 0] = s
+    R[..., 1, 1] = c
+    R[..., 2, 2] = 1.0
+    return R
+
+
+def _skew(r):
+    S = np.zeros(r.shape[:-1] + (3, 3))
+    S[..., 0, 1] = -r[..., 2]
+    S[..., 0, 2] = r[..., 1]
+    S[..., 1, 0] = r[..., 2]
+    S[..., 1, 2] = -r[..., 0]
+    S[..., 2, 0] = -r[..., 1]
+    S[..., 2, 1] = r[..., 0]
+    return S
+
+
+def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
+               dt=None, as_float32=True):
+    """Build a batch of problems.
+
+    config   name in CONFIGS or a dict with the same keys
+    indices  problem indices to draw (default range(batch))
+    n_max    padded horizon (default: the largest drawn horizon)
+
+    Returns a dict of arrays (float32 unless ``as_float32`` is False):
+      N [B] int32, A [B,n,13,13], B [B,n,13,12], e [B,n,13], x0 [B,13],
+      u_prev [B,12], x_ref [B,n,13] (reference for x_{k+1}), u_ref [B,n,12],
+      Q [B,13], R [B,12] (diagonals), contact [B,n,2] uint8 (1 = stance),
+      mu [B], fz_max [B], tau_max [B], weight [B] (m g, the force scale).
+    Stages k >= N[b] are padding: A = I, B = 0, e = 0, references 0, swing.
+    """
+    cfg = _cfg(config)
+    if seed is None:
+        seed = cfg["seed"]
+    if dt is None:
+        dt = cfg["dt"]
+    if indices is None:
+        indices = np.arange(cfg["batch"] if batch is None else batch)
+    indices = np.asarray(indices, dtype=np.int64)
+    Bn = len(indices)
+    draws = [_draw(cfg, seed, i) for i in indices]
+    Nh = np.array([d["N"] for d in draws], dtype=np.int32)
+    if n_max is None:
+        n_max = int(Nh.max()) if Bn else int(max(cfg["horizons"]))
+    if Bn and int(Nh.max()) > n_max:
+        raise ValueError("n_max smaller than a drawn horizon")
+    n = n_max
+
+    if Bn == 0:
+        return _empty(n)
+
+    def col(key):
+        return np.array([d[key] for d in draws], dtype=np.float64)
+
+    mass = col("mass")
+    inertia = col("inertia")
+    yaw = col("yaw")
+    vx = col("vx")
+    mu = col("mu")
+    phase = col("phase")
+    q = col("q")
+    foot_off = col("foot_off")
+    push = col("push")
+    duty = col("duty")
+
+    Rz = _rotz(yaw)                                            # [B,3,3]
+    Iw = Rz @ (inertia[:, :, None] * np.swapaxes(Rz, 1, 2))      # R diag(I) R^T
+    Iw_inv = np.linalg.inv(Iw)
+    vel_w = Rz @ np.array([1.0, 0.0, 0.0]) * vx[:, None]        # [B,3]
+    c0 = np.array([0.0, 0.0, COM_HEIGHT])
+    kk = np.arange(n + 1, dtype=np.float64)
+    c_ref = c0[None, None, :] + kk[None, :, None] * dt * vel_w[:, None, :]  # [B,n+1,3]
+
+    side = np.array([FOOT_HALF_WIDTH, -FOOT_HALF_WIDTH])
+    feet = np.zeros((Bn, NC, 3))
+    for i in range(NC):
+        feet[:, i, :] = (Rz @ np.array([0.0, side[i], 0.0])) + foot_off[:, i, :]
+        feet[:, i, 2] = foot_off[:, i, 2]
+
+    # continuous-time A_c and the forward-Euler A_k (identical over k: the yaw
+    # linearisation point is the constant reference yaw)
+    Ac = np.zeros((Bn, NX, NX))
+    Ac[:, 0:3, 6:9] = np.swapaxes(Rz, 1, 2)
+    Ac[:, 3:6, 9:12] = np.eye(3)
+    Ac[:, 11, 12] = 1.0
+    A1 = np.eye(NX)[None] + dt * Ac                              # [B,13,13]
+
+    stage = np.arange(n)
+    valid = stage[None, :] < Nh[:, None]                         # [B,n]
+    A = np.where(valid[:, :, None, None], A1[:, None], np.eye(NX)[None, None])
+
+    Bm = np.zeros((Bn, n, NX, NU))
+    for i in range(NC):
+        r = feet[:, None, i, :] - c_ref[:, :n, :]                # [B,n,3]
+        Bm[:, :, 6:9, 6 * i:6 * i + 3] = Iw_inv[:, None] @ _skew(r)
+        Bm[:, :, 6:9, 6 * i + 3:6 * i + 6] = Iw_inv[:, None]
+        Bm[:, :, 9:12, 6 * i:6 * i + 3] = np.eye(3)[None, None] / mass[:, None, None, None]
+    Bm *= dt
+    Bm[~valid] = 0.0
+
+    # reference state at stage j (time j*dt); x_ref[k] is the target of x_{k+1}
+    xr = np.zeros((Bn, n + 1, NX))
+    xr[:, :, 2] = yaw[:, None]
+    xr[:, :, 3:6] = c_ref
+    xr[:, :, 9:12] = vel_w[:, None, :]
+    xr[:, :, 12] = -GRAVITY
+    x_ref = xr[:, 1:, :].copy()
+    x_ref[~valid] = 0.0
+    x0 = xr[:, 0, :].copy()
+    x0[:, 9:12] += push
+
+    ph = phase[:, None, None] + stage[None, :, None] * dt / GAIT_PERIOD \
+        + np.arange(NC)[None, None, :] / NC
+    frac = ph - np.floor(ph)
+    contact = (frac < duty[:, None, None]) & valid[:, :, None]
+
+    out = {
+        "N": Nh,
+        "A": A,
+        "B": Bm,
+        "e": np.zeros((Bn, n, NX)),
+        "x0": x0,
+        "u_prev": np.zeros((Bn, NU)),
+        "x_ref": x_ref,
+        "u_ref": np.zeros((Bn, n, NU)),
+        "Q": q,
+        "R": np.full((Bn, NU), 1e-5),
+        "contact": contact.astype(np.uint8),
+        "mu": mu,
+        "fz_max": np.full(Bn, 1000.0),
+        "tau_max": np.full(Bn, 50.0),
+        "weight": mass * GRAVITY,
+    }
+    if as_float32:
+        for k, v in out.items():
+            if v.dtype == np.float64:
+                out[k] = np.ascontiguousarray(v.astype(np.float32))
+    for k, v in out.items():
+        out[k] = np.ascontiguousarray(v)
+    return out
+
+
+def _empty(n):
+    f = np.float32
+    return {
+        "N": np.zeros(0, np.int32), "A": np.zeros((0, n, NX, NX), f),
+        "B": np.zeros((0, n, NX, NU), f), "e": np.zeros((0, n, NX), f),
+        "x0": np.zeros((0, NX), f), "u_prev": np.zeros((0, NU), f),
+        "x_ref": np.zeros((0, n, NX), f), "u_ref": np.zeros((0, n, NU), f),
+        "Q": np.zeros((0, NX), f), "R": np.zeros((0, NU), f),
+        "contact": np.zeros((0, n, NC), np.uint8), "mu": np.zeros(0, f),
+        "fz_max": np.zeros(0, f), "tau_max": np.zeros(0, f),
+        "weight": np.zeros(0, f),
+    }
+
+
+def problem_slice(batch, idx):
+    """Sub-batch with the problems ``idx`` (array of positions)."""
+    idx = np.asarray(idx)
+    return {k: np.ascontiguousarray(v[idx]) for k, v in batch.items()}
+
+
+def problem_fp64(batch, b):
+    """Problem ``b`` of a batch, trimmed to its own horizon, as float64."""
+    N = int(batch["N"][b])
+    p = {"N": N}
+    for k, v in batch.items():
+        if k == "N":
+            continue
+        a = v[b]
+        if a.ndim >= 1 and k in ("A", "B", "e", "x_ref", "u_ref", "contact"):
+            a = a[:N]
+        p[k] = a.astype(np.float64) if k != "contact" else a.astype(bool)
+    return p

@@ -1,0 +1,477 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these re-types the oracle: each check uses a different algorithm or a
+property that characterises the answer (textbook Riccati recursion, a closed
+form, brute-force enumeration of active faces, first-order optimality of the
+Euclidean projection, the augmented Lagrangian of Sec. III differentiated
+numerically, the lifting identity of Sec. III).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import mpcgen
+from oracle import admm, kkt, projection, qp
+
+NX, NU = 13, 12
+
+
+def _prob(config="small_b64_n10", b=0, **over):
+    batch = mpcgen.make_batch(config, indices=[b])
+    p = mpcgen.problem_fp64(batch, 0)
+    p.update(over)
+    return p
+
+
+# --------------------------------------------------------------- projection
+
+def _vertices(mu, fz):
+    return [np.zeros(3)] + [np.array([sx * mu * fz, sy * mu * fz, fz])
+                            for sx in (-1, 1) for sy in (-1, 1)]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_projection_first_order_optimality(seed):
+    """P(y) is the projection iff it is feasible and <y-P, w-P> <= 0 for all
+    w in the set; for a polytope checking the vertices suffices."""
+    rng = np.random.default_rng(seed)
+    mu, fz = 0.3 + 0.6 * rng.random(), 200 + 800 * rng.random()
+    G, h = projection.force_rows(mu, fz)
+    pts = [rng.normal(0, 400, 3) for _ in range(60)]
+    pts += [rng.normal(0, 1e-3, 3), np.array([0.0, 0.0, -5.0]),
+            np.array([10.0, -3.0, 3 * fz]), np.array([mu * fz, mu * fz, fz])]
+    for y in pts:
+        P = projection.project_force(y, mu, fz)
+        assert np.max(G @ P - h) <= 1e-9 * fz
+        for w in _vertices(mu, fz):
+            assert (y - P) @ (w - P) <= 1e-7 * (1 + np.linalg.norm(y) ** 2)
+        # idempotent
+        assert np.allclose(projection.project_force(P, mu, fz), P, atol=1e-9 * fz)
+
+
+def test_projection_nonexpansive_and_swing():
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        a, b = rng.normal(0, 500, 3), rng.normal(0, 500, 3)
+        Pa = projection.project_force(a, 0.5, 700.0)
+        Pb = projection.project_force(b, 0.5, 700.0)
+        assert np.linalg.norm(Pa - Pb) <= np.linalg.norm(a - b) * (1 + 1e-12)
+    y = rng.normal(0, 100, 6)
+    assert np.all(projection.project_contact(y, False, 0.5, 700.0, 50.0) == 0)
+    m = projection.project_contact(np.array([0, 0, 10, 80, -80, 3.0]), True, 0.5, 700.0, 50.0)
+    assert np.allclose(m[3:], [50, -50, 3])
+
+
+# ----------------------------------------------------- unconstrained special
+
+def _riccati_lq(p):
+    """Textbook time-varying finite-horizon LQ tracking by backward Riccati."""
+    N = p["N"]
+    Q, R = np.diag(p["Q"]), np.diag(p["R"])
+    S = np.zeros((NX, NX))
+    s = np.zeros(NX)
+    K = [None] * N
+    kf = [None] * N
+    for k in range(N - 1, -1, -1):
+        A, B, e = p["A"][k], p["B"][k], p["e"][k]
+        W = Q + S
+        w = s - Q @ p["x_ref"][k]
+        Huu = R + B.T @ W @ B
+        Hux = B.T @ W @ A
+        hu = B.T @ (W @ e + w) - R @ p["u_ref"][k]
+        K[k] = -np.linalg.solve(Huu, Hux)
+        kf[k] = -np.linalg.solve(Huu, hu)
+        S = A.T @ W @ A + Hux.T @ K[k]
+        s = A.T @ (W @ e + w) + Hux.T @ kf[k]
+    x = p["x0"].copy()
+    u = np.zeros((N, NU))
+    for k in range(N):
+        u[k] = K[k] @ x + kf[k]
+        x = p["A"][k] @ x + p["B"][k] @ u[k] + p["e"][k]
+    return u
+
+
+def _loose(p):
+    q = dict(p)
+    q["contact"] = np.ones_like(p["contact"])
+    q["mu"], q["fz_max"], q["tau_max"] = 1e6, 1e9, 1e9
+    return q
+
+
+@pytest.mark.parametrize("config,b", [("small_b64_n10", 0), ("small_b64_n10", 3),
+                                      ("plain_b4096_n20", 1)])
+def test_unconstrained_equals_riccati(config, b):
+    p = _loose(_prob(config, b))
+    u_ric = _riccati_lq(p)
+    Gc, hc = projection.wrench_rows(p["mu"], p["fz_max"], p["tau_max"])
+    slack = min(np.min(hc - Gc @ u_ric[k, 6 * i:6 * i + 6]) for k in range(p["N"]) for i in range(2))
+    assert slack > 0, "case must be strictly inside the loose set"
+    sol = qp.solve(p)
+    assert np.max(np.abs(sol["u"] - u_ric)) <= 1e-8 * max(1.0, np.max(np.abs(u_ric)))
+    # the dense condensed normal equations agree too
+    H, g, G, h, free, _ = qp.dense_qp(p)
+    U = np.linalg.solve(H, -g)
+    assert np.max(np.abs(U - u_ric.reshape(-1)[free])) <= 1e-8 * np.max(np.abs(u_ric))
+
+
+def test_single_stage_closed_form():
+    p = _loose(_prob("small_b64_n10", 5))
+    p["N"] = 1
+    for key in ("A", "B", "e", "x_ref", "u_ref", "contact"):
+        p[key] = p[key][:1]
+    A, B, e = p["A"][0], p["B"][0], p["e"][0]
+    Q, R = np.diag(p["Q"]), np.diag(p["R"])
+    u = np.linalg.solve(R + B.T @ Q @ B,
+                        B.T @ Q @ (p["x_ref"][0] - A @ p["x0"] - e) + R @ p["u_ref"][0])
+    sol = qp.solve(p)
+    assert np.allclose(sol["u"][0], u, rtol=0, atol=1e-8 * np.max(np.abs(u)))
+
+
+# ------------------------------------------------------------- brute force
+
+FORCE_FACES = [(), (0,), (1,), (2,), (3,), (4,), (0, 2), (0, 3), (1, 2), (1, 3),
+               (0, 4), (1, 4), (2, 4), (3, 4), (0, 2, 4), (0, 3, 4), (1, 2, 4),
+               (1, 3, 4), (0, 1, 2, 3)]
+
+
+def _brute_force(p, with_moments):
+    """Least-cost feasible candidate over every face combination.
+
+    The optimum of a convex QP lies in the relative interior of one face of
+    the feasible polytope and minimises the cost over that face's affine hull,
+    so the feasible face minimiser of least cost is the optimum."""
+    N = p["N"]
+    stance = [(k, i) for k in range(N) for i in range(2) if p["contact"][k][i]]
+    nv = 6 * len(stance)
+
+    def cost(U):
+        u = np.zeros((N, NU))
+        for j, (k, i) in enumerate(stance):
+            u[k, 6 * i:6 * i + 6] = U[6 * j:6 * j + 6]
+        x, c = p["x0"], 0.0
+        for k in range(N):
+            x = p["A"][k] @ x + p["B"][k] @ u[k] + p["e"][k]
+            c += 0.5 * np.sum(p["Q"] * (x - p["x_ref"][k]) ** 2)
+            c += 0.5 * np.sum(p["R"] * (u[k] - p["u_ref"][k]) ** 2)
+        return c
+
+    # exact quadratic model by polarisation (unit steps of 1 N / 1 N m)
+    c0 = cost(np.zeros(nv))
+    E = np.eye(nv)
+    ci = np.array([cost(E[a]) for a in range(nv)])
+    H = np.zeros((nv, nv))
+    for a in range(nv):
+        for b in range(a, nv):
+            H[a, b] = H[b, a] = cost(E[a] + E[b]) - ci[a] - ci[b] + c0
+    g = ci - c0 - 0.5 * np.diag(H)
+
+    mu, fz, tm = p["mu"], p["fz_max"], p["tau_max"]
+    Gf = np.array([[1, 0, -mu], [-1, 0, -mu], [0, 1, -mu], [0, -1, -mu], [0, 0, 1.0]])
+    hf = np.array([0, 0, 0, 0, fz])
+    rowsG, rowsh = [], []
+    for j in range(len(stance)):
+        for r in range(5):
+            v = np.zeros(nv)
+            v[6 * j:6 * j + 3] = Gf[r]
+            rowsG.append(v)
+            rowsh.append(hf[r])
+        for a in range(3):
+            for sgn in (1.0, -1.0):
+                v = np.zeros(nv)
+                v[6 * j + 3 + a] = sgn
+                rowsG.append(v)
+                rowsh.append(tm)
+    G, h = np.array(rowsG), np.array(rowsh)
+
+    moment_states = list(itertools.product((0, 1, -1), repeat=3)) if with_moments else [(0, 0, 0)]
+    per_contact = list(itertools.product(FORCE_FACES, moment_states))
+    best, best_c, best_nact = None, np.inf, 0
+    for combo in itertools.product(per_contact, repeat=len(stance)):
+        eqG, eqh = [], []
+        for j, (ff, ms) in enumerate(combo):
+            for r in ff:
+                eqG.append(G[11 * j + r])
+                eqh.append(h[11 * j + r])
+            for a, st in enumerate(ms):
+                if st:
+                    v = np.zeros(nv)
+                    v[6 * j + 3 + a] = 1.0
+                    eqG.append(v)
+                    eqh.append(st * tm)
+        m = len(eqG)
+        Kmat = np.zeros((nv + m, nv + m))
+        Kmat[:nv, :nv] = H
+        rhs = np.concatenate([-g, np.array(eqh, dtype=float)])
+        if m:
+            Ge = np.array(eqG)
+            Kmat[:nv, nv:] = Ge.T
+            Kmat[nv:, :nv] = Ge
+        sol = np.linalg.lstsq(Kmat, rhs, rcond=None)[0]
+        U = sol[:nv]
+        if m and np.max(np.abs(np.array(eqG) @ U - eqh)) > 1e-7 * (1 + fz):
+            continue
+        if np.max(G @ U - h) > 1e-7 * (1 + fz):
+            continue
+        cU = 0.5 * U @ H @ U + g @ U
+        if cU < best_c:
+            best, best_c, best_nact = U, cU, m
+    return best, stance, best_nact
+
+
+def _to_u(U, stance, N):
+    u = np.zeros((N, NU))
+    for j, (k, i) in enumerate(stance):
+        u[k, 6 * i:6 * i + 6] = U[6 * j:6 * j + 6]
+    return u
+
+
+def _trim(p, N, contact, **over):
+    q = dict(p)
+    q["N"] = N
+    for key in ("A", "B", "e", "x_ref", "u_ref"):
+        q[key] = p[key][:N]
+    q["contact"] = np.array(contact, dtype=bool)
+    q.update(over)
+    return q
+
+
+@pytest.mark.parametrize("b", [0, 2])
+def test_bruteforce_one_stage_full_wrench(b):
+    p = _prob("small_b64_n10", b)
+    p = _trim(p, 1, [[True, False]], tau_max=2.0, fz_max=0.45 * p["weight"])
+    U, stance, nact = _brute_force(p, with_moments=True)
+    assert nact >= 1
+    u_bf = _to_u(U, stance, 1)
+    sol = qp.solve(p)
+    assert np.max(np.abs(sol["u"] - u_bf)) <= 1e-6 * p["weight"]
+
+
+def test_bruteforce_three_stages_forces():
+    p = _prob("small_b64_n10", 1)
+    p = _trim(p, 3, [[True, False], [True, False], [False, True]], tau_max=1e6,
+              fz_max=0.8 * p["weight"], mu=0.35)
+    U, stance, nact = _brute_force(p, with_moments=False)
+    assert nact >= 1
+    sol = qp.solve(p)
+    assert np.max(np.abs(sol["u"] - _to_u(U, stance, 3))) <= 1e-6 * p["weight"]
+
+
+def test_bruteforce_double_support_forces():
+    p = _prob("plain_b4096_n20", 4)
+    p = _trim(p, 1, [[True, True]], tau_max=1e6, fz_max=0.4 * p["weight"], mu=0.3)
+    U, stance, nact = _brute_force(p, with_moments=False)
+    assert nact >= 1
+    sol = qp.solve(p)
+    assert np.max(np.abs(sol["u"] - _to_u(U, stance, 1))) <= 1e-6 * p["weight"]
+
+
+# -------------------------------------------------------------- certificate
+
+@pytest.mark.parametrize("config,count", [("small_b64_n10", 6), ("plain_b4096_n20", 3),
+                                          ("uneven_b16384", 2)])
+def test_oracle_kkt_certificate(config, count):
+    batch = mpcgen.make_batch(config, indices=range(count))
+    for b in range(count):
+        p = mpcgen.problem_fp64(batch, b)
+        sol = qp.solve(p)
+        r = kkt.residuals(p, sol["u"], sol["x"], sol["lam"], sol["mu"])
+        assert r["kkt"] <= 1e-10, r
+        r2 = kkt.residuals(p, sol["u"], sol["x"])     # multipliers refitted
+        assert r2["kkt"] <= 1e-10, r2
+        assert np.all(sol["mu"] >= 0)
+
+
+def test_kkt_measure_detects_planted_errors():
+    p = _prob("small_b64_n10", 2)
+    sol = qp.solve(p)
+    u = sol["u"].copy()
+    k, i = np.argwhere(p["contact"])[0]
+    u[k, 6 * i + 2] += 5.0             # 5 N off the optimum on a stance f_z
+    r = kkt.residuals(p, u, qp.rollout(p, u))
+    assert r["r_stat"] > 1e-6
+    x = sol["x"].copy()
+    x[3, 4] += 1e-3                    # dynamics violated
+    assert kkt.residuals(p, sol["u"], x)["r_dyn"] > 1e-5
+    u2 = sol["u"].copy()
+    sw = np.argwhere(~p["contact"])[0]
+    u2[sw[0], 6 * sw[1]] = 1.0          # swing contact carries a force
+    assert kkt.residuals(p, u2, qp.rollout(p, u2))["r_ineq"] > 1e-3
+    eu, ex = kkt.rel_err(u, sol["u"], sol["x"], sol["x"], p["weight"])
+    assert eu > 1e-3 and ex == 0
+
+
+# ----------------------------------------------------- ADMM (Sec. III) pins
+
+def _lifted(p):
+    """Abar, Bbar, ebar, Qbar, qbar written from Sec. III directly."""
+    N = p["N"]
+    Ab = [np.block([[p["A"][k], p["B"][k]], [np.zeros((NU, NX)), np.eye(NU)]]) for k in range(N)]
+    Bb = [np.vstack([p["B"][k], np.eye(NU)]) for k in range(N)]
+    eb = [np.concatenate([p["e"][k], np.zeros(NU)]) for k in range(N)]
+    Qb = np.diag(np.concatenate([p["Q"], p["R"]]))
+    qb = [Qb @ np.concatenate([p["x_ref"][k], p["u_ref"][k]]) for k in range(N)]
+    return Ab, Bb, eb, Qb, qb
+
+
+def test_lifting_identity():
+    p = _prob("small_b64_n10", 4)
+    rng = np.random.default_rng(3)
+    u = rng.normal(0, 200, (p["N"], NU))
+    u_prev = rng.normal(0, 50, NU)
+    x = qp.rollout(p, u)
+    c = admm.setup(p, 1.0, scaling=False)
+    xi = np.concatenate([p["x0"], u_prev])
+    prev = u_prev
+    for k in range(p["N"]):
+        xi = c["Ab"][k] @ xi + c["Bb"][k] @ (u[k] - prev) + c["eb"][k]
+        prev = u[k]
+        assert np.allclose(xi[:NX], x[k + 1], atol=1e-9 * (1 + np.abs(x[k + 1]).max()))
+        assert np.allclose(xi[NX:], u[k])
+    Ab, Bb, eb, _, _ = _lifted(p)
+    for k in range(p["N"]):
+        assert np.allclose(Ab[k], c["Ab"][k]) and np.allclose(Bb[k], c["Bb"][k])
+        # B_bar^T B_bar = B^T B + I (Sec. III) and J_k B_bar_k = I
+        assert np.allclose(Bb[k].T @ Bb[k], p["B"][k].T @ p["B"][k] + np.eye(NU))
+        assert np.allclose(c["J"][k] @ Bb[k], np.eye(NU), atol=1e-12)
+
+
+def _aug_lagrangian(p, rho, xi0, du, xi, z, v, th, be, la, Ab, Bb, eb, Qb, qb):
+    """Scaled augmented Lagrangian of Sec. III (indicator omitted; the second
+    penalty uses Bbar_k)."""
+    L = 0.0
+    for k in range(p["N"]):
+        prev = xi0 if k == 0 else xi[k - 1]
+        L += 0.5 * xi[k] @ Qb @ xi[k] - qb[k] @ xi[k]
+        L += 0.5 * rho * np.sum((xi[k] - z[k] + th[k]) ** 2)
+        L += 0.5 * rho * np.sum((Bb[k] @ du[k] - v[k] + be[k]) ** 2)
+        L += 0.5 * rho * np.sum((z[k] - Ab[k] @ prev - v[k] - eb[k] + la[k]) ** 2)
+    return L
+
+
+def _random_state(p, seed):
+    rng = np.random.default_rng(seed)
+    N = p["N"]
+    return {k: rng.normal(0, 1, (N, 25)) * np.concatenate([np.ones(NX), 100 * np.ones(NU)])
+            for k in ("z", "v", "th", "be", "la")}
+
+
+def test_admm_block1_is_exact_minimiser():
+    p = _prob("small_b64_n10", 6)
+    p["N"] = 4
+    for key in ("A", "B", "e", "x_ref", "u_ref", "contact"):
+        p[key] = p[key][:4]
+    rho = 0.7
+    st = _random_state(p, 11)
+    c = admm.setup(p, rho, scaling=False)
+    _, aux = admm.iterate(p, c, st)
+    Ab, Bb, eb, Qb, qb = _lifted(p)
+    xi0 = np.concatenate([p["x0"], p["u_prev"]])
+
+    def L(du, xi):
+        return _aug_lagrangian(p, rho, xi0, du, xi, st["z"], st["v"], st["th"], st["be"],
+                               st["la"], Ab, Bb, eb, Qb, qb)
+
+    du, xi = aux["du"], aux["xi"]
+    base = L(du, xi)
+    for arr, name in ((du, "du"), (xi, "xi")):
+        for idx in [(0, 0), (1, 5), (3, 11), (2, 3)] + ([(0, 20), (3, 24)] if name == "xi" else []):
+            h = 1e-2
+            a1 = arr.copy()
+            a1[idx] += h
+            a2 = arr.copy()
+            a2[idx] -= h
+            if name == "du":
+                grad = (L(a1, xi) - L(a2, xi)) / (2 * h)
+                curv = (L(a1, xi) - 2 * base + L(a2, xi)) / h ** 2
+            else:
+                grad = (L(du, a1) - L(du, a2)) / (2 * h)
+                curv = (L(du, a1) - 2 * base + L(du, a2)) / h ** 2
+            assert abs(grad) <= 1e-6 * (1 + abs(base)) ** 0.5 * max(curv, 1), (name, idx, grad)
+
+
+def _sample_feasible(rng, p, k):
+    """A random point of Xbar_k = R^13 x U_k (convex combination of
+    pyramid vertices, box moments, zero on swing)."""
+    w = rng.normal(0, 1, NX)
+    u = np.zeros(NU)
+    for i in range(2):
+        if p["contact"][k][i]:
+            lam = rng.dirichlet(np.ones(5))
+            verts = _vertices(p["mu"], p["fz_max"])
+            u[6 * i:6 * i + 3] = sum(l * v for l, v in zip(lam, verts))
+            u[6 * i + 3:6 * i + 6] = rng.uniform(-p["tau_max"], p["tau_max"], 3)
+    return np.concatenate([w, u])
+
+
+def test_admm_block2_is_minimiser_over_set():
+    p = _prob("small_b64_n10", 7)
+    rho = 1.3
+    st = _random_state(p, 5)
+    c = admm.setup(p, rho, scaling=False)
+    new, aux = admm.iterate(p, c, st)
+    Ab, Bb, eb, _, _ = _lifted(p)
+    xi0 = np.concatenate([p["x0"], p["u_prev"]])
+    rng = np.random.default_rng(0)
+    for k in range(p["N"]):
+        prev = xi0 if k == 0 else aux["xi"][k - 1]
+        a = aux["xi"][k] + st["th"][k]
+        b = Bb[k] @ aux["du"][k] + st["be"][k]
+        cc = Ab[k] @ prev + eb[k] - st["la"][k]
+
+        def phi(z, v):
+            return np.sum((z - a) ** 2) + np.sum((v - b) ** 2) + np.sum((z - v - cc) ** 2)
+
+        z, v = new["z"][k], new["v"][k]
+        assert np.allclose(v, 0.5 * (b + z - cc), atol=1e-9 * (1 + np.abs(v).max()))
+        best = phi(z, v)
+        for _ in range(200):
+            zt = _sample_feasible(rng, p, k)
+            t = rng.uniform(0, 1)
+            zt = z + t * (zt - z)            # points along feasible directions
+            vt = 0.5 * (b + zt - cc)
+            assert phi(zt, vt) >= best - 1e-9 * (1 + best)
+
+
+def test_admm_fixed_point_is_the_qp_optimum():
+    """At an ADMM fixed point the KKT conditions hold (Sec. III updates), so
+    the iterates converge to the oracle optimum, whatever u_prev is."""
+    p = _prob("small_b64_n10", 8)
+    p = _trim(p, 4, [[True, False], [True, False], [True, True], [False, True]],
+              R=np.full(NU, 2e-3))
+    ref = qp.solve(p)
+    for u_prev in (np.zeros(NU), np.linspace(-50, 50, NU)):
+        p["u_prev"] = u_prev
+        out = admm.solve(p, iters=2500, rho=10.0, scaling=True, accel=True)
+        eu, ex = kkt.rel_err(out["u"], ref["u"], out["x"], ref["x"], p["weight"])
+        assert eu <= 1e-6 and ex <= 1e-6, (eu, ex)
+        # multiplier recovery at the fixed point: p_{k+1} = -rho lambda_{k,x}
+        assert np.allclose(out["lam_x"], ref["lam"], atol=1e-3 * (1 + np.abs(ref["lam"]).max()))
+
+
+# ---------------------------------------------------------------- generator
+
+def test_generator_subsets_are_reproducible():
+    full = mpcgen.make_batch("uneven_b16384", indices=range(12), n_max=60)
+    sub = mpcgen.make_batch("uneven_b16384", indices=[3, 7, 11], n_max=60)
+    for k in full:
+        assert np.array_equal(full[k][[3, 7, 11]], sub[k]), k
+    assert full["A"].dtype == np.float32 and full["contact"].dtype == np.uint8
+    for b in range(12):
+        N = full["N"][b]
+        assert np.all(full["B"][b, N:] == 0) and np.all(full["contact"][b, N:] == 0)
+        assert set(np.unique(full["N"])) <= {10, 20, 30, 40, 60}
+    empty = mpcgen.make_batch("plain_b4096_n20", indices=[])
+    assert empty["A"].shape == (0, 20, 13, 13)
+
+
+def test_generator_dynamics_structure():
+    b = mpcgen.make_batch("small_b64_n10", indices=[0])
+    A, B = b["A"][0, 0].astype(np.float64), b["B"][0, 0].astype(np.float64)
+    dt = mpcgen.CONFIGS["small_b64_n10"]["dt"]
+    # gravity enters v_z through the constant gravity state
+    assert np.isclose(A[11, 12], dt)
+    # only the angular and linear acceleration rows of B are nonzero: rank 6
+    assert np.all(B[:6] == 0) and np.all(B[12] == 0)
+    assert np.linalg.matrix_rank(B) == 6
+    assert np.isclose(B[9, 0], dt * mpcgen.GRAVITY / b["weight"][0], rtol=1e-5)
