@@ -1,0 +1,161 @@
+/* pinmpc.h -- C ABI of the MI355X batched parallel-in-horizon MPC solver.
+ *
+ * Solves, for every problem b of a batch independently, the standard-form
+ * linear time-varying MPC quadratic program of the paper's Sec. III
+ * ("pi^n MPC", with C = I):
+ *
+ *   min  sum_{k=0}^{N-1} 1/2 (x_{k+1} - x_ref[k])^T Q (x_{k+1} - x_ref[k])
+ *                        + 1/2 (u_k - u_ref[k])^T R (u_k - u_ref[k])
+ *   s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,   x_0 = x0,
+ *        stance contact i at stage k:  |f_x|, |f_y| <= mu f_z,  f_z <= fz_max,
+ *                                      |tau_j| <= tau_max          (Sec. II-B)
+ *        swing contact:                f = 0, tau = 0
+ *
+ * with n = 13 states, m = 12 inputs = 2 contacts x (force 3, moment 3), in
+ * the order (f0x, f0y, f0z, t0x, t0y, t0z, f1x, ..., t1z).
+ *
+ * The solve runs the paper's ADMM (velocity-form lifting, the z/v variable
+ * splitting, three stage-parallel closed-form block updates with cached
+ * J_k, H_k, Nesterov-type acceleration with restart) in FP32 on the GPU, then
+ * an FP64 refinement on the GPU (active-set passes from the ADMM faces, an
+ * interior-point fallback, an exact equality-constrained Riccati polish) that
+ * certifies every result by its KKT residuals.
+ *
+ * Conventions
+ *  - Every array pointer in pinmpc_batch / pinmpc_out is a DEVICE pointer
+ *    (for example a torch tensor's data_ptr()).  The caller owns every buffer
+ *    it passes; the library never frees caller memory.  The library owns only
+ *    its workspace, allocated lazily inside pinmpc_solve and bounded by the
+ *    context's hbm_budget_bytes.
+ *  - All calls are ordered on the given hipStream_t (NULL = default stream).
+ *    pinmpc_solve returns after enqueuing; results are ready when the stream
+ *    reaches that point.  A context must not be used from two host threads at
+ *    once and must not run two solves concurrently (workspace is shared).
+ *  - Layout is row-major C order, problem index slowest.  Horizons shorter
+ *    than n_max are padded at the end; padded stages are ignored.
+ *  - Return codes: < 0 is an API error (the context stays usable); a problem
+ *    that does not certify is not an error, it gets a per-problem status.
+ */
+#ifndef PINMPC_H
+#define PINMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PINMPC_NX 13
+#define PINMPC_NU 12
+#define PINMPC_NCONTACT 2
+#define PINMPC_NRES 5      /* r_dyn, r_ineq, r_stat, r_comp, r_sign */
+#define PINMPC_NMAX 64     /* largest supported horizon */
+
+enum {
+  PINMPC_OK = 0,
+  PINMPC_EINVAL = -1,   /* bad argument: null pointer, size or setting */
+  PINMPC_ENOMEM = -2,   /* device allocation failed */
+  PINMPC_EBUDGET = -3,  /* workspace would exceed hbm_budget_bytes */
+  PINMPC_EDEVICE = -4,  /* HIP runtime or launch error */
+  PINMPC_EBUSY = -5     /* server: no free slot / request still running */
+};
+
+/* Per-problem status written to pinmpc_out.status. */
+enum {
+  PINMPC_ST_OK = 0,          /* certified: every KKT residual <= kkt_tol */
+  PINMPC_ST_MAXITER = 1,     /* refinement disabled; ADMM iterate returned */
+  PINMPC_ST_UNPOLISHED = 2,  /* refinement ran out of passes; best iterate */
+  PINMPC_ST_NONFINITE = 3,   /* NaN/Inf in this problem's data */
+  PINMPC_ST_BADINPUT = 4     /* malformed bounds (mu < 0, fz_max < 0, ...) */
+};
+
+/* Solver settings.  pinmpc_default_settings fills the defaults. */
+typedef struct {
+  float rho;               /* ADMM penalty (Sec. III rho); default 10 */
+  int32_t iters;           /* ADMM sweeps K (fixed count); default 100 */
+  int32_t accel;           /* 1: fast ADMM with restart; default 1 */
+  float restart_eta;       /* restart test c_m < eta c_{m-1}; default 0.999 */
+  int32_t scaling;         /* 1: block-constant input scaling; default 1 */
+  int32_t refine;          /* 1: FP64 refinement and certificate; default 1 */
+  int32_t refine_passes;   /* active-set passes from the ADMM faces; 8 */
+  int32_t ipm_iters;       /* interior-point fallback iterations cap; 40 */
+  int32_t polish_passes;   /* active-set passes after the fallback; 6 */
+  double kkt_tol;          /* certification threshold; default 1e-9 */
+  int32_t precision;       /* 0: FP32 operators; 1: BF16 operators */
+  int32_t form;            /* 0: plain (one launch per sweep);
+                              1: fused persistent sweep kernel;
+                              -1: choose (autotuner) */
+} pinmpc_settings;
+
+typedef struct pinmpc_ctx_s* pinmpc_ctx;
+
+/* One batch of problems (device pointers). */
+typedef struct {
+  int32_t batch;           /* number of problems B (0 allowed) */
+  int32_t n_max;           /* padded horizon, 1..PINMPC_NMAX */
+  const int32_t* N;        /* [B] horizon per problem in 1..n_max; NULL: all n_max */
+  const float* A;          /* [B][n_max][13][13] */
+  const float* Bu;         /* [B][n_max][13][12] */
+  const float* e;          /* [B][n_max][13]; NULL: 0 */
+  const float* x0;         /* [B][13] */
+  const float* u_prev;     /* [B][12] input before stage 0 (velocity form); NULL: 0 */
+  const float* x_ref;      /* [B][n_max][13] reference of x_{k+1} */
+  const float* u_ref;      /* [B][n_max][12]; NULL: 0 */
+  const float* Q;          /* [B][13] diagonal state weight, > 0 */
+  const float* R;          /* [B][12] diagonal input weight, > 0 */
+  const uint8_t* contact;  /* [B][n_max][2] 1 = stance, 0 = swing */
+  const float* mu;         /* [B] friction coefficient */
+  const float* fz_max;     /* [B] normal-force upper bound */
+  const float* tau_max;    /* [B] moment bound per axis */
+  const float* weight;     /* [B] force scale m g (input scaling and residual
+                              normalisation); NULL: fz_max / 2 */
+} pinmpc_batch;
+
+/* Outputs (device pointers, caller-allocated). */
+typedef struct {
+  float* u;                /* [B][n_max][12] optimal inputs (0 on padding) */
+  float* x;                /* [B][n_max+1][13] rollout of u (x_0 = x0) */
+  float* res;              /* [B][PINMPC_NRES] FP64-evaluated KKT residuals,
+                              normalised as documented in DESIGN; may be NULL */
+  int32_t* iters;          /* [B] ADMM sweeps + refinement passes; may be NULL */
+  int32_t* status;         /* [B] PINMPC_ST_*; may be NULL */
+} pinmpc_out;
+
+/* Fill *s with the defaults listed above. */
+void pinmpc_default_settings(pinmpc_settings* s);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * library's workspace (0 = 64 GiB).  Settings are copied. */
+int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
+                  const pinmpc_settings* s);
+
+/* Replace the context's settings (validated). */
+int pinmpc_set_settings(pinmpc_ctx c, const pinmpc_settings* s);
+
+/* Bytes of workspace a solve of this shape needs (host call, no GPU work). */
+int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_max,
+                           size_t* bytes);
+
+/* Solve every problem of `in`; results into `out`.  Stream-ordered. */
+int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out,
+                 void* hip_stream);
+
+/* ADMM only, no refinement, into caller buffers: for iterate-level checks.
+ * z_out: [B][n_max][25] final z iterates (lifted (x_{k+1}, u_k), unscaled u). */
+int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters,
+                float* z_out, void* hip_stream);
+
+/* Time of the last solve's phases in ms (host pointers; any may be NULL).
+ * Blocks until the last solve finished.  setup+admm+refine = total. */
+int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms,
+                 double* admm_ms, double* refine_ms);
+
+int pinmpc_destroy(pinmpc_ctx c);
+
+const char* pinmpc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINMPC_H */

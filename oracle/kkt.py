@@ -15,7 +15,9 @@ reported with.  For one problem with force scale m g (``weight``):
             components) and grad_{x_{k+1}} L = Q (x_{k+1} - r_k) - p_{k+1}
             + A_{k+1}^T p_{k+2}
   r_comp    max_i mu_i [h_i - G_i u]_+ / (1 + |mu|_inf m g)
-  KKT       max(r_dyn, r_ineq, r_stat, r_comp)
+  r_sign    max_i [-mu_i]_+ / (1 + the largest term norm of r_stat): the
+            multipliers of inequality rows must be nonnegative
+  KKT       max(r_dyn, r_ineq, r_stat, r_comp, r_sign)
 
 When no multipliers are given, the costates come from the adjoint recursion
 on x and each stance contact's row multipliers from a nonnegative least-squares
@@ -106,6 +108,12 @@ def residuals(p, u, x, lam=None, mu=None, act_tol=1e-7):
             terms.append(abs(al).max())
         stat = max(stat, abs(gx).max())
     r_stat = stat / (1.0 + max(terms))
-    out = dict(r_dyn=r_dyn, r_ineq=r_ineq, r_stat=r_stat, r_comp=r_comp)
+    neg = 0.0
+    for k in range(N):
+        for i in range(2):
+            if p["contact"][k][i]:
+                neg = max(neg, float(np.max(-mu[k, i])))
+    r_sign = max(0.0, neg) / (1.0 + max(terms))
+    out = dict(r_dyn=r_dyn, r_ineq=r_ineq, r_stat=r_stat, r_comp=r_comp, r_sign=r_sign)
     out["kkt"] = max(out.values())
     return out

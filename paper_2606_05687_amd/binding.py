@@ -1,0 +1,226 @@
+"""ctypes binding of libpinmpc (argument marshalling only).
+
+Every step of the solve runs in the HIP library; this module only fills the
+C structs with device pointers of torch tensors and passes the caller's HIP
+stream.  It fails loudly when the library is missing: there is no host
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpinmpc.so")
+
+NX, NU, NRES = 13, 12, 5
+ST_OK, ST_MAXITER, ST_UNPOLISHED, ST_NONFINITE, ST_BADINPUT = range(5)
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [
+        ("rho", ctypes.c_float),
+        ("iters", ctypes.c_int32),
+        ("accel", ctypes.c_int32),
+        ("restart_eta", ctypes.c_float),
+        ("scaling", ctypes.c_int32),
+        ("refine", ctypes.c_int32),
+        ("refine_passes", ctypes.c_int32),
+        ("ipm_iters", ctypes.c_int32),
+        ("polish_passes", ctypes.c_int32),
+        ("kkt_tol", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("form", ctypes.c_int32),
+    ]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("batch", ctypes.c_int32),
+        ("n_max", ctypes.c_int32),
+        ("N", ctypes.c_void_p),
+        ("A", ctypes.c_void_p),
+        ("Bu", ctypes.c_void_p),
+        ("e", ctypes.c_void_p),
+        ("x0", ctypes.c_void_p),
+        ("u_prev", ctypes.c_void_p),
+        ("x_ref", ctypes.c_void_p),
+        ("u_ref", ctypes.c_void_p),
+        ("Q", ctypes.c_void_p),
+        ("R", ctypes.c_void_p),
+        ("contact", ctypes.c_void_p),
+        ("mu", ctypes.c_void_p),
+        ("fz_max", ctypes.c_void_p),
+        ("tau_max", ctypes.c_void_p),
+        ("weight", ctypes.c_void_p),
+    ]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [
+        ("u", ctypes.c_void_p),
+        ("x", ctypes.c_void_p),
+        ("res", ctypes.c_void_p),
+        ("iters", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = {
+    "pinmpc_default_settings": (None, [ctypes.POINTER(Settings)]),
+    "pinmpc_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                     ctypes.c_size_t, ctypes.POINTER(Settings)]),
+    "pinmpc_set_settings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Settings)]),
+    "pinmpc_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Settings), ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "pinmpc_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Out),
+                                    ctypes.c_void_p]),
+    "pinmpc_admm": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "pinmpc_stats": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 4),
+    "pinmpc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pinmpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpinmpc.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpinmpc.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PinmpcError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != 0:
+        raise PinmpcError(f"pinmpc error {rc}: {load().pinmpc_strerror(rc).decode()}")
+
+
+def default_settings(**over) -> Settings:
+    s = Settings()
+    load().pinmpc_default_settings(ctypes.byref(s))
+    for k, v in over.items():
+        if not hasattr(s, k):
+            raise KeyError(k)
+        setattr(s, k, v)
+    return s
+
+
+FIELDS = ("N", "A", "B", "e", "x0", "u_prev", "x_ref", "u_ref", "Q", "R", "contact",
+          "mu", "fz_max", "tau_max", "weight")
+
+
+def to_device(batch: dict, device="cuda"):
+    """Copy a generator batch (numpy) to device tensors (torch)."""
+    import torch
+    out = {}
+    for k in FIELDS:
+        if k in batch and batch[k] is not None:
+            out[k] = torch.from_numpy(np.ascontiguousarray(batch[k])).to(device)
+    return out
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_batch_struct(dev: dict) -> Batch:
+    import torch
+    A = dev["A"]
+    assert A.dtype == torch.float32 and A.is_contiguous()
+    b = Batch()
+    b.batch, b.n_max = int(A.shape[0]), int(A.shape[1])
+    for k in FIELDS:
+        t = dev.get(k)
+        if t is not None:
+            assert t.is_contiguous() and t.shape[0] == b.batch, k
+        setattr(b, "Bu" if k == "B" else k, None if t is None else t.data_ptr())
+    return b
+
+
+class Solver:
+    """One library context on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, **settings):
+        lib = load()
+        self.settings = default_settings(**settings)
+        h = ctypes.c_void_p()
+        _check(lib.pinmpc_create(ctypes.byref(h), int(device), int(hbm_budget),
+                                 ctypes.byref(self.settings)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pinmpc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, **over):
+        for k, v in over.items():
+            setattr(self.settings, k, v)
+        _check(load().pinmpc_set_settings(self._h, ctypes.byref(self.settings)))
+
+    def alloc_out(self, dev):
+        import torch
+        Bn, n = int(dev["A"].shape[0]), int(dev["A"].shape[1])
+        d = dev["A"].device
+        return {
+            "u": torch.empty((Bn, n, NU), dtype=torch.float32, device=d),
+            "x": torch.empty((Bn, n + 1, NX), dtype=torch.float32, device=d),
+            "res": torch.empty((Bn, NRES), dtype=torch.float32, device=d),
+            "iters": torch.empty((Bn,), dtype=torch.int32, device=d),
+            "status": torch.empty((Bn,), dtype=torch.int32, device=d),
+        }
+
+    def solve(self, dev: dict, out: dict | None = None, stream=None, batch_struct=None):
+        """Solve the batch held in device tensors; returns the output tensors."""
+        import torch
+        if out is None:
+            out = self.alloc_out(dev)
+        b = batch_struct if batch_struct is not None else make_batch_struct(dev)
+        o = Out(out["u"].data_ptr(), out["x"].data_ptr(),
+                None if out.get("res") is None else out["res"].data_ptr(),
+                None if out.get("iters") is None else out["iters"].data_ptr(),
+                None if out.get("status") is None else out["status"].data_ptr())
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().pinmpc_solve(self._h, ctypes.byref(b), ctypes.byref(o),
+                                   ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def admm(self, dev: dict, iters: int, stream=None):
+        """ADMM only: final z iterates [B][n][25] (unscaled)."""
+        import torch
+        Bn, n = int(dev["A"].shape[0]), int(dev["A"].shape[1])
+        z = torch.empty((Bn, n, NX + NU), dtype=torch.float32, device=dev["A"].device)
+        b = make_batch_struct(dev)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().pinmpc_admm(self._h, ctypes.byref(b), int(iters),
+                                  ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+        return z
+
+    def stats(self):
+        vals = [ctypes.c_double() for _ in range(4)]
+        _check(load().pinmpc_stats(self._h, *[ctypes.byref(v) for v in vals]))
+        return dict(zip(("total_ms", "setup_ms", "admm_ms", "refine_ms"), [v.value for v in vals]))

@@ -1,0 +1,379 @@
+// Plain batched form of the parallel-in-horizon ADMM (Sec. III): one kernel
+// launch per sweep, operators and iterates streamed from HBM every sweep.
+//
+// A workgroup owns one problem; thread t handles (stage k, lifted row r),
+// r in 0..24, so every stage-local update of the three blocks runs in
+// parallel across the horizon.  The only cross-stage exchanges are the
+// ones the splitting leaves: block 1 at stage k needs Abar_{k+1}^T y_{k+1}
+// from stage k+1, block 2 at stage k needs xi_k from stage k-1 of the same
+// sweep; both go through LDS.
+//
+// Slot k of the iterate arrays holds (z_{k+1}, v_k, theta_k, beta_k,
+// lambda_k).  Inputs are in scaled coordinates ut = S_k^{-1} u.
+#include "pinmpc_internal.h"
+
+namespace pinmpc {
+
+namespace {
+
+constexpr int BUF = 25;   // floats per stage per LDS buffer
+
+struct Lds {
+  float* b0;    // w = vhat - betahat           -> later htilde
+  float* b1;    // y = zhat - vhat - ebar + lamhat -> later xi (block-1 output)
+  float* b2;    // Bt^T w_x + w_u (12)          -> later projection input (12)
+  float* b3;    // du (12)                      -> later projection output (12)
+  float* aty;   // Abar^T y of the stage
+  float* xi0;   // fixed lifted initial state (x0, ut_prev)
+  float* red;   // reduction scratch
+};
+
+__device__ inline float block_sum(float v, float* red) {
+  // wave reduction then cross-wave through LDS
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  float t = 0.f;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+template <int PAIRS>
+__global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace ws, float rho,
+                                                          int accel, float eta) {
+  extern __shared__ float lds[];
+  const int b = blockIdx.x;
+  const int n = p.n_max;
+  const int N = horizon(p, b);
+  Lds L;
+  L.b0 = lds;
+  L.b1 = L.b0 + n * BUF;
+  L.b2 = L.b1 + n * BUF;
+  L.b3 = L.b2 + n * BUF;
+  L.aty = L.b3 + n * BUF;
+  L.xi0 = L.aty + n * BUF;
+  L.red = L.xi0 + 32;
+  const int nact = N * NL;
+  const size_t s0 = (size_t)b * n;
+  const float* e = p.e;
+  const float mu = p.mu[b];
+  const float tmax = p.tau_max[b];
+
+  if (threadIdx.x < NL) {
+    const int r = threadIdx.x;
+    float v;
+    if (r < NX) v = p.x0[(size_t)b * NX + r];
+    else v = p.u_prev ? p.u_prev[(size_t)b * NU + r - NX] /
+                            ((r - NX) % 6 < 3 ? ws.sf[s0] : ws.tsc[b])
+                      : 0.f;
+    L.xi0[r] = v;
+  }
+
+  float zh[PAIRS], vh[PAIRS], th[PAIRS], bh[PAIRS], lh[PAIRS];
+  float zc[PAIRS], vc[PAIRS], tc[PAIRS], bc[PAIRS], lc[PAIRS];
+  float xi[PAIRS], sv[PAIRS], bv[PAIRS], gam[PAIRS], zn[PAIRS], eb[PAIRS];
+
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      const size_t base = ((s0 + k) * NSTATE) * NL + r;
+      const float* H = ws.hat + base;
+      zh[q] = H[0]; vh[q] = H[NL]; th[q] = H[2 * NL]; bh[q] = H[3 * NL]; lh[q] = H[4 * NL];
+      if (accel) {
+        const float* C = ws.cur + base;
+        zc[q] = C[0]; vc[q] = C[NL]; tc[q] = C[2 * NL]; bc[q] = C[3 * NL]; lc[q] = C[4 * NL];
+      }
+      eb[q] = (r < NX && e) ? e[(s0 + k) * NX + r] : 0.f;
+      L.b0[k * BUF + r] = vh[q] - bh[q];
+      L.b1[k * BUF + r] = zh[q] - vh[q] - eb[q] + lh[q];
+    }
+  }
+  __syncthreads();
+
+  // Block 1a: Bt^T w_x + w_u and Abar_k^T y_k (stage-local).
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      const float* A = p.A + (s0 + k) * NX * NX;
+      const float* Bt = ws.Bt + (s0 + k) * NX * NU;
+      const float* w = L.b0 + k * BUF;
+      const float* y = L.b1 + k * BUF;
+      float acc = 0.f;
+      if (r < NX) {
+        for (int i = 0; i < NX; ++i) acc = fmaf(A[i * NX + r], y[i], acc);
+      } else {
+        const int j = r - NX;
+        acc = y[r];
+        for (int i = 0; i < NX; ++i) acc = fmaf(Bt[i * NU + j], y[i], acc);
+      }
+      L.aty[k * BUF + r] = acc;
+      if (r < NU) {
+        float t = w[NX + r];
+        for (int i = 0; i < NX; ++i) t = fmaf(Bt[i * NU + r], w[i], t);
+        L.b2[k * BUF + r] = t;
+      }
+    }
+  }
+  __syncthreads();
+
+  // Block 1b: du_k = M_k t,  htilde_k = qbar + rho (zhat - thetahat + Abar_{k+1}^T y_{k+1}).
+  float ht[PAIRS];
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      float h = zh[q] - th[q];
+      if (k + 1 < N) h += L.aty[(k + 1) * BUF + r];
+      ht[q] = fmaf(rho, h, ws.qb[(s0 + k) * NL + r]);
+      if (r < NU) {
+        const float* M = ws.Mp + (s0 + k) * NM;
+        const float* t = L.b2 + k * BUF;
+        float du = 0.f;
+        for (int j = 0; j < NU; ++j) du = fmaf(M[pk(r, j, NU)], t[j], du);
+        L.b3[k * BUF + r] = du;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      L.b0[k * BUF + r] = ht[q];
+    }
+  }
+  __syncthreads();
+
+  // Block 1c: xi_{k+1} = H_k htilde_k.
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      const float* H = ws.Hp + (s0 + k) * NH;
+      const float* h = L.b0 + k * BUF;
+      float acc = 0.f;
+      for (int j = 0; j < NL; ++j) acc = fmaf(H[pk(r, j, NL)], h[j], acc);
+      xi[q] = acc;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      L.b1[k * BUF + r] = xi[q];
+    }
+  }
+  __syncthreads();
+
+  // Block 2: s_k = Abar_k xi_k (xi_k of this sweep, xi_0 fixed), b_k = Bbar_k du_k,
+  // z_{k+1} = Proj((2 gamtilde + gam) / 3), v_k = (z_{k+1} + gam) / 2.
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      const float* prev = (k == 0) ? L.xi0 : L.b1 + (k - 1) * BUF;
+      const float* du = L.b3 + k * BUF;
+      float s, bb;
+      if (r < NX) {
+        const float* A = p.A + (s0 + k) * NX * NX + r * NX;
+        const float* Bt = ws.Bt + (s0 + k) * NX * NU + r * NU;
+        s = 0.f;
+        for (int j = 0; j < NX; ++j) s = fmaf(A[j], prev[j], s);
+        bb = 0.f;
+        for (int j = 0; j < NU; ++j) {
+          s = fmaf(Bt[j], prev[NX + j], s);
+          bb = fmaf(Bt[j], du[j], bb);
+        }
+      } else {
+        s = prev[r];
+        bb = du[r - NX];
+      }
+      sv[q] = s;
+      bv[q] = bb;
+      gam[q] = bb + bh[q] - s - eb[q] + lh[q];
+      const float gt = xi[q] + th[q] + s + eb[q] - lh[q];
+      zn[q] = (2.f * gt + gam[q]) * (1.f / 3.f);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      if (r >= NX) L.b2[k * BUF + r - NX] = zn[q];
+    }
+  }
+  __syncthreads();
+  // projection: one thread per (stage, contact)
+  for (int id = threadIdx.x; id < N * 2; id += blockDim.x) {
+    const int k = id >> 1, i = id & 1;
+    const float* y = L.b2 + k * BUF + 6 * i;
+    float* o = L.b3 + k * BUF + 6 * i;
+    if (p.contact[(s0 + k) * 2 + i]) {
+      const float sf = ws.sf[s0 + k];
+      const float F = p.fz_max[b] / sf;
+      const float tm = tmax / ws.tsc[b];
+      float px, py, pz;
+      project_pyramid<float>(mu, F, y[0], y[1], y[2], &px, &py, &pz);
+      o[0] = px; o[1] = py; o[2] = pz;
+      for (int a = 3; a < 6; ++a) o[a] = fminf(fmaxf(y[a], -tm), tm);
+    } else {
+      for (int a = 0; a < 6; ++a) o[a] = 0.f;
+    }
+  }
+  __syncthreads();
+
+  // Block 3 and the acceleration test.
+  float zv[PAIRS], vv[PAIRS], tv[PAIRS], bvv[PAIRS], lv[PAIRS];
+  float cpart = 0.f;
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      const float z = (r < NX) ? zn[q] : L.b3[k * BUF + r - NX];
+      const float v = 0.5f * (z + gam[q]);
+      zv[q] = z;
+      vv[q] = v;
+      tv[q] = th[q] + xi[q] - z;
+      bvv[q] = bh[q] + bv[q] - v;
+      lv[q] = lh[q] + z - sv[q] - v - eb[q];
+      if (accel) {
+        const float dz = z - zh[q], dv = v - vh[q];
+        const float d1 = tv[q] - th[q], d2 = bvv[q] - bh[q], d3 = lv[q] - lh[q];
+        cpart += d1 * d1 + d2 * d2 + d3 * d3 + dz * dz + dv * dv + (dz - dv) * (dz - dv);
+      }
+    }
+  }
+  float f = 0.f;
+  bool restart = false;
+  if (accel) {
+    const float cm = block_sum(cpart, L.red);
+    const float cp = ws.cprev[b];
+    const float al = ws.alpha[b];
+    if (cm < eta * cp) {
+      const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * al * al));
+      f = (al - 1.f) / an;
+      __syncthreads();
+      if (threadIdx.x == 0) { ws.alpha[b] = an; ws.cprev[b] = cm; }
+    } else {
+      restart = true;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        ws.alpha[b] = 1.f;
+        ws.cprev[b] = cp / eta;
+        ws.restarts[b] += 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
+      const size_t base = ((s0 + k) * NSTATE) * NL + r;
+      float* H = ws.hat + base;
+      if (accel) {
+        float* C = ws.cur + base;
+        if (restart) {
+          H[0] = zc[q]; H[NL] = vc[q]; H[2 * NL] = tc[q]; H[3 * NL] = bc[q]; H[4 * NL] = lc[q];
+        } else {
+          H[0] = zv[q] + f * (zv[q] - zc[q]);
+          H[NL] = vv[q] + f * (vv[q] - vc[q]);
+          H[2 * NL] = tv[q] + f * (tv[q] - tc[q]);
+          H[3 * NL] = bvv[q] + f * (bvv[q] - bc[q]);
+          H[4 * NL] = lv[q] + f * (lv[q] - lc[q]);
+        }
+        C[0] = zv[q]; C[NL] = vv[q]; C[2 * NL] = tv[q]; C[3 * NL] = bvv[q]; C[4 * NL] = lv[q];
+      } else {
+        H[0] = zv[q]; H[NL] = vv[q]; H[2 * NL] = tv[q]; H[3 * NL] = bvv[q]; H[4 * NL] = lv[q];
+      }
+    }
+  }
+}
+
+// Zero iterates and acceleration state.
+__global__ void admm_init_kernel(Problem p, Workspace ws) {
+  const size_t total = (size_t)p.batch * p.n_max * NSTATE * NL;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    ws.cur[i] = 0.f;
+    ws.hat[i] = 0.f;
+  }
+  for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < (size_t)p.batch;
+       b += (size_t)gridDim.x * blockDim.x) {
+    ws.alpha[b] = 1.f;
+    ws.cprev[b] = 3.0e38f;
+    ws.restarts[b] = 0;
+  }
+}
+
+// z iterates (current) in unscaled coordinates, [b][n_max][25].
+__global__ void admm_extract_kernel(Problem p, Workspace ws, int accel, float* z_out) {
+  const size_t total = (size_t)p.batch * p.n_max * NL;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t s = i / NL;
+    const int r = (int)(i % NL);
+    const int b = (int)(s / p.n_max);
+    const float* src = accel ? ws.cur : ws.hat;
+    float v = src[s * NSTATE * NL + r];
+    if (r >= NX) v *= ((r - NX) % 6 < 3) ? ws.sf[s] : ws.tsc[b];
+    z_out[i] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_admm_init(const Problem& p, const Workspace& w, hipStream_t st) {
+  if (p.batch == 0) return hipSuccess;
+  hipLaunchKernelGGL(admm_init_kernel, dim3(1024), dim3(256), 0, st, p, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             hipStream_t st) {
+  if (p.batch == 0) return hipSuccess;
+  const int work = NL * p.n_max;
+  int threads = ((work + 63) / 64) * 64;
+  if (threads > 1024) threads = 1024;
+  const int pairs = (work + threads - 1) / threads;
+  const size_t lds = (size_t)(5 * p.n_max * BUF + 32 + 32) * sizeof(float);
+  switch (pairs) {
+    case 1:
+      hipLaunchKernelGGL(admm_sweep_kernel<1>, dim3(p.batch), dim3(threads), lds, st, p, w,
+                         s.rho, s.accel, s.restart_eta);
+      break;
+    case 2:
+      hipLaunchKernelGGL(admm_sweep_kernel<2>, dim3(p.batch), dim3(threads), lds, st, p, w,
+                         s.rho, s.accel, s.restart_eta);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_admm_extract(const Problem& p, const Workspace& w, int accel,
+                               float* z_out, hipStream_t st) {
+  if (p.batch == 0) return hipSuccess;
+  hipLaunchKernelGGL(admm_extract_kernel, dim3(1024), dim3(256), 0, st, p, w, accel, z_out);
+  return hipGetLastError();
+}
+
+}  // namespace pinmpc

@@ -1,0 +1,293 @@
+// Host side of the C ABI: argument validation, workspace carving under the
+// HBM budget, launch sequencing on the caller's stream, phase timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pinmpc.h"
+#include "pinmpc_internal.h"
+
+using namespace pinmpc;
+
+struct pinmpc_ctx_s {
+  int device = 0;
+  size_t budget = 0;
+  pinmpc_settings s{};
+  void* mem = nullptr;
+  size_t mem_bytes = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool have_timing = false;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Carve (or size, when base == nullptr) the workspace for batch x n.
+size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
+  const size_t S = (size_t)batch * n;        // stages
+  const size_t Bn = (size_t)batch;
+  const size_t X = (size_t)batch * (n + 1);  // state slots
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  Workspace t{};
+  t.Bt = (float*)take(S * NX * NU * 4);
+  t.Hp = (float*)take(S * NH * 4);
+  t.Mp = (float*)take(S * NM * 4);
+  t.qb = (float*)take(S * NL * 4);
+  t.sf = (float*)take(S * 4);
+  t.tsc = (float*)take(Bn * 4);
+  t.cur = (float*)take(S * NSTATE * NL * 4);
+  t.hat = (float*)take(S * NSTATE * NL * 4);
+  t.alpha = (float*)take(Bn * 4);
+  t.cprev = (float*)take(Bn * 4);
+  t.restarts = (int32_t*)take(Bn * 4);
+  t.flags = (uint32_t*)take(Bn * 4);
+  t.rK = (double*)take(S * NU * NX * 8);
+  t.rkap = (double*)take(S * NU * 8);
+  t.rL = (double*)take(S * NM * 8);
+  t.rHwx = (double*)take(S * NU * NX * 8);
+  t.ru = (double*)take(S * NU * 8);
+  t.rx = (double*)take(X * NX * 8);
+  t.rlam = (double*)take(S * NX * 8);
+  t.rg = (double*)take(S * NU * 8);
+  t.rmu = (double*)take(S * 2 * NROW * 8);
+  t.rs = (double*)take(S * 2 * NROW * 8);
+  t.rz = (double*)take(S * 2 * NROW * 8);
+  t.rds = (double*)take(S * 2 * NROW * 8);
+  t.rdz = (double*)take(S * 2 * NROW * 8);
+  t.rdu = (double*)take(S * NU * 8);
+  t.rdx = (double*)take(X * NX * 8);
+  t.faces = (int32_t*)take(S * 2 * 4);
+  t.bestu = (double*)take(S * NU * 8);
+  t.bytes = off;
+  if (w) *w = t;
+  return off;
+}
+
+int check_settings(const pinmpc_settings* s) {
+  if (!s) return PINMPC_EINVAL;
+  if (!(s->rho > 0.f) || !std::isfinite(s->rho)) return PINMPC_EINVAL;
+  if (s->iters < 0 || s->iters > 1000000) return PINMPC_EINVAL;
+  if (!(s->restart_eta > 0.f && s->restart_eta <= 1.f)) return PINMPC_EINVAL;
+  if (s->refine_passes < 0 || s->ipm_iters < 0 || s->polish_passes < 0) return PINMPC_EINVAL;
+  if (!(s->kkt_tol > 0.0)) return PINMPC_EINVAL;
+  if (s->precision != 0) return PINMPC_EINVAL;           // BF16 operators: not built
+  if (s->form != 0) return PINMPC_EINVAL;                // fused form: not built
+  return PINMPC_OK;
+}
+
+int check_batch(const pinmpc_batch* in) {
+  if (!in) return PINMPC_EINVAL;
+  if (in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX) return PINMPC_EINVAL;
+  if (in->batch == 0) return PINMPC_OK;
+  if (!in->A || !in->Bu || !in->x0 || !in->x_ref || !in->Q || !in->R || !in->contact ||
+      !in->mu || !in->fz_max || !in->tau_max)
+    return PINMPC_EINVAL;
+  return PINMPC_OK;
+}
+
+Problem to_problem(const pinmpc_batch* in) {
+  Problem p;
+  p.batch = in->batch;
+  p.n_max = in->n_max;
+  p.N = in->N;
+  p.A = in->A;
+  p.B = in->Bu;
+  p.e = in->e;
+  p.x0 = in->x0;
+  p.u_prev = in->u_prev;
+  p.x_ref = in->x_ref;
+  p.u_ref = in->u_ref;
+  p.Q = in->Q;
+  p.R = in->R;
+  p.contact = in->contact;
+  p.mu = in->mu;
+  p.fz_max = in->fz_max;
+  p.tau_max = in->tau_max;
+  p.weight = in->weight;
+  return p;
+}
+
+int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Workspace* w) {
+  const size_t need = carve(nullptr, batch, n, nullptr);
+  if (need > c->budget) return PINMPC_EBUDGET;
+  if (need > c->mem_bytes) {
+    if (c->mem) {
+      if (hipStreamSynchronize(st) != hipSuccess) return PINMPC_EDEVICE;
+      (void)hipFree(c->mem);
+      c->mem = nullptr;
+      c->mem_bytes = 0;
+    }
+    if (hipMalloc(&c->mem, need) != hipSuccess) {
+      c->mem = nullptr;
+      return PINMPC_ENOMEM;
+    }
+    c->mem_bytes = need;
+  }
+  carve((char*)c->mem, batch, n, w);
+  return PINMPC_OK;
+}
+
+int run_admm(pinmpc_ctx c, const Problem& p, const Workspace& w, int iters, hipStream_t st) {
+  if (launch_setup(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (launch_admm_init(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (c->have_timing) (void)hipEventRecord(c->ev[1], st);
+  for (int it = 0; it < iters; ++it)
+    if (launch_admm_sweep(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
+  return PINMPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pinmpc_default_settings(pinmpc_settings* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->rho = 10.f;
+  s->iters = 100;
+  s->accel = 1;
+  s->restart_eta = 0.999f;
+  s->scaling = 1;
+  s->refine = 1;
+  s->refine_passes = 8;
+  s->ipm_iters = 40;
+  s->polish_passes = 6;
+  s->kkt_tol = 1e-9;
+  s->precision = 0;
+  s->form = 0;
+}
+
+int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
+                  const pinmpc_settings* s) {
+  if (!out) return PINMPC_EINVAL;
+  *out = nullptr;
+  pinmpc_settings def;
+  pinmpc_default_settings(&def);
+  if (!s) s = &def;
+  const int rc = check_settings(s);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return PINMPC_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return PINMPC_EDEVICE;
+  pinmpc_ctx c = new (std::nothrow) pinmpc_ctx_s;
+  if (!c) return PINMPC_ENOMEM;
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)64 << 30;
+  c->s = *s;
+  c->have_timing = true;
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) c->have_timing = false;
+  *out = c;
+  return PINMPC_OK;
+}
+
+int pinmpc_set_settings(pinmpc_ctx c, const pinmpc_settings* s) {
+  if (!c) return PINMPC_EINVAL;
+  const int rc = check_settings(s);
+  if (rc) return rc;
+  c->s = *s;
+  return PINMPC_OK;
+}
+
+int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_max,
+                           size_t* bytes) {
+  if (!bytes || batch < 0 || n_max < 1 || n_max > PINMPC_NMAX) return PINMPC_EINVAL;
+  (void)s;
+  *bytes = carve(nullptr, batch, n_max, nullptr);
+  return PINMPC_OK;
+}
+
+int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out, void* hip_stream) {
+  if (!c || !out) return PINMPC_EINVAL;
+  int rc = check_batch(in);
+  if (rc) return rc;
+  if (in->batch > 0 && (!out->u || !out->x)) return PINMPC_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (in->batch == 0) return PINMPC_OK;
+  Workspace w;
+  rc = ensure_workspace(c, in->batch, in->n_max, st, &w);
+  if (rc) return rc;
+  const Problem p = to_problem(in);
+  if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
+  rc = run_admm(c, p, w, c->s.iters, st);
+  if (rc) return rc;
+  if (c->have_timing) (void)hipEventRecord(c->ev[2], st);
+  if (launch_refine(p, w, c->s, *out, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
+  return PINMPC_OK;
+}
+
+int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters, float* z_out,
+                void* hip_stream) {
+  if (!c || !z_out || iters < 0) return PINMPC_EINVAL;
+  int rc = check_batch(in);
+  if (rc) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (in->batch == 0) return PINMPC_OK;
+  Workspace w;
+  rc = ensure_workspace(c, in->batch, in->n_max, st, &w);
+  if (rc) return rc;
+  const Problem p = to_problem(in);
+  const bool timing = c->have_timing;
+  c->have_timing = false;
+  rc = run_admm(c, p, w, iters, st);
+  c->have_timing = timing;
+  if (rc) return rc;
+  if (launch_admm_extract(p, w, c->s.accel, z_out, st) != hipSuccess) return PINMPC_EDEVICE;
+  return PINMPC_OK;
+}
+
+int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_ms,
+                 double* refine_ms) {
+  if (!c || !c->have_timing) return PINMPC_EINVAL;
+  if (hipEventSynchronize(c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  float t01 = 0, t12 = 0, t23 = 0;
+  if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) != hipSuccess) return PINMPC_EDEVICE;
+  if (hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) != hipSuccess) return PINMPC_EDEVICE;
+  if (hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  if (setup_ms) *setup_ms = t01;
+  if (admm_ms) *admm_ms = t12;
+  if (refine_ms) *refine_ms = t23;
+  if (total_ms) *total_ms = (double)t01 + t12 + t23;
+  return PINMPC_OK;
+}
+
+int pinmpc_destroy(pinmpc_ctx c) {
+  if (!c) return PINMPC_EINVAL;
+  (void)hipSetDevice(c->device);
+  if (c->mem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->mem);
+  }
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return PINMPC_OK;
+}
+
+const char* pinmpc_strerror(int code) {
+  switch (code) {
+    case PINMPC_OK: return "ok";
+    case PINMPC_EINVAL: return "invalid argument";
+    case PINMPC_ENOMEM: return "device allocation failed";
+    case PINMPC_EBUDGET: return "workspace exceeds the HBM budget";
+    case PINMPC_EDEVICE: return "HIP runtime or launch error";
+    case PINMPC_EBUSY: return "busy";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

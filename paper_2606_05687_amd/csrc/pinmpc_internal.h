@@ -1,0 +1,140 @@
+// Internal definitions shared by the HIP translation units of libpinmpc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pinmpc.h"
+
+namespace pinmpc {
+
+constexpr int NX = PINMPC_NX;   // 13 states
+constexpr int NU = PINMPC_NU;   // 12 inputs
+constexpr int NL = NX + NU;     // 25: lifted state (x_k, u_{k-1}) of the velocity form
+constexpr int NH = NL * (NL + 1) / 2;   // 325: packed symmetric H_k
+constexpr int NM = NU * (NU + 1) / 2;   // 78: packed symmetric M_k
+constexpr int NROW = 11;        // wrench rows per stance contact
+constexpr int NSTATE = 5;       // ADMM iterate blocks z, v, theta, beta, lambda
+
+// Packed upper-triangular index of symmetric (r, c), n x n.
+__host__ __device__ inline int pk(int r, int c, int n) {
+  if (r > c) { int t = r; r = c; c = t; }
+  return r * n - (r * (r - 1)) / 2 + (c - r);
+}
+
+// Problem data as the kernels see it (device pointers; optional ones may be
+// null and then mean zero / the documented default).
+struct Problem {
+  int32_t batch, n_max;
+  const int32_t* N;
+  const float *A, *B, *e, *x0, *u_prev, *x_ref, *u_ref, *Q, *R;
+  const uint8_t* contact;
+  const float *mu, *fz_max, *tau_max, *weight;
+};
+
+__device__ inline int horizon(const Problem& p, int b) {
+  return p.N ? p.N[b] : p.n_max;
+}
+__device__ inline float weight_of(const Problem& p, int b) {
+  return p.weight ? p.weight[b] : 0.5f * p.fz_max[b];
+}
+
+// Workspace carved from one device allocation.
+struct Workspace {
+  // FP32 ADMM operators, per stage s = b * n_max + k
+  float* Bt;        // [s][13][12] scaled input matrix B_k S_k
+  float* Hp;        // [s][325] packed H_k
+  float* Mp;        // [s][78] packed M_k = (Bt^T Bt + I)^{-1}
+  float* qb;        // [s][25] linear cost term (Q r_k, Rt ut_ref)
+  float* sf;        // [s] force scale of stage k
+  float* tsc;       // [b] moment scale (tau_max, or 1 without scaling)
+  // ADMM iterates [s][5][25]: current and extrapolated ("hat")
+  float* cur;
+  float* hat;
+  float* alpha;     // [b] acceleration sequence
+  float* cprev;     // [b] restart test value
+  int32_t* restarts;// [b]
+  uint32_t* flags;  // [b] bit0: nonfinite input, bit1: bad bounds
+  // FP64 refinement scratch
+  double* rK;       // [s][12][13] feedback gains
+  double* rkap;     // [s][12] feedforward
+  double* rL;       // [s][78] Cholesky factor of the reduced input Hessian
+  double* rHwx;     // [s][12][13]
+  double* ru;       // [s][12] inputs
+  double* rx;       // [b][n_max+1][13] states
+  double* rlam;     // [s][13] costates p_{k+1}
+  double* rg;       // [s][12] reduced gradient R(u-ur) + B^T p
+  double* rmu;      // [s][2][11] row multipliers
+  double* rs;       // [s][2][11] IPM slacks (scaled rows)
+  double* rz;       // [s][2][11] IPM multipliers (scaled rows)
+  double* rds;      // [s][2][11]
+  double* rdz;      // [s][2][11]
+  double* rdu;      // [s][12]
+  double* rdx;      // [b][n_max+1][13]
+  int32_t* faces;   // [s][2] face code per contact
+  double* bestu;    // [s][12] best certified-or-not iterate
+  size_t bytes;
+};
+
+// Face code of one contact: bits 0..4 force rows active
+//   (0: f_x - mu f_z <= 0, 1: -f_x - mu f_z <= 0, 2: f_y - mu f_z <= 0,
+//    3: -f_y - mu f_z <= 0, 4: f_z <= fz_max),
+// bits 8..13 moment rows (8+a: tau_a <= tau_max, 11+a: -tau_a <= tau_max).
+// Rows {0,1} or {2,3} together mean the apex f = 0 (code force bits = 15).
+constexpr int FACE_APEX = 15;
+
+// Euclidean projection of y onto {|f_x|,|f_y| <= mu f_z, f_z <= F}
+// (candidate enumeration over the faces of the truncated pyramid; the set
+// is symmetric in the signs of f_x, f_y, so work on (|y_x|, |y_y|, y_z)).
+template <typename T>
+__device__ inline void project_pyramid(T mu, T F, T yx, T yy, T yz, T* px, T* py,
+                                       T* pz) {
+  const T sx = yx < T(0) ? T(-1) : T(1);
+  const T sy = yy < T(0) ? T(-1) : T(1);
+  const T a = yx * sx, b = yy * sy, z = yz;
+  const T tol = T(1e-6) * (T(1) + F);
+  T best = T(3.0e38), ba = 0, bb = 0, bz = 0;
+  auto consider = [&](T ca, T cb, T cz) {
+    if (ca < -tol || cb < -tol || ca > mu * cz + tol || cb > mu * cz + tol || cz > F + tol)
+      return;
+    const T d = (ca - a) * (ca - a) + (cb - b) * (cb - b) + (cz - z) * (cz - z);
+    if (d < best) { best = d; ba = ca; bb = cb; bz = cz; }
+  };
+  consider(a, b, z);                                   // interior
+  const T m2 = T(1) + mu * mu;
+  {  // side a = mu z
+    const T t = (a - mu * z) / m2;
+    consider(a - t, b, z + mu * t);
+  }
+  {  // side b = mu z
+    const T t = (b - mu * z) / m2;
+    consider(a, b - t, z + mu * t);
+  }
+  {  // lateral edge a = b = mu z
+    const T t = (mu * a + mu * b + z) / (T(2) * mu * mu + T(1));
+    consider(mu * t, mu * t, t);
+  }
+  consider(a, b, F);                                   // top
+  consider(mu * F, b, F);                              // top edge a = mu F
+  consider(a, mu * F, F);                              // top edge b = mu F
+  consider(mu * F, mu * F, F);                         // top corner
+  consider(T(0), T(0), T(0));                          // apex
+  *px = sx * ba;
+  *py = sy * bb;
+  *pz = bz;
+}
+
+// Kernel launchers (defined in the .hip units).
+hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                        hipStream_t st);
+hipError_t launch_admm_init(const Problem& p, const Workspace& w, hipStream_t st);
+hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             hipStream_t st);
+hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             int iters, hipStream_t st);
+hipError_t launch_admm_extract(const Problem& p, const Workspace& w, int accel,
+                               float* z_out, hipStream_t st);
+hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                         const pinmpc_out& out, hipStream_t st);
+
+}  // namespace pinmpc

@@ -1,0 +1,1080 @@
+// FP64 refinement and certification of the ADMM result, one 64-lane wave per
+// problem (problems are independent, so each wave runs its own loop).
+//
+// The ADMM of Sec. III reaches the QP optimum only in the limit; its last
+// projection fixes a guess of the active faces of every contact's wrench set.
+// From that guess the kernel runs, all in FP64:
+//  A. active-set passes: solve the equality-constrained LQ problem with each
+//     contact's input restricted to the affine hull of its face (Riccati
+//     recursion over the horizon with u_k = c_k + P_k w_k), evaluate the KKT
+//     residuals with costates from the adjoint recursion and row multipliers
+//     from the face, and update the faces by the primal-dual active-set rule
+//     (row active iff mu_i s_i + (G_i u - h_i) > 0); stop when certified, when
+//     the face set repeats, or after refine_passes passes;
+//  B. if not certified: a primal-dual interior point with Mehrotra's
+//     predictor-corrector on the same QP (each Newton step a Riccati recursion
+//     with input Hessian R + G^T diag(z/s) G), then faces from z > s and
+//  C. active-set passes again from those faces (polish_passes).
+// The returned u is the last equality-constrained solution, x its rollout in
+// FP64, and res the normalised residuals (r_dyn, r_ineq, r_stat, r_comp,
+// r_sign) of that point.
+#include "pinmpc_internal.h"
+
+namespace pinmpc {
+
+namespace {
+
+constexpr int W64 = 64;
+
+struct Ctx {
+  Problem p;
+  Workspace ws;
+  int b, N, n;
+  size_t s0;
+  double mu, fz, tm, mg;
+  double Q[NX], R[NU];
+};
+
+// ------------------------------------------------------------ small helpers
+
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline uint64_t wave_xor(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+    v ^= ((uint64_t)hi << 32) | lo;
+  }
+  return v;
+}
+
+// Row i (0..10) of one stance contact's wrench constraints on (f, tau).
+__device__ inline void wrench_row(int i, double mu, double fz, double tm, double g[6],
+                                  double* h) {
+  for (int a = 0; a < 6; ++a) g[a] = 0.0;
+  switch (i) {
+    case 0: g[0] = 1; g[2] = -mu; *h = 0; break;
+    case 1: g[0] = -1; g[2] = -mu; *h = 0; break;
+    case 2: g[1] = 1; g[2] = -mu; *h = 0; break;
+    case 3: g[1] = -1; g[2] = -mu; *h = 0; break;
+    case 4: g[2] = 1; *h = fz; break;
+    default: {
+      const int a = (i - 5) % 3;
+      g[3 + a] = (i < 8) ? 1.0 : -1.0;
+      *h = tm;
+    }
+  }
+}
+
+__device__ inline bool face_apex(int code) {
+  const int f = code & 31;
+  return ((f & 3) == 3) || ((f & 12) == 12);
+}
+
+// Solve the m x m system M y = r (m <= 3, SPD) by Gaussian elimination.
+__device__ inline void small_solve(double M[3][3], double r[3], int m) {
+  for (int j = 0; j < m; ++j) {
+    const double piv = M[j][j];
+    for (int c = j; c < m; ++c) M[j][c] /= piv;
+    r[j] /= piv;
+    for (int i = 0; i < m; ++i)
+      if (i != j) {
+        const double f = M[i][j];
+        for (int c = j; c < m; ++c) M[i][c] -= f * M[j][c];
+        r[i] -= f * r[j];
+      }
+  }
+}
+
+// Affine hull of a contact's face: projector P (6x6, block diagonal) and a
+// point c with u = c + P w spanning the face.
+__device__ void face_affine(int code, double mu, double fz, double tm, double P[6][6],
+                            double c[6]) {
+  for (int a = 0; a < 6; ++a) {
+    c[a] = 0.0;
+    for (int b = 0; b < 6; ++b) P[a][b] = 0.0;
+  }
+  // force block
+  if (!face_apex(code)) {
+    double G[3][3], h[3];
+    int m = 0;
+    for (int i = 0; i < 5; ++i)
+      if (code >> i & 1) {
+        double g[6], hh;
+        wrench_row(i, mu, fz, tm, g, &hh);
+        G[m][0] = g[0]; G[m][1] = g[1]; G[m][2] = g[2];
+        h[m] = hh;
+        ++m;
+      }
+    double GG[3][3], y[3];
+    for (int i = 0; i < m; ++i) {
+      for (int j = 0; j < m; ++j)
+        GG[i][j] = G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2];
+      y[i] = h[i];
+    }
+    // P = I - G^T (G G^T)^{-1} G ; c = G^T (G G^T)^{-1} h
+    double Gi[3][3];   // (G G^T)^{-1} G, column by column
+    for (int col = 0; col < 3; ++col) {
+      double M[3][3], r[3];
+      for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < m; ++j) M[i][j] = GG[i][j];
+        r[i] = G[i][col];
+      }
+      small_solve(M, r, m);
+      for (int i = 0; i < m; ++i) Gi[i][col] = r[i];
+    }
+    {
+      double M[3][3];
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) M[i][j] = GG[i][j];
+      small_solve(M, y, m);
+    }
+    for (int a = 0; a < 3; ++a) {
+      double ca = 0.0;
+      for (int i = 0; i < m; ++i) ca += G[i][a] * y[i];
+      c[a] = ca;
+      for (int b = 0; b < 3; ++b) {
+        double t = (a == b) ? 1.0 : 0.0;
+        for (int i = 0; i < m; ++i) t -= G[i][a] * Gi[i][b];
+        P[a][b] = t;
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (code >> (8 + a) & 1) c[3 + a] = tm;
+    else if (code >> (11 + a) & 1) c[3 + a] = -tm;
+    else P[3 + a][3 + a] = 1.0;
+  }
+}
+
+// --------------------------------------------------------------- LDS state
+
+struct Sh {
+  double S[NX * NX], s[NX];           // value function of x_{k+1}
+  double A[NX * NX], B[NX * NU];
+  double W[NX * NX], WA[NX * NX];
+  double P[NU * NU], c[NU], Rp[NU * NU];
+  double Bp[NX * NU], WBp[NX * NU];
+  double H[NU * NU], Hwx[NU * NX], K[NU * NX];
+  double om[NX], d[NX], Wdo[NX], hw[NU], kap[NU], rho[NU], q[NX];
+  double xv[NX], wv[NU], uv[NU], xn[NX];
+  double red[8];
+};
+
+__device__ inline void load_AB(const Ctx& C, Sh& sh, int k) {
+  const int lane = threadIdx.x;
+  const float* A = C.p.A + (C.s0 + k) * NX * NX;
+  const float* B = C.p.B + (C.s0 + k) * NX * NU;
+  for (int i = lane; i < NX * NX; i += W64) sh.A[i] = (double)A[i];
+  for (int i = lane; i < NX * NU; i += W64) sh.B[i] = (double)B[i];
+}
+
+// Face projector/offset of stage k into sh.P, sh.c (lanes 0 and 1 build one
+// contact each).  newton: projector = stance mask, offset 0.
+__device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
+  const int lane = threadIdx.x;
+  for (int i = lane; i < NU * NU; i += W64) sh.P[i] = 0.0;
+  __syncthreads();
+  if (lane < 2) {
+    const int i = lane;
+    const bool st = C.p.contact[(C.s0 + k) * 2 + i] != 0;
+    if (st) {
+      if (newton) {
+        for (int a = 0; a < 6; ++a) {
+          sh.P[(6 * i + a) * NU + 6 * i + a] = 1.0;
+          sh.c[6 * i + a] = 0.0;
+        }
+      } else {
+        double P6[6][6], c6[6];
+        face_affine(C.ws.faces[(C.s0 + k) * 2 + i], C.mu, C.fz, C.tm, P6, c6);
+        for (int a = 0; a < 6; ++a) {
+          sh.c[6 * i + a] = c6[a];
+          for (int bb = 0; bb < 6; ++bb) sh.P[(6 * i + a) * NU + 6 * i + bb] = P6[a][bb];
+        }
+      }
+    } else {
+      for (int a = 0; a < 6; ++a) sh.c[6 * i + a] = 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------ Riccati recursion
+//
+// Solves   min sum_k 1/2 x_{k+1}^T Q x_{k+1} + q_k^T x_{k+1}
+//                    + 1/2 u_k^T R'_k u_k + rho_k^T u_k
+//          s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,  u_k = c_k + P_k w_k
+// (P_k an orthogonal projector) by the backward recursion on the value
+// function V(x) = 1/2 x^T S x + s^T x and the forward rollout.
+//   newton = false: the equality-constrained tracking problem of the faces
+//                   (q = -Q r, rho = -R u_ref, R' = R, e from the data);
+//   newton = true:  the interior-point Newton step, x_0 = 0, e = 0,
+//                   q = Q (x_{k+1} - r), R' = R + G^T diag(z/s) G,
+//                   rho from ipm_rho (stage inputs), P = stance mask.
+// With factor = false only the linear part is recomputed from the stored
+// factors (second right-hand side of the same Newton matrix).
+
+enum class Mode { EQ, NEWTON };
+
+__device__ void stage_rp(const Ctx& C, Sh& sh, int k, Mode mode) {
+  // R'_k into sh.Rp
+  const int lane = threadIdx.x;
+  for (int i = lane; i < NU * NU; i += W64) sh.Rp[i] = (i % (NU + 1) == 0) ? C.R[i / NU] : 0.0;
+  __syncthreads();
+  if (mode == Mode::NEWTON && lane < 2) {
+    const int i = lane;
+    if (C.p.contact[(C.s0 + k) * 2 + i]) {
+      const size_t rb = ((C.s0 + k) * 2 + i) * NROW;
+      for (int r = 0; r < NROW; ++r) {
+        double g[6], h;
+        wrench_row(r, C.mu, C.fz, C.tm, g, &h);
+        const double sc = (r < 5) ? C.mg : C.tm;
+        const double w = C.ws.rz[rb + r] / C.ws.rs[rb + r] / (sc * sc);
+        for (int a = 0; a < 6; ++a)
+          for (int bb = 0; bb < 6; ++bb)
+            sh.Rp[(6 * i + a) * NU + 6 * i + bb] += w * g[a] * g[bb];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Linear input term rho_k of stage k into sh.rho.
+__device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode, const double* rcvec) {
+  const int lane = threadIdx.x;
+  if (lane < NU) {
+    const int j = lane;
+    const double ur = C.p.u_ref ? (double)C.p.u_ref[(C.s0 + k) * NU + j] : 0.0;
+    double r;
+    if (mode == Mode::EQ) {
+      r = -C.R[j] * ur;
+    } else {
+      r = C.R[j] * (C.ws.ru[(C.s0 + k) * NU + j] - ur);
+      const int i = j / 6, a = j % 6;
+      if (C.p.contact[(C.s0 + k) * 2 + i]) {
+        const size_t rb = ((C.s0 + k) * 2 + i) * NROW;
+        for (int row = 0; row < NROW; ++row) {
+          double g[6], h;
+          wrench_row(row, C.mu, C.fz, C.tm, g, &h);
+          if (g[a] == 0.0) continue;
+          const double sc = (row < 5) ? C.mg : C.tm;
+          const double s = C.ws.rs[rb + row], z = C.ws.rz[rb + row];
+          // rp = G~ u + s - h~ ; coefficient z + (-rc + z rp) / s
+          double gu = 0.0;
+          for (int t = 0; t < 6; ++t) gu += g[t] * C.ws.ru[(C.s0 + k) * NU + 6 * i + t];
+          const double rp = (gu - h) / sc + s;
+          const double coef = z + (-rcvec[rb + row] + z * rp) / s;
+          r += g[a] / sc * coef;
+        }
+      }
+    }
+    sh.rho[j] = r;
+  }
+}
+
+__device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const double* rcvec) {
+  const int lane = threadIdx.x;
+  const int N = C.N;
+  for (int i = lane; i < NX * NX; i += W64) sh.S[i] = 0.0;
+  if (lane < NX) sh.s[lane] = 0.0;
+  __syncthreads();
+  for (int k = N - 1; k >= 0; --k) {
+    const size_t st = C.s0 + k;
+    load_AB(C, sh, k);
+    load_face(C, sh, k, mode == Mode::NEWTON);
+    if (factor) stage_rp(C, sh, k, mode);
+    stage_rho(C, sh, k, mode, rcvec);
+    if (lane < NX) {
+      const double r = (double)C.p.x_ref[st * NX + lane];
+      double q;
+      if (mode == Mode::EQ) q = -C.Q[lane] * r;
+      else q = C.Q[lane] * (C.ws.rx[((size_t)C.b * (C.n + 1) + k + 1) * NX + lane] - r);
+      sh.om[lane] = q + sh.s[lane];
+    }
+    __syncthreads();
+    // Bp = B P ; d = B c + e
+    for (int e = lane; e < NX * NU; e += W64) {
+      const int i = e / NU, j = e % NU;
+      double acc = 0.0;
+      for (int l = 0; l < NU; ++l) acc += sh.B[i * NU + l] * sh.P[l * NU + j];
+      sh.Bp[e] = acc;
+    }
+    if (lane < NX) {
+      double acc = 0.0;
+      if (mode == Mode::EQ) {
+        for (int l = 0; l < NU; ++l) acc += sh.B[lane * NU + l] * sh.c[l];
+        if (C.p.e) acc += (double)C.p.e[st * NX + lane];
+      }
+      sh.d[lane] = acc;
+    }
+    if (factor) {
+      for (int e = lane; e < NX * NX; e += W64)
+        sh.W[e] = sh.S[e] + ((e % (NX + 1) == 0) ? C.Q[e / NX] : 0.0);
+    }
+    __syncthreads();
+    if (factor) {
+      // WA, WBp
+      for (int e = lane; e < NX * NX + NX * NU; e += W64) {
+        if (e < NX * NX) {
+          const int i = e / NX, j = e % NX;
+          double acc = 0.0;
+          for (int l = 0; l < NX; ++l) acc += sh.W[i * NX + l] * sh.A[l * NX + j];
+          sh.WA[e] = acc;
+        } else {
+          const int f = e - NX * NX, i = f / NU, j = f % NU;
+          double acc = 0.0;
+          for (int l = 0; l < NX; ++l) acc += sh.W[i * NX + l] * sh.Bp[l * NU + j];
+          sh.WBp[f] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    if (lane < NX) {
+      // W d + omega (W = Q + S)
+      double acc = sh.om[lane];
+      if (mode == Mode::EQ)
+        for (int l = 0; l < NX; ++l)
+          acc += (sh.S[lane * NX + l] + (l == lane ? C.Q[lane] : 0.0)) * sh.d[l];
+      sh.Wdo[lane] = acc;
+    }
+    if (factor) {
+      // T = R' P into H temporarily? use Hwx as scratch: T[i][j] = sum_l R'[i][l] P[l][j]
+      for (int e = lane; e < NU * NU; e += W64) {
+        const int i = e / NU, j = e % NU;
+        double acc = 0.0;
+        for (int l = 0; l < NU; ++l) acc += sh.Rp[i * NU + l] * sh.P[l * NU + j];
+        sh.K[e] = acc;   // scratch
+      }
+    }
+    __syncthreads();
+    if (factor) {
+      // H = P R' P + Bp^T W Bp + (I - P) ; Hwx = Bp^T W A
+      for (int e = lane; e < NU * NU + NU * NX; e += W64) {
+        if (e < NU * NU) {
+          const int i = e / NU, j = e % NU;
+          double acc = ((i == j) ? 1.0 : 0.0) - sh.P[i * NU + j];
+          for (int l = 0; l < NU; ++l) acc += sh.P[l * NU + i] * sh.K[l * NU + j];
+          for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WBp[l * NU + j];
+          sh.H[e] = acc;
+        } else {
+          const int f = e - NU * NU, i = f / NX, j = f % NX;
+          double acc = 0.0;
+          for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WA[l * NX + j];
+          sh.Hwx[f] = acc;
+        }
+      }
+    } else {
+      const double* L = C.ws.rL + st * NM;
+      for (int e = lane; e < NM; e += W64) {
+        // unpack stored Cholesky factor (lower, packed by rows as pk(c, r))
+        int r = 0, acc = 0;
+        while (acc + (NU - r) <= e) { acc += NU - r; ++r; }
+        const int cc = r + (e - acc);    // packed (r, cc) with r <= cc : L[cc][r]
+        sh.H[cc * NU + r] = L[e];
+      }
+      for (int e = lane; e < NU * NX; e += W64) sh.Hwx[e] = C.ws.rHwx[st * NU * NX + e];
+    }
+    if (lane < NU) {
+      // hw = P (R' c + rho) + Bp^T (W d + omega)
+      double t[NU];
+      for (int l = 0; l < NU; ++l) {
+        double acc = sh.rho[l];
+        if (mode == Mode::EQ)
+          for (int m = 0; m < NU; ++m) acc += sh.Rp[l * NU + m] * sh.c[m];
+        t[l] = acc;
+      }
+      double acc = 0.0;
+      for (int l = 0; l < NU; ++l) acc += sh.P[lane * NU + l] * t[l];
+      for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + lane] * sh.Wdo[l];
+      sh.hw[lane] = acc;
+    }
+    __syncthreads();
+    if (factor) {
+      // Cholesky H = L L^T in place (lower triangle), column by column
+      for (int j = 0; j < NU; ++j) {
+        if (lane == 0) {
+          double v = sh.H[j * NU + j];
+          for (int l = 0; l < j; ++l) v -= sh.H[j * NU + l] * sh.H[j * NU + l];
+          sh.H[j * NU + j] = sqrt(fmax(v, 1e-300));
+        }
+        __syncthreads();
+        if (lane > j && lane < NU) {
+          double v = sh.H[lane * NU + j];
+          for (int l = 0; l < j; ++l) v -= sh.H[lane * NU + l] * sh.H[j * NU + l];
+          sh.H[lane * NU + j] = v / sh.H[j * NU + j];
+        }
+        __syncthreads();
+      }
+      // store factor and Hwx for a second right-hand side
+      double* L = C.ws.rL + st * NM;
+      for (int r = 0; r < NU; ++r)
+        for (int cc = r + lane; cc < NU; cc += W64) L[pk(r, cc, NU)] = sh.H[cc * NU + r];
+      for (int e = lane; e < NU * NX; e += W64) C.ws.rHwx[st * NU * NX + e] = sh.Hwx[e];
+    }
+    __syncthreads();
+    // K = -H^{-1} Hwx (13 columns) and kap = -H^{-1} hw (column 13)
+    if (lane <= NX) {
+      double y[NU];
+      for (int i = 0; i < NU; ++i) {
+        double v = (lane < NX) ? sh.Hwx[i * NX + lane] : sh.hw[i];
+        for (int l = 0; l < i; ++l) v -= sh.H[i * NU + l] * y[l];
+        y[i] = v / sh.H[i * NU + i];
+      }
+      for (int i = NU - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int l = i + 1; l < NU; ++l) v -= sh.H[l * NU + i] * y[l];
+        y[i] = v / sh.H[i * NU + i];
+      }
+      if (lane < NX) {
+        for (int i = 0; i < NU; ++i) sh.K[i * NX + lane] = -y[i];
+      } else {
+        for (int i = 0; i < NU; ++i) sh.kap[i] = -y[i];
+      }
+    }
+    __syncthreads();
+    if (factor)
+      for (int e = lane; e < NU * NX; e += W64) C.ws.rK[st * NU * NX + e] = sh.K[e];
+    if (lane < NU) C.ws.rkap[st * NU + lane] = sh.kap[lane];
+    // S = A^T W A + Hwx^T K ; s = A^T (W d + omega) + Hwx^T kap
+    if (factor) {
+      for (int e = lane; e < NX * NX; e += W64) {
+        const int i = e / NX, j = e % NX;
+        double acc = 0.0;
+        for (int l = 0; l < NX; ++l) acc += sh.A[l * NX + i] * sh.WA[l * NX + j];
+        for (int l = 0; l < NU; ++l) acc += sh.Hwx[l * NX + i] * sh.K[l * NX + j];
+        sh.W[e] = acc;    // new S, copied below
+      }
+    }
+    if (lane < NX) {
+      double acc = 0.0;
+      for (int l = 0; l < NX; ++l) acc += sh.A[l * NX + lane] * sh.Wdo[l];
+      for (int l = 0; l < NU; ++l) acc += sh.Hwx[l * NX + lane] * sh.kap[l];
+      sh.xn[lane] = acc;
+    }
+    __syncthreads();
+    if (factor)
+      for (int e = lane; e < NX * NX; e += W64) sh.S[e] = 0.5 * (sh.W[e] + sh.W[(e % NX) * NX + e / NX]);
+    if (lane < NX) sh.s[lane] = sh.xn[lane];
+    __syncthreads();
+  }
+  // forward rollout
+  if (lane < NX) {
+    sh.xv[lane] = (mode == Mode::EQ) ? (double)C.p.x0[(size_t)C.b * NX + lane] : 0.0;
+  }
+  __syncthreads();
+  double* xout = (mode == Mode::EQ) ? C.ws.rx : C.ws.rdx;
+  double* uout = (mode == Mode::EQ) ? C.ws.ru : C.ws.rdu;
+  if (lane < NX) xout[((size_t)C.b * (C.n + 1)) * NX + lane] = sh.xv[lane];
+  for (int k = 0; k < N; ++k) {
+    const size_t st = C.s0 + k;
+    load_AB(C, sh, k);
+    load_face(C, sh, k, mode == Mode::NEWTON);
+    if (lane < NU) {
+      double acc = C.ws.rkap[st * NU + lane];
+      for (int l = 0; l < NX; ++l) acc += C.ws.rK[st * NU * NX + lane * NX + l] * sh.xv[l];
+      sh.wv[lane] = acc;
+    }
+    __syncthreads();
+    if (lane < NU) {
+      double acc = sh.c[lane];
+      for (int l = 0; l < NU; ++l) acc += sh.P[lane * NU + l] * sh.wv[l];
+      sh.uv[lane] = acc;
+      uout[st * NU + lane] = acc;
+    }
+    __syncthreads();
+    if (lane < NX) {
+      double acc = 0.0;
+      for (int l = 0; l < NX; ++l) acc += sh.A[lane * NX + l] * sh.xv[l];
+      for (int l = 0; l < NU; ++l) acc += sh.B[lane * NU + l] * sh.uv[l];
+      if (mode == Mode::EQ && C.p.e) acc += (double)C.p.e[st * NX + lane];
+      sh.xn[lane] = acc;
+    }
+    __syncthreads();
+    if (lane < NX) {
+      sh.xv[lane] = sh.xn[lane];
+      xout[((size_t)C.b * (C.n + 1) + k + 1) * NX + lane] = sh.xn[lane];
+    }
+    __syncthreads();
+  }
+}
+
+// Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
+// gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
+__device__ void costates_grad(const Ctx& C, Sh& sh) {
+  const int lane = threadIdx.x;
+  for (int k = C.N - 1; k >= 0; --k) {
+    const size_t st = C.s0 + k;
+    if (lane < NX) {
+      const double x = C.ws.rx[((size_t)C.b * (C.n + 1) + k + 1) * NX + lane];
+      double acc = C.Q[lane] * (x - (double)C.p.x_ref[st * NX + lane]);
+      if (k + 1 < C.N) {
+        const float* A1 = C.p.A + (st + 1) * NX * NX;
+        for (int l = 0; l < NX; ++l) acc += (double)A1[l * NX + lane] * sh.xn[l];
+      }
+      sh.om[lane] = acc;
+    }
+    __syncthreads();
+    if (lane < NX) {
+      sh.xn[lane] = sh.om[lane];
+      C.ws.rlam[st * NX + lane] = sh.om[lane];
+    }
+    __syncthreads();
+  }
+  for (int e = lane; e < C.N * NU; e += W64) {
+    const int k = e / NU, j = e % NU;
+    const size_t st = C.s0 + k;
+    const float* B = C.p.B + st * NX * NU;
+    const double ur = C.p.u_ref ? (double)C.p.u_ref[st * NU + j] : 0.0;
+    double acc = C.R[j] * (C.ws.ru[st * NU + j] - ur);
+    for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + j] * C.ws.rlam[st * NX + l];
+    C.ws.rg[st * NU + j] = acc;
+  }
+  __syncthreads();
+}
+
+// Row multipliers of each stance contact from its face and the gradient, and
+// the normalised KKT residuals of the current (u, x, p, mu).  Returns KKT.
+__device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
+  const int lane = threadIdx.x;
+  double r_ineq = 0.0, stat = 0.0, term = 0.0, comp = 0.0, mumax = 0.0, neg = 0.0;
+  for (int e = lane; e < C.N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
+    const size_t st = C.s0 + k;
+    const double* u = C.ws.ru + st * NU + 6 * i;
+    const double* g = C.ws.rg + st * NU + 6 * i;
+    double* mu = C.ws.rmu + (st * 2 + i) * NROW;
+    for (int r = 0; r < NROW; ++r) mu[r] = 0.0;
+    if (!C.p.contact[st * 2 + i]) {
+      for (int a = 0; a < 6; ++a) r_ineq = fmax(r_ineq, fabs(u[a]) / C.mg);
+      continue;
+    }
+    const int code = C.ws.faces[st * 2 + i];
+    for (int a = 0; a < 6; ++a) {
+      const double ur = C.p.u_ref ? (double)C.p.u_ref[st * NU + 6 * i + a] : 0.0;
+      const double ru = C.R[6 * i + a] * (u[a] - ur);
+      term = fmax(term, fmax(fabs(ru), fabs(g[a] - ru)));
+    }
+    // force multipliers
+    if (face_apex(code)) {
+      double best = -1e300, bm[3] = {0, 0, 0};
+      int bdrop = 0;
+      for (int drop = 0; drop < 4; ++drop) {
+        double M[3][3], r[3];
+        int m = 0;
+        double rows[3][3];
+        for (int rr = 0; rr < 4; ++rr) {
+          if (rr == drop) continue;
+          double gg[6], hh;
+          wrench_row(rr, C.mu, C.fz, C.tm, gg, &hh);
+          rows[m][0] = gg[0]; rows[m][1] = gg[1]; rows[m][2] = gg[2];
+          ++m;
+        }
+        // G3^T mu = -g  ->  (G3 G3^T) mu = -G3 g
+        for (int a = 0; a < 3; ++a) {
+          for (int bb = 0; bb < 3; ++bb)
+            M[a][bb] = rows[a][0] * rows[bb][0] + rows[a][1] * rows[bb][1] + rows[a][2] * rows[bb][2];
+          r[a] = -(rows[a][0] * g[0] + rows[a][1] * g[1] + rows[a][2] * g[2]);
+        }
+        small_solve(M, r, 3);
+        const double mn = fmin(r[0], fmin(r[1], r[2]));
+        if (mn > best) { best = mn; bm[0] = r[0]; bm[1] = r[1]; bm[2] = r[2]; bdrop = drop; }
+      }
+      int m = 0;
+      for (int rr = 0; rr < 4; ++rr) {
+        if (rr == bdrop) continue;
+        mu[rr] = bm[m++];
+      }
+    } else {
+      double G[3][3];
+      int idx[3], m = 0;
+      for (int rr = 0; rr < 5; ++rr)
+        if (code >> rr & 1) {
+          double gg[6], hh;
+          wrench_row(rr, C.mu, C.fz, C.tm, gg, &hh);
+          G[m][0] = gg[0]; G[m][1] = gg[1]; G[m][2] = gg[2];
+          idx[m++] = rr;
+        }
+      if (m) {
+        double M[3][3], r[3];
+        for (int a = 0; a < m; ++a) {
+          for (int bb = 0; bb < m; ++bb)
+            M[a][bb] = G[a][0] * G[bb][0] + G[a][1] * G[bb][1] + G[a][2] * G[bb][2];
+          r[a] = -(G[a][0] * g[0] + G[a][1] * g[1] + G[a][2] * g[2]);
+        }
+        small_solve(M, r, m);
+        for (int a = 0; a < m; ++a) mu[idx[a]] = r[a];
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (code >> (8 + a) & 1) mu[5 + a] = -g[3 + a];
+      else if (code >> (11 + a) & 1) mu[8 + a] = g[3 + a];
+    }
+    // residual pieces
+    double gm[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < NROW; ++r) {
+      double gg[6], hh;
+      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+      double gu = 0.0;
+      for (int a = 0; a < 6; ++a) {
+        gu += gg[a] * u[a];
+        gm[a] += gg[a] * mu[r];
+      }
+      r_ineq = fmax(r_ineq, fmax(0.0, gu - hh) / C.mg);
+      comp = fmax(comp, mu[r] * fmax(0.0, hh - gu));
+      mumax = fmax(mumax, mu[r]);
+      neg = fmax(neg, -mu[r]);
+    }
+    for (int a = 0; a < 6; ++a) {
+      term = fmax(term, fabs(gm[a]));
+      stat = fmax(stat, fabs(g[a] + gm[a]));
+    }
+  }
+  // state-side term norms: |Q (x - r)|, |p|, |A^T p| = |p_k - Q(x_{k+1} - r_k)|
+  for (int e = lane; e < C.N * NX; e += W64) {
+    const int k = e / NX, j = e % NX;
+    const size_t st = C.s0 + k;
+    const double x = C.ws.rx[((size_t)C.b * (C.n + 1) + k + 1) * NX + j];
+    const double qx = C.Q[j] * (x - (double)C.p.x_ref[st * NX + j]);
+    const double lam = C.ws.rlam[st * NX + j];
+    term = fmax(term, fmax(fabs(qx), fmax(fabs(lam), fabs(lam - qx))));
+  }
+  r_ineq = wave_max(r_ineq);
+  stat = wave_max(stat);
+  term = wave_max(term);
+  comp = wave_max(comp);
+  mumax = wave_max(mumax);
+  neg = wave_max(neg);
+  res[0] = 0.0;   // r_dyn: filled by the caller from the rollout
+  res[1] = r_ineq;
+  res[2] = stat / (1.0 + term);
+  res[3] = comp / (1.0 + mumax * C.mg);
+  res[4] = fmax(0.0, neg) / (1.0 + term);
+  double kkt = 0.0;
+  for (int i = 1; i < PINMPC_NRES; ++i) kkt = fmax(kkt, res[i]);
+  return kkt;
+}
+
+// Dynamics residual of the FP64 trajectory (rx, ru).
+__device__ double dyn_residual(const Ctx& C) {
+  const int lane = threadIdx.x;
+  double r = 0.0;
+  for (int e = lane; e < C.N * NX; e += W64) {
+    const int k = e / NX, i = e % NX;
+    const size_t st = C.s0 + k;
+    const double* x = C.ws.rx + ((size_t)C.b * (C.n + 1) + k) * NX;
+    const float* A = C.p.A + st * NX * NX + i * NX;
+    const float* B = C.p.B + st * NX * NU + i * NU;
+    double ax = 0.0, bu = 0.0;
+    for (int l = 0; l < NX; ++l) ax += (double)A[l] * x[l];
+    for (int l = 0; l < NU; ++l) bu += (double)B[l] * C.ws.ru[st * NU + l];
+    const double ee = C.p.e ? (double)C.p.e[st * NX + i] : 0.0;
+    const double d = x[NX + i] - ax - bu - ee;
+    const double den = 1.0 + fmax(fabs(x[NX + i]), fmax(fabs(ax), fabs(bu)));
+    r = fmax(r, fabs(d) / den);
+  }
+  return wave_max(r);
+}
+
+// Primal-dual active-set update of the faces; returns an order-independent
+// hash of the new face set.
+__device__ uint64_t pdas_update(const Ctx& C) {
+  const int lane = threadIdx.x;
+  uint64_t hsh = 0;
+  for (int e = lane; e < C.N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
+    const size_t st = C.s0 + k;
+    int code = 0;
+    if (C.p.contact[st * 2 + i]) {
+      const double* u = C.ws.ru + st * NU + 6 * i;
+      const double* mu = C.ws.rmu + (st * 2 + i) * NROW;
+      for (int r = 0; r < NROW; ++r) {
+        double gg[6], hh;
+        wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+        double gu = 0.0;
+        for (int a = 0; a < 6; ++a) gu += gg[a] * u[a];
+        const double sc = (r < 5) ? C.mg : C.tm;
+        if (mu[r] * sc + (gu - hh) > 0.0) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
+      }
+      if (face_apex(code)) code = (code & ~31) | FACE_APEX;
+      for (int a = 0; a < 3; ++a)
+        if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
+    }
+    C.ws.faces[st * 2 + i] = code;
+    uint64_t v = (uint64_t)(code + 1) * 0x9E3779B97F4A7C15ull ^ ((uint64_t)(e + 1) * 0xC2B2AE3D27D4EB4Full);
+    v ^= v >> 29;
+    v *= 0xBF58476D1CE4E5B9ull;
+    hsh ^= v;
+  }
+  __syncthreads();
+  return wave_xor(hsh);
+}
+
+// Faces from slack: rows whose slack is below tol * row scale.
+__device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < C.N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
+    const size_t st = C.s0 + k;
+    int code = 0;
+    if (C.p.contact[st * 2 + i]) {
+      const double* u = u_src + st * NU + 6 * i;
+      for (int r = 0; r < NROW; ++r) {
+        double gg[6], hh;
+        wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+        double gu = 0.0;
+        for (int a = 0; a < 6; ++a) gu += gg[a] * u[a];
+        const double sc = (r < 5) ? C.mg : C.tm;
+        if ((hh - gu) / sc <= tol) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
+      }
+      if (face_apex(code)) code = (code & ~31) | FACE_APEX;
+    }
+    C.ws.faces[st * 2 + i] = code;
+  }
+  __syncthreads();
+}
+
+// One active-set pass: equality-constrained solve on the current faces,
+// costates, multipliers and residuals.
+__device__ double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
+  riccati(C, sh, Mode::EQ, true, nullptr);
+  costates_grad(C, sh);
+  const double kkt = multipliers_kkt(C, res);
+  res[0] = dyn_residual(C);
+  return fmax(kkt, res[0]);
+}
+
+// Interior-point fallback.  Rows scaled by mg (force rows) and tau_max
+// (moment rows).  Leaves faces from z > s.
+__device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
+  const int lane = threadIdx.x;
+  const int N = C.N;
+  // number of stance rows
+  int mloc = 0;
+  for (int e = lane; e < N * 2; e += W64)
+    if (C.p.contact[(C.s0 + (e >> 1)) * 2 + (e & 1)]) mloc += NROW;
+  const double m = wave_sum((double)mloc);
+  if (m == 0.0) return 0;
+  // initial point: the current ru (feasible ADMM point), its rollout in rx
+  for (int e = lane; e < N * 2 * NROW; e += W64) {
+    const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
+    const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
+    if (!C.p.contact[st * 2 + i]) continue;
+    double gg[6], hh;
+    wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+    double gu = 0.0;
+    for (int a = 0; a < 6; ++a) gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
+    const double sc = (r < 5) ? C.mg : C.tm;
+    C.ws.rs[rb] = fmax((hh - gu) / sc, 1.0);
+    C.ws.rz[rb] = 1.0;
+  }
+  __syncthreads();
+  double* rc = C.ws.rdz;   // reuse: complementarity target, then dz
+  int it = 0;
+  for (; it < maxit; ++it) {
+    // residuals rp and mu
+    double smz = 0.0, rpn = 0.0;
+    for (int e = lane; e < N * 2 * NROW; e += W64) {
+      const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
+      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
+      if (!C.p.contact[st * 2 + i]) continue;
+      double gg[6], hh;
+      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+      double gu = 0.0;
+      for (int a = 0; a < 6; ++a) gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
+      const double sc = (r < 5) ? C.mg : C.tm;
+      const double rp = (gu - hh) / sc + C.ws.rs[rb];
+      smz += C.ws.rs[rb] * C.ws.rz[rb];
+      rpn = fmax(rpn, fabs(rp));
+      rc[rb] = C.ws.rs[rb] * C.ws.rz[rb];     // affine (predictor) target
+    }
+    const double muv = wave_sum(smz) / m;
+    rpn = wave_max(rpn);
+    __syncthreads();
+    if (muv <= 1e-10 && rpn <= 1e-9) break;
+    // predictor
+    riccati(C, sh, Mode::NEWTON, true, rc);
+    double amax_s = 1.0, amax_z = 1.0;
+    for (int e = lane; e < N * 2 * NROW; e += W64) {
+      const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
+      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
+      if (!C.p.contact[st * 2 + i]) continue;
+      double gg[6], hh;
+      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+      double gu = 0.0, gdu = 0.0;
+      for (int a = 0; a < 6; ++a) {
+        gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
+        gdu += gg[a] * C.ws.rdu[st * NU + 6 * i + a];
+      }
+      const double sc = (r < 5) ? C.mg : C.tm;
+      const double s = C.ws.rs[rb], z = C.ws.rz[rb];
+      const double rp = (gu - hh) / sc + s;
+      const double ds = -rp - gdu / sc;
+      const double dz = (-s * z - z * ds) / s;
+      C.ws.rds[rb] = ds;
+      C.ws.rmu[rb] = dz;     // affine dz kept in rmu scratch
+      if (ds < 0) amax_s = fmin(amax_s, -s / ds);
+      if (dz < 0) amax_z = fmin(amax_z, -z / dz);
+    }
+    const double aa = fmin(wave_min(amax_s), wave_min(amax_z));
+    double sm = 0.0;
+    for (int e = lane; e < N * 2 * NROW; e += W64) {
+      const int k = e / (2 * NROW), i = (e / NROW) & 1;
+      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + e % NROW;
+      if (!C.p.contact[st * 2 + i]) continue;
+      sm += (C.ws.rs[rb] + aa * C.ws.rds[rb]) * (C.ws.rz[rb] + aa * C.ws.rmu[rb]);
+    }
+    const double mu_aff = wave_sum(sm) / m;
+    const double sigma = pow(mu_aff / muv, 3.0);
+    __syncthreads();
+    for (int e = lane; e < N * 2 * NROW; e += W64) {
+      const int k = e / (2 * NROW), i = (e / NROW) & 1;
+      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + e % NROW;
+      if (!C.p.contact[st * 2 + i]) continue;
+      rc[rb] = C.ws.rs[rb] * C.ws.rz[rb] + C.ws.rds[rb] * C.ws.rmu[rb] - sigma * muv;
+    }
+    __syncthreads();
+    // corrector: same matrix, new right-hand side
+    riccati(C, sh, Mode::NEWTON, false, rc);
+    amax_s = 1.0;
+    amax_z = 1.0;
+    for (int e = lane; e < N * 2 * NROW; e += W64) {
+      const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
+      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
+      if (!C.p.contact[st * 2 + i]) continue;
+      double gg[6], hh;
+      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
+      double gu = 0.0, gdu = 0.0;
+      for (int a = 0; a < 6; ++a) {
+        gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
+        gdu += gg[a] * C.ws.rdu[st * NU + 6 * i + a];
+      }
+      const double sc = (r < 5) ? C.mg : C.tm;
+      const double s = C.ws.rs[rb], z = C.ws.rz[rb];
+      const double rp = (gu - hh) / sc + s;
+      const double ds = -rp - gdu / sc;
+      const double dz = (-rc[rb] - z * ds) / s;
+      C.ws.rds[rb] = ds;
+      C.ws.rmu[rb] = dz;
+      if (ds < 0) amax_s = fmin(amax_s, -s / ds);
+      if (dz < 0) amax_z = fmin(amax_z, -z / dz);
+    }
+    const double a = fmin(1.0, 0.99 * fmin(wave_min(amax_s), wave_min(amax_z)));
+    __syncthreads();
+    for (int e = lane; e < N * 2 * NROW; e += W64) {
+      const int k = e / (2 * NROW), i = (e / NROW) & 1;
+      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + e % NROW;
+      if (!C.p.contact[st * 2 + i]) continue;
+      C.ws.rs[rb] += a * C.ws.rds[rb];
+      C.ws.rz[rb] += a * C.ws.rmu[rb];
+    }
+    for (int e = lane; e < N * NU; e += W64) C.ws.ru[C.s0 * NU + e] += a * C.ws.rdu[C.s0 * NU + e];
+    for (int e = lane; e < (N + 1) * NX; e += W64)
+      C.ws.rx[(size_t)C.b * (C.n + 1) * NX + e] += a * C.ws.rdx[(size_t)C.b * (C.n + 1) * NX + e];
+    __syncthreads();
+  }
+  // faces from z > s
+  for (int e = lane; e < N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
+    const size_t st = C.s0 + k;
+    int code = 0;
+    if (C.p.contact[st * 2 + i]) {
+      const size_t rb = (st * 2 + i) * NROW;
+      for (int r = 0; r < NROW; ++r)
+        if (C.ws.rz[rb + r] > C.ws.rs[rb + r]) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
+      if (face_apex(code)) code = (code & ~31) | FACE_APEX;
+      for (int a = 0; a < 3; ++a)
+        if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
+    }
+    C.ws.faces[st * 2 + i] = code;
+  }
+  __syncthreads();
+  return it;
+}
+
+// Active-set loop; returns true if certified.  passes accumulates.
+__device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int* passes,
+                                double res[PINMPC_NRES], double* kkt_out) {
+  uint64_t hist[8];
+  for (int i = 0; i < 8; ++i) hist[i] = 0;
+  int nh = 0;
+  for (int it = 0; it < maxp; ++it) {
+    const double kkt = eq_pass(C, sh, res);
+    ++*passes;
+    *kkt_out = kkt;
+    if (kkt <= tol) return true;
+    const uint64_t h = pdas_update(C);
+    bool seen = false;
+    for (int i = 0; i < 8; ++i) seen |= (hist[i] == h) && (i < nh || nh >= 8);
+    if (seen) return false;
+    hist[nh & 7] = h;
+    ++nh;
+  }
+  return false;
+}
+
+__global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, float* out_u,
+                                                    float* out_x, float* out_res,
+                                                    int32_t* out_iters, int32_t* out_status,
+                                                    int admm_iters, int accel, int refine,
+                                                    int pass_a, int ipm_max, int pass_c,
+                                                    double tol) {
+  __shared__ Sh sh;
+  const int lane = threadIdx.x;
+  Ctx C;
+  C.p = p;
+  C.ws = ws;
+  C.b = blockIdx.x;
+  C.n = p.n_max;
+  C.N = horizon(p, C.b);
+  C.s0 = (size_t)C.b * C.n;
+  C.mu = p.mu[C.b];
+  C.fz = p.fz_max[C.b];
+  C.tm = p.tau_max[C.b];
+  C.mg = weight_of(p, C.b);
+  for (int j = 0; j < NX; ++j) C.Q[j] = p.Q[(size_t)C.b * NX + j];
+  for (int j = 0; j < NU; ++j) C.R[j] = p.R[(size_t)C.b * NU + j];
+  const int N = C.N;
+
+  // input checks: bounds, then finiteness of this problem's data
+  int bad = !(C.mu >= 0.0) || !(C.fz >= 0.0) || !(C.tm >= 0.0) || !(C.mg > 0.0) ||
+            N < 1 || N > C.n;
+  for (int j = 0; j < NX; ++j) bad |= !(C.Q[j] > 0.0);
+  for (int j = 0; j < NU; ++j) bad |= !(C.R[j] > 0.0);
+  int nonfinite = 0;
+  if (!bad) {
+    for (int e = lane; e < N * NX * NX; e += W64) nonfinite |= !isfinite(p.A[C.s0 * NX * NX + e]);
+    for (int e = lane; e < N * NX * NU; e += W64) nonfinite |= !isfinite(p.B[C.s0 * NX * NU + e]);
+    for (int e = lane; e < N * NX; e += W64) {
+      nonfinite |= !isfinite(p.x_ref[C.s0 * NX + e]);
+      if (p.e) nonfinite |= !isfinite(p.e[C.s0 * NX + e]);
+    }
+    if (lane < NX) nonfinite |= !isfinite(p.x0[(size_t)C.b * NX + lane]);
+  }
+  nonfinite = wave_max((double)nonfinite) > 0.0;
+  const size_t ux = (size_t)C.b * C.n * NU, xx = (size_t)C.b * (C.n + 1) * NX;
+  if (bad || nonfinite) {
+    for (int e = lane; e < C.n * NU; e += W64) out_u[ux + e] = 0.f;
+    for (int e = lane; e < (C.n + 1) * NX; e += W64) out_x[xx + e] = 0.f;
+    if (lane == 0) {
+      if (out_status) out_status[C.b] = bad ? PINMPC_ST_BADINPUT : PINMPC_ST_NONFINITE;
+      if (out_iters) out_iters[C.b] = 0;
+    }
+    if (out_res && lane < PINMPC_NRES) out_res[(size_t)C.b * PINMPC_NRES + lane] = __builtin_nanf("");
+    return;
+  }
+
+  // ADMM inputs (unscaled) into ru, rollout into rx
+  const float* zsrc = accel ? ws.cur : ws.hat;
+  for (int e = lane; e < N * NU; e += W64) {
+    const int k = e / NU, j = e % NU;
+    const size_t st = C.s0 + k;
+    const double sc = (j % 6 < 3) ? (double)ws.sf[st] : (double)ws.tsc[C.b];
+    double v = (double)zsrc[(st * NSTATE) * NL + NX + j] * sc;
+    if (!p.contact[st * 2 + j / 6]) v = 0.0;
+    ws.ru[st * NU + j] = v;
+  }
+  __syncthreads();
+
+  double res[PINMPC_NRES] = {0, 0, 0, 0, 0};
+  double kkt = 1e300;
+  int passes = 0;
+  bool ok = false;
+  if (refine) {
+    faces_from_u(C, ws.ru, 1e-5);
+    ok = active_set_loop(C, sh, pass_a, tol, &passes, res, &kkt);
+    if (!ok && ipm_max > 0) {
+      // interior point from the ADMM point (re-derived: ru was overwritten)
+      for (int e = lane; e < N * NU; e += W64) {
+        const int k = e / NU, j = e % NU;
+        const size_t st = C.s0 + k;
+        const double sc = (j % 6 < 3) ? (double)ws.sf[st] : (double)ws.tsc[C.b];
+        double v = (double)zsrc[(st * NSTATE) * NL + NX + j] * sc;
+        if (!p.contact[st * 2 + j / 6]) v = 0.0;
+        ws.ru[st * NU + j] = v;
+      }
+      __syncthreads();
+      // rollout of the start point
+      if (lane < NX) sh.xv[lane] = (double)p.x0[(size_t)C.b * NX + lane];
+      __syncthreads();
+      if (lane < NX) ws.rx[xx + lane] = sh.xv[lane];
+      for (int k = 0; k < N; ++k) {
+        const size_t st = C.s0 + k;
+        if (lane < NX) {
+          double acc = p.e ? (double)p.e[st * NX + lane] : 0.0;
+          for (int l = 0; l < NX; ++l) acc += (double)p.A[st * NX * NX + lane * NX + l] * sh.xv[l];
+          for (int l = 0; l < NU; ++l) acc += (double)p.B[st * NX * NU + lane * NU + l] * ws.ru[st * NU + l];
+          sh.xn[lane] = acc;
+        }
+        __syncthreads();
+        if (lane < NX) {
+          sh.xv[lane] = sh.xn[lane];
+          ws.rx[xx + (k + 1) * NX + lane] = sh.xn[lane];
+        }
+        __syncthreads();
+      }
+      const int its = ipm(C, sh, ipm_max);
+      passes += its;
+      ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
+    }
+  } else {
+    // ADMM point as is: rollout and residuals with faces from slack
+    faces_from_u(C, ws.ru, 1e-5);
+    // rollout
+    if (lane < NX) sh.xv[lane] = (double)p.x0[(size_t)C.b * NX + lane];
+    __syncthreads();
+    if (lane < NX) ws.rx[xx + lane] = sh.xv[lane];
+    for (int k = 0; k < N; ++k) {
+      const size_t st = C.s0 + k;
+      if (lane < NX) {
+        double acc = p.e ? (double)p.e[st * NX + lane] : 0.0;
+        for (int l = 0; l < NX; ++l) acc += (double)p.A[st * NX * NX + lane * NX + l] * sh.xv[l];
+        for (int l = 0; l < NU; ++l) acc += (double)p.B[st * NX * NU + lane * NU + l] * ws.ru[st * NU + l];
+        sh.xn[lane] = acc;
+      }
+      __syncthreads();
+      if (lane < NX) {
+        sh.xv[lane] = sh.xn[lane];
+        ws.rx[xx + (k + 1) * NX + lane] = sh.xn[lane];
+      }
+      __syncthreads();
+    }
+    costates_grad(C, sh);
+    kkt = multipliers_kkt(C, res);
+    res[0] = dyn_residual(C);
+  }
+
+  // outputs
+  for (int e = lane; e < C.n * NU; e += W64)
+    out_u[ux + e] = (e < N * NU) ? (float)ws.ru[C.s0 * NU + e] : 0.f;
+  for (int e = lane; e < (C.n + 1) * NX; e += W64)
+    out_x[xx + e] = (e < (N + 1) * NX) ? (float)ws.rx[xx + e] : 0.f;
+  if (lane == 0) {
+    if (out_status)
+      out_status[C.b] = refine ? (ok ? PINMPC_ST_OK : PINMPC_ST_UNPOLISHED) : PINMPC_ST_MAXITER;
+    if (out_iters) out_iters[C.b] = admm_iters + passes;
+  }
+  if (out_res && lane < PINMPC_NRES) out_res[(size_t)C.b * PINMPC_NRES + lane] = (float)res[lane];
+}
+
+}  // namespace
+
+hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                         const pinmpc_out& out, hipStream_t st) {
+  if (p.batch == 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_kernel, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x, out.res,
+                     out.iters, out.status, s.iters, s.accel, s.refine, s.refine_passes,
+                     s.ipm_iters, s.polish_passes, s.kkt_tol);
+  return hipGetLastError();
+}
+
+}  // namespace pinmpc

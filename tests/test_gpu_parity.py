@@ -1,0 +1,189 @@
+"""GPU solves through the C-ABI compared with the FP64 oracle.
+
+Bar (every compared problem): status certified; solution error against the
+oracle optimum <= 1e-4 in u and in x (relative, see oracle.kkt); the KKT
+residuals the library reports <= 1e-5; and the oracle's own evaluation of the
+returned FP32 (u, x), with multipliers refitted by the oracle, <= 1e-5.
+Invariants on every problem: swing inputs exactly 0, wrench sets satisfied,
+x the rollout of u.
+"""
+import numpy as np
+import pytest
+
+import mpcgen
+from oracle import kkt, qp
+
+pytestmark = pytest.mark.gpu
+
+TOL_ERR = 1e-4
+TOL_KKT = 1e-5
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch  # noqa: F401
+    from paper_2606_05687_amd import binding
+    s = binding.Solver(0)
+    yield s
+    s.close()
+
+
+def _solve(solver, batch, **settings):
+    import torch
+    from paper_2606_05687_amd import binding
+    base = binding.default_settings()
+    for f, _ in binding.Settings._fields_:
+        setattr(solver.settings, f, getattr(base, f))
+    if settings:
+        solver.set(**settings)
+    else:
+        solver.set()
+    dev = binding.to_device(batch)
+    out = solver.solve(dev)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _check_invariants(batch, out, idx):
+    for b in idx:
+        p = mpcgen.problem_fp64(batch, b)
+        N = p["N"]
+        u = out["u"][b, :N].astype(np.float64)
+        x = out["x"][b, :N + 1].astype(np.float64)
+        sw = ~p["contact"]
+        for i in range(2):
+            assert np.all(out["u"][b, :N, 6 * i:6 * i + 6][sw[:, i]] == 0.0)
+        assert np.all(out["u"][b, N:] == 0)
+        r = kkt.residuals(p, u, x)
+        assert r["r_ineq"] <= 1e-6, (b, r)
+        assert r["r_dyn"] <= 1e-6, (b, r)
+
+
+def _compare(batch, out, idx, refs=None):
+    worst = dict(eu=0.0, ex=0.0, kkt_lib=0.0, kkt_oracle=0.0)
+    for j, b in enumerate(idx):
+        p = mpcgen.problem_fp64(batch, b)
+        ref = refs[j] if refs is not None else qp.solve(p)
+        N = p["N"]
+        u = out["u"][b, :N].astype(np.float64)
+        x = out["x"][b, :N + 1].astype(np.float64)
+        assert out["status"][b] == 0, (b, out["status"][b], out["res"][b])
+        eu, ex = kkt.rel_err(u, ref["u"], x, ref["x"], p["weight"])
+        r = kkt.residuals(p, u, x)
+        worst["eu"] = max(worst["eu"], eu)
+        worst["ex"] = max(worst["ex"], ex)
+        worst["kkt_lib"] = max(worst["kkt_lib"], float(np.max(out["res"][b])))
+        worst["kkt_oracle"] = max(worst["kkt_oracle"], r["kkt"])
+        assert eu <= TOL_ERR and ex <= TOL_ERR, (b, eu, ex)
+        assert np.max(out["res"][b]) <= TOL_KKT, (b, out["res"][b])
+        assert r["kkt"] <= TOL_KKT, (b, r)
+    print("worst", {k: f"{v:.2e}" for k, v in worst.items()})
+    return worst
+
+
+def test_parity_small_b64_n10(solver):
+    batch = mpcgen.make_batch("small_b64_n10")
+    out = _solve(solver, batch)
+    _check_invariants(batch, out, range(64))
+    _compare(batch, out, range(64))
+
+
+def test_parity_plain_b4096_n20_full_launch(solver):
+    """The benchmark's launch: all 4096 problems in one solve; the first 24
+    compared with the oracle, every problem checked for status and the
+    residual bar."""
+    batch = mpcgen.make_batch("plain_b4096_n20")
+    out = _solve(solver, batch)
+    ok = out["status"] == 0
+    print("certified", ok.mean(), "max res", out["res"][ok].max())
+    assert ok.mean() >= 0.99
+    assert np.all(out["res"][ok] <= TOL_KKT)
+    _compare(batch, out, range(24))
+    _check_invariants(batch, out, range(0, 4096, 97))
+
+
+def test_parity_uneven_horizons(solver):
+    batch = mpcgen.make_batch("uneven_b16384", indices=range(96), n_max=60)
+    out = _solve(solver, batch)
+    assert (out["status"] == 0).all(), out["status"]
+    pick = [int(np.argmax(batch["N"] == n)) for n in (10, 20, 30, 40, 60)]
+    _compare(batch, out, pick + list(range(6)))
+    _check_invariants(batch, out, range(96))
+
+
+def test_edge_cases(solver):
+    import torch
+    from paper_2606_05687_amd import binding
+    # empty batch is a no-op
+    empty = mpcgen.make_batch("plain_b4096_n20", indices=[])
+    dev = binding.to_device(empty)
+    out = solver.alloc_out(dev)
+    solver.solve(dev, out)
+    torch.cuda.synchronize()
+    # horizon 1, flight (no contact anywhere), ragged horizons padded
+    batch = mpcgen.make_batch("small_b64_n10", indices=range(6))
+    batch["N"][0] = 1
+    batch["contact"][1] = 0
+    batch["N"][2] = 3
+    batch["contact"][3, :, 0] = 1
+    batch["contact"][3, :, 1] = 1        # double support everywhere
+    for b in (0, 2):
+        n = batch["N"][b]
+        batch["contact"][b, n:] = 0
+    o = _solve(solver, batch)
+    assert np.all(o["u"][1] == 0)
+    _compare(batch, o, range(6))
+    _check_invariants(batch, o, range(6))
+
+
+def test_determinism(solver):
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(256))
+    a = _solve(solver, batch)
+    b = _solve(solver, batch)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_nonfinite_and_bad_input_isolated(solver):
+    batch = mpcgen.make_batch("small_b64_n10", indices=range(8))
+    clean = _solve(solver, batch)
+    bad = {k: v.copy() for k, v in batch.items()}
+    bad["A"][3, 2, 4, 4] = np.nan
+    bad["mu"][5] = -0.5
+    o = _solve(solver, bad)
+    assert o["status"][3] == 3 and o["status"][5] == 4
+    for b in (0, 1, 2, 4, 6, 7):
+        for k in ("u", "x", "res", "status"):
+            assert np.array_equal(o[k][b], clean[k][b]), (b, k)
+
+
+def test_admm_first_sweeps_match_fp64_reference(solver):
+    """Iterate-level check of the Sec. III sweep against the oracle's FP64
+    ADMM from the same zero start (same rho, scaling, restart rule).  After
+    one sweep the FP32 iterate agrees to FP32 rounding; later sweeps drift
+    with the conditioning (reported, not a bar: the paper fixes no rho or
+    initial iterate, so iterate parity is unpinned)."""
+    import torch
+    from oracle import admm
+    from paper_2606_05687_amd import binding
+    batch = mpcgen.make_batch("small_b64_n10", indices=range(4))
+    base = binding.default_settings()
+    for f, _ in binding.Settings._fields_:
+        setattr(solver.settings, f, getattr(base, f))
+    solver.set()
+    dev = binding.to_device(batch)
+    for K, tol in ((1, 1e-4), (3, 1e-3), (20, None)):
+        z = solver.admm(dev, K)
+        torch.cuda.synchronize()
+        z = z.cpu().numpy().astype(np.float64)
+        for b in range(4):
+            p = mpcgen.problem_fp64(batch, b)
+            ref = admm.solve(p, iters=K, rho=10.0, scaling=True, accel=True)
+            zr = ref["iterates"]["z"].copy()
+            zr[:, 13:] *= ref["setup"]["S"]
+            N = p["N"]
+            scale = np.concatenate([np.ones(13), np.full(12, p["weight"])])
+            d = np.max(np.abs(z[b, :N] - zr) / scale) / max(1.0, np.max(np.abs(zr) / scale))
+            print(f"K={K} b={b} scaled max diff {d:.2e}")
+            if tol is not None:
+                assert d <= tol, (K, b, d)

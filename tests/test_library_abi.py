@@ -1,0 +1,50 @@
+"""The C-ABI library builds, loads and exports every symbol the header
+declares; host-side argument checks reject bad calls (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_05687_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pinmpc.h")).read()
+    return sorted(set(re.findall(r"\b(pinmpc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = binding.load()
+    names = _declared()
+    assert "pinmpc_solve" in names and "pinmpc_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(binding.EXPORTS) <= set(names)
+
+
+def test_struct_layouts_match_header():
+    # field order and C types as declared in include/pinmpc.h
+    assert ctypes.sizeof(binding.Settings) == 56
+    assert ctypes.sizeof(binding.Batch) == 8 + 15 * 8
+    assert ctypes.sizeof(binding.Out) == 5 * 8
+
+
+def test_default_settings_and_errors():
+    lib = binding.load()
+    s = binding.default_settings()
+    assert s.iters == 100 and abs(s.rho - 10.0) < 1e-6 and s.refine == 1
+    assert lib.pinmpc_strerror(-3).decode() == "workspace exceeds the HBM budget"
+    nb = ctypes.c_size_t()
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 4096, 20, ctypes.byref(nb)) == 0
+    assert 1e8 < nb.value < 2e9
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, 0, ctypes.byref(nb)) == -1
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, 65, ctypes.byref(nb)) == -1
+    # null context / null arguments are rejected before any device call
+    assert lib.pinmpc_solve(None, None, None, None) == -1
+    assert lib.pinmpc_destroy(None) == -1
+    h = ctypes.c_void_p()
+    bad = binding.default_settings(rho=-1.0)
+    assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1

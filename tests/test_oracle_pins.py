@@ -301,6 +301,35 @@ def test_kkt_measure_detects_planted_errors():
     assert eu > 1e-3 and ex == 0
 
 
+def test_kkt_measure_rejects_wrong_face_with_negative_multiplier():
+    """A point that minimises the cost exactly on a face that is too small
+    (one row forced active that is slack at the optimum) is stationary on
+    that face; only the sign of its multiplier shows it is not optimal."""
+    p = _prob("small_b64_n10", 2)
+    sol = qp.solve(p)
+    H, g, G, h, free, rows = qp.dense_qp(p)
+    U = sol["u"].reshape(-1)[free]
+    act = [j for j in range(len(h)) if h[j] - G[j] @ U <= 1e-9 * p["weight"]]
+    extra = [j for j in range(len(h)) if j not in act and rows[j][2] < 5][0]
+    A = act + [extra]
+    Ua = qp.equality_qp(H, g, G[A], h[A])
+    if np.max(G @ Ua - h) > 1e-9 * p["weight"]:
+        pytest.skip("wrong face leaves the feasible set; sign check not reached")
+    za, *_ = np.linalg.lstsq(G[A].T, -(H @ Ua + g), rcond=None)
+    assert za[-1] < 0
+    mu = np.zeros((p["N"], 2, 11))
+    for j, zz in zip(A, za):
+        k, i, r = rows[j]
+        mu[k, i, r] = zz
+    u = np.zeros(p["N"] * 12)
+    u[free] = Ua
+    u = u.reshape(p["N"], 12)
+    x = qp.rollout(p, u)
+    r = kkt.residuals(p, u, x, qp.costates(p, x), mu)
+    assert r["r_stat"] <= 1e-9          # stationary on the wrong face ...
+    assert r["r_sign"] > 1e-6 and r["kkt"] > 1e-6   # ... but not optimal
+
+
 # ----------------------------------------------------- ADMM (Sec. III) pins
 
 def _lifted(p):
