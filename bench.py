@@ -1,0 +1,204 @@
+"""Benchmark: certified MPC solves per second on one MI355X.
+
+Workload: 4096 problems, horizon 20, dt 0.03 s, mixed single and double
+support, pushes on the initial velocity (the "plain_b4096_n20" generator
+configuration), inputs resident in HBM.  One step = one pinmpc_solve of the
+whole batch: setup, the ADMM sweeps, FP64 refinement and certificate.  Only
+problems whose reported KKT residuals are all <= 1e-5 count as solves.
+
+Prints one JSON line.  Also reports p50/p99 latency of a batch solve, the
+roofline of the dominant kernel measured with HIP events inside the library,
+and the FP64 oracle timed on the host cores as a reference baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MPC solves/sec at KKT resid ≤1e-5 (batch 4096, N=20); p99 solve latency"
+WORKLOAD = "plain_b4096_n20"
+KKT_BAR = 1e-5
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# Algorithmic bytes of one plain ADMM sweep per stage (FP32):
+#   operators A 676 + Bt 624 + H packed 1300 + M packed 312 + qbar 100
+#   + e 52 + contact 2 + force scale 4 = 3070 B read,
+#   iterates (current and extrapolated, 5 x 25 each) 1000 B read + 1000 B written
+SWEEP_BYTES_PER_STAGE = 3070 + 2000
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=100, help="ADMM sweeps per solve")
+    ap.add_argument("--cpu-sample", type=int, default=256,
+                    help="problems in the oracle CPU-baseline sample (0: skip)")
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    return ap.parse_args()
+
+
+def _oracle_chunk(idx):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import mpcgen
+    from oracle import qp
+    batch = mpcgen.make_batch(WORKLOAD, indices=idx)
+    t = time.perf_counter()
+    for b in range(len(idx)):
+        qp.solve(mpcgen.problem_fp64(batch, b))
+    return time.perf_counter() - t
+
+
+def cpu_baseline(sample, workers):
+    """The FP64 oracle on the host cores: `sample` problems of the workload,
+    one process per worker, BLAS single-threaded per process."""
+    import multiprocessing as mp
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    chunks = [list(range(i, sample, workers)) for i in range(workers)]
+    chunks = [c for c in chunks if c]
+    env_keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in env_keys}
+    for k in env_keys:
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(chunks)) as pool:
+        busy = pool.map(_oracle_chunk, chunks)
+    wall = time.perf_counter() - t0
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+    return {
+        "value": sample / wall,
+        "unit": "solves/s",
+        "cores": len(chunks),
+        "kind": "oracle",
+        "sample": f"{sample} problems of {WORKLOAD} (problem indices 0..{sample - 1}), "
+                  f"dense-condensed FP64 interior point + certified active-set polish, "
+                  f"{sum(busy):.1f} core-s",
+    }
+
+
+def _kernel_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel_src, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current source of the kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != _kernel_sha(kernel_src):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the batch shards across GPUs with no communication, see DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import mpcgen
+    from paper_2606_05687_amd import binding
+
+    torch.cuda.set_device(0)
+    batch = mpcgen.make_batch(WORKLOAD)
+    Bn, n = batch["A"].shape[0], batch["A"].shape[1]
+    stages = int(batch["N"].sum())
+    dev = binding.to_device(batch, "cuda:0")
+    solver = binding.Solver(0, iters=args.iters)
+    out = solver.alloc_out(dev)
+    bstruct = binding.make_batch_struct(dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        solver.solve(dev, out, stream=stream, batch_struct=bstruct)
+    torch.cuda.synchronize()
+
+    step_ms, phase = [], []
+    certified = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        solver.solve(dev, out, stream=stream, batch_struct=bstruct)
+        ph = solver.stats()            # waits for this solve (HIP events)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        phase.append(ph)
+        res = out["res"]
+        ok = (out["status"] == 0) & (res.max(dim=1).values <= KKT_BAR)
+        certified += int(ok.sum().item())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = certified / elapsed
+
+    admm_ms = float(np.mean([p["admm_ms"] for p in phase]))
+    refine_ms = float(np.mean([p["refine_ms"] for p in phase]))
+    setup_ms = float(np.mean([p["setup_ms"] for p in phase]))
+    sweep_ms = admm_ms / max(1, args.iters)
+    sweep_bytes = stages * SWEEP_BYTES_PER_STAGE
+    # dominant phase: ADMM sweeps (HBM-bound) or the FP64 refinement
+    if admm_ms >= refine_ms:
+        achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+        src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_plain.hip")
+        roof = {"kernel": "admm_sweep_kernel", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(src, sweep_bytes),
+                "launch_ms": sweep_ms, "bytes_per_launch": sweep_bytes}
+    else:
+        roof = {"kernel": "refine_kernel", "bound": "fp64", "achieved": None,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "launch_ms": refine_ms}
+    status = out["status"].cpu().numpy()
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (ADMM) + f64 (refinement)",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "batch": int(Bn), "horizon": int(n),
+                   "admm_iters": args.iters, "form": "plain"},
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "certified_frac": certified / (Bn * args.steps),
+        "status_counts": {str(k): int((status == k).sum()) for k in range(5)},
+        "phase_ms": {"setup": setup_ms, "admm": admm_ms, "refine": refine_ms},
+        "roofline": roof,
+    }
+    solver.close()
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_workers)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,8 +84,12 @@ typedef struct {
   double kkt_tol;          /* certification threshold; default 1e-9 */
   int32_t precision;       /* 0: FP32 operators; 1: BF16 operators */
   int32_t form;            /* 0: plain (one launch per sweep);
-                              1: fused persistent sweep kernel;
-                              -1: choose (autotuner) */
+                              1: fused sweep kernel (all sweeps in one launch,
+                                 horizons up to 40);
+                              -1: choose (fused when it fits) */
+  int32_t graph;           /* 1: capture the whole solve as a hipGraph on first
+                              use and replay it while the batch shape, buffers
+                              and settings are unchanged; default 1 */
 } pinmpc_settings;
 
 typedef struct pinmpc_ctx_s* pinmpc_ctx;

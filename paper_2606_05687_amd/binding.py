@@ -33,6 +33,7 @@ class Settings(ctypes.Structure):
         ("kkt_tol", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("form", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 

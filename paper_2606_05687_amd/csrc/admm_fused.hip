@@ -1,0 +1,266 @@
+// Fused form of the parallel-in-horizon ADMM (Sec. III): all sweeps of a
+// problem in one launch, with every thread's share of the stage operators
+// loaded once into registers and kept there across the sweeps.
+//
+// A workgroup owns one problem; thread (k, r) owns lifted row r of stage k:
+//   r < 13 : row r of H_k, row r and column r of A_k, row r of Bt_k
+//   r >= 13: row r of H_k, column j = r-13 of Bt_k, row j of M_k
+// which is exactly what its share of the stage products needs:
+//   (Abar^T y)_r, (Bt^T w)_j, (M t)_j, (H htilde)_r, (Abar xi)_r, (Bbar du)_r.
+// Vectors that a product needs whole (w, y, t, htilde, xi_k of the
+// neighbour stage, du) are exchanged through LDS; the iterates stay in
+// registers and are written back once at the end.  HBM traffic per solve is
+// the operators once plus the iterates once, independent of the sweep count.
+#include "pinmpc_internal.h"
+
+namespace pinmpc {
+
+namespace {
+
+constexpr int V25 = 25;
+
+__device__ inline float block_sum(float v, float* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  float t = 0.f;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+template <int MAXT>
+__global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace ws, float rho,
+                                                          int accel, float eta, int iters,
+                                                          const int32_t* order) {
+  extern __shared__ float lds[];
+  const int b = order ? order[blockIdx.x] : (int)blockIdx.x;
+  const int n = p.n_max;
+  const int N = horizon(p, b);
+  // LDS: per stage vectors
+  float* W = lds;                 // w = vhat - betahat           [N][25]
+  float* Y = W + n * V25;         // y = zhat - vhat - e + lamhat [N][25]
+  float* ATY = Y + n * V25;       // Abar^T y                     [N][25]
+  float* HT = ATY + n * V25;      // htilde                       [N][25]
+  float* XI = HT + n * V25;       // xi_{k+1}                     [N][25]
+  float* T1 = XI + n * V25;       // Bt^T w_x + w_u               [N][12]
+  float* DU = T1 + n * NU;        // du                           [N][12]
+  float* PIN = DU + n * NU;       // projection input (u part)    [N][12]
+  float* PO = PIN + n * NU;       // projection output            [N][12]
+  float* XI0 = PO + n * NU;       // [32]
+  float* RED = XI0 + 32;          // [16]
+
+  const int tid = threadIdx.x;
+  const bool act = tid < N * NL;
+  const int k = act ? tid / NL : 0;
+  const int r = act ? tid % NL : 0;
+  const size_t s0 = (size_t)b * n;
+  const size_t st = s0 + k;
+  const float mu = p.mu[b];
+  const float tmax = p.tau_max[b];
+  const float tsc = ws.tsc[b];
+
+  if (tid < NL) {
+    float v;
+    if (tid < NX) v = p.x0[(size_t)b * NX + tid];
+    else v = p.u_prev ? p.u_prev[(size_t)b * NU + tid - NX] /
+                            ((tid - NX) % 6 < 3 ? ws.sf[s0] : tsc)
+                      : 0.f;
+    XI0[tid] = v;
+  }
+
+  // operators into registers
+  float hrow[NL], o1[NX], o2[NX], o3[NU];
+  float qb = 0.f, eb = 0.f;
+  if (act) {
+    const float* Hp = ws.Hp + st * NH;
+    for (int j = 0; j < NL; ++j) hrow[j] = Hp[pk(r, j, NL)];
+    const float* A = p.A + st * NX * NX;
+    const float* Bt = ws.Bt + st * NX * NU;
+    if (r < NX) {
+      for (int j = 0; j < NX; ++j) o1[j] = A[r * NX + j];      // row r of A
+      for (int j = 0; j < NX; ++j) o2[j] = A[j * NX + r];      // column r of A
+      for (int j = 0; j < NU; ++j) o3[j] = Bt[r * NU + j];     // row r of Bt
+    } else {
+      const int jj = r - NX;
+      for (int i = 0; i < NX; ++i) o1[i] = Bt[i * NU + jj];    // column jj of Bt
+      for (int i = 0; i < NX; ++i) o2[i] = 0.f;
+      const float* M = ws.Mp + st * NM;
+      for (int l = 0; l < NU; ++l) o3[l] = M[pk(jj, l, NU)];   // row jj of M
+    }
+    qb = ws.qb[st * NL + r];
+    eb = (r < NX && p.e) ? p.e[st * NX + r] : 0.f;
+  }
+  // iterates
+  float zh = 0, vh = 0, th = 0, bh = 0, lh = 0;
+  float zc = 0, vc = 0, tc = 0, bc = 0, lc = 0;
+  if (act) {
+    const size_t base = (st * NSTATE) * NL + r;
+    zh = ws.hat[base]; vh = ws.hat[base + NL]; th = ws.hat[base + 2 * NL];
+    bh = ws.hat[base + 3 * NL]; lh = ws.hat[base + 4 * NL];
+    zc = ws.cur[base]; vc = ws.cur[base + NL]; tc = ws.cur[base + 2 * NL];
+    bc = ws.cur[base + 3 * NL]; lc = ws.cur[base + 4 * NL];
+  }
+  float alpha = ws.alpha[b], cprev = ws.cprev[b];
+  int restarts = 0;
+  const float Fz = p.fz_max[b];
+  __syncthreads();
+
+  for (int it = 0; it < iters; ++it) {
+    if (act) {
+      W[k * V25 + r] = vh - bh;
+      Y[k * V25 + r] = zh - vh - eb + lh;
+    }
+    __syncthreads();
+    if (act) {
+      const float* y = Y + k * V25;
+      float aty;
+      if (r < NX) {
+        aty = 0.f;
+        for (int i = 0; i < NX; ++i) aty = fmaf(o2[i], y[i], aty);
+      } else {
+        const int jj = r - NX;
+        const float* w = W + k * V25;
+        aty = y[r];
+        float t = w[r];
+        for (int i = 0; i < NX; ++i) {
+          aty = fmaf(o1[i], y[i], aty);
+          t = fmaf(o1[i], w[i], t);
+        }
+        T1[k * NU + jj] = t;
+      }
+      ATY[k * V25 + r] = aty;
+    }
+    __syncthreads();
+    if (act) {
+      float h = zh - th;
+      if (k + 1 < N) h += ATY[(k + 1) * V25 + r];
+      HT[k * V25 + r] = fmaf(rho, h, qb);
+      if (r >= NX) {
+        const float* t = T1 + k * NU;
+        float du = 0.f;
+        for (int l = 0; l < NU; ++l) du = fmaf(o3[l], t[l], du);
+        DU[k * NU + r - NX] = du;
+      }
+    }
+    __syncthreads();
+    float xi = 0.f;
+    if (act) {
+      const float* h = HT + k * V25;
+      for (int l = 0; l < NL; ++l) xi = fmaf(hrow[l], h[l], xi);
+      XI[k * V25 + r] = xi;
+    }
+    __syncthreads();
+    float s = 0.f, bb = 0.f, gam = 0.f, zin = 0.f;
+    if (act) {
+      const float* prev = (k == 0) ? XI0 : XI + (k - 1) * V25;
+      const float* du = DU + k * NU;
+      if (r < NX) {
+        for (int j = 0; j < NX; ++j) s = fmaf(o1[j], prev[j], s);
+        for (int j = 0; j < NU; ++j) {
+          s = fmaf(o3[j], prev[NX + j], s);
+          bb = fmaf(o3[j], du[j], bb);
+        }
+      } else {
+        s = prev[r];
+        bb = du[r - NX];
+      }
+      gam = bb + bh - s - eb + lh;
+      const float gt = xi + th + s + eb - lh;
+      zin = (2.f * gt + gam) * (1.f / 3.f);
+      if (r >= NX) PIN[k * NU + r - NX] = zin;
+    }
+    __syncthreads();
+    if (tid < 2 * N) {
+      const int kk = tid >> 1, i = tid & 1;
+      const float* yv = PIN + kk * NU + 6 * i;
+      float* o = PO + kk * NU + 6 * i;
+      if (p.contact[(s0 + kk) * 2 + i]) {
+        const float F = Fz / ws.sf[s0 + kk];
+        const float tm = tmax / tsc;
+        float px, py, pz;
+        project_pyramid<float>(mu, F, yv[0], yv[1], yv[2], &px, &py, &pz);
+        o[0] = px; o[1] = py; o[2] = pz;
+        for (int a = 3; a < 6; ++a) o[a] = fminf(fmaxf(yv[a], -tm), tm);
+      } else {
+        for (int a = 0; a < 6; ++a) o[a] = 0.f;
+      }
+    }
+    __syncthreads();
+    float zv = 0, vv = 0, tv = 0, bv = 0, lv = 0, cpart = 0.f;
+    if (act) {
+      zv = (r < NX) ? zin : PO[k * NU + r - NX];
+      vv = 0.5f * (zv + gam);
+      tv = th + xi - zv;
+      bv = bh + bb - vv;
+      lv = lh + zv - s - vv - eb;
+      if (accel) {
+        const float dz = zv - zh, dv = vv - vh;
+        const float d1 = tv - th, d2 = bv - bh, d3 = lv - lh;
+        cpart = d1 * d1 + d2 * d2 + d3 * d3 + dz * dz + dv * dv + (dz - dv) * (dz - dv);
+      }
+    }
+    if (accel) {
+      const float cm = block_sum(cpart, RED);
+      if (cm < eta * cprev) {
+        const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * alpha * alpha));
+        const float f = (alpha - 1.f) / an;
+        zh = zv + f * (zv - zc); vh = vv + f * (vv - vc); th = tv + f * (tv - tc);
+        bh = bv + f * (bv - bc); lh = lv + f * (lv - lc);
+        alpha = an;
+        cprev = cm;
+      } else {
+        zh = zc; vh = vc; th = tc; bh = bc; lh = lc;
+        alpha = 1.f;
+        cprev = cprev / eta;
+        ++restarts;
+      }
+      zc = zv; vc = vv; tc = tv; bc = bv; lc = lv;
+    } else {
+      zh = zv; vh = vv; th = tv; bh = bv; lh = lv;
+      __syncthreads();
+    }
+  }
+  if (act) {
+    const size_t base = (st * NSTATE) * NL + r;
+    ws.hat[base] = zh; ws.hat[base + NL] = vh; ws.hat[base + 2 * NL] = th;
+    ws.hat[base + 3 * NL] = bh; ws.hat[base + 4 * NL] = lh;
+    if (accel) {
+      ws.cur[base] = zc; ws.cur[base + NL] = vc; ws.cur[base + 2 * NL] = tc;
+      ws.cur[base + 3 * NL] = bc; ws.cur[base + 4 * NL] = lc;
+    }
+  }
+  if (tid == 0) {
+    ws.alpha[b] = alpha;
+    ws.cprev[b] = cprev;
+    ws.restarts[b] += restarts;
+  }
+}
+
+}  // namespace
+
+size_t fused_lds_bytes(int n_max) {
+  return (size_t)(5 * n_max * V25 + 4 * n_max * NU + 32 + 16) * sizeof(float);
+}
+
+hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             int iters, hipStream_t st) {
+  if (p.batch == 0 || iters == 0) return hipSuccess;
+  const int work = NL * p.n_max;
+  if (work > 1024) return hipErrorInvalidValue;
+  const int threads = ((work + 63) / 64) * 64;
+  // up to 512 threads the kernel may use 256 VGPRs (two waves per SIMD)
+  if (threads <= 512)
+    hipLaunchKernelGGL(admm_fused_kernel<512>, dim3(p.batch), dim3(threads),
+                       fused_lds_bytes(p.n_max), st, p, w, s.rho, s.accel, s.restart_eta, iters,
+                       (const int32_t*)nullptr);
+  else
+    hipLaunchKernelGGL(admm_fused_kernel<1024>, dim3(p.batch), dim3(threads),
+                       fused_lds_bytes(p.n_max), st, p, w, s.rho, s.accel, s.restart_eta, iters,
+                       (const int32_t*)nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace pinmpc

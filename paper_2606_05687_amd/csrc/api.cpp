@@ -11,6 +11,28 @@
 
 using namespace pinmpc;
 
+struct GraphKey {
+  pinmpc_batch in;
+  pinmpc_out out;
+  pinmpc_settings s;
+  hipStream_t stream;
+  void* mem;
+};
+
+static bool same_settings(const pinmpc_settings& a, const pinmpc_settings& b) {
+  return a.rho == b.rho && a.iters == b.iters && a.accel == b.accel &&
+         a.restart_eta == b.restart_eta && a.scaling == b.scaling && a.refine == b.refine &&
+         a.refine_passes == b.refine_passes && a.ipm_iters == b.ipm_iters &&
+         a.polish_passes == b.polish_passes && a.kkt_tol == b.kkt_tol &&
+         a.precision == b.precision && a.form == b.form && a.graph == b.graph;
+}
+
+static bool same_key(const GraphKey& a, const GraphKey& b) {
+  return std::memcmp(&a.in, &b.in, sizeof(a.in)) == 0 &&
+         std::memcmp(&a.out, &b.out, sizeof(a.out)) == 0 && same_settings(a.s, b.s) &&
+         a.stream == b.stream && a.mem == b.mem;
+}
+
 struct pinmpc_ctx_s {
   int device = 0;
   size_t budget = 0;
@@ -19,6 +41,9 @@ struct pinmpc_ctx_s {
   size_t mem_bytes = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool have_timing = false;
+  bool last_graph = false;      // last solve replayed a graph (no phase split)
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey{};
 };
 
 namespace {
@@ -81,7 +106,8 @@ int check_settings(const pinmpc_settings* s) {
   if (s->refine_passes < 0 || s->ipm_iters < 0 || s->polish_passes < 0) return PINMPC_EINVAL;
   if (!(s->kkt_tol > 0.0)) return PINMPC_EINVAL;
   if (s->precision != 0) return PINMPC_EINVAL;           // BF16 operators: not built
-  if (s->form != 0) return PINMPC_EINVAL;                // fused form: not built
+  if (s->form < -1 || s->form > 1) return PINMPC_EINVAL;
+  if (s->graph < 0 || s->graph > 1) return PINMPC_EINVAL;
   return PINMPC_OK;
 }
 
@@ -123,6 +149,10 @@ int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Wor
   if (need > c->mem_bytes) {
     if (c->mem) {
       if (hipStreamSynchronize(st) != hipSuccess) return PINMPC_EDEVICE;
+      if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+      }
       (void)hipFree(c->mem);
       c->mem = nullptr;
       c->mem_bytes = 0;
@@ -137,12 +167,25 @@ int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Wor
   return PINMPC_OK;
 }
 
+// The fused kernel holds one problem per workgroup with one thread per
+// (stage, lifted row): horizons up to 1024 / 25 = 40 stages.
+bool use_fused(const pinmpc_settings& s, int n_max) {
+  const bool fits = NL * n_max <= 1024;
+  if (s.form == 1) return fits;
+  if (s.form == -1) return fits;
+  return false;
+}
+
 int run_admm(pinmpc_ctx c, const Problem& p, const Workspace& w, int iters, hipStream_t st) {
   if (launch_setup(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
   if (launch_admm_init(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[1], st);
-  for (int it = 0; it < iters; ++it)
-    if (launch_admm_sweep(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (use_fused(c->s, p.n_max)) {
+    if (launch_admm_fused(p, w, c->s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
+  } else {
+    for (int it = 0; it < iters; ++it)
+      if (launch_admm_sweep(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
+  }
   return PINMPC_OK;
 }
 
@@ -165,6 +208,7 @@ void pinmpc_default_settings(pinmpc_settings* s) {
   s->kkt_tol = 1e-9;
   s->precision = 0;
   s->form = 0;
+  s->graph = 1;
 }
 
 int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
@@ -220,6 +264,52 @@ int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out, void* hi
   rc = ensure_workspace(c, in->batch, in->n_max, st, &w);
   if (rc) return rc;
   const Problem p = to_problem(in);
+  if (c->s.graph) {
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    std::memcpy(&key.in, in, sizeof(*in));
+    std::memcpy(&key.out, out, sizeof(*out));
+    key.s = c->s;
+    key.stream = st;
+    key.mem = c->mem;
+    if (!c->gexec || !same_key(key, c->gkey)) {
+      if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+      }
+      // capture setup -> sweeps -> refinement; only kernel launches (no
+      // memset nodes), timing events stay outside the graph
+      hipStream_t cap;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return PINMPC_EDEVICE;
+      const bool timing = c->have_timing;
+      c->have_timing = false;
+      hipGraph_t g = nullptr;
+      int crc = PINMPC_OK;
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        crc = PINMPC_EDEVICE;
+      } else {
+        crc = run_admm(c, p, w, c->s.iters, cap);
+        if (!crc && launch_refine(p, w, c->s, *out, cap) != hipSuccess) crc = PINMPC_EDEVICE;
+        if (hipStreamEndCapture(cap, &g) != hipSuccess) crc = PINMPC_EDEVICE;
+      }
+      c->have_timing = timing;
+      (void)hipStreamDestroy(cap);
+      if (!crc && hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        c->gexec = nullptr;
+        crc = PINMPC_EDEVICE;
+      }
+      if (g) (void)hipGraphDestroy(g);
+      if (crc) return crc;
+      std::memcpy(&c->gkey, &key, sizeof(key));
+    }
+    if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
+    if (hipGraphLaunch(c->gexec, st) != hipSuccess) return PINMPC_EDEVICE;
+    if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
+    c->last_graph = true;
+    return PINMPC_OK;
+  }
+  c->last_graph = false;
   if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
   rc = run_admm(c, p, w, c->s.iters, st);
   if (rc) return rc;
@@ -254,6 +344,15 @@ int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_
                  double* refine_ms) {
   if (!c || !c->have_timing) return PINMPC_EINVAL;
   if (hipEventSynchronize(c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  if (c->last_graph) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, c->ev[0], c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+    if (total_ms) *total_ms = t;
+    if (setup_ms) *setup_ms = -1.0;
+    if (admm_ms) *admm_ms = -1.0;
+    if (refine_ms) *refine_ms = -1.0;
+    return PINMPC_OK;
+  }
   float t01 = 0, t12 = 0, t23 = 0;
   if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) != hipSuccess) return PINMPC_EDEVICE;
   if (hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) != hipSuccess) return PINMPC_EDEVICE;
@@ -268,10 +367,9 @@ int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_
 int pinmpc_destroy(pinmpc_ctx c) {
   if (!c) return PINMPC_EINVAL;
   (void)hipSetDevice(c->device);
-  if (c->mem) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(c->mem);
-  }
+  (void)hipDeviceSynchronize();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->mem) (void)hipFree(c->mem);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;

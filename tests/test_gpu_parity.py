@@ -187,3 +187,65 @@ def test_admm_first_sweeps_match_fp64_reference(solver):
             print(f"K={K} b={b} scaled max diff {d:.2e}")
             if tol is not None:
                 assert d <= tol, (K, b, d)
+
+
+def test_fused_form_matches_plain_form(solver):
+    """The fused kernel runs the same per-stage arithmetic in the same order as
+    the one-launch-per-sweep kernel, only with operators held in registers:
+    identical iterates, identical certified solutions."""
+    import torch
+    from paper_2606_05687_amd import binding
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(512))
+    base = binding.default_settings()
+    for f, _ in binding.Settings._fields_:
+        setattr(solver.settings, f, getattr(base, f))
+    dev = binding.to_device(batch)
+    zs = []
+    for form in (0, 1):
+        solver.set(form=form)
+        z = solver.admm(dev, 37)
+        torch.cuda.synchronize()
+        zs.append(z.cpu().numpy())
+    assert np.array_equal(zs[0], zs[1])
+    plain = _solve(solver, batch, form=0)
+    fused = _solve(solver, batch, form=1)
+    for k in plain:
+        assert np.array_equal(plain[k], fused[k]), k
+    _compare(batch, fused, range(8))
+
+
+def test_fused_form_uneven_horizons_up_to_40(solver):
+    batch = mpcgen.make_batch("uneven_b16384", indices=range(64), n_max=40)
+    keep = batch["N"] <= 40
+    batch = mpcgen.problem_slice(batch, np.where(keep)[0])
+    out = _solve(solver, batch, form=1)
+    assert (out["status"] == 0).all()
+    _compare(batch, out, range(0, len(batch["N"]), 7))
+
+
+def test_graph_replay_matches_eager(solver):
+    """The whole solve captured once as a hipGraph and replayed: every replay,
+    with unrelated eager GPU work and synchronisations in between, equals the
+    eager (uncaptured) solve bitwise."""
+    import torch
+    from paper_2606_05687_amd import binding
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(300))
+    eager = _solve(solver, batch, graph=0)
+    base = binding.default_settings()
+    for f, _ in binding.Settings._fields_:
+        setattr(solver.settings, f, getattr(base, f))
+    solver.set(graph=1)
+    dev = binding.to_device(batch)
+    out = solver.alloc_out(dev)
+    bs = binding.make_batch_struct(dev)
+    for rep in range(4):
+        for v in out.values():
+            v.fill_(-7)
+        solver.solve(dev, out, batch_struct=bs)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        for k in eager:
+            assert np.array_equal(got[k], eager[k]), (rep, k)
+        a = torch.randn(512, 512, device="cuda")
+        (a @ a).sum().item()
+        torch.cuda.synchronize()

@@ -27,7 +27,7 @@ def test_header_symbols_exported():
 
 def test_struct_layouts_match_header():
     # field order and C types as declared in include/pinmpc.h
-    assert ctypes.sizeof(binding.Settings) == 56
+    assert ctypes.sizeof(binding.Settings) == 64
     assert ctypes.sizeof(binding.Batch) == 8 + 15 * 8
     assert ctypes.sizeof(binding.Out) == 5 * 8
 
