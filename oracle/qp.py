@@ -125,7 +125,7 @@ def dense_qp(p):
                 Grows.append(gr)
                 hrows.append(hc[j])
                 rows.append((k, i, j))
-    G = np.array(Grows).reshape(-1, len(free))
+    G = np.array(Grows, dtype=np.float64).reshape(len(Grows), len(free))
     h = np.array(hrows, dtype=np.float64)
     Hf = H[np.ix_(free, free)]
     gf = g[free]

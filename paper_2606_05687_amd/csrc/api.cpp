@@ -78,7 +78,7 @@ size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.flags = (uint32_t*)take(Bn * 4);
   t.rK = (double*)take(S * NU * NX * 8);
   t.rkap = (double*)take(S * NU * 8);
-  t.rL = (double*)take(S * NM * 8);
+  t.rL = (double*)take(S * NU * NU * 8);
   t.rHwx = (double*)take(S * NU * NX * 8);
   t.ru = (double*)take(S * NU * 8);
   t.rx = (double*)take(X * NX * 8);

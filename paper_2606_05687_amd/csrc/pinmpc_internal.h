@@ -58,7 +58,7 @@ struct Workspace {
   // FP64 refinement scratch
   double* rK;       // [s][12][13] feedback gains
   double* rkap;     // [s][12] feedforward
-  double* rL;       // [s][78] Cholesky factor of the reduced input Hessian
+  double* rL;       // [s][12][12] inverse of the reduced input Hessian
   double* rHwx;     // [s][12][13]
   double* ru;       // [s][12] inputs
   double* rx;       // [b][n_max+1][13] states

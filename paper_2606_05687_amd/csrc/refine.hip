@@ -25,6 +25,7 @@ namespace pinmpc {
 namespace {
 
 constexpr int W64 = 64;
+constexpr int GJW = NU + NX + 1 + NU;   // 38 columns of the augmented system
 
 struct Ctx {
   Problem p;
@@ -32,7 +33,8 @@ struct Ctx {
   int b, N, n;
   size_t s0;
   double mu, fz, tm, mg;
-  double Q[NX], R[NU];
+  const double* Q;   // LDS copies of the diagonal weights
+  const double* R;
 };
 
 // ------------------------------------------------------------ small helpers
@@ -165,10 +167,12 @@ struct Sh {
   double W[NX * NX], WA[NX * NX];
   double P[NU * NU], c[NU], Rp[NU * NU];
   double Bp[NX * NU], WBp[NX * NU];
-  double H[NU * NU], Hwx[NU * NX], K[NU * NX];
+  double Hwx[NU * NX], K[NU * NX];
   double om[NX], d[NX], Wdo[NX], hw[NU], kap[NU], rho[NU], q[NX];
   double xv[NX], wv[NU], uv[NU], xn[NX];
-  double red[8];
+  double G[NU * GJW];                 // Gauss-Jordan augmented [H | Hwx | hw | I]
+  double fac[16];
+  double Qd[NX], Rd[NU];              // diagonal weights of the problem
 };
 
 __device__ inline void load_AB(const Ctx& C, Sh& sh, int k) {
@@ -348,7 +352,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       sh.Wdo[lane] = acc;
     }
     if (factor) {
-      // T = R' P into H temporarily? use Hwx as scratch: T[i][j] = sum_l R'[i][l] P[l][j]
+      // T = R' P, held in K until K itself is formed
       for (int e = lane; e < NU * NU; e += W64) {
         const int i = e / NU, j = e % NU;
         double acc = 0.0;
@@ -358,88 +362,74 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     }
     __syncthreads();
     if (factor) {
-      // H = P R' P + Bp^T W Bp + (I - P) ; Hwx = Bp^T W A
+      // H = P R' P + Bp^T W Bp + (I - P) ; Hwx = Bp^T W A, straight into the
+      // augmented Gauss-Jordan system [H | Hwx | hw | I]
       for (int e = lane; e < NU * NU + NU * NX; e += W64) {
         if (e < NU * NU) {
           const int i = e / NU, j = e % NU;
           double acc = ((i == j) ? 1.0 : 0.0) - sh.P[i * NU + j];
           for (int l = 0; l < NU; ++l) acc += sh.P[l * NU + i] * sh.K[l * NU + j];
           for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WBp[l * NU + j];
-          sh.H[e] = acc;
+          sh.G[i * GJW + j] = acc;
+          sh.G[i * GJW + NU + NX + 1 + j] = (i == j) ? 1.0 : 0.0;
         } else {
           const int f = e - NU * NU, i = f / NX, j = f % NX;
           double acc = 0.0;
           for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WA[l * NX + j];
           sh.Hwx[f] = acc;
+          sh.G[i * GJW + NU + j] = acc;
         }
       }
     } else {
-      const double* L = C.ws.rL + st * NM;
-      for (int e = lane; e < NM; e += W64) {
-        // unpack stored Cholesky factor (lower, packed by rows as pk(c, r))
-        int r = 0, acc = 0;
-        while (acc + (NU - r) <= e) { acc += NU - r; ++r; }
-        const int cc = r + (e - acc);    // packed (r, cc) with r <= cc : L[cc][r]
-        sh.H[cc * NU + r] = L[e];
-      }
       for (int e = lane; e < NU * NX; e += W64) sh.Hwx[e] = C.ws.rHwx[st * NU * NX + e];
     }
     if (lane < NU) {
       // hw = P (R' c + rho) + Bp^T (W d + omega)
-      double t[NU];
-      for (int l = 0; l < NU; ++l) {
-        double acc = sh.rho[l];
-        if (mode == Mode::EQ)
-          for (int m = 0; m < NU; ++m) acc += sh.Rp[l * NU + m] * sh.c[m];
-        t[l] = acc;
-      }
       double acc = 0.0;
-      for (int l = 0; l < NU; ++l) acc += sh.P[lane * NU + l] * t[l];
+      for (int l = 0; l < NU; ++l) {
+        double t = sh.rho[l];
+        if (mode == Mode::EQ)
+          for (int m = 0; m < NU; ++m) t += sh.Rp[l * NU + m] * sh.c[m];
+        acc += sh.P[lane * NU + l] * t;
+      }
       for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + lane] * sh.Wdo[l];
       sh.hw[lane] = acc;
+      if (factor) sh.G[lane * GJW + NU + NX] = acc;
     }
     __syncthreads();
     if (factor) {
-      // Cholesky H = L L^T in place (lower triangle), column by column
+      // Gauss-Jordan elimination (H is SPD: no pivoting) over all 64 lanes:
+      // afterwards G = [I | H^{-1} Hwx | H^{-1} hw | H^{-1}]
       for (int j = 0; j < NU; ++j) {
-        if (lane == 0) {
-          double v = sh.H[j * NU + j];
-          for (int l = 0; l < j; ++l) v -= sh.H[j * NU + l] * sh.H[j * NU + l];
-          sh.H[j * NU + j] = sqrt(fmax(v, 1e-300));
-        }
+        const double piv = sh.G[j * GJW + j];
         __syncthreads();
-        if (lane > j && lane < NU) {
-          double v = sh.H[lane * NU + j];
-          for (int l = 0; l < j; ++l) v -= sh.H[lane * NU + l] * sh.H[j * NU + l];
-          sh.H[lane * NU + j] = v / sh.H[j * NU + j];
+        for (int c = lane; c < GJW; c += W64) sh.G[j * GJW + c] /= piv;
+        __syncthreads();
+        if (lane < NU) sh.fac[lane] = sh.G[lane * GJW + j];
+        __syncthreads();
+        for (int e = lane; e < NU * GJW; e += W64) {
+          const int r = e / GJW, c = e % GJW;
+          if (r != j) sh.G[e] -= sh.fac[r] * sh.G[j * GJW + c];
         }
         __syncthreads();
       }
-      // store factor and Hwx for a second right-hand side
-      double* L = C.ws.rL + st * NM;
-      for (int r = 0; r < NU; ++r)
-        for (int cc = r + lane; cc < NU; cc += W64) L[pk(r, cc, NU)] = sh.H[cc * NU + r];
+      for (int e = lane; e < NU * NX; e += W64) {
+        const int i = e / NX, j = e % NX;
+        sh.K[e] = -sh.G[i * GJW + NU + j];
+      }
+      if (lane < NU) sh.kap[lane] = -sh.G[lane * GJW + NU + NX];
+      // keep H^{-1} and Hwx for a second right-hand side of the same matrix
+      double* Hi = C.ws.rL + st * NU * NU;
+      for (int e = lane; e < NU * NU; e += W64) Hi[e] = sh.G[(e / NU) * GJW + NU + NX + 1 + e % NU];
       for (int e = lane; e < NU * NX; e += W64) C.ws.rHwx[st * NU * NX + e] = sh.Hwx[e];
-    }
-    __syncthreads();
-    // K = -H^{-1} Hwx (13 columns) and kap = -H^{-1} hw (column 13)
-    if (lane <= NX) {
-      double y[NU];
-      for (int i = 0; i < NU; ++i) {
-        double v = (lane < NX) ? sh.Hwx[i * NX + lane] : sh.hw[i];
-        for (int l = 0; l < i; ++l) v -= sh.H[i * NU + l] * y[l];
-        y[i] = v / sh.H[i * NU + i];
+    } else {
+      const double* Hi = C.ws.rL + st * NU * NU;
+      if (lane < NU) {
+        double acc = 0.0;
+        for (int l = 0; l < NU; ++l) acc += Hi[lane * NU + l] * sh.hw[l];
+        sh.kap[lane] = -acc;
       }
-      for (int i = NU - 1; i >= 0; --i) {
-        double v = y[i];
-        for (int l = i + 1; l < NU; ++l) v -= sh.H[l * NU + i] * y[l];
-        y[i] = v / sh.H[i * NU + i];
-      }
-      if (lane < NX) {
-        for (int i = 0; i < NU; ++i) sh.K[i * NX + lane] = -y[i];
-      } else {
-        for (int i = 0; i < NU; ++i) sh.kap[i] = -y[i];
-      }
+      for (int e = lane; e < NU * NX; e += W64) sh.K[e] = C.ws.rK[st * NU * NX + e];
     }
     __syncthreads();
     if (factor)
@@ -941,8 +931,11 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
   C.fz = p.fz_max[C.b];
   C.tm = p.tau_max[C.b];
   C.mg = weight_of(p, C.b);
-  for (int j = 0; j < NX; ++j) C.Q[j] = p.Q[(size_t)C.b * NX + j];
-  for (int j = 0; j < NU; ++j) C.R[j] = p.R[(size_t)C.b * NU + j];
+  if (lane < NX) sh.Qd[lane] = p.Q[(size_t)C.b * NX + lane];
+  if (lane < NU) sh.Rd[lane] = p.R[(size_t)C.b * NU + lane];
+  __syncthreads();
+  C.Q = sh.Qd;
+  C.R = sh.Rd;
   const int N = C.N;
 
   // input checks: bounds, then finiteness of this problem's data
