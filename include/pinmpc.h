@@ -159,6 +159,44 @@ int pinmpc_destroy(pinmpc_ctx c);
 
 const char* pinmpc_strerror(int code);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous-batching front end: requests (batches of problems in caller
+ * device memory, typically one environment group's problems of one control
+ * tick) are queued and packed into whichever of n_lanes concurrent lanes
+ * (each with its own HIP stream and workspace) frees up first; a lane takes
+ * every waiting request that fits its capacity.  Caller buffers of a request
+ * must stay valid and untouched until the request is done.  Each problem is
+ * solved exactly as pinmpc_solve would solve it alone (bitwise), whatever
+ * else shares its launch.  Warm start: problem i of a request submitted with
+ * warm_base >= 0 starts from the iterates kept in device slot warm_base + i
+ * (shifted by one stage) and leaves its final iterates there; slots persist
+ * for the server's lifetime. */
+typedef struct pinmpc_server_s* pinmpc_server;
+
+/* hbm_budget_bytes bounds lanes x (workspace + staging) + warm slots
+ * (0 = 64 GiB); exceeding it returns PINMPC_EBUDGET.  lane_capacity is the
+ * most problems one launch holds; a request larger than it is rejected. */
+int pinmpc_server_create(pinmpc_server* out, int device, const pinmpc_settings* s,
+                         int n_lanes, int32_t lane_capacity, int32_t warm_slots,
+                         size_t hbm_budget_bytes);
+
+/* Queue one request; *ticket identifies it.  Thread-safe. */
+int pinmpc_submit(pinmpc_server s, const pinmpc_batch* req, const pinmpc_out* out,
+                  int32_t warm_base, int64_t* ticket);
+
+/* *done = 1 once the request's outputs are in its buffers; latency_ms is
+ * submit-to-ready.  A finished ticket is released by the call that reports it. */
+int pinmpc_poll(pinmpc_server s, int64_t ticket, int* done, double* latency_ms);
+
+/* Block until the request is done (then as pinmpc_poll). */
+int pinmpc_wait(pinmpc_server s, int64_t ticket, double* latency_ms);
+
+/* Launches made and problems solved so far; returns the first launch error. */
+int pinmpc_server_stats(pinmpc_server s, int64_t* launches, int64_t* problems);
+
+/* Finish every queued request, then free the server. */
+int pinmpc_server_destroy(pinmpc_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,17 @@ EXPORTS = {
     "pinmpc_stats": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 4),
     "pinmpc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pinmpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pinmpc_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                            ctypes.POINTER(Settings), ctypes.c_int, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_size_t]),
+    "pinmpc_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Out),
+                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "pinmpc_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "pinmpc_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "pinmpc_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+    "pinmpc_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _lib = None
@@ -225,3 +236,67 @@ class Solver:
         vals = [ctypes.c_double() for _ in range(4)]
         _check(load().pinmpc_stats(self._h, *[ctypes.byref(v) for v in vals]))
         return dict(zip(("total_ms", "setup_ms", "admm_ms", "refine_ms"), [v.value for v in vals]))
+
+
+def _out_struct(out):
+    return Out(out["u"].data_ptr(), out["x"].data_ptr(),
+               None if out.get("res") is None else out["res"].data_ptr(),
+               None if out.get("iters") is None else out["iters"].data_ptr(),
+               None if out.get("status") is None else out["status"].data_ptr())
+
+
+class Server:
+    """Continuous-batching server (pinmpc_server_*) on one GPU."""
+
+    def __init__(self, device=0, lanes=3, capacity=4096, warm_slots=0, hbm_budget=0,
+                 **settings):
+        lib = load()
+        self.settings = default_settings(**settings)
+        h = ctypes.c_void_p()
+        _check(lib.pinmpc_server_create(ctypes.byref(h), int(device), ctypes.byref(self.settings),
+                                        int(lanes), int(capacity), int(warm_slots),
+                                        int(hbm_budget)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, dev, out, warm_base=-1):
+        """Queue a request (device tensors stay referenced until it is done)."""
+        b = make_batch_struct(dev)
+        o = _out_struct(out)
+        t = ctypes.c_int64()
+        _check(load().pinmpc_submit(self._h, ctypes.byref(b), ctypes.byref(o), int(warm_base),
+                                    ctypes.byref(t)))
+        self._keep[t.value] = (dev, out)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(load().pinmpc_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(lat)))
+        if done.value:
+            self._keep.pop(ticket, None)
+            return lat.value
+        return None
+
+    def wait(self, ticket):
+        lat = ctypes.c_double()
+        _check(load().pinmpc_wait(self._h, int(ticket), ctypes.byref(lat)))
+        self._keep.pop(ticket, None)
+        return lat.value
+
+    def stats(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().pinmpc_server_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return {"launches": a.value, "problems": b.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().pinmpc_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

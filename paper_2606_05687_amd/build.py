@@ -11,13 +11,14 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpinmpc.so")
 
-SOURCES = ["api.cpp", "setup.hip", "admm_plain.hip", "admm_fused.hip", "refine.hip"]
+SOURCES = ["api.cpp", "server.cpp", "setup.hip", "admm_plain.hip", "admm_fused.hip",
+           "refine.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # keep FP32 arithmetic in unpacked VALU forms
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument", "-Wl,--no-undefined",
+    "-Wno-unused-command-line-argument", "-Wl,--no-undefined", "-pthread",
 ]
 
 

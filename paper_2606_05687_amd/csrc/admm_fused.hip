@@ -19,18 +19,6 @@ namespace {
 
 constexpr int V25 = 25;
 
-__device__ inline float block_sum(float v, float* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  float t = 0.f;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int i = 0; i < nw; ++i) t += red[i];
-  __syncthreads();
-  return t;
-}
-
 template <int MAXT>
 __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace ws, float rho,
                                                           int accel, float eta, int iters,
@@ -40,7 +28,7 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
   const int n = p.n_max;
   const int N = horizon(p, b);
   // LDS: per stage vectors
-  float* W = lds;                 // w = vhat - betahat           [N][25]
+  float* W = lds;                 // w = vhat - betahat; restart terms [N][25]
   float* Y = W + n * V25;         // y = zhat - vhat - e + lamhat [N][25]
   float* ATY = Y + n * V25;       // Abar^T y                     [N][25]
   float* HT = ATY + n * V25;      // htilde                       [N][25]
@@ -189,7 +177,7 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
       }
     }
     __syncthreads();
-    float zv = 0, vv = 0, tv = 0, bv = 0, lv = 0, cpart = 0.f;
+    float zv = 0, vv = 0, tv = 0, bv = 0, lv = 0;
     if (act) {
       zv = (r < NX) ? zin : PO[k * NU + r - NX];
       vv = 0.5f * (zv + gam);
@@ -199,11 +187,11 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
       if (accel) {
         const float dz = zv - zh, dv = vv - vh;
         const float d1 = tv - th, d2 = bv - bh, d3 = lv - lh;
-        cpart = d1 * d1 + d2 * d2 + d3 * d3 + dz * dz + dv * dv + (dz - dv) * (dz - dv);
+        W[k * V25 + r] = d1 * d1 + d2 * d2 + d3 * d3 + dz * dz + dv * dv + (dz - dv) * (dz - dv);
       }
     }
     if (accel) {
-      const float cm = block_sum(cpart, RED);
+      const float cm = stage_ordered_sum(W, T1, N);
       if (cm < eta * cprev) {
         const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * alpha * alpha));
         const float f = (alpha - 1.f) / an;

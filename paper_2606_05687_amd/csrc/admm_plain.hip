@@ -19,7 +19,7 @@ namespace {
 constexpr int BUF = 25;   // floats per stage per LDS buffer
 
 struct Lds {
-  float* b0;    // w = vhat - betahat           -> later htilde
+  float* b0;    // w = vhat - betahat           -> later htilde -> restart terms
   float* b1;    // y = zhat - vhat - ebar + lamhat -> later xi (block-1 output)
   float* b2;    // Bt^T w_x + w_u (12)          -> later projection input (12)
   float* b3;    // du (12)                      -> later projection output (12)
@@ -27,20 +27,6 @@ struct Lds {
   float* xi0;   // fixed lifted initial state (x0, ut_prev)
   float* red;   // reduction scratch
 };
-
-__device__ inline float block_sum(float v, float* red) {
-  // wave reduction then cross-wave through LDS
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  float t = 0.f;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int i = 0; i < nw; ++i) t += red[i];
-  __syncthreads();
-  return t;
-}
 
 template <int PAIRS>
 __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace ws, float rho,
@@ -240,7 +226,6 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
 
   // Block 3 and the acceleration test.
   float zv[PAIRS], vv[PAIRS], tv[PAIRS], bvv[PAIRS], lv[PAIRS];
-  float cpart = 0.f;
 #pragma unroll
   for (int q = 0; q < PAIRS; ++q) {
     const int id = threadIdx.x + q * blockDim.x;
@@ -256,14 +241,15 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
       if (accel) {
         const float dz = z - zh[q], dv = v - vh[q];
         const float d1 = tv[q] - th[q], d2 = bvv[q] - bh[q], d3 = lv[q] - lh[q];
-        cpart += d1 * d1 + d2 * d2 + d3 * d3 + dz * dz + dv * dv + (dz - dv) * (dz - dv);
+        L.b0[k * BUF + r] =
+            d1 * d1 + d2 * d2 + d3 * d3 + dz * dz + dv * dv + (dz - dv) * (dz - dv);
       }
     }
   }
   float f = 0.f;
   bool restart = false;
   if (accel) {
-    const float cm = block_sum(cpart, L.red);
+    const float cm = stage_ordered_sum(L.b0, L.b2, N);
     const float cp = ws.cprev[b];
     const float al = ws.alpha[b];
     if (cm < eta * cp) {
@@ -307,13 +293,28 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
   }
 }
 
-// Zero iterates and acceleration state.
+// Initial iterates: zero, or (warm start) the stored iterates of the
+// problem's slot shifted by one stage (slot k takes stored slot k+1, the last
+// stage repeats).  Acceleration state restarts.
 __global__ void admm_init_kernel(Problem p, Workspace ws) {
   const size_t total = (size_t)p.batch * p.n_max * NSTATE * NL;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
-    ws.cur[i] = 0.f;
-    ws.hat[i] = 0.f;
+    float v = 0.f;
+    if (ws.warm_idx) {
+      const size_t per = (size_t)NSTATE * NL;
+      const int b = (int)(i / ((size_t)p.n_max * per));
+      const int k = (int)((i / per) % p.n_max);
+      const int e = (int)(i % per);
+      const int slot = ws.warm_idx[b];
+      const int N = horizon(p, b);
+      if (slot >= 0 && k < N) {
+        const int ks = (k + 1 < N) ? k + 1 : N - 1;
+        v = ws.warm_store[((size_t)slot * PINMPC_NMAX + ks) * per + e];
+      }
+    }
+    ws.cur[i] = v;
+    ws.hat[i] = v;
   }
   for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < (size_t)p.batch;
        b += (size_t)gridDim.x * blockDim.x) {
@@ -321,6 +322,39 @@ __global__ void admm_init_kernel(Problem p, Workspace ws) {
     ws.cprev[b] = 3.0e38f;
     ws.restarts[b] = 0;
   }
+}
+
+// Store the final iterates of warm-started problems into their slots.
+__global__ void warm_save_kernel(Problem p, Workspace ws, int accel) {
+  const size_t per = (size_t)NSTATE * NL;
+  const size_t total = (size_t)p.batch * p.n_max * per;
+  const float* src = accel ? ws.cur : ws.hat;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(i / ((size_t)p.n_max * per));
+    const int k = (int)((i / per) % p.n_max);
+    const int slot = ws.warm_idx[b];
+    if (slot < 0 || k >= horizon(p, b)) continue;
+    ws.warm_store[((size_t)slot * PINMPC_NMAX + k) * per + i % per] = src[i];
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* dst, size_t n, int32_t base, int32_t step) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = base + step * (int32_t)i;
+}
+
+__global__ void fill_f32_kernel(float* dst, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+__global__ void half_of_kernel(float* dst, const float* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = 0.5f * src[i];
 }
 
 // z iterates (current) in unscaled coordinates, [b][n_max][25].
@@ -343,6 +377,36 @@ __global__ void admm_extract_kernel(Problem p, Workspace ws, int accel, float* z
 hipError_t launch_admm_init(const Problem& p, const Workspace& w, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
   hipLaunchKernelGGL(admm_init_kernel, dim3(1024), dim3(256), 0, st, p, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm_save(const Problem& p, const Workspace& w, int accel, hipStream_t st) {
+  if (p.batch == 0 || !w.warm_idx) return hipSuccess;
+  hipLaunchKernelGGL(warm_save_kernel, dim3(1024), dim3(256), 0, st, p, w, accel);
+  return hipGetLastError();
+}
+
+static unsigned grid_for(size_t n) {
+  size_t g = (n + 255) / 256;
+  if (g > 2048) g = 2048;
+  return (unsigned)(g ? g : 1);
+}
+
+hipError_t launch_fill_i32(int32_t* dst, size_t n, int32_t base, int32_t step, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, n, base, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* dst, size_t n, float value, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(half_of_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

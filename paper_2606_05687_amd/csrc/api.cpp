@@ -164,6 +164,8 @@ int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Wor
     c->mem_bytes = need;
   }
   carve((char*)c->mem, batch, n, w);
+  w->warm_idx = nullptr;
+  w->warm_store = nullptr;
   return PINMPC_OK;
 }
 
@@ -252,19 +254,27 @@ int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_ma
   return PINMPC_OK;
 }
 
-int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out, void* hip_stream) {
-  if (!c || !out) return PINMPC_EINVAL;
+}  // extern "C"
+
+namespace pinmpc {
+
+int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_in,
+                   hipStream_t st, const int32_t* warm_idx, float* warm_store) {
+  if (!c || !out_in) return PINMPC_EINVAL;
+  pinmpc_out outv = *out_in;
+  pinmpc_out* out = &outv;
   int rc = check_batch(in);
   if (rc) return rc;
   if (in->batch > 0 && (!out->u || !out->x)) return PINMPC_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
-  hipStream_t st = (hipStream_t)hip_stream;
   if (in->batch == 0) return PINMPC_OK;
   Workspace w;
   rc = ensure_workspace(c, in->batch, in->n_max, st, &w);
   if (rc) return rc;
+  w.warm_idx = warm_idx;
+  w.warm_store = warm_store;
   const Problem p = to_problem(in);
-  if (c->s.graph) {
+  if (c->s.graph && !warm_idx) {
     GraphKey key;
     std::memset(&key, 0, sizeof(key));
     std::memcpy(&key.in, in, sizeof(*in));
@@ -313,10 +323,26 @@ int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out, void* hi
   if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
   rc = run_admm(c, p, w, c->s.iters, st);
   if (rc) return rc;
+  if (warm_idx && launch_warm_save(p, w, c->s.accel, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[2], st);
   if (launch_refine(p, w, c->s, *out, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
   return PINMPC_OK;
+}
+
+int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n) {
+  if (!c) return PINMPC_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
+  Workspace w;
+  return ensure_workspace(c, batch, n, nullptr, &w);
+}
+
+}  // namespace pinmpc
+
+extern "C" {
+
+int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out, void* hip_stream) {
+  return pinmpc::solve_internal(c, in, out, (hipStream_t)hip_stream, nullptr, nullptr);
 }
 
 int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters, float* z_out,

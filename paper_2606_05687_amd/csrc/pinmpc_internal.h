@@ -74,6 +74,10 @@ struct Workspace {
   int32_t* faces;   // [s][2] face code per contact
   double* bestu;    // [s][12] best certified-or-not iterate
   size_t bytes;
+  // warm start (serving): per problem slot index into a device store of
+  // iterates [slot][PINMPC_NMAX][5][25]; null / negative index = cold start
+  const int32_t* warm_idx;
+  float* warm_store;
 };
 
 // Face code of one contact: bits 0..4 force rows active
@@ -124,10 +128,46 @@ __device__ inline void project_pyramid(T mu, T F, T yx, T yy, T yz, T* px, T* py
   *pz = bz;
 }
 
+// Sum of one value per (stage k < N, lifted row r < 25) held in LDS at
+// cp[k * 25 + r], in an order fixed by N alone (rows in order, then a binary
+// tree over stages), so the result does not depend on the launch shape and a
+// problem computes bitwise the same alone or inside any batch.  ss: N floats
+// of LDS scratch.  Requires blockDim.x >= N; every thread must call it.
+__device__ inline float stage_ordered_sum(const float* cp, float* ss, int N) {
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < N) {
+    float a = 0.f;
+    for (int r = 0; r < NL; ++r) a += cp[t * NL + r];
+    ss[t] = a;
+  }
+  __syncthreads();
+  for (int w = 1; w < N; w <<= 1) {
+    if (t < N && (t % (2 * w)) == 0 && t + w < N) ss[t] += ss[t + w];
+    __syncthreads();
+  }
+  const float v = ss[0];
+  __syncthreads();
+  return v;
+}
+
+// Solve on a given stream, optionally warm-started from (and saving into) a
+// device store of iterates (the serving loop uses this; pinmpc_solve passes
+// null).  Defined in api.cpp.
+int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out,
+                   hipStream_t st, const int32_t* warm_idx, float* warm_store);
+
+// Allocate the context's workspace for batch x n ahead of the first solve.
+int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n);
+
 // Kernel launchers (defined in the .hip units).
 hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                         hipStream_t st);
 hipError_t launch_admm_init(const Problem& p, const Workspace& w, hipStream_t st);
+hipError_t launch_warm_save(const Problem& p, const Workspace& w, int accel, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* dst, size_t n, int32_t base, int32_t step, hipStream_t st);
+hipError_t launch_fill_f32(float* dst, size_t n, float value, hipStream_t st);
+hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st);
 hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                              hipStream_t st);
 hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
