@@ -19,24 +19,33 @@ namespace {
 
 constexpr int V25 = 25;
 
-template <int MAXT>
+template <int MAXT, bool BF16>
 __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace ws, float rho,
                                                           int accel, float eta, int iters,
-                                                          const int32_t* order) {
+                                                          const int32_t* order,
+                                                          const int32_t* count, int lds_n) {
+  OpLoad<BF16> op;
+  if constexpr (BF16) {
+    op.A = ws.Abf; op.Bt = ws.Btbf; op.H = ws.Hbf; op.M = ws.Mbf;
+  } else {
+    op.A = p.A; op.Bt = ws.Bt; op.H = ws.Hp; op.M = ws.Mp;
+  }
   extern __shared__ float lds[];
+  if (count && (int)blockIdx.x >= *count) return;
   const int b = order ? order[blockIdx.x] : (int)blockIdx.x;
-  const int n = p.n_max;
+  const int n = p.n_max;          // stage stride of the global arrays
   const int N = horizon(p, b);
+  const int ln = lds_n;           // stage capacity of the LDS buffers (>= N)
   // LDS: per stage vectors
   float* W = lds;                 // w = vhat - betahat; restart terms [N][25]
-  float* Y = W + n * V25;         // y = zhat - vhat - e + lamhat [N][25]
-  float* ATY = Y + n * V25;       // Abar^T y                     [N][25]
-  float* HT = ATY + n * V25;      // htilde                       [N][25]
-  float* XI = HT + n * V25;       // xi_{k+1}                     [N][25]
-  float* T1 = XI + n * V25;       // Bt^T w_x + w_u               [N][12]
-  float* DU = T1 + n * NU;        // du                           [N][12]
-  float* PIN = DU + n * NU;       // projection input (u part)    [N][12]
-  float* PO = PIN + n * NU;       // projection output            [N][12]
+  float* Y = W + ln * V25;        // y = zhat - vhat - e + lamhat [N][25]
+  float* ATY = Y + ln * V25;      // Abar^T y                     [N][25]
+  float* HT = ATY + ln * V25;     // htilde                       [N][25]
+  float* XI = HT + ln * V25;      // xi_{k+1}                     [N][25]
+  float* T1 = XI + ln * V25;      // Bt^T w_x + w_u               [N][12]
+  float* DU = T1 + ln * NU;       // du                           [N][12]
+  float* PIN = DU + ln * NU;      // projection input (u part)    [N][12]
+  float* PO = PIN + ln * NU;      // projection output            [N][12]
   float* XI0 = PO + n * NU;       // [32]
   float* RED = XI0 + 32;          // [16]
 
@@ -63,20 +72,17 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
   float hrow[NL], o1[NX], o2[NX], o3[NU];
   float qb = 0.f, eb = 0.f;
   if (act) {
-    const float* Hp = ws.Hp + st * NH;
-    for (int j = 0; j < NL; ++j) hrow[j] = Hp[pk(r, j, NL)];
-    const float* A = p.A + st * NX * NX;
-    const float* Bt = ws.Bt + st * NX * NU;
+    const size_t H0 = st * NH, A0 = st * NX * NX, B0 = st * NX * NU, M0 = st * NM;
+    for (int j = 0; j < NL; ++j) hrow[j] = op.h(H0 + pk(r, j, NL));
     if (r < NX) {
-      for (int j = 0; j < NX; ++j) o1[j] = A[r * NX + j];      // row r of A
-      for (int j = 0; j < NX; ++j) o2[j] = A[j * NX + r];      // column r of A
-      for (int j = 0; j < NU; ++j) o3[j] = Bt[r * NU + j];     // row r of Bt
+      for (int j = 0; j < NX; ++j) o1[j] = op.a(A0 + r * NX + j);    // row r of A
+      for (int j = 0; j < NX; ++j) o2[j] = op.a(A0 + j * NX + r);    // column r of A
+      for (int j = 0; j < NU; ++j) o3[j] = op.bt(B0 + r * NU + j);   // row r of Bt
     } else {
       const int jj = r - NX;
-      for (int i = 0; i < NX; ++i) o1[i] = Bt[i * NU + jj];    // column jj of Bt
+      for (int i = 0; i < NX; ++i) o1[i] = op.bt(B0 + i * NU + jj);  // column jj of Bt
       for (int i = 0; i < NX; ++i) o2[i] = 0.f;
-      const float* M = ws.Mp + st * NM;
-      for (int l = 0; l < NU; ++l) o3[l] = M[pk(jj, l, NU)];   // row jj of M
+      for (int l = 0; l < NU; ++l) o3[l] = op.m(M0 + pk(jj, l, NU)); // row jj of M
     }
     qb = ws.qb[st * NL + r];
     eb = (r < NX && p.e) ? p.e[st * NX + r] : 0.f;
@@ -240,14 +246,36 @@ hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_
   if (work > 1024) return hipErrorInvalidValue;
   const int threads = ((work + 63) / 64) * 64;
   // up to 512 threads the kernel may use 256 VGPRs (two waves per SIMD)
-  if (threads <= 512)
-    hipLaunchKernelGGL(admm_fused_kernel<512>, dim3(p.batch), dim3(threads),
-                       fused_lds_bytes(p.n_max), st, p, w, s.rho, s.accel, s.restart_eta, iters,
-                       (const int32_t*)nullptr);
-  else
-    hipLaunchKernelGGL(admm_fused_kernel<1024>, dim3(p.batch), dim3(threads),
-                       fused_lds_bytes(p.n_max), st, p, w, s.rho, s.accel, s.restart_eta, iters,
-                       (const int32_t*)nullptr);
+#define PINMPC_FUSED(T, BF)                                                                 \
+  hipLaunchKernelGGL((admm_fused_kernel<T, BF>), dim3(p.batch), dim3(threads),                \
+                     fused_lds_bytes(p.n_max), st, p, w, s.rho, s.accel, s.restart_eta, iters, \
+                     (const int32_t*)nullptr, (const int32_t*)nullptr, p.n_max)
+  if (threads <= 512 && !s.precision) PINMPC_FUSED(512, false);
+  else if (threads <= 512) PINMPC_FUSED(512, true);
+  else if (!s.precision) PINMPC_FUSED(1024, false);
+  else PINMPC_FUSED(1024, true);
+#undef PINMPC_FUSED
+  return hipGetLastError();
+}
+
+// Problems of horizon class cls, walked through the order array; the grid
+// covers the whole batch and blocks past the class count exit at once.
+hipError_t launch_admm_fused_class(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                                   int iters, int cls, hipStream_t st) {
+  if (p.batch == 0 || iters == 0) return hipSuccess;
+  const int cap = CLASS_N[cls] < p.n_max ? CLASS_N[cls] : p.n_max;
+  const int threads = ((NL * cap + 63) / 64) * 64;
+  const int32_t* ord = w.order + (size_t)cls * p.batch;
+  const int32_t* cnt = w.counts + cls;
+#define PINMPC_FUSED_C(T, BF)                                                              \
+  hipLaunchKernelGGL((admm_fused_kernel<T, BF>), dim3(p.batch), dim3(threads),             \
+                     fused_lds_bytes(cap), st, p, w, s.rho, s.accel, s.restart_eta, iters, \
+                     ord, cnt, cap)
+  if (threads <= 512 && !s.precision) PINMPC_FUSED_C(512, false);
+  else if (threads <= 512) PINMPC_FUSED_C(512, true);
+  else if (!s.precision) PINMPC_FUSED_C(1024, false);
+  else PINMPC_FUSED_C(1024, true);
+#undef PINMPC_FUSED_C
   return hipGetLastError();
 }
 

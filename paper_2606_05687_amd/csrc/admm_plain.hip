@@ -28,11 +28,20 @@ struct Lds {
   float* red;   // reduction scratch
 };
 
-template <int PAIRS>
+template <int PAIRS, bool BF16>
 __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace ws, float rho,
-                                                          int accel, float eta) {
+                                                          int accel, float eta,
+                                                          const int32_t* order,
+                                                          const int32_t* count) {
+  if (count && (int)blockIdx.x >= *count) return;
+  OpLoad<BF16> op;
+  if constexpr (BF16) {
+    op.A = ws.Abf; op.Bt = ws.Btbf; op.H = ws.Hbf; op.M = ws.Mbf;
+  } else {
+    op.A = p.A; op.Bt = ws.Bt; op.H = ws.Hp; op.M = ws.Mp;
+  }
   extern __shared__ float lds[];
-  const int b = blockIdx.x;
+  const int b = order ? order[blockIdx.x] : (int)blockIdx.x;
   const int n = p.n_max;
   const int N = horizon(p, b);
   Lds L;
@@ -88,22 +97,22 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
     const int id = threadIdx.x + q * blockDim.x;
     if (id < nact) {
       const int k = id / NL, r = id % NL;
-      const float* A = p.A + (s0 + k) * NX * NX;
-      const float* Bt = ws.Bt + (s0 + k) * NX * NU;
+      const size_t A0 = (s0 + k) * NX * NX;
+      const size_t B0 = (s0 + k) * NX * NU;
       const float* w = L.b0 + k * BUF;
       const float* y = L.b1 + k * BUF;
       float acc = 0.f;
       if (r < NX) {
-        for (int i = 0; i < NX; ++i) acc = fmaf(A[i * NX + r], y[i], acc);
+        for (int i = 0; i < NX; ++i) acc = fmaf(op.a(A0 + i * NX + r), y[i], acc);
       } else {
         const int j = r - NX;
         acc = y[r];
-        for (int i = 0; i < NX; ++i) acc = fmaf(Bt[i * NU + j], y[i], acc);
+        for (int i = 0; i < NX; ++i) acc = fmaf(op.bt(B0 + i * NU + j), y[i], acc);
       }
       L.aty[k * BUF + r] = acc;
       if (r < NU) {
         float t = w[NX + r];
-        for (int i = 0; i < NX; ++i) t = fmaf(Bt[i * NU + r], w[i], t);
+        for (int i = 0; i < NX; ++i) t = fmaf(op.bt(B0 + i * NU + r), w[i], t);
         L.b2[k * BUF + r] = t;
       }
     }
@@ -121,10 +130,10 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
       if (k + 1 < N) h += L.aty[(k + 1) * BUF + r];
       ht[q] = fmaf(rho, h, ws.qb[(s0 + k) * NL + r]);
       if (r < NU) {
-        const float* M = ws.Mp + (s0 + k) * NM;
+        const size_t M0 = (s0 + k) * NM;
         const float* t = L.b2 + k * BUF;
         float du = 0.f;
-        for (int j = 0; j < NU; ++j) du = fmaf(M[pk(r, j, NU)], t[j], du);
+        for (int j = 0; j < NU; ++j) du = fmaf(op.m(M0 + pk(r, j, NU)), t[j], du);
         L.b3[k * BUF + r] = du;
       }
     }
@@ -146,10 +155,10 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
     const int id = threadIdx.x + q * blockDim.x;
     if (id < nact) {
       const int k = id / NL, r = id % NL;
-      const float* H = ws.Hp + (s0 + k) * NH;
+      const size_t H0 = (s0 + k) * NH;
       const float* h = L.b0 + k * BUF;
       float acc = 0.f;
-      for (int j = 0; j < NL; ++j) acc = fmaf(H[pk(r, j, NL)], h[j], acc);
+      for (int j = 0; j < NL; ++j) acc = fmaf(op.h(H0 + pk(r, j, NL)), h[j], acc);
       xi[q] = acc;
     }
   }
@@ -175,14 +184,15 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
       const float* du = L.b3 + k * BUF;
       float s, bb;
       if (r < NX) {
-        const float* A = p.A + (s0 + k) * NX * NX + r * NX;
-        const float* Bt = ws.Bt + (s0 + k) * NX * NU + r * NU;
+        const size_t A0 = (s0 + k) * NX * NX + r * NX;
+        const size_t B0 = (s0 + k) * NX * NU + r * NU;
         s = 0.f;
-        for (int j = 0; j < NX; ++j) s = fmaf(A[j], prev[j], s);
+        for (int j = 0; j < NX; ++j) s = fmaf(op.a(A0 + j), prev[j], s);
         bb = 0.f;
         for (int j = 0; j < NU; ++j) {
-          s = fmaf(Bt[j], prev[NX + j], s);
-          bb = fmaf(Bt[j], du[j], bb);
+          const float bt = op.bt(B0 + j);
+          s = fmaf(bt, prev[NX + j], s);
+          bb = fmaf(bt, du[j], bb);
         }
       } else {
         s = prev[r];
@@ -410,26 +420,57 @@ hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
-                             hipStream_t st) {
+static hipError_t sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                        const int32_t* ord, const int32_t* cnt, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
   const int work = NL * p.n_max;
   int threads = ((work + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
   const int pairs = (work + threads - 1) / threads;
   const size_t lds = (size_t)(5 * p.n_max * BUF + 32 + 32) * sizeof(float);
-  switch (pairs) {
-    case 1:
-      hipLaunchKernelGGL(admm_sweep_kernel<1>, dim3(p.batch), dim3(threads), lds, st, p, w,
-                         s.rho, s.accel, s.restart_eta);
-      break;
-    case 2:
-      hipLaunchKernelGGL(admm_sweep_kernel<2>, dim3(p.batch), dim3(threads), lds, st, p, w,
-                         s.rho, s.accel, s.restart_eta);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+#define PINMPC_SWEEP(P, BF)                                                                \
+  hipLaunchKernelGGL((admm_sweep_kernel<P, BF>), dim3(p.batch), dim3(threads), lds, st, p, w, \
+                     s.rho, s.accel, s.restart_eta, ord, cnt)
+  if (pairs == 1 && !s.precision) PINMPC_SWEEP(1, false);
+  else if (pairs == 1) PINMPC_SWEEP(1, true);
+  else if (pairs == 2 && !s.precision) PINMPC_SWEEP(2, false);
+  else if (pairs == 2) PINMPC_SWEEP(2, true);
+  else return hipErrorInvalidValue;
+#undef PINMPC_SWEEP
+  return hipGetLastError();
+}
+
+hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             hipStream_t st) {
+  return sweep(p, w, s, nullptr, nullptr, st);
+}
+
+hipError_t launch_admm_sweep_class(const Problem& p, const Workspace& w,
+                                   const pinmpc_settings& s, int cls, hipStream_t st) {
+  return sweep(p, w, s, w.order + (size_t)cls * p.batch, w.counts + cls, st);
+}
+
+namespace {
+
+__global__ void zero_counts_kernel(int32_t* counts) {
+  if (threadIdx.x < 4) counts[threadIdx.x] = 0;
+}
+
+__global__ void classify_kernel(Problem p, Workspace ws) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.batch) return;
+  const int N = horizon(p, b);
+  const int cls = N <= CLASS_N[0] ? 0 : (N <= CLASS_N[1] ? 1 : 2);
+  const int slot = atomicAdd(ws.counts + cls, 1);
+  ws.order[(size_t)cls * p.batch + slot] = b;
+}
+
+}  // namespace
+
+hipError_t launch_classify(const Problem& p, const Workspace& w, hipStream_t st) {
+  if (p.batch == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, w.counts);
+  hipLaunchKernelGGL(classify_kernel, dim3((p.batch + 255) / 256), dim3(256), 0, st, p, w);
   return hipGetLastError();
 }
 

@@ -68,6 +68,10 @@ size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.Hp = (float*)take(S * NH * 4);
   t.Mp = (float*)take(S * NM * 4);
   t.qb = (float*)take(S * NL * 4);
+  t.Abf = (uint16_t*)take(S * NX * NX * 2);
+  t.Btbf = (uint16_t*)take(S * NX * NU * 2);
+  t.Hbf = (uint16_t*)take(S * NH * 2);
+  t.Mbf = (uint16_t*)take(S * NM * 2);
   t.sf = (float*)take(S * 4);
   t.tsc = (float*)take(Bn * 4);
   t.cur = (float*)take(S * NSTATE * NL * 4);
@@ -92,6 +96,8 @@ size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.rdu = (double*)take(S * NU * 8);
   t.rdx = (double*)take(X * NX * 8);
   t.faces = (int32_t*)take(S * 2 * 4);
+  t.order = (int32_t*)take(Bn * 3 * 4);
+  t.counts = (int32_t*)take(4 * 4);
   t.bestu = (double*)take(S * NU * 8);
   t.bytes = off;
   if (w) *w = t;
@@ -105,7 +111,7 @@ int check_settings(const pinmpc_settings* s) {
   if (!(s->restart_eta > 0.f && s->restart_eta <= 1.f)) return PINMPC_EINVAL;
   if (s->refine_passes < 0 || s->ipm_iters < 0 || s->polish_passes < 0) return PINMPC_EINVAL;
   if (!(s->kkt_tol > 0.0)) return PINMPC_EINVAL;
-  if (s->precision != 0) return PINMPC_EINVAL;           // BF16 operators: not built
+  if (s->precision < 0 || s->precision > 1) return PINMPC_EINVAL;
   if (s->form < -1 || s->form > 1) return PINMPC_EINVAL;
   if (s->graph < 0 || s->graph > 1) return PINMPC_EINVAL;
   return PINMPC_OK;
@@ -182,7 +188,17 @@ int run_admm(pinmpc_ctx c, const Problem& p, const Workspace& w, int iters, hipS
   if (launch_setup(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
   if (launch_admm_init(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[1], st);
-  if (use_fused(c->s, p.n_max)) {
+  if (c->s.form == -1 && p.n_max > CLASS_N[0] && iters > 0) {
+    // pack problems by horizon class: fused kernels sized for each class,
+    // one-launch-per-sweep for the longest horizons
+    if (launch_classify(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
+    for (int cls = 0; cls < 2; ++cls)
+      if (launch_admm_fused_class(p, w, c->s, iters, cls, st) != hipSuccess)
+        return PINMPC_EDEVICE;
+    if (p.n_max > CLASS_N[1])
+      for (int it = 0; it < iters; ++it)
+        if (launch_admm_sweep_class(p, w, c->s, 2, st) != hipSuccess) return PINMPC_EDEVICE;
+  } else if (use_fused(c->s, p.n_max)) {
     if (launch_admm_fused(p, w, c->s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
   } else {
     for (int it = 0; it < iters; ++it)

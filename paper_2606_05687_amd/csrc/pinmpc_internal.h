@@ -16,6 +16,41 @@ constexpr int NM = NU * (NU + 1) / 2;   // 78: packed symmetric M_k
 constexpr int NROW = 11;        // wrench rows per stance contact
 constexpr int NSTATE = 5;       // ADMM iterate blocks z, v, theta, beta, lambda
 
+// BF16 (bfloat16) storage: round to nearest even from FP32, and back.
+__host__ __device__ inline uint16_t to_bf16(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 1u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float from_bf16(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+// Operator loads of the sweep kernels: FP32 arrays, or their BF16 copies.
+template <bool BF16>
+struct OpLoad;
+template <>
+struct OpLoad<false> {
+  const float *A, *Bt, *H, *M;
+  __device__ float a(size_t i) const { return A[i]; }
+  __device__ float bt(size_t i) const { return Bt[i]; }
+  __device__ float h(size_t i) const { return H[i]; }
+  __device__ float m(size_t i) const { return M[i]; }
+};
+template <>
+struct OpLoad<true> {
+  const uint16_t *A, *Bt, *H, *M;
+  __device__ float a(size_t i) const { return from_bf16(A[i]); }
+  __device__ float bt(size_t i) const { return from_bf16(Bt[i]); }
+  __device__ float h(size_t i) const { return from_bf16(H[i]); }
+  __device__ float m(size_t i) const { return from_bf16(M[i]); }
+};
+
 // Packed upper-triangular index of symmetric (r, c), n x n.
 __host__ __device__ inline int pk(int r, int c, int n) {
   if (r > c) { int t = r; r = c; c = t; }
@@ -46,6 +81,11 @@ struct Workspace {
   float* Hp;        // [s][325] packed H_k
   float* Mp;        // [s][78] packed M_k = (Bt^T Bt + I)^{-1}
   float* qb;        // [s][25] linear cost term (Q r_k, Rt ut_ref)
+  // BF16 copies of the operators (precision = 1)
+  uint16_t* Abf;    // [s][13][13]
+  uint16_t* Btbf;   // [s][13][12]
+  uint16_t* Hbf;    // [s][325]
+  uint16_t* Mbf;    // [s][78]
   float* sf;        // [s] force scale of stage k
   float* tsc;       // [b] moment scale (tau_max, or 1 without scaling)
   // ADMM iterates [s][5][25]: current and extrapolated ("hat")
@@ -72,6 +112,8 @@ struct Workspace {
   double* rdu;      // [s][12]
   double* rdx;      // [b][n_max+1][13]
   int32_t* faces;   // [s][2] face code per contact
+  int32_t* order;   // [3][b] problems of each horizon class (packing)
+  int32_t* counts;  // [4] problems per class
   double* bestu;    // [s][12] best certified-or-not iterate
   size_t bytes;
   // warm start (serving): per problem slot index into a device store of
@@ -172,6 +214,13 @@ hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_
                              hipStream_t st);
 hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                              int iters, hipStream_t st);
+// Horizon-class packing: class 0 N <= 20, class 1 20 < N <= 40, class 2 N > 40.
+constexpr int CLASS_N[3] = {20, 40, PINMPC_NMAX};
+hipError_t launch_classify(const Problem& p, const Workspace& w, hipStream_t st);
+hipError_t launch_admm_fused_class(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                                   int iters, int cls, hipStream_t st);
+hipError_t launch_admm_sweep_class(const Problem& p, const Workspace& w,
+                                   const pinmpc_settings& s, int cls, hipStream_t st);
 hipError_t launch_admm_extract(const Problem& p, const Workspace& w, int accel,
                                float* z_out, hipStream_t st);
 hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,

@@ -48,7 +48,7 @@ __device__ void gj_inverse(double* aug, int n) {
 }
 
 __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, float rho,
-                                                   int scaling) {
+                                                   int scaling, int bf16) {
   const int s = blockIdx.x;                    // stage index b * n_max + k
   const int b = s / p.n_max, k = s % p.n_max;
   const int lane = threadIdx.x;
@@ -133,6 +133,18 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
     for (int c = r + lane; c < NL; c += 64)
       ws.Hp[(size_t)s * NH + pk(r, c, NL)] =
           (float)(0.5 * (augH[r * 2 * NL + NL + c] + augH[c * 2 * NL + NL + r]));
+  if (bf16) {
+    const float* A = p.A + (size_t)s * NX * NX;
+    for (int i = lane; i < NX * NX; i += 64) ws.Abf[(size_t)s * NX * NX + i] = to_bf16(A[i]);
+    for (int i = lane; i < NX * NU; i += 64)
+      ws.Btbf[(size_t)s * NX * NU + i] = to_bf16((float)sBt[i]);
+    for (int r = 0; r < NU; ++r)
+      for (int c = r + lane; c < NU; c += 64)
+        ws.Mbf[(size_t)s * NM + pk(r, c, NU)] = to_bf16(ws.Mp[(size_t)s * NM + pk(r, c, NU)]);
+    for (int r = 0; r < NL; ++r)
+      for (int c = r + lane; c < NL; c += 64)
+        ws.Hbf[(size_t)s * NH + pk(r, c, NL)] = to_bf16(ws.Hp[(size_t)s * NH + pk(r, c, NL)]);
+  }
   if (lane < NL) {
     double q;
     if (lane < NX) {
@@ -153,7 +165,7 @@ hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_setti
   const size_t stages = (size_t)p.batch * p.n_max;
   if (stages == 0) return hipSuccess;
   hipLaunchKernelGGL(setup_kernel, dim3((unsigned)stages), dim3(64), 0, st, p, w, s.rho,
-                     s.scaling);
+                     s.scaling, s.precision);
   return hipGetLastError();
 }
 

@@ -249,3 +249,31 @@ def test_graph_replay_matches_eager(solver):
         a = torch.randn(512, 512, device="cuda")
         (a @ a).sum().item()
         torch.cuda.synchronize()
+
+
+def test_bf16_operators_then_fp64_refinement(solver):
+    """Precision variant: ADMM operators stored in BF16 (FP32 accumulation),
+    then the FP64 refinement; the certified result meets the same bar."""
+    batch = mpcgen.make_batch("precision_b16384_n30", indices=range(256))
+    out = _solve(solver, batch, precision=1)
+    ok = out["status"] == 0
+    print("bf16 certified", ok.mean())
+    assert ok.mean() >= 0.99
+    _compare(batch, out, range(0, 256, 32))
+    ref32 = _solve(solver, batch, precision=0)
+    both = ok & (ref32["status"] == 0)
+    d = np.max(np.abs(out["u"][both] - ref32["u"][both]))
+    print("max |u_bf16 - u_fp32| over certified", d)
+    assert d <= 1e-4 * np.max(np.abs(ref32["u"]))
+
+
+def test_horizon_class_packing_matches_plain(solver):
+    """Auto form on uneven horizons (10..60): problems are bucketed by horizon
+    into 512- and 1024-thread fused launches and one-launch-per-sweep for the
+    longest; every result equals the all-plain solve bitwise."""
+    batch = mpcgen.make_batch("uneven_b16384", indices=range(200), n_max=60)
+    plain = _solve(solver, batch, form=0)
+    auto = _solve(solver, batch, form=-1)
+    for k in plain:
+        assert np.array_equal(plain[k], auto[k]), k
+    assert (auto["status"] == 0).all()
