@@ -33,6 +33,11 @@ FP64_PEAK_TFLOPS = 78.6
 #   + e 52 + contact 2 + force scale 4 = 3070 B read,
 #   iterates (current and extrapolated, 5 x 25 each) 1000 B read + 1000 B written
 SWEEP_BYTES_PER_STAGE = 3070 + 2000
+# Algorithmic flops of one sweep per stage: block 1 (Abar^T y 338, Bt^T w 312,
+# M t 288, H htilde 1250, vector ops 100), block 2 (Abar xi 650, Bbar du 312,
+# vector ops + projection 150), block 3 and the restart test 200
+SWEEP_FLOPS_PER_STAGE = 338 + 312 + 288 + 1250 + 100 + 650 + 312 + 150 + 200
+FP32_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -41,6 +46,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=100, help="ADMM sweeps per solve")
+    ap.add_argument("--form", type=int, default=0, help="0 plain, 1 fused, -1 packed")
+    ap.add_argument("--rho", type=float, default=10.0)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: choose form/K/rho with the autotuner on a held-out batch "
+                         "(problems 4096..8191 of the same generator) before timing")
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="problems in the oracle CPU-baseline sample (0: skip)")
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -123,12 +133,27 @@ def main():
     from paper_2606_05687_amd import binding
 
     torch.cuda.set_device(0)
+    settings = dict(iters=args.iters, form=args.form, rho=args.rho)
+    tuned = None
+    if args.autotune:
+        from paper_2606_05687_amd import autotune
+        held = mpcgen.make_batch(WORKLOAD, indices=range(4096, 8192))
+        hdev = binding.to_device(held, "cuda:0")
+        tuned = autotune.tune(hdev, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
+                              force=True)
+        settings.update(tuned)
+        del hdev
     batch = mpcgen.make_batch(WORKLOAD)
     Bn, n = batch["A"].shape[0], batch["A"].shape[1]
     stages = int(batch["N"].sum())
     dev = binding.to_device(batch, "cuda:0")
-    solver = binding.Solver(0, iters=args.iters)
+    solver = binding.Solver(0, **settings)
+    # phase split (setup / sweeps / refinement) from an uncaptured solve
+    solver.set(graph=0)
     out = solver.alloc_out(dev)
+    solver.solve(dev, out)
+    phase_split = solver.stats()
+    solver.set(graph=1)
     bstruct = binding.make_batch_struct(dev)
     stream = torch.cuda.current_stream()
 
@@ -154,19 +179,26 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = certified / elapsed
 
-    admm_ms = float(np.mean([p["admm_ms"] for p in phase]))
-    refine_ms = float(np.mean([p["refine_ms"] for p in phase]))
-    setup_ms = float(np.mean([p["setup_ms"] for p in phase]))
-    sweep_ms = admm_ms / max(1, args.iters)
+    admm_ms = phase_split["admm_ms"]
+    refine_ms = phase_split["refine_ms"]
+    setup_ms = phase_split["setup_ms"]
+    K = settings["iters"]
+    sweep_ms = admm_ms / max(1, K)
     sweep_bytes = stages * SWEEP_BYTES_PER_STAGE
     # dominant phase: ADMM sweeps (HBM-bound) or the FP64 refinement
-    if admm_ms >= refine_ms:
+    if admm_ms >= refine_ms and settings["form"] == 0:
         achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_plain.hip")
         roof = {"kernel": "admm_sweep_kernel", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(src, sweep_bytes),
                 "launch_ms": sweep_ms, "bytes_per_launch": sweep_bytes}
+    elif admm_ms >= refine_ms:
+        flops = stages * SWEEP_FLOPS_PER_STAGE * K
+        achieved = flops / (admm_ms * 1e-3) / 1e12
+        roof = {"kernel": "admm_fused_kernel", "bound": "alu", "achieved": achieved,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": None, "launch_ms": admm_ms, "flops_per_launch": flops}
     else:
         roof = {"kernel": "refine_kernel", "bound": "fp64", "achieved": None,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
@@ -186,7 +218,10 @@ def main():
         "dtype": "f32 (ADMM) + f64 (refinement)",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "batch": int(Bn), "horizon": int(n),
-                   "admm_iters": args.iters, "form": "plain"},
+                   "admm_iters": K, "rho": settings["rho"],
+                   "form": {0: "plain", 1: "fused", -1: "packed"}[settings["form"]],
+                   "precision": "bf16" if settings.get("precision") else "fp32",
+                   "autotuned": bool(tuned)},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),
         "certified_frac": certified / (Bn * args.steps),

@@ -1,0 +1,90 @@
+"""Autotuner for the solve schedule (driver over the C ABI).
+
+Chooses, by measurement on a sample of the workload, the sweep form (one
+launch per sweep, fused, or horizon-class packed), the number of ADMM sweeps
+K (more sweeps cost sweep time but give the FP64 refinement a better active
+set and fewer passes), the penalty rho and the operator precision.  The score
+is certified solves per second: problems whose status is certified and whose
+reported KKT residuals are all <= the bar, divided by the measured solve time;
+a candidate that certifies fewer than ``min_certified`` of the sample is
+rejected.  Results are cached in a JSON file keyed by device architecture,
+batch size, horizon mix and precision policy.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import os
+import time
+
+import numpy as np
+
+from . import binding
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pinmpc_tune.json")
+
+
+def _key(dev, allow_bf16):
+    import torch
+    N = dev["N"].cpu().numpy() if "N" in dev else np.full(int(dev["A"].shape[0]),
+                                                          int(dev["A"].shape[1]))
+    hist = np.bincount(N, minlength=65)
+    mix = hashlib.sha1(np.round(hist / max(1, len(N)), 2).tobytes()).hexdigest()[:10]
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return f"{arch}|B{int(dev['A'].shape[0])}|n{int(dev['A'].shape[1])}|mix{mix}|bf16{int(allow_bf16)}"
+
+
+def candidates(n_max, allow_bf16=False):
+    forms = [0, 1] if n_max <= 40 else [0, -1]
+    iters = [25, 50, 100, 150]
+    rhos = [3.0, 10.0, 30.0]
+    precs = [0, 1] if allow_bf16 else [0]
+    for f, k, r, p in itertools.product(forms, iters, rhos, precs):
+        yield dict(form=f, iters=k, rho=r, precision=p)
+
+
+def measure(solver, dev, out, bs, settings, reps=3, kkt_bar=1e-5):
+    import torch
+    solver.set(**settings)
+    solver.solve(dev, out, batch_struct=bs)        # warm-up (and graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        solver.solve(dev, out, batch_struct=bs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ok = (out["status"] == 0) & (out["res"].max(dim=1).values <= kkt_bar)
+    frac = float(ok.float().mean().item())
+    return dt, frac
+
+
+def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, verbose=False,
+         force=False):
+    """Best settings (dict) for batches shaped like ``dev``; cached."""
+    key = _key(dev, allow_bf16)
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if key in cache and not force:
+        return cache[key]["settings"]
+    solver = binding.Solver(0)
+    out = solver.alloc_out(dev)
+    bs = binding.make_batch_struct(dev)
+    Bn = int(dev["A"].shape[0])
+    best, best_score, log = None, -1.0, []
+    for cand in candidates(int(dev["A"].shape[1]), allow_bf16):
+        dt, frac = measure(solver, dev, out, bs, cand)
+        score = frac * Bn / dt if frac >= min_certified else 0.0
+        log.append(dict(cand, ms=dt * 1e3, certified=frac, score=score))
+        if verbose:
+            print(f"  {cand} {dt * 1e3:.2f} ms certified {frac:.4f} -> {score:.0f}/s", flush=True)
+        if score > best_score:
+            best, best_score = cand, score
+    solver.close()
+    cache[key] = {"settings": best, "score": best_score, "log": log}
+    os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
+    with open(cache_path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return best
