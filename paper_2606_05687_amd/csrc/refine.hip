@@ -159,6 +159,13 @@ __device__ void face_affine(int code, double mu, double fz, double tm, double P[
   }
 }
 
+// Input blocks: force triples (3 x 3) and single moment components.  Face
+// projectors P_k and the interior-point input Hessian R' are block diagonal
+// in these blocks, so products with them only run over the block of the
+// column (exact, not an approximation).
+__device__ inline int blk_start(int j) { return (j % 6 < 3) ? j - j % 6 : j; }
+__device__ inline int blk_len(int j) { return (j % 6 < 3) ? 3 : 1; }
+
 // --------------------------------------------------------------- LDS state
 
 struct Sh {
@@ -309,8 +316,9 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     // Bp = B P ; d = B c + e
     for (int e = lane; e < NX * NU; e += W64) {
       const int i = e / NU, j = e % NU;
+      const int l0 = blk_start(j), l1 = l0 + blk_len(j);
       double acc = 0.0;
-      for (int l = 0; l < NU; ++l) acc += sh.B[i * NU + l] * sh.P[l * NU + j];
+      for (int l = l0; l < l1; ++l) acc += sh.B[i * NU + l] * sh.P[l * NU + j];
       sh.Bp[e] = acc;
     }
     if (lane < NX) {
@@ -355,8 +363,10 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       // T = R' P, held in K until K itself is formed
       for (int e = lane; e < NU * NU; e += W64) {
         const int i = e / NU, j = e % NU;
+        const int l0 = blk_start(j), l1 = l0 + blk_len(j);
         double acc = 0.0;
-        for (int l = 0; l < NU; ++l) acc += sh.Rp[i * NU + l] * sh.P[l * NU + j];
+        if (blk_start(i) == l0)
+          for (int l = l0; l < l1; ++l) acc += sh.Rp[i * NU + l] * sh.P[l * NU + j];
         sh.K[e] = acc;   // scratch
       }
     }
@@ -368,10 +378,12 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
         if (e < NU * NU) {
           const int i = e / NU, j = e % NU;
           double acc = ((i == j) ? 1.0 : 0.0) - sh.P[i * NU + j];
-          for (int l = 0; l < NU; ++l) acc += sh.P[l * NU + i] * sh.K[l * NU + j];
+          const int l0 = blk_start(i), l1 = l0 + blk_len(i);
+          if (blk_start(j) == l0)
+            for (int l = l0; l < l1; ++l) acc += sh.P[l * NU + i] * sh.K[l * NU + j];
           for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WBp[l * NU + j];
           sh.G[i * GJW + j] = acc;
-          sh.G[i * GJW + NU + NX + 1 + j] = (i == j) ? 1.0 : 0.0;
+          if (mode == Mode::NEWTON) sh.G[i * GJW + NU + NX + 1 + j] = (i == j) ? 1.0 : 0.0;
         } else {
           const int f = e - NU * NU, i = f / NX, j = f % NX;
           double acc = 0.0;
@@ -386,10 +398,11 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     if (lane < NU) {
       // hw = P (R' c + rho) + Bp^T (W d + omega)
       double acc = 0.0;
-      for (int l = 0; l < NU; ++l) {
+      const int l0 = blk_start(lane), l1 = l0 + blk_len(lane);
+      for (int l = l0; l < l1; ++l) {
         double t = sh.rho[l];
         if (mode == Mode::EQ)
-          for (int m = 0; m < NU; ++m) t += sh.Rp[l * NU + m] * sh.c[m];
+          for (int m = l0; m < l1; ++m) t += sh.Rp[l * NU + m] * sh.c[m];
         acc += sh.P[lane * NU + l] * t;
       }
       for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + lane] * sh.Wdo[l];
@@ -399,17 +412,19 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     __syncthreads();
     if (factor) {
       // Gauss-Jordan elimination (H is SPD: no pivoting) over all 64 lanes:
-      // afterwards G = [I | H^{-1} Hwx | H^{-1} hw | H^{-1}]
+      // afterwards G = [I | H^{-1} Hwx | H^{-1} hw | H^{-1}]; the equality
+      // pass needs no explicit inverse, so it stops at column 25.
+      const int gw = (mode == Mode::NEWTON) ? GJW : NU + NX + 1;
       for (int j = 0; j < NU; ++j) {
         const double piv = sh.G[j * GJW + j];
         __syncthreads();
-        for (int c = lane; c < GJW; c += W64) sh.G[j * GJW + c] /= piv;
+        for (int c = j + lane; c < gw; c += W64) sh.G[j * GJW + c] /= piv;
         __syncthreads();
         if (lane < NU) sh.fac[lane] = sh.G[lane * GJW + j];
         __syncthreads();
-        for (int e = lane; e < NU * GJW; e += W64) {
-          const int r = e / GJW, c = e % GJW;
-          if (r != j) sh.G[e] -= sh.fac[r] * sh.G[j * GJW + c];
+        for (int e = lane; e < NU * (gw - j - 1); e += W64) {
+          const int r = e / (gw - j - 1), c = j + 1 + e % (gw - j - 1);
+          if (r != j) sh.G[r * GJW + c] -= sh.fac[r] * sh.G[j * GJW + c];
         }
         __syncthreads();
       }
@@ -419,9 +434,12 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       }
       if (lane < NU) sh.kap[lane] = -sh.G[lane * GJW + NU + NX];
       // keep H^{-1} and Hwx for a second right-hand side of the same matrix
-      double* Hi = C.ws.rL + st * NU * NU;
-      for (int e = lane; e < NU * NU; e += W64) Hi[e] = sh.G[(e / NU) * GJW + NU + NX + 1 + e % NU];
-      for (int e = lane; e < NU * NX; e += W64) C.ws.rHwx[st * NU * NX + e] = sh.Hwx[e];
+      if (mode == Mode::NEWTON) {
+        double* Hi = C.ws.rL + st * NU * NU;
+        for (int e = lane; e < NU * NU; e += W64)
+          Hi[e] = sh.G[(e / NU) * GJW + NU + NX + 1 + e % NU];
+        for (int e = lane; e < NU * NX; e += W64) C.ws.rHwx[st * NU * NX + e] = sh.Hwx[e];
+      }
     } else {
       const double* Hi = C.ws.rL + st * NU * NU;
       if (lane < NU) {
@@ -437,12 +455,15 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     if (lane < NU) C.ws.rkap[st * NU + lane] = sh.kap[lane];
     // S = A^T W A + Hwx^T K ; s = A^T (W d + omega) + Hwx^T kap
     if (factor) {
-      for (int e = lane; e < NX * NX; e += W64) {
-        const int i = e / NX, j = e % NX;
+      // upper triangle of the (symmetric) new S, mirrored below
+      for (int e = lane; e < NX * (NX + 1) / 2; e += W64) {
+        int i = 0, rem = e;
+        while (rem >= NX - i) { rem -= NX - i; ++i; }
+        const int j = i + rem;
         double acc = 0.0;
         for (int l = 0; l < NX; ++l) acc += sh.A[l * NX + i] * sh.WA[l * NX + j];
         for (int l = 0; l < NU; ++l) acc += sh.Hwx[l * NX + i] * sh.K[l * NX + j];
-        sh.W[e] = acc;    // new S, copied below
+        sh.W[i * NX + j] = acc;    // new S, copied below
       }
     }
     if (lane < NX) {
@@ -453,7 +474,10 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     }
     __syncthreads();
     if (factor)
-      for (int e = lane; e < NX * NX; e += W64) sh.S[e] = 0.5 * (sh.W[e] + sh.W[(e % NX) * NX + e / NX]);
+      for (int e = lane; e < NX * NX; e += W64) {
+        const int i = e / NX, j = e % NX;
+        sh.S[e] = (i <= j) ? sh.W[i * NX + j] : sh.W[j * NX + i];
+      }
     if (lane < NX) sh.s[lane] = sh.xn[lane];
     __syncthreads();
   }

@@ -215,9 +215,11 @@ def test_fused_form_matches_plain_form(solver):
 
 
 def test_fused_form_uneven_horizons_up_to_40(solver):
-    batch = mpcgen.make_batch("uneven_b16384", indices=range(64), n_max=40)
-    keep = batch["N"] <= 40
-    batch = mpcgen.problem_slice(batch, np.where(keep)[0])
+    batch = mpcgen.make_batch("uneven_b16384", indices=range(64), n_max=60)
+    keep = np.where(batch["N"] <= 40)[0]
+    batch = mpcgen.problem_slice(batch, keep)
+    for k in ("A", "B", "e", "x_ref", "u_ref", "contact"):
+        batch[k] = np.ascontiguousarray(batch[k][:, :40])
     out = _solve(solver, batch, form=1)
     assert (out["status"] == 0).all()
     _compare(batch, out, range(0, len(batch["N"]), 7))
