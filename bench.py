@@ -204,6 +204,7 @@ def main():
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None, "launch_ms": refine_ms}
     status = out["status"].cpu().numpy()
+    passes = out["iters"].cpu().numpy() - K
     line = {
         "metric": METRIC,
         "value": value,
@@ -226,6 +227,8 @@ def main():
         "p99_ms": float(np.percentile(step_ms, 99)),
         "certified_frac": certified / (Bn * args.steps),
         "status_counts": {str(k): int((status == k).sum()) for k in range(5)},
+        "refine_passes": {"mean": float(passes.mean()), "p99": float(np.percentile(passes, 99)),
+                          "max": int(passes.max())},
         "phase_ms": {"setup": setup_ms, "admm": admm_ms, "refine": refine_ms},
         "roofline": roof,
     }

@@ -13,6 +13,11 @@
 // the operators once plus the iterates once, independent of the sweep count.
 #include "pinmpc_internal.h"
 
+// Every multiply-add below is either an explicit fmaf or a separate multiply
+// and add: no compiler contraction, so every instantiation of the sweep
+// (plain or fused, any block size) computes bitwise the same iterates.
+#pragma clang fp contract(off)
+
 namespace pinmpc {
 
 namespace {

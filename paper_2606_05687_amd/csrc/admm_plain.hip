@@ -12,6 +12,11 @@
 // lambda_k).  Inputs are in scaled coordinates ut = S_k^{-1} u.
 #include "pinmpc_internal.h"
 
+// Every multiply-add below is either an explicit fmaf or a separate multiply
+// and add: no compiler contraction, so every instantiation of the sweep
+// (plain or fused, any block size) computes bitwise the same iterates.
+#pragma clang fp contract(off)
+
 namespace pinmpc {
 
 namespace {

@@ -171,10 +171,11 @@ __device__ inline void project_pyramid(T mu, T F, T yx, T yy, T yz, T* px, T* py
 }
 
 // Sum of one value per (stage k < N, lifted row r < 25) held in LDS at
-// cp[k * 25 + r], in an order fixed by N alone (rows in order, then a binary
-// tree over stages), so the result does not depend on the launch shape and a
-// problem computes bitwise the same alone or inside any batch.  ss: N floats
-// of LDS scratch.  Requires blockDim.x >= N; every thread must call it.
+// cp[k * 25 + r], in an order fixed by N alone (rows in order within a
+// stage, then stages in order), so the result does not depend on the launch
+// shape and a problem computes bitwise the same alone or inside any batch.
+// ss: N + 1 floats of LDS scratch.  Requires blockDim.x >= N; every thread
+// must call it.
 __device__ inline float stage_ordered_sum(const float* cp, float* ss, int N) {
   __syncthreads();
   const int t = threadIdx.x;
@@ -184,11 +185,13 @@ __device__ inline float stage_ordered_sum(const float* cp, float* ss, int N) {
     ss[t] = a;
   }
   __syncthreads();
-  for (int w = 1; w < N; w <<= 1) {
-    if (t < N && (t % (2 * w)) == 0 && t + w < N) ss[t] += ss[t + w];
-    __syncthreads();
+  if (t == 0) {
+    float a = 0.f;
+    for (int k = 0; k < N; ++k) a += ss[k];
+    ss[N] = a;
   }
-  const float v = ss[0];
+  __syncthreads();
+  const float v = ss[N];
   __syncthreads();
   return v;
 }
