@@ -40,7 +40,8 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
   const int b = order ? order[blockIdx.x] : (int)blockIdx.x;
   const int n = p.n_max;          // stage stride of the global arrays
   const int N = horizon(p, b);
-  const int ln = lds_n;           // stage capacity of the LDS buffers (>= N)
+  const int ln = lds_n;           // stage capacity of the LDS buffers
+  if (N > ln) return;             // never for a valid packing: keeps LDS in bounds
   // LDS: per stage vectors
   float* W = lds;                 // w = vhat - betahat; restart terms [N][25]
   float* Y = W + ln * V25;        // y = zhat - vhat - e + lamhat [N][25]
@@ -51,8 +52,7 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
   float* DU = T1 + ln * NU;       // du                           [N][12]
   float* PIN = DU + ln * NU;      // projection input (u part)    [N][12]
   float* PO = PIN + ln * NU;      // projection output            [N][12]
-  float* XI0 = PO + n * NU;       // [32]
-  float* RED = XI0 + 32;          // [16]
+  float* XI0 = PO + ln * NU;      // [32]
 
   const int tid = threadIdx.x;
   const bool act = tid < N * NL;
@@ -240,8 +240,10 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
 
 }  // namespace
 
-size_t fused_lds_bytes(int n_max) {
-  return (size_t)(5 * n_max * V25 + 4 * n_max * NU + 32 + 16) * sizeof(float);
+// LDS of one workgroup for a capacity of n stages: five 25-vectors and four
+// 12-vectors per stage, then the fixed initial lifted state (32 floats).
+size_t fused_lds_bytes(int n) {
+  return (size_t)(5 * n * V25 + 4 * n * NU + 32) * sizeof(float);
 }
 
 hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,

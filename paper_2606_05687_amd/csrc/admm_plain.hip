@@ -30,7 +30,6 @@ struct Lds {
   float* b3;    // du (12)                      -> later projection output (12)
   float* aty;   // Abar^T y of the stage
   float* xi0;   // fixed lifted initial state (x0, ut_prev)
-  float* red;   // reduction scratch
 };
 
 template <int PAIRS, bool BF16>
@@ -56,7 +55,6 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
   L.b3 = L.b2 + n * BUF;
   L.aty = L.b3 + n * BUF;
   L.xi0 = L.aty + n * BUF;
-  L.red = L.xi0 + 32;
   const int nact = N * NL;
   const size_t s0 = (size_t)b * n;
   const float* e = p.e;
@@ -432,7 +430,7 @@ static hipError_t sweep(const Problem& p, const Workspace& w, const pinmpc_setti
   int threads = ((work + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
   const int pairs = (work + threads - 1) / threads;
-  const size_t lds = (size_t)(5 * p.n_max * BUF + 32 + 32) * sizeof(float);
+  const size_t lds = (size_t)(5 * p.n_max * BUF + 32) * sizeof(float);
 #define PINMPC_SWEEP(P, BF)                                                                \
   hipLaunchKernelGGL((admm_sweep_kernel<P, BF>), dim3(p.batch), dim3(threads), lds, st, p, w, \
                      s.rho, s.accel, s.restart_eta, ord, cnt)

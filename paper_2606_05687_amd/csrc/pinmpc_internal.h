@@ -67,7 +67,15 @@ struct Problem {
   const float *mu, *fz_max, *tau_max, *weight;
 };
 
+// Horizon of problem b clamped to [0, n_max], so that no kernel indexes past
+// its problem's stages whatever the caller passed (the refinement flags an
+// out-of-range horizon as bad input from the raw value).
 __device__ inline int horizon(const Problem& p, int b) {
+  if (!p.N) return p.n_max;
+  const int N = p.N[b];
+  return N < 0 ? 0 : (N > p.n_max ? p.n_max : N);
+}
+__device__ inline int horizon_raw(const Problem& p, int b) {
   return p.N ? p.N[b] : p.n_max;
 }
 __device__ inline float weight_of(const Problem& p, int b) {

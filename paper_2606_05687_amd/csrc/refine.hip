@@ -963,8 +963,9 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
   const int N = C.N;
 
   // input checks: bounds, then finiteness of this problem's data
+  const int Nraw = horizon_raw(p, C.b);
   int bad = !(C.mu >= 0.0) || !(C.fz >= 0.0) || !(C.tm >= 0.0) || !(C.mg > 0.0) ||
-            N < 1 || N > C.n;
+            Nraw < 1 || Nraw > C.n;
   for (int j = 0; j < NX; ++j) bad |= !(C.Q[j] > 0.0);
   for (int j = 0; j < NU; ++j) bad |= !(C.R[j] > 0.0);
   int nonfinite = 0;

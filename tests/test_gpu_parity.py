@@ -150,9 +150,12 @@ def test_nonfinite_and_bad_input_isolated(solver):
     bad = {k: v.copy() for k, v in batch.items()}
     bad["A"][3, 2, 4, 4] = np.nan
     bad["mu"][5] = -0.5
+    bad["N"][6] = 99           # horizon beyond n_max: clamped for the sweeps, flagged
+    bad["N"][1] = 0
     o = _solve(solver, bad)
     assert o["status"][3] == 3 and o["status"][5] == 4
-    for b in (0, 1, 2, 4, 6, 7):
+    assert o["status"][6] == 4 and o["status"][1] == 4
+    for b in (0, 2, 4, 7):
         for k in ("u", "x", "res", "status"):
             assert np.array_equal(o[k][b], clean[k][b]), (b, k)
 
