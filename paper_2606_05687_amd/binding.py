@@ -106,6 +106,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libpinmpc.so not built at {path}; run __graft_entry__.build()")
+    # torch ships its own HIP runtime; load it first so that the library binds
+    # to the same runtime instance torch's tensors and streams live in
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)

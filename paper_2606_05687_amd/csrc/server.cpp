@@ -62,7 +62,8 @@ struct Lane {
   float *u, *x, *res;
   int32_t *iters, *status;
   std::vector<Request*> inflight;
-  bool busy = false;
+  bool busy = false;      // owns requests (set by the scheduler before enqueueing)
+  bool launched = false;  // its event was recorded after the last enqueued work
 };
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -255,10 +256,14 @@ void pinmpc_server_s::sched_loop() {
       queue.pop_front();
     }
     free_lane->busy = true;
+    free_lane->launched = false;
     free_lane->inflight = rq;
     lk.unlock();
     const int rc = launch(*free_lane, rq);
     lk.lock();
+    // only now may the completion thread look at this lane's event: before
+    // the record an earlier (or never recorded) event reads as complete
+    free_lane->launched = (rc == PINMPC_OK);
     if (rc) {
       error = rc;
       for (Request* r : rq) {
@@ -286,6 +291,7 @@ void pinmpc_server_s::done_loop() {
     for (auto& L : lanes) {
       if (!L.busy || L.inflight.empty()) continue;
       any = true;
+      if (!L.launched) continue;
       const hipError_t q = hipEventQuery(L.ev);
       if (q == hipErrorNotReady) continue;
       const auto now = Clock::now();
@@ -296,6 +302,7 @@ void pinmpc_server_s::done_loop() {
       }
       L.inflight.clear();
       L.busy = false;
+      L.launched = false;
       cv_sched.notify_all();
       cv_done.notify_all();
     }
