@@ -80,25 +80,10 @@ size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.cprev = (float*)take(Bn * 4);
   t.restarts = (int32_t*)take(Bn * 4);
   t.flags = (uint32_t*)take(Bn * 4);
-  t.rK = (double*)take(S * NU * NX * 8);
-  t.rkap = (double*)take(S * NU * 8);
-  t.rL = (double*)take(S * NU * NU * 8);
-  t.rHwx = (double*)take(S * NU * NX * 8);
-  t.ru = (double*)take(S * NU * 8);
-  t.rx = (double*)take(X * NX * 8);
-  t.rlam = (double*)take(S * NX * 8);
-  t.rg = (double*)take(S * NU * 8);
-  t.rmu = (double*)take(S * 2 * NROW * 8);
-  t.rs = (double*)take(S * 2 * NROW * 8);
-  t.rz = (double*)take(S * 2 * NROW * 8);
-  t.rds = (double*)take(S * 2 * NROW * 8);
-  t.rdz = (double*)take(S * 2 * NROW * 8);
-  t.rdu = (double*)take(S * NU * 8);
-  t.rdx = (double*)take(X * NX * 8);
+  t.rblk = (double*)take(Bn * refine_block_doubles(n) * 8);
   t.faces = (int32_t*)take(S * 2 * 4);
   t.order = (int32_t*)take(Bn * 3 * 4);
   t.counts = (int32_t*)take(4 * 4);
-  t.bestu = (double*)take(S * NU * 8);
   t.bytes = off;
   if (w) *w = t;
   return off;

@@ -103,32 +103,28 @@ struct Workspace {
   float* cprev;     // [b] restart test value
   int32_t* restarts;// [b]
   uint32_t* flags;  // [b] bit0: nonfinite input, bit1: bad bounds
-  // FP64 refinement scratch
-  double* rK;       // [s][12][13] feedback gains
-  double* rkap;     // [s][12] feedforward
-  double* rL;       // [s][12][12] inverse of the reduced input Hessian
-  double* rHwx;     // [s][12][13]
-  double* ru;       // [s][12] inputs
-  double* rx;       // [b][n_max+1][13] states
-  double* rlam;     // [s][13] costates p_{k+1}
-  double* rg;       // [s][12] reduced gradient R(u-ur) + B^T p
-  double* rmu;      // [s][2][11] row multipliers
-  double* rs;       // [s][2][11] IPM slacks (scaled rows)
-  double* rz;       // [s][2][11] IPM multipliers (scaled rows)
-  double* rds;      // [s][2][11]
-  double* rdz;      // [s][2][11]
-  double* rdu;      // [s][12]
-  double* rdx;      // [b][n_max+1][13]
+  // FP64 refinement scratch: one contiguous block per problem
+  // (refine_block_doubles(n_max) doubles each), see refine.hip
+  double* rblk;
   int32_t* faces;   // [s][2] face code per contact
   int32_t* order;   // [3][b] problems of each horizon class (packing)
   int32_t* counts;  // [4] problems per class
-  double* bestu;    // [s][12] best certified-or-not iterate
   size_t bytes;
   // warm start (serving): per problem slot index into a device store of
   // iterates [slot][PINMPC_NMAX][5][25]; null / negative index = cold start
   const int32_t* warm_idx;
   float* warm_store;
 };
+
+// FP64 scratch of the refinement per problem with n stages: gains K (12x13),
+// feedforward (12), inverse input Hessian (12x12), Hwx (12x13), inputs (12),
+// states ((n+1) x 13), costates (13), gradient (12), row multipliers, slacks,
+// interior-point multipliers and their steps (4 x 22 + 22), step du (12) and
+// dx ((n+1) x 13).
+__host__ __device__ constexpr size_t refine_block_doubles(int n) {
+  return (size_t)n * (NU * NX + NU + NU * NU + NU * NX + NU + NX + NU + 5 * 2 * NROW + NU) +
+         2 * (size_t)(n + 1) * NX;
+}
 
 // Face code of one contact: bits 0..4 force rows active
 //   (0: f_x - mu f_z <= 0, 1: -f_x - mu f_z <= 0, 2: f_y - mu f_z <= 0,

@@ -27,14 +27,17 @@ namespace {
 constexpr int W64 = 64;
 constexpr int GJW = NU + NX + 1 + NU;   // 38 columns of the augmented system
 
+// One problem's view: its inputs and its FP64 scratch block, all as
+// pointers to the problem's own first stage, so stage k is plain k.
 struct Ctx {
-  Problem p;
-  Workspace ws;
   int b, N, n;
-  size_t s0;
   double mu, fz, tm, mg;
   const double* Q;   // LDS copies of the diagonal weights
   const double* R;
+  const float *A, *B, *e, *x_ref, *u_ref, *x0;
+  const uint8_t* contact;
+  double *rK, *rkap, *rL, *rHwx, *ru, *rx, *rlam, *rg, *rmu, *rs, *rz, *rds, *rdz, *rdu, *rdx;
+  int32_t* faces;
 };
 
 // ------------------------------------------------------------ small helpers
@@ -83,75 +86,111 @@ __device__ inline bool face_apex(int code) {
   return ((f & 3) == 3) || ((f & 12) == 12);
 }
 
-// Solve the m x m system M y = r (m <= 3, SPD) by Gaussian elimination.
-__device__ inline void small_solve(double M[3][3], double r[3], int m) {
-  for (int j = 0; j < m; ++j) {
-    const double piv = M[j][j];
-    for (int c = j; c < m; ++c) M[j][c] /= piv;
-    r[j] /= piv;
-    for (int i = 0; i < m; ++i)
-      if (i != j) {
-        const double f = M[i][j];
-        for (int c = j; c < m; ++c) M[i][c] -= f * M[j][c];
-        r[i] -= f * r[j];
-      }
+// Force rows of the pyramid as fixed vectors: row i (0..4) is g_i^T f <= h_i.
+__device__ inline void force_row(int i, double mu, double g[3]) {
+  g[0] = (i == 0) ? 1.0 : (i == 1 ? -1.0 : 0.0);
+  g[1] = (i == 2) ? 1.0 : (i == 3 ? -1.0 : 0.0);
+  g[2] = (i < 4) ? -mu : 1.0;
+}
+
+// Solve the 5 x 5 system M y = r in place (Gauss-Jordan, no pivoting; M is
+// SPD on the active rows and the identity on the others).  All indices are
+// compile-time after unrolling, so the arrays stay in registers.
+__device__ inline void solve5(double M[5][5], double r[5]) {
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const double inv = 1.0 / M[j][j];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) M[j][c] *= inv;
+    r[j] *= inv;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      if (i == j) continue;
+      const double f = M[i][j];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) M[i][c] -= f * M[j][c];
+      r[i] -= f * r[j];
+    }
+  }
+}
+
+// Masked Gram system of the active force rows: (G_A G_A^T) on active rows,
+// identity elsewhere.
+__device__ inline void gram5(int mask, double mu, double M[5][5]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double gi[3];
+    force_row(i, mu, gi);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      double gj[3];
+      force_row(j, mu, gj);
+      const bool ai = (mask >> i) & 1, aj = (mask >> j) & 1;
+      M[i][j] = (ai && aj) ? gi[0] * gj[0] + gi[1] * gj[1] + gi[2] * gj[2] : (i == j ? 1.0 : 0.0);
+    }
   }
 }
 
 // Affine hull of a contact's face: projector P (6x6, block diagonal) and a
-// point c with u = c + P w spanning the face.
+// point c with u = c + P w spanning the face.  For the force block with
+// active rows A (independent unless the face is the apex):
+//   P = I - G_A^T (G_A G_A^T)^{-1} G_A,   c = G_A^T (G_A G_A^T)^{-1} h_A.
 __device__ void face_affine(int code, double mu, double fz, double tm, double P[6][6],
                             double c[6]) {
+#pragma unroll
   for (int a = 0; a < 6; ++a) {
     c[a] = 0.0;
+#pragma unroll
     for (int b = 0; b < 6; ++b) P[a][b] = 0.0;
   }
-  // force block
   if (!face_apex(code)) {
-    double G[3][3], h[3];
-    int m = 0;
-    for (int i = 0; i < 5; ++i)
-      if (code >> i & 1) {
-        double g[6], hh;
-        wrench_row(i, mu, fz, tm, g, &hh);
-        G[m][0] = g[0]; G[m][1] = g[1]; G[m][2] = g[2];
-        h[m] = hh;
-        ++m;
-      }
-    double GG[3][3], y[3];
-    for (int i = 0; i < m; ++i) {
-      for (int j = 0; j < m; ++j)
-        GG[i][j] = G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2];
-      y[i] = h[i];
-    }
-    // P = I - G^T (G G^T)^{-1} G ; c = G^T (G G^T)^{-1} h
-    double Gi[3][3];   // (G G^T)^{-1} G, column by column
+    const int mask = code & 31;
+    double M[5][5], y[5];
+    gram5(mask, mu, M);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) y[i] = ((mask >> i) & 1) && i == 4 ? fz : 0.0;
+    // columns of (G G^T)^{-1} G, one solve per coordinate, and the point c
+    double Gi[5][3];
+#pragma unroll
     for (int col = 0; col < 3; ++col) {
-      double M[3][3], r[3];
-      for (int i = 0; i < m; ++i) {
-        for (int j = 0; j < m; ++j) M[i][j] = GG[i][j];
-        r[i] = G[i][col];
+      double Mc[5][5], r[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) Mc[i][j] = M[i][j];
+        double gi[3];
+        force_row(i, mu, gi);
+        r[i] = ((mask >> i) & 1) ? gi[col] : 0.0;
       }
-      small_solve(M, r, m);
-      for (int i = 0; i < m; ++i) Gi[i][col] = r[i];
+      solve5(Mc, r);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) Gi[i][col] = r[i];
     }
-    {
-      double M[3][3];
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) M[i][j] = GG[i][j];
-      small_solve(M, y, m);
-    }
+    solve5(M, y);
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       double ca = 0.0;
-      for (int i = 0; i < m; ++i) ca += G[i][a] * y[i];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        double gi[3];
+        force_row(i, mu, gi);
+        if ((mask >> i) & 1) ca += gi[a] * y[i];
+      }
       c[a] = ca;
+#pragma unroll
       for (int b = 0; b < 3; ++b) {
         double t = (a == b) ? 1.0 : 0.0;
-        for (int i = 0; i < m; ++i) t -= G[i][a] * Gi[i][b];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          double gi[3];
+          force_row(i, mu, gi);
+          if ((mask >> i) & 1) t -= gi[a] * Gi[i][b];
+        }
         P[a][b] = t;
       }
     }
   }
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (code >> (8 + a) & 1) c[3 + a] = tm;
     else if (code >> (11 + a) & 1) c[3 + a] = -tm;
@@ -184,8 +223,8 @@ struct Sh {
 
 __device__ inline void load_AB(const Ctx& C, Sh& sh, int k) {
   const int lane = threadIdx.x;
-  const float* A = C.p.A + (C.s0 + k) * NX * NX;
-  const float* B = C.p.B + (C.s0 + k) * NX * NU;
+  const float* A = C.A + k * NX * NX;
+  const float* B = C.B + k * NX * NU;
   for (int i = lane; i < NX * NX; i += W64) sh.A[i] = (double)A[i];
   for (int i = lane; i < NX * NU; i += W64) sh.B[i] = (double)B[i];
 }
@@ -198,7 +237,7 @@ __device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
   __syncthreads();
   if (lane < 2) {
     const int i = lane;
-    const bool st = C.p.contact[(C.s0 + k) * 2 + i] != 0;
+    const bool st = C.contact[k * 2 + i] != 0;
     if (st) {
       if (newton) {
         for (int a = 0; a < 6; ++a) {
@@ -207,7 +246,7 @@ __device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
         }
       } else {
         double P6[6][6], c6[6];
-        face_affine(C.ws.faces[(C.s0 + k) * 2 + i], C.mu, C.fz, C.tm, P6, c6);
+        face_affine(C.faces[k * 2 + i], C.mu, C.fz, C.tm, P6, c6);
         for (int a = 0; a < 6; ++a) {
           sh.c[6 * i + a] = c6[a];
           for (int bb = 0; bb < 6; ++bb) sh.P[(6 * i + a) * NU + 6 * i + bb] = P6[a][bb];
@@ -244,13 +283,13 @@ __device__ void stage_rp(const Ctx& C, Sh& sh, int k, Mode mode) {
   __syncthreads();
   if (mode == Mode::NEWTON && lane < 2) {
     const int i = lane;
-    if (C.p.contact[(C.s0 + k) * 2 + i]) {
-      const size_t rb = ((C.s0 + k) * 2 + i) * NROW;
+    if (C.contact[k * 2 + i]) {
+      const size_t rb = (k * 2 + i) * NROW;
       for (int r = 0; r < NROW; ++r) {
         double g[6], h;
         wrench_row(r, C.mu, C.fz, C.tm, g, &h);
         const double sc = (r < 5) ? C.mg : C.tm;
-        const double w = C.ws.rz[rb + r] / C.ws.rs[rb + r] / (sc * sc);
+        const double w = C.rz[rb + r] / C.rs[rb + r] / (sc * sc);
         for (int a = 0; a < 6; ++a)
           for (int bb = 0; bb < 6; ++bb)
             sh.Rp[(6 * i + a) * NU + 6 * i + bb] += w * g[a] * g[bb];
@@ -265,24 +304,24 @@ __device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode, const double* 
   const int lane = threadIdx.x;
   if (lane < NU) {
     const int j = lane;
-    const double ur = C.p.u_ref ? (double)C.p.u_ref[(C.s0 + k) * NU + j] : 0.0;
+    const double ur = C.u_ref ? (double)C.u_ref[k * NU + j] : 0.0;
     double r;
     if (mode == Mode::EQ) {
       r = -C.R[j] * ur;
     } else {
-      r = C.R[j] * (C.ws.ru[(C.s0 + k) * NU + j] - ur);
+      r = C.R[j] * (C.ru[k * NU + j] - ur);
       const int i = j / 6, a = j % 6;
-      if (C.p.contact[(C.s0 + k) * 2 + i]) {
-        const size_t rb = ((C.s0 + k) * 2 + i) * NROW;
+      if (C.contact[k * 2 + i]) {
+        const size_t rb = (k * 2 + i) * NROW;
         for (int row = 0; row < NROW; ++row) {
           double g[6], h;
           wrench_row(row, C.mu, C.fz, C.tm, g, &h);
           if (g[a] == 0.0) continue;
           const double sc = (row < 5) ? C.mg : C.tm;
-          const double s = C.ws.rs[rb + row], z = C.ws.rz[rb + row];
+          const double s = C.rs[rb + row], z = C.rz[rb + row];
           // rp = G~ u + s - h~ ; coefficient z + (-rc + z rp) / s
           double gu = 0.0;
-          for (int t = 0; t < 6; ++t) gu += g[t] * C.ws.ru[(C.s0 + k) * NU + 6 * i + t];
+          for (int t = 0; t < 6; ++t) gu += g[t] * C.ru[k * NU + 6 * i + t];
           const double rp = (gu - h) / sc + s;
           const double coef = z + (-rcvec[rb + row] + z * rp) / s;
           r += g[a] / sc * coef;
@@ -300,16 +339,16 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
   if (lane < NX) sh.s[lane] = 0.0;
   __syncthreads();
   for (int k = N - 1; k >= 0; --k) {
-    const size_t st = C.s0 + k;
+    const int st = k;
     load_AB(C, sh, k);
     load_face(C, sh, k, mode == Mode::NEWTON);
     if (factor) stage_rp(C, sh, k, mode);
     stage_rho(C, sh, k, mode, rcvec);
     if (lane < NX) {
-      const double r = (double)C.p.x_ref[st * NX + lane];
+      const double r = (double)C.x_ref[st * NX + lane];
       double q;
       if (mode == Mode::EQ) q = -C.Q[lane] * r;
-      else q = C.Q[lane] * (C.ws.rx[((size_t)C.b * (C.n + 1) + k + 1) * NX + lane] - r);
+      else q = C.Q[lane] * (C.rx[(k + 1) * NX + lane] - r);
       sh.om[lane] = q + sh.s[lane];
     }
     __syncthreads();
@@ -325,7 +364,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       double acc = 0.0;
       if (mode == Mode::EQ) {
         for (int l = 0; l < NU; ++l) acc += sh.B[lane * NU + l] * sh.c[l];
-        if (C.p.e) acc += (double)C.p.e[st * NX + lane];
+        if (C.e) acc += (double)C.e[st * NX + lane];
       }
       sh.d[lane] = acc;
     }
@@ -393,7 +432,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
         }
       }
     } else {
-      for (int e = lane; e < NU * NX; e += W64) sh.Hwx[e] = C.ws.rHwx[st * NU * NX + e];
+      for (int e = lane; e < NU * NX; e += W64) sh.Hwx[e] = C.rHwx[st * NU * NX + e];
     }
     if (lane < NU) {
       // hw = P (R' c + rho) + Bp^T (W d + omega)
@@ -435,24 +474,24 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       if (lane < NU) sh.kap[lane] = -sh.G[lane * GJW + NU + NX];
       // keep H^{-1} and Hwx for a second right-hand side of the same matrix
       if (mode == Mode::NEWTON) {
-        double* Hi = C.ws.rL + st * NU * NU;
+        double* Hi = C.rL + st * NU * NU;
         for (int e = lane; e < NU * NU; e += W64)
           Hi[e] = sh.G[(e / NU) * GJW + NU + NX + 1 + e % NU];
-        for (int e = lane; e < NU * NX; e += W64) C.ws.rHwx[st * NU * NX + e] = sh.Hwx[e];
+        for (int e = lane; e < NU * NX; e += W64) C.rHwx[st * NU * NX + e] = sh.Hwx[e];
       }
     } else {
-      const double* Hi = C.ws.rL + st * NU * NU;
+      const double* Hi = C.rL + st * NU * NU;
       if (lane < NU) {
         double acc = 0.0;
         for (int l = 0; l < NU; ++l) acc += Hi[lane * NU + l] * sh.hw[l];
         sh.kap[lane] = -acc;
       }
-      for (int e = lane; e < NU * NX; e += W64) sh.K[e] = C.ws.rK[st * NU * NX + e];
+      for (int e = lane; e < NU * NX; e += W64) sh.K[e] = C.rK[st * NU * NX + e];
     }
     __syncthreads();
     if (factor)
-      for (int e = lane; e < NU * NX; e += W64) C.ws.rK[st * NU * NX + e] = sh.K[e];
-    if (lane < NU) C.ws.rkap[st * NU + lane] = sh.kap[lane];
+      for (int e = lane; e < NU * NX; e += W64) C.rK[st * NU * NX + e] = sh.K[e];
+    if (lane < NU) C.rkap[st * NU + lane] = sh.kap[lane];
     // S = A^T W A + Hwx^T K ; s = A^T (W d + omega) + Hwx^T kap
     if (factor) {
       // upper triangle of the (symmetric) new S, mirrored below
@@ -483,19 +522,19 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
   }
   // forward rollout
   if (lane < NX) {
-    sh.xv[lane] = (mode == Mode::EQ) ? (double)C.p.x0[(size_t)C.b * NX + lane] : 0.0;
+    sh.xv[lane] = (mode == Mode::EQ) ? (double)C.x0[lane] : 0.0;
   }
   __syncthreads();
-  double* xout = (mode == Mode::EQ) ? C.ws.rx : C.ws.rdx;
-  double* uout = (mode == Mode::EQ) ? C.ws.ru : C.ws.rdu;
-  if (lane < NX) xout[((size_t)C.b * (C.n + 1)) * NX + lane] = sh.xv[lane];
+  double* xout = (mode == Mode::EQ) ? C.rx : C.rdx;
+  double* uout = (mode == Mode::EQ) ? C.ru : C.rdu;
+  if (lane < NX) xout[0 + lane] = sh.xv[lane];
   for (int k = 0; k < N; ++k) {
-    const size_t st = C.s0 + k;
+    const int st = k;
     load_AB(C, sh, k);
     load_face(C, sh, k, mode == Mode::NEWTON);
     if (lane < NU) {
-      double acc = C.ws.rkap[st * NU + lane];
-      for (int l = 0; l < NX; ++l) acc += C.ws.rK[st * NU * NX + lane * NX + l] * sh.xv[l];
+      double acc = C.rkap[st * NU + lane];
+      for (int l = 0; l < NX; ++l) acc += C.rK[st * NU * NX + lane * NX + l] * sh.xv[l];
       sh.wv[lane] = acc;
     }
     __syncthreads();
@@ -510,13 +549,13 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       double acc = 0.0;
       for (int l = 0; l < NX; ++l) acc += sh.A[lane * NX + l] * sh.xv[l];
       for (int l = 0; l < NU; ++l) acc += sh.B[lane * NU + l] * sh.uv[l];
-      if (mode == Mode::EQ && C.p.e) acc += (double)C.p.e[st * NX + lane];
+      if (mode == Mode::EQ && C.e) acc += (double)C.e[st * NX + lane];
       sh.xn[lane] = acc;
     }
     __syncthreads();
     if (lane < NX) {
       sh.xv[lane] = sh.xn[lane];
-      xout[((size_t)C.b * (C.n + 1) + k + 1) * NX + lane] = sh.xn[lane];
+      xout[(k + 1) * NX + lane] = sh.xn[lane];
     }
     __syncthreads();
   }
@@ -527,12 +566,12 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
 __device__ void costates_grad(const Ctx& C, Sh& sh) {
   const int lane = threadIdx.x;
   for (int k = C.N - 1; k >= 0; --k) {
-    const size_t st = C.s0 + k;
+    const int st = k;
     if (lane < NX) {
-      const double x = C.ws.rx[((size_t)C.b * (C.n + 1) + k + 1) * NX + lane];
-      double acc = C.Q[lane] * (x - (double)C.p.x_ref[st * NX + lane]);
+      const double x = C.rx[(k + 1) * NX + lane];
+      double acc = C.Q[lane] * (x - (double)C.x_ref[st * NX + lane]);
       if (k + 1 < C.N) {
-        const float* A1 = C.p.A + (st + 1) * NX * NX;
+        const float* A1 = C.A + (st + 1) * NX * NX;
         for (int l = 0; l < NX; ++l) acc += (double)A1[l * NX + lane] * sh.xn[l];
       }
       sh.om[lane] = acc;
@@ -540,18 +579,18 @@ __device__ void costates_grad(const Ctx& C, Sh& sh) {
     __syncthreads();
     if (lane < NX) {
       sh.xn[lane] = sh.om[lane];
-      C.ws.rlam[st * NX + lane] = sh.om[lane];
+      C.rlam[st * NX + lane] = sh.om[lane];
     }
     __syncthreads();
   }
   for (int e = lane; e < C.N * NU; e += W64) {
     const int k = e / NU, j = e % NU;
-    const size_t st = C.s0 + k;
-    const float* B = C.p.B + st * NX * NU;
-    const double ur = C.p.u_ref ? (double)C.p.u_ref[st * NU + j] : 0.0;
-    double acc = C.R[j] * (C.ws.ru[st * NU + j] - ur);
-    for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + j] * C.ws.rlam[st * NX + l];
-    C.ws.rg[st * NU + j] = acc;
+    const int st = k;
+    const float* B = C.B + st * NX * NU;
+    const double ur = C.u_ref ? (double)C.u_ref[st * NU + j] : 0.0;
+    double acc = C.R[j] * (C.ru[st * NU + j] - ur);
+    for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + j] * C.rlam[st * NX + l];
+    C.rg[st * NU + j] = acc;
   }
   __syncthreads();
 }
@@ -563,70 +602,67 @@ __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
   double r_ineq = 0.0, stat = 0.0, term = 0.0, comp = 0.0, mumax = 0.0, neg = 0.0;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
-    const size_t st = C.s0 + k;
-    const double* u = C.ws.ru + st * NU + 6 * i;
-    const double* g = C.ws.rg + st * NU + 6 * i;
-    double* mu = C.ws.rmu + (st * 2 + i) * NROW;
+    const int st = k;
+    const double* u = C.ru + st * NU + 6 * i;
+    const double* g = C.rg + st * NU + 6 * i;
+    double* mu = C.rmu + (st * 2 + i) * NROW;
     for (int r = 0; r < NROW; ++r) mu[r] = 0.0;
-    if (!C.p.contact[st * 2 + i]) {
+    if (!C.contact[st * 2 + i]) {
       for (int a = 0; a < 6; ++a) r_ineq = fmax(r_ineq, fabs(u[a]) / C.mg);
       continue;
     }
-    const int code = C.ws.faces[st * 2 + i];
+    const int code = C.faces[st * 2 + i];
     for (int a = 0; a < 6; ++a) {
-      const double ur = C.p.u_ref ? (double)C.p.u_ref[st * NU + 6 * i + a] : 0.0;
+      const double ur = C.u_ref ? (double)C.u_ref[st * NU + 6 * i + a] : 0.0;
       const double ru = C.R[6 * i + a] * (u[a] - ur);
       term = fmax(term, fmax(fabs(ru), fabs(g[a] - ru)));
     }
-    // force multipliers
+    // force multipliers: G_A^T mu_A = -g_f on the face's rows (least squares
+    // through the masked Gram system); at the apex the four side rows are
+    // dependent, so take the three-row subset whose multipliers are most
+    // nonnegative (some subset is nonnegative exactly when -g_f lies in the
+    // normal cone of the apex)
     if (face_apex(code)) {
-      double best = -1e300, bm[3] = {0, 0, 0};
-      int bdrop = 0;
+      double best = -1e300, bm[5] = {0, 0, 0, 0, 0};
+#pragma unroll
       for (int drop = 0; drop < 4; ++drop) {
-        double M[3][3], r[3];
-        int m = 0;
-        double rows[3][3];
-        for (int rr = 0; rr < 4; ++rr) {
-          if (rr == drop) continue;
-          double gg[6], hh;
-          wrench_row(rr, C.mu, C.fz, C.tm, gg, &hh);
-          rows[m][0] = gg[0]; rows[m][1] = gg[1]; rows[m][2] = gg[2];
-          ++m;
+        const int mask = 15 & ~(1 << drop);
+        double M[5][5], r[5];
+        gram5(mask, C.mu, M);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          double gi[3];
+          force_row(i, C.mu, gi);
+          r[i] = ((mask >> i) & 1) ? -(gi[0] * g[0] + gi[1] * g[1] + gi[2] * g[2]) : 0.0;
         }
-        // G3^T mu = -g  ->  (G3 G3^T) mu = -G3 g
-        for (int a = 0; a < 3; ++a) {
-          for (int bb = 0; bb < 3; ++bb)
-            M[a][bb] = rows[a][0] * rows[bb][0] + rows[a][1] * rows[bb][1] + rows[a][2] * rows[bb][2];
-          r[a] = -(rows[a][0] * g[0] + rows[a][1] * g[1] + rows[a][2] * g[2]);
+        solve5(M, r);
+        double mn = 1e300;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if ((mask >> i) & 1) mn = fmin(mn, r[i]);
+        if (mn > best) {
+          best = mn;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) bm[i] = ((mask >> i) & 1) ? r[i] : 0.0;
         }
-        small_solve(M, r, 3);
-        const double mn = fmin(r[0], fmin(r[1], r[2]));
-        if (mn > best) { best = mn; bm[0] = r[0]; bm[1] = r[1]; bm[2] = r[2]; bdrop = drop; }
       }
-      int m = 0;
-      for (int rr = 0; rr < 4; ++rr) {
-        if (rr == bdrop) continue;
-        mu[rr] = bm[m++];
-      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mu[i] = bm[i];
     } else {
-      double G[3][3];
-      int idx[3], m = 0;
-      for (int rr = 0; rr < 5; ++rr)
-        if (code >> rr & 1) {
-          double gg[6], hh;
-          wrench_row(rr, C.mu, C.fz, C.tm, gg, &hh);
-          G[m][0] = gg[0]; G[m][1] = gg[1]; G[m][2] = gg[2];
-          idx[m++] = rr;
+      const int mask = code & 31;
+      if (mask) {
+        double M[5][5], r[5];
+        gram5(mask, C.mu, M);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          double gi[3];
+          force_row(i, C.mu, gi);
+          r[i] = ((mask >> i) & 1) ? -(gi[0] * g[0] + gi[1] * g[1] + gi[2] * g[2]) : 0.0;
         }
-      if (m) {
-        double M[3][3], r[3];
-        for (int a = 0; a < m; ++a) {
-          for (int bb = 0; bb < m; ++bb)
-            M[a][bb] = G[a][0] * G[bb][0] + G[a][1] * G[bb][1] + G[a][2] * G[bb][2];
-          r[a] = -(G[a][0] * g[0] + G[a][1] * g[1] + G[a][2] * g[2]);
-        }
-        small_solve(M, r, m);
-        for (int a = 0; a < m; ++a) mu[idx[a]] = r[a];
+        solve5(M, r);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+          if ((mask >> i) & 1) mu[i] = r[i];
       }
     }
     for (int a = 0; a < 3; ++a) {
@@ -656,10 +692,10 @@ __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
   // state-side term norms: |Q (x - r)|, |p|, |A^T p| = |p_k - Q(x_{k+1} - r_k)|
   for (int e = lane; e < C.N * NX; e += W64) {
     const int k = e / NX, j = e % NX;
-    const size_t st = C.s0 + k;
-    const double x = C.ws.rx[((size_t)C.b * (C.n + 1) + k + 1) * NX + j];
-    const double qx = C.Q[j] * (x - (double)C.p.x_ref[st * NX + j]);
-    const double lam = C.ws.rlam[st * NX + j];
+    const int st = k;
+    const double x = C.rx[(k + 1) * NX + j];
+    const double qx = C.Q[j] * (x - (double)C.x_ref[st * NX + j]);
+    const double lam = C.rlam[st * NX + j];
     term = fmax(term, fmax(fabs(qx), fmax(fabs(lam), fabs(lam - qx))));
   }
   r_ineq = wave_max(r_ineq);
@@ -684,14 +720,14 @@ __device__ double dyn_residual(const Ctx& C) {
   double r = 0.0;
   for (int e = lane; e < C.N * NX; e += W64) {
     const int k = e / NX, i = e % NX;
-    const size_t st = C.s0 + k;
-    const double* x = C.ws.rx + ((size_t)C.b * (C.n + 1) + k) * NX;
-    const float* A = C.p.A + st * NX * NX + i * NX;
-    const float* B = C.p.B + st * NX * NU + i * NU;
+    const int st = k;
+    const double* x = C.rx + k * NX;
+    const float* A = C.A + st * NX * NX + i * NX;
+    const float* B = C.B + st * NX * NU + i * NU;
     double ax = 0.0, bu = 0.0;
     for (int l = 0; l < NX; ++l) ax += (double)A[l] * x[l];
-    for (int l = 0; l < NU; ++l) bu += (double)B[l] * C.ws.ru[st * NU + l];
-    const double ee = C.p.e ? (double)C.p.e[st * NX + i] : 0.0;
+    for (int l = 0; l < NU; ++l) bu += (double)B[l] * C.ru[st * NU + l];
+    const double ee = C.e ? (double)C.e[st * NX + i] : 0.0;
     const double d = x[NX + i] - ax - bu - ee;
     const double den = 1.0 + fmax(fabs(x[NX + i]), fmax(fabs(ax), fabs(bu)));
     r = fmax(r, fabs(d) / den);
@@ -706,11 +742,11 @@ __device__ uint64_t pdas_update(const Ctx& C) {
   uint64_t hsh = 0;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
-    const size_t st = C.s0 + k;
+    const int st = k;
     int code = 0;
-    if (C.p.contact[st * 2 + i]) {
-      const double* u = C.ws.ru + st * NU + 6 * i;
-      const double* mu = C.ws.rmu + (st * 2 + i) * NROW;
+    if (C.contact[st * 2 + i]) {
+      const double* u = C.ru + st * NU + 6 * i;
+      const double* mu = C.rmu + (st * 2 + i) * NROW;
       for (int r = 0; r < NROW; ++r) {
         double gg[6], hh;
         wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
@@ -723,7 +759,7 @@ __device__ uint64_t pdas_update(const Ctx& C) {
       for (int a = 0; a < 3; ++a)
         if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
     }
-    C.ws.faces[st * 2 + i] = code;
+    C.faces[st * 2 + i] = code;
     uint64_t v = (uint64_t)(code + 1) * 0x9E3779B97F4A7C15ull ^ ((uint64_t)(e + 1) * 0xC2B2AE3D27D4EB4Full);
     v ^= v >> 29;
     v *= 0xBF58476D1CE4E5B9ull;
@@ -738,9 +774,9 @@ __device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
-    const size_t st = C.s0 + k;
+    const int st = k;
     int code = 0;
-    if (C.p.contact[st * 2 + i]) {
+    if (C.contact[st * 2 + i]) {
       const double* u = u_src + st * NU + 6 * i;
       for (int r = 0; r < NROW; ++r) {
         double gg[6], hh;
@@ -752,7 +788,7 @@ __device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
       }
       if (face_apex(code)) code = (code & ~31) | FACE_APEX;
     }
-    C.ws.faces[st * 2 + i] = code;
+    C.faces[st * 2 + i] = code;
   }
   __syncthreads();
 }
@@ -775,41 +811,43 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
   // number of stance rows
   int mloc = 0;
   for (int e = lane; e < N * 2; e += W64)
-    if (C.p.contact[(C.s0 + (e >> 1)) * 2 + (e & 1)]) mloc += NROW;
+    if (C.contact[(e >> 1) * 2 + (e & 1)]) mloc += NROW;
   const double m = wave_sum((double)mloc);
   if (m == 0.0) return 0;
   // initial point: the current ru (feasible ADMM point), its rollout in rx
   for (int e = lane; e < N * 2 * NROW; e += W64) {
     const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-    const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
-    if (!C.p.contact[st * 2 + i]) continue;
+    const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
+    if (!C.contact[st * 2 + i]) continue;
     double gg[6], hh;
     wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
     double gu = 0.0;
-    for (int a = 0; a < 6; ++a) gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
+    for (int a = 0; a < 6; ++a) gu += gg[a] * C.ru[st * NU + 6 * i + a];
     const double sc = (r < 5) ? C.mg : C.tm;
-    C.ws.rs[rb] = fmax((hh - gu) / sc, 1.0);
-    C.ws.rz[rb] = 1.0;
+    C.rs[rb] = fmax((hh - gu) / sc, 1.0);
+    C.rz[rb] = 1.0;
   }
   __syncthreads();
-  double* rc = C.ws.rdz;   // reuse: complementarity target, then dz
+  double* rc = C.rdz;   // reuse: complementarity target, then dz
   int it = 0;
   for (; it < maxit; ++it) {
     // residuals rp and mu
     double smz = 0.0, rpn = 0.0;
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
-      if (!C.p.contact[st * 2 + i]) continue;
+      const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
+      if (!C.contact[st * 2 + i]) continue;
       double gg[6], hh;
       wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
       double gu = 0.0;
-      for (int a = 0; a < 6; ++a) gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
+      for (int a = 0; a < 6; ++a) gu += gg[a] * C.ru[st * NU + 6 * i + a];
       const double sc = (r < 5) ? C.mg : C.tm;
-      const double rp = (gu - hh) / sc + C.ws.rs[rb];
-      smz += C.ws.rs[rb] * C.ws.rz[rb];
+      const double rp = (gu - hh) / sc + C.rs[rb];
+      smz += C.rs[rb] * C.rz[rb];
       rpn = fmax(rpn, fabs(rp));
-      rc[rb] = C.ws.rs[rb] * C.ws.rz[rb];     // affine (predictor) target
+      rc[rb] = C.rs[rb] * C.rz[rb];     // affine (predictor) target
     }
     const double muv = wave_sum(smz) / m;
     rpn = wave_max(rpn);
@@ -820,22 +858,23 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     double amax_s = 1.0, amax_z = 1.0;
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
-      if (!C.p.contact[st * 2 + i]) continue;
+      const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
+      if (!C.contact[st * 2 + i]) continue;
       double gg[6], hh;
       wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
       double gu = 0.0, gdu = 0.0;
       for (int a = 0; a < 6; ++a) {
-        gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
-        gdu += gg[a] * C.ws.rdu[st * NU + 6 * i + a];
+        gu += gg[a] * C.ru[st * NU + 6 * i + a];
+        gdu += gg[a] * C.rdu[st * NU + 6 * i + a];
       }
       const double sc = (r < 5) ? C.mg : C.tm;
-      const double s = C.ws.rs[rb], z = C.ws.rz[rb];
+      const double s = C.rs[rb], z = C.rz[rb];
       const double rp = (gu - hh) / sc + s;
       const double ds = -rp - gdu / sc;
       const double dz = (-s * z - z * ds) / s;
-      C.ws.rds[rb] = ds;
-      C.ws.rmu[rb] = dz;     // affine dz kept in rmu scratch
+      C.rds[rb] = ds;
+      C.rmu[rb] = dz;     // affine dz kept in rmu scratch
       if (ds < 0) amax_s = fmin(amax_s, -s / ds);
       if (dz < 0) amax_z = fmin(amax_z, -z / dz);
     }
@@ -843,18 +882,20 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     double sm = 0.0;
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1;
-      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + e % NROW;
-      if (!C.p.contact[st * 2 + i]) continue;
-      sm += (C.ws.rs[rb] + aa * C.ws.rds[rb]) * (C.ws.rz[rb] + aa * C.ws.rmu[rb]);
+      const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + e % NROW;
+      if (!C.contact[st * 2 + i]) continue;
+      sm += (C.rs[rb] + aa * C.rds[rb]) * (C.rz[rb] + aa * C.rmu[rb]);
     }
     const double mu_aff = wave_sum(sm) / m;
     const double sigma = pow(mu_aff / muv, 3.0);
     __syncthreads();
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1;
-      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + e % NROW;
-      if (!C.p.contact[st * 2 + i]) continue;
-      rc[rb] = C.ws.rs[rb] * C.ws.rz[rb] + C.ws.rds[rb] * C.ws.rmu[rb] - sigma * muv;
+      const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + e % NROW;
+      if (!C.contact[st * 2 + i]) continue;
+      rc[rb] = C.rs[rb] * C.rz[rb] + C.rds[rb] * C.rmu[rb] - sigma * muv;
     }
     __syncthreads();
     // corrector: same matrix, new right-hand side
@@ -863,22 +904,23 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     amax_z = 1.0;
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + r;
-      if (!C.p.contact[st * 2 + i]) continue;
+      const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
+      if (!C.contact[st * 2 + i]) continue;
       double gg[6], hh;
       wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
       double gu = 0.0, gdu = 0.0;
       for (int a = 0; a < 6; ++a) {
-        gu += gg[a] * C.ws.ru[st * NU + 6 * i + a];
-        gdu += gg[a] * C.ws.rdu[st * NU + 6 * i + a];
+        gu += gg[a] * C.ru[st * NU + 6 * i + a];
+        gdu += gg[a] * C.rdu[st * NU + 6 * i + a];
       }
       const double sc = (r < 5) ? C.mg : C.tm;
-      const double s = C.ws.rs[rb], z = C.ws.rz[rb];
+      const double s = C.rs[rb], z = C.rz[rb];
       const double rp = (gu - hh) / sc + s;
       const double ds = -rp - gdu / sc;
       const double dz = (-rc[rb] - z * ds) / s;
-      C.ws.rds[rb] = ds;
-      C.ws.rmu[rb] = dz;
+      C.rds[rb] = ds;
+      C.rmu[rb] = dz;
       if (ds < 0) amax_s = fmin(amax_s, -s / ds);
       if (dz < 0) amax_z = fmin(amax_z, -z / dz);
     }
@@ -886,30 +928,31 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     __syncthreads();
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1;
-      const size_t st = C.s0 + k, rb = (st * 2 + i) * NROW + e % NROW;
-      if (!C.p.contact[st * 2 + i]) continue;
-      C.ws.rs[rb] += a * C.ws.rds[rb];
-      C.ws.rz[rb] += a * C.ws.rmu[rb];
+      const int st = k;
+      const size_t rb = ((size_t)st * 2 + i) * NROW + e % NROW;
+      if (!C.contact[st * 2 + i]) continue;
+      C.rs[rb] += a * C.rds[rb];
+      C.rz[rb] += a * C.rmu[rb];
     }
-    for (int e = lane; e < N * NU; e += W64) C.ws.ru[C.s0 * NU + e] += a * C.ws.rdu[C.s0 * NU + e];
+    for (int e = lane; e < N * NU; e += W64) C.ru[e] += a * C.rdu[e];
     for (int e = lane; e < (N + 1) * NX; e += W64)
-      C.ws.rx[(size_t)C.b * (C.n + 1) * NX + e] += a * C.ws.rdx[(size_t)C.b * (C.n + 1) * NX + e];
+      C.rx[e] += a * C.rdx[e];
     __syncthreads();
   }
   // faces from z > s
   for (int e = lane; e < N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
-    const size_t st = C.s0 + k;
+    const int st = k;
     int code = 0;
-    if (C.p.contact[st * 2 + i]) {
+    if (C.contact[st * 2 + i]) {
       const size_t rb = (st * 2 + i) * NROW;
       for (int r = 0; r < NROW; ++r)
-        if (C.ws.rz[rb + r] > C.ws.rs[rb + r]) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
+        if (C.rz[rb + r] > C.rs[rb + r]) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
       if (face_apex(code)) code = (code & ~31) | FACE_APEX;
       for (int a = 0; a < 3; ++a)
         if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
     }
-    C.ws.faces[st * 2 + i] = code;
+    C.faces[st * 2 + i] = code;
   }
   __syncthreads();
   return it;
@@ -936,6 +979,41 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int*
   return false;
 }
 
+__device__ void rollout_ru(const Ctx& C, Sh& sh) {
+  // x = rollout of ru from x0, in FP64, into rx
+  const int lane = threadIdx.x;
+  if (lane < NX) sh.xv[lane] = (double)C.x0[lane];
+  __syncthreads();
+  if (lane < NX) C.rx[lane] = sh.xv[lane];
+  for (int k = 0; k < C.N; ++k) {
+    if (lane < NX) {
+      double acc = C.e ? (double)C.e[k * NX + lane] : 0.0;
+      for (int l = 0; l < NX; ++l) acc += (double)C.A[k * NX * NX + lane * NX + l] * sh.xv[l];
+      for (int l = 0; l < NU; ++l) acc += (double)C.B[k * NX * NU + lane * NU + l] * C.ru[k * NU + l];
+      sh.xn[lane] = acc;
+    }
+    __syncthreads();
+    if (lane < NX) {
+      sh.xv[lane] = sh.xn[lane];
+      C.rx[(k + 1) * NX + lane] = sh.xn[lane];
+    }
+    __syncthreads();
+  }
+}
+
+// The ADMM's input iterate, unscaled, into ru (swing inputs exactly 0).
+__device__ void admm_point(const Ctx& C, const float* zsrc, const float* sf, float tsc) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < C.N * NU; e += W64) {
+    const int k = e / NU, j = e % NU;
+    const double sc = (j % 6 < 3) ? (double)sf[k] : (double)tsc;
+    double v = (double)zsrc[((size_t)k * NSTATE) * NL + NX + j] * sc;
+    if (!C.contact[k * 2 + j / 6]) v = 0.0;
+    C.ru[k * NU + j] = v;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, float* out_u,
                                                     float* out_x, float* out_res,
                                                     int32_t* out_iters, int32_t* out_status,
@@ -943,23 +1021,53 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
                                                     int pass_a, int ipm_max, int pass_c,
                                                     double tol) {
   __shared__ Sh sh;
+  // the problem context lives in LDS: its pointers are loaded where they are
+  // used instead of being held in registers across the whole kernel
+  __shared__ Ctx C;
   const int lane = threadIdx.x;
-  Ctx C;
-  C.p = p;
-  C.ws = ws;
+  if (lane == 0) {
   C.b = blockIdx.x;
   C.n = p.n_max;
   C.N = horizon(p, C.b);
-  C.s0 = (size_t)C.b * C.n;
+  const size_t s0 = (size_t)C.b * C.n;
   C.mu = p.mu[C.b];
   C.fz = p.fz_max[C.b];
   C.tm = p.tau_max[C.b];
   C.mg = weight_of(p, C.b);
-  if (lane < NX) sh.Qd[lane] = p.Q[(size_t)C.b * NX + lane];
-  if (lane < NU) sh.Rd[lane] = p.R[(size_t)C.b * NU + lane];
-  __syncthreads();
   C.Q = sh.Qd;
   C.R = sh.Rd;
+  C.A = p.A + s0 * NX * NX;
+  C.B = p.B + s0 * NX * NU;
+  C.e = p.e ? p.e + s0 * NX : nullptr;
+  C.x_ref = p.x_ref + s0 * NX;
+  C.u_ref = p.u_ref ? p.u_ref + s0 * NU : nullptr;
+  C.x0 = p.x0 + (size_t)C.b * NX;
+  C.contact = p.contact + s0 * 2;
+  {
+    const int n = C.n;
+    double* blk = ws.rblk + (size_t)C.b * refine_block_doubles(n);
+    C.rK = blk;                       blk += (size_t)n * NU * NX;
+    C.rkap = blk;                     blk += (size_t)n * NU;
+    C.rL = blk;                       blk += (size_t)n * NU * NU;
+    C.rHwx = blk;                     blk += (size_t)n * NU * NX;
+    C.ru = blk;                       blk += (size_t)n * NU;
+    C.rx = blk;                       blk += (size_t)(n + 1) * NX;
+    C.rlam = blk;                     blk += (size_t)n * NX;
+    C.rg = blk;                       blk += (size_t)n * NU;
+    C.rmu = blk;                      blk += (size_t)n * 2 * NROW;
+    C.rs = blk;                       blk += (size_t)n * 2 * NROW;
+    C.rz = blk;                       blk += (size_t)n * 2 * NROW;
+    C.rds = blk;                      blk += (size_t)n * 2 * NROW;
+    C.rdz = blk;                      blk += (size_t)n * 2 * NROW;
+    C.rdu = blk;                      blk += (size_t)n * NU;
+    C.rdx = blk;
+    C.faces = ws.faces + s0 * 2;
+  }
+  }
+  if (lane < NX) sh.Qd[lane] = p.Q[(size_t)blockIdx.x * NX + lane];
+  if (lane < NU) sh.Rd[lane] = p.R[(size_t)blockIdx.x * NU + lane];
+  __syncthreads();
+  const size_t s0 = (size_t)blockIdx.x * p.n_max;
   const int N = C.N;
 
   // input checks: bounds, then finiteness of this problem's data
@@ -970,13 +1078,13 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
   for (int j = 0; j < NU; ++j) bad |= !(C.R[j] > 0.0);
   int nonfinite = 0;
   if (!bad) {
-    for (int e = lane; e < N * NX * NX; e += W64) nonfinite |= !isfinite(p.A[C.s0 * NX * NX + e]);
-    for (int e = lane; e < N * NX * NU; e += W64) nonfinite |= !isfinite(p.B[C.s0 * NX * NU + e]);
+    for (int e = lane; e < N * NX * NX; e += W64) nonfinite |= !isfinite(C.A[e]);
+    for (int e = lane; e < N * NX * NU; e += W64) nonfinite |= !isfinite(C.B[e]);
     for (int e = lane; e < N * NX; e += W64) {
-      nonfinite |= !isfinite(p.x_ref[C.s0 * NX + e]);
-      if (p.e) nonfinite |= !isfinite(p.e[C.s0 * NX + e]);
+      nonfinite |= !isfinite(C.x_ref[e]);
+      if (C.e) nonfinite |= !isfinite(C.e[e]);
     }
-    if (lane < NX) nonfinite |= !isfinite(p.x0[(size_t)C.b * NX + lane]);
+    if (lane < NX) nonfinite |= !isfinite(C.x0[lane]);
   }
   nonfinite = wave_max((double)nonfinite) > 0.0;
   const size_t ux = (size_t)C.b * C.n * NU, xx = (size_t)C.b * (C.n + 1) * NX;
@@ -991,81 +1099,30 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
     return;
   }
 
-  // ADMM inputs (unscaled) into ru, rollout into rx
-  const float* zsrc = accel ? ws.cur : ws.hat;
-  for (int e = lane; e < N * NU; e += W64) {
-    const int k = e / NU, j = e % NU;
-    const size_t st = C.s0 + k;
-    const double sc = (j % 6 < 3) ? (double)ws.sf[st] : (double)ws.tsc[C.b];
-    double v = (double)zsrc[(st * NSTATE) * NL + NX + j] * sc;
-    if (!p.contact[st * 2 + j / 6]) v = 0.0;
-    ws.ru[st * NU + j] = v;
-  }
-  __syncthreads();
+  const float* zsrc = (accel ? ws.cur : ws.hat) + s0 * NSTATE * NL;
+  const float* sf = ws.sf + s0;
+  const float tsc = ws.tsc[C.b];
+  admm_point(C, zsrc, sf, tsc);
 
   double res[PINMPC_NRES] = {0, 0, 0, 0, 0};
   double kkt = 1e300;
   int passes = 0;
   bool ok = false;
   if (refine) {
-    faces_from_u(C, ws.ru, 1e-5);
+    faces_from_u(C, C.ru, 1e-5);
     ok = active_set_loop(C, sh, pass_a, tol, &passes, res, &kkt);
     if (!ok && ipm_max > 0) {
-      // interior point from the ADMM point (re-derived: ru was overwritten)
-      for (int e = lane; e < N * NU; e += W64) {
-        const int k = e / NU, j = e % NU;
-        const size_t st = C.s0 + k;
-        const double sc = (j % 6 < 3) ? (double)ws.sf[st] : (double)ws.tsc[C.b];
-        double v = (double)zsrc[(st * NSTATE) * NL + NX + j] * sc;
-        if (!p.contact[st * 2 + j / 6]) v = 0.0;
-        ws.ru[st * NU + j] = v;
-      }
-      __syncthreads();
-      // rollout of the start point
-      if (lane < NX) sh.xv[lane] = (double)p.x0[(size_t)C.b * NX + lane];
-      __syncthreads();
-      if (lane < NX) ws.rx[xx + lane] = sh.xv[lane];
-      for (int k = 0; k < N; ++k) {
-        const size_t st = C.s0 + k;
-        if (lane < NX) {
-          double acc = p.e ? (double)p.e[st * NX + lane] : 0.0;
-          for (int l = 0; l < NX; ++l) acc += (double)p.A[st * NX * NX + lane * NX + l] * sh.xv[l];
-          for (int l = 0; l < NU; ++l) acc += (double)p.B[st * NX * NU + lane * NU + l] * ws.ru[st * NU + l];
-          sh.xn[lane] = acc;
-        }
-        __syncthreads();
-        if (lane < NX) {
-          sh.xv[lane] = sh.xn[lane];
-          ws.rx[xx + (k + 1) * NX + lane] = sh.xn[lane];
-        }
-        __syncthreads();
-      }
+      // interior point from the ADMM point (ru was overwritten by the passes)
+      admm_point(C, zsrc, sf, tsc);
+      rollout_ru(C, sh);
       const int its = ipm(C, sh, ipm_max);
       passes += its;
       ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
     }
   } else {
-    // ADMM point as is: rollout and residuals with faces from slack
-    faces_from_u(C, ws.ru, 1e-5);
-    // rollout
-    if (lane < NX) sh.xv[lane] = (double)p.x0[(size_t)C.b * NX + lane];
-    __syncthreads();
-    if (lane < NX) ws.rx[xx + lane] = sh.xv[lane];
-    for (int k = 0; k < N; ++k) {
-      const size_t st = C.s0 + k;
-      if (lane < NX) {
-        double acc = p.e ? (double)p.e[st * NX + lane] : 0.0;
-        for (int l = 0; l < NX; ++l) acc += (double)p.A[st * NX * NX + lane * NX + l] * sh.xv[l];
-        for (int l = 0; l < NU; ++l) acc += (double)p.B[st * NX * NU + lane * NU + l] * ws.ru[st * NU + l];
-        sh.xn[lane] = acc;
-      }
-      __syncthreads();
-      if (lane < NX) {
-        sh.xv[lane] = sh.xn[lane];
-        ws.rx[xx + (k + 1) * NX + lane] = sh.xn[lane];
-      }
-      __syncthreads();
-    }
+    // the ADMM point as it is: rollout, faces from slack, residuals
+    faces_from_u(C, C.ru, 1e-5);
+    rollout_ru(C, sh);
     costates_grad(C, sh);
     kkt = multipliers_kkt(C, res);
     res[0] = dyn_residual(C);
@@ -1073,15 +1130,18 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
 
   // outputs
   for (int e = lane; e < C.n * NU; e += W64)
-    out_u[ux + e] = (e < N * NU) ? (float)ws.ru[C.s0 * NU + e] : 0.f;
+    out_u[ux + e] = (e < N * NU) ? (float)C.ru[e] : 0.f;
   for (int e = lane; e < (C.n + 1) * NX; e += W64)
-    out_x[xx + e] = (e < (N + 1) * NX) ? (float)ws.rx[xx + e] : 0.f;
+    out_x[xx + e] = (e < (N + 1) * NX) ? (float)C.rx[e] : 0.f;
   if (lane == 0) {
     if (out_status)
       out_status[C.b] = refine ? (ok ? PINMPC_ST_OK : PINMPC_ST_UNPOLISHED) : PINMPC_ST_MAXITER;
     if (out_iters) out_iters[C.b] = admm_iters + passes;
   }
-  if (out_res && lane < PINMPC_NRES) out_res[(size_t)C.b * PINMPC_NRES + lane] = (float)res[lane];
+  if (out_res) {
+    for (int i = 0; i < PINMPC_NRES; ++i)
+      if (lane == i) out_res[(size_t)C.b * PINMPC_NRES + i] = (float)res[i];
+  }
 }
 
 }  // namespace
