@@ -36,12 +36,13 @@ def _key(dev, allow_bf16):
 
 
 def candidates(n_max, allow_bf16=False):
-    forms = [0, 1] if n_max <= 40 else [0, -1]
-    iters = [25, 50, 100, 150]
-    rhos = [3.0, 10.0, 30.0]
+    forms = [1] if n_max <= 40 else [-1]
+    iters = [50, 100, 200, 400]
+    rhos = [10.0, 30.0]
+    passes = [3, 5, 8]
     precs = [0, 1] if allow_bf16 else [0]
-    for f, k, r, p in itertools.product(forms, iters, rhos, precs):
-        yield dict(form=f, iters=k, rho=r, precision=p)
+    for f, k, r, pa, p in itertools.product(forms, iters, rhos, passes, precs):
+        yield dict(form=f, iters=k, rho=r, refine_passes=pa, precision=p)
 
 
 def measure(solver, dev, out, bs, settings, reps=3, kkt_bar=1e-5):
