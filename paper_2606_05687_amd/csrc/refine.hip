@@ -42,6 +42,18 @@ struct Ctx {
 
 // ------------------------------------------------------------ small helpers
 
+// The refinement runs one 64-lane wave per workgroup.  LDS operations of a
+// wave execute in issue order, so handing data between the lanes of the wave
+// through LDS needs only a point the compiler does not move memory accesses
+// across (wsync).  Global memory written by one lane and read by another needs
+// the workgroup barrier with its memory fence (gsync); it is used where one
+// phase's global outputs feed the next phase, not inside the stage loops.
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+__device__ inline void gsync() { __syncthreads(); }
+
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
@@ -234,7 +246,7 @@ __device__ inline void load_AB(const Ctx& C, Sh& sh, int k) {
 __device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
   const int lane = threadIdx.x;
   for (int i = lane; i < NU * NU; i += W64) sh.P[i] = 0.0;
-  __syncthreads();
+  wsync();
   if (lane < 2) {
     const int i = lane;
     const bool st = C.contact[k * 2 + i] != 0;
@@ -256,7 +268,7 @@ __device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
       for (int a = 0; a < 6; ++a) sh.c[6 * i + a] = 0.0;
     }
   }
-  __syncthreads();
+  wsync();
 }
 
 // ------------------------------------------------------ Riccati recursion
@@ -280,7 +292,7 @@ __device__ void stage_rp(const Ctx& C, Sh& sh, int k, Mode mode) {
   // R'_k into sh.Rp
   const int lane = threadIdx.x;
   for (int i = lane; i < NU * NU; i += W64) sh.Rp[i] = (i % (NU + 1) == 0) ? C.R[i / NU] : 0.0;
-  __syncthreads();
+  wsync();
   if (mode == Mode::NEWTON && lane < 2) {
     const int i = lane;
     if (C.contact[k * 2 + i]) {
@@ -296,7 +308,7 @@ __device__ void stage_rp(const Ctx& C, Sh& sh, int k, Mode mode) {
       }
     }
   }
-  __syncthreads();
+  wsync();
 }
 
 // Linear input term rho_k of stage k into sh.rho.
@@ -333,11 +345,12 @@ __device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode, const double* 
 }
 
 __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const double* rcvec) {
+  gsync();
   const int lane = threadIdx.x;
   const int N = C.N;
   for (int i = lane; i < NX * NX; i += W64) sh.S[i] = 0.0;
   if (lane < NX) sh.s[lane] = 0.0;
-  __syncthreads();
+  wsync();
   for (int k = N - 1; k >= 0; --k) {
     const int st = k;
     load_AB(C, sh, k);
@@ -351,7 +364,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       else q = C.Q[lane] * (C.rx[(k + 1) * NX + lane] - r);
       sh.om[lane] = q + sh.s[lane];
     }
-    __syncthreads();
+    wsync();
     // Bp = B P ; d = B c + e
     for (int e = lane; e < NX * NU; e += W64) {
       const int i = e / NU, j = e % NU;
@@ -372,7 +385,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       for (int e = lane; e < NX * NX; e += W64)
         sh.W[e] = sh.S[e] + ((e % (NX + 1) == 0) ? C.Q[e / NX] : 0.0);
     }
-    __syncthreads();
+    wsync();
     if (factor) {
       // WA, WBp
       for (int e = lane; e < NX * NX + NX * NU; e += W64) {
@@ -389,7 +402,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
         }
       }
     }
-    __syncthreads();
+    wsync();
     if (lane < NX) {
       // W d + omega (W = Q + S)
       double acc = sh.om[lane];
@@ -409,7 +422,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
         sh.K[e] = acc;   // scratch
       }
     }
-    __syncthreads();
+    wsync();
     if (factor) {
       // H = P R' P + Bp^T W Bp + (I - P) ; Hwx = Bp^T W A, straight into the
       // augmented Gauss-Jordan system [H | Hwx | hw | I]
@@ -448,7 +461,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       sh.hw[lane] = acc;
       if (factor) sh.G[lane * GJW + NU + NX] = acc;
     }
-    __syncthreads();
+    wsync();
     if (factor) {
       // Gauss-Jordan elimination (H is SPD: no pivoting) over all 64 lanes:
       // afterwards G = [I | H^{-1} Hwx | H^{-1} hw | H^{-1}]; the equality
@@ -456,16 +469,16 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       const int gw = (mode == Mode::NEWTON) ? GJW : NU + NX + 1;
       for (int j = 0; j < NU; ++j) {
         const double piv = sh.G[j * GJW + j];
-        __syncthreads();
+        wsync();
         for (int c = j + lane; c < gw; c += W64) sh.G[j * GJW + c] /= piv;
-        __syncthreads();
+        wsync();
         if (lane < NU) sh.fac[lane] = sh.G[lane * GJW + j];
-        __syncthreads();
+        wsync();
         for (int e = lane; e < NU * (gw - j - 1); e += W64) {
           const int r = e / (gw - j - 1), c = j + 1 + e % (gw - j - 1);
           if (r != j) sh.G[r * GJW + c] -= sh.fac[r] * sh.G[j * GJW + c];
         }
-        __syncthreads();
+        wsync();
       }
       for (int e = lane; e < NU * NX; e += W64) {
         const int i = e / NX, j = e % NX;
@@ -488,7 +501,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       }
       for (int e = lane; e < NU * NX; e += W64) sh.K[e] = C.rK[st * NU * NX + e];
     }
-    __syncthreads();
+    wsync();
     if (factor)
       for (int e = lane; e < NU * NX; e += W64) C.rK[st * NU * NX + e] = sh.K[e];
     if (lane < NU) C.rkap[st * NU + lane] = sh.kap[lane];
@@ -511,20 +524,21 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       for (int l = 0; l < NU; ++l) acc += sh.Hwx[l * NX + lane] * sh.kap[l];
       sh.xn[lane] = acc;
     }
-    __syncthreads();
+    wsync();
     if (factor)
       for (int e = lane; e < NX * NX; e += W64) {
         const int i = e / NX, j = e % NX;
         sh.S[e] = (i <= j) ? sh.W[i * NX + j] : sh.W[j * NX + i];
       }
     if (lane < NX) sh.s[lane] = sh.xn[lane];
-    __syncthreads();
+    wsync();
   }
-  // forward rollout
+  // forward rollout (reads the gains written by other lanes above)
+  gsync();
   if (lane < NX) {
     sh.xv[lane] = (mode == Mode::EQ) ? (double)C.x0[lane] : 0.0;
   }
-  __syncthreads();
+  wsync();
   double* xout = (mode == Mode::EQ) ? C.rx : C.rdx;
   double* uout = (mode == Mode::EQ) ? C.ru : C.rdu;
   if (lane < NX) xout[0 + lane] = sh.xv[lane];
@@ -537,14 +551,14 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       for (int l = 0; l < NX; ++l) acc += C.rK[st * NU * NX + lane * NX + l] * sh.xv[l];
       sh.wv[lane] = acc;
     }
-    __syncthreads();
+    wsync();
     if (lane < NU) {
       double acc = sh.c[lane];
       for (int l = 0; l < NU; ++l) acc += sh.P[lane * NU + l] * sh.wv[l];
       sh.uv[lane] = acc;
       uout[st * NU + lane] = acc;
     }
-    __syncthreads();
+    wsync();
     if (lane < NX) {
       double acc = 0.0;
       for (int l = 0; l < NX; ++l) acc += sh.A[lane * NX + l] * sh.xv[l];
@@ -552,18 +566,20 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
       if (mode == Mode::EQ && C.e) acc += (double)C.e[st * NX + lane];
       sh.xn[lane] = acc;
     }
-    __syncthreads();
+    wsync();
     if (lane < NX) {
       sh.xv[lane] = sh.xn[lane];
       xout[(k + 1) * NX + lane] = sh.xn[lane];
     }
-    __syncthreads();
+    wsync();
   }
+  gsync();
 }
 
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
 // gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
 __device__ void costates_grad(const Ctx& C, Sh& sh) {
+  gsync();
   const int lane = threadIdx.x;
   for (int k = C.N - 1; k >= 0; --k) {
     const int st = k;
@@ -576,13 +592,14 @@ __device__ void costates_grad(const Ctx& C, Sh& sh) {
       }
       sh.om[lane] = acc;
     }
-    __syncthreads();
+    wsync();
     if (lane < NX) {
       sh.xn[lane] = sh.om[lane];
       C.rlam[st * NX + lane] = sh.om[lane];
     }
-    __syncthreads();
+    wsync();
   }
+  gsync();
   for (int e = lane; e < C.N * NU; e += W64) {
     const int k = e / NU, j = e % NU;
     const int st = k;
@@ -592,12 +609,13 @@ __device__ void costates_grad(const Ctx& C, Sh& sh) {
     for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + j] * C.rlam[st * NX + l];
     C.rg[st * NU + j] = acc;
   }
-  __syncthreads();
+  gsync();
 }
 
 // Row multipliers of each stance contact from its face and the gradient, and
 // the normalised KKT residuals of the current (u, x, p, mu).  Returns KKT.
 __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
+  gsync();
   const int lane = threadIdx.x;
   double r_ineq = 0.0, stat = 0.0, term = 0.0, comp = 0.0, mumax = 0.0, neg = 0.0;
   for (int e = lane; e < C.N * 2; e += W64) {
@@ -716,6 +734,7 @@ __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
 
 // Dynamics residual of the FP64 trajectory (rx, ru).
 __device__ double dyn_residual(const Ctx& C) {
+  gsync();
   const int lane = threadIdx.x;
   double r = 0.0;
   for (int e = lane; e < C.N * NX; e += W64) {
@@ -738,6 +757,7 @@ __device__ double dyn_residual(const Ctx& C) {
 // Primal-dual active-set update of the faces; returns an order-independent
 // hash of the new face set.
 __device__ uint64_t pdas_update(const Ctx& C) {
+  gsync();
   const int lane = threadIdx.x;
   uint64_t hsh = 0;
   for (int e = lane; e < C.N * 2; e += W64) {
@@ -765,12 +785,13 @@ __device__ uint64_t pdas_update(const Ctx& C) {
     v *= 0xBF58476D1CE4E5B9ull;
     hsh ^= v;
   }
-  __syncthreads();
+  wsync();
   return wave_xor(hsh);
 }
 
 // Faces from slack: rows whose slack is below tol * row scale.
 __device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
+  gsync();
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
@@ -790,7 +811,7 @@ __device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
     }
     C.faces[st * 2 + i] = code;
   }
-  __syncthreads();
+  wsync();
 }
 
 // One active-set pass: equality-constrained solve on the current faces,
@@ -806,6 +827,7 @@ __device__ double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
 // Interior-point fallback.  Rows scaled by mg (force rows) and tau_max
 // (moment rows).  Leaves faces from z > s.
 __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
+  gsync();
   const int lane = threadIdx.x;
   const int N = C.N;
   // number of stance rows
@@ -828,7 +850,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     C.rs[rb] = fmax((hh - gu) / sc, 1.0);
     C.rz[rb] = 1.0;
   }
-  __syncthreads();
+  wsync();
   double* rc = C.rdz;   // reuse: complementarity target, then dz
   int it = 0;
   for (; it < maxit; ++it) {
@@ -851,7 +873,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     }
     const double muv = wave_sum(smz) / m;
     rpn = wave_max(rpn);
-    __syncthreads();
+    wsync();
     if (muv <= 1e-10 && rpn <= 1e-9) break;
     // predictor
     riccati(C, sh, Mode::NEWTON, true, rc);
@@ -889,7 +911,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     }
     const double mu_aff = wave_sum(sm) / m;
     const double sigma = pow(mu_aff / muv, 3.0);
-    __syncthreads();
+    wsync();
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1;
       const int st = k;
@@ -897,7 +919,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
       if (!C.contact[st * 2 + i]) continue;
       rc[rb] = C.rs[rb] * C.rz[rb] + C.rds[rb] * C.rmu[rb] - sigma * muv;
     }
-    __syncthreads();
+    wsync();
     // corrector: same matrix, new right-hand side
     riccati(C, sh, Mode::NEWTON, false, rc);
     amax_s = 1.0;
@@ -925,7 +947,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
       if (dz < 0) amax_z = fmin(amax_z, -z / dz);
     }
     const double a = fmin(1.0, 0.99 * fmin(wave_min(amax_s), wave_min(amax_z)));
-    __syncthreads();
+    wsync();
     for (int e = lane; e < N * 2 * NROW; e += W64) {
       const int k = e / (2 * NROW), i = (e / NROW) & 1;
       const int st = k;
@@ -937,9 +959,10 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     for (int e = lane; e < N * NU; e += W64) C.ru[e] += a * C.rdu[e];
     for (int e = lane; e < (N + 1) * NX; e += W64)
       C.rx[e] += a * C.rdx[e];
-    __syncthreads();
+    wsync();
   }
-  // faces from z > s
+  // faces from z > s (rows were updated by other lanes)
+  gsync();
   for (int e = lane; e < N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     const int st = k;
@@ -954,7 +977,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     }
     C.faces[st * 2 + i] = code;
   }
-  __syncthreads();
+  wsync();
   return it;
 }
 
@@ -980,10 +1003,11 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int*
 }
 
 __device__ void rollout_ru(const Ctx& C, Sh& sh) {
+  gsync();
   // x = rollout of ru from x0, in FP64, into rx
   const int lane = threadIdx.x;
   if (lane < NX) sh.xv[lane] = (double)C.x0[lane];
-  __syncthreads();
+  wsync();
   if (lane < NX) C.rx[lane] = sh.xv[lane];
   for (int k = 0; k < C.N; ++k) {
     if (lane < NX) {
@@ -992,17 +1016,18 @@ __device__ void rollout_ru(const Ctx& C, Sh& sh) {
       for (int l = 0; l < NU; ++l) acc += (double)C.B[k * NX * NU + lane * NU + l] * C.ru[k * NU + l];
       sh.xn[lane] = acc;
     }
-    __syncthreads();
+    wsync();
     if (lane < NX) {
       sh.xv[lane] = sh.xn[lane];
       C.rx[(k + 1) * NX + lane] = sh.xn[lane];
     }
-    __syncthreads();
+    wsync();
   }
 }
 
 // The ADMM's input iterate, unscaled, into ru (swing inputs exactly 0).
 __device__ void admm_point(const Ctx& C, const float* zsrc, const float* sf, float tsc) {
+  gsync();
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * NU; e += W64) {
     const int k = e / NU, j = e % NU;
@@ -1011,7 +1036,7 @@ __device__ void admm_point(const Ctx& C, const float* zsrc, const float* sf, flo
     if (!C.contact[k * 2 + j / 6]) v = 0.0;
     C.ru[k * NU + j] = v;
   }
-  __syncthreads();
+  wsync();
 }
 
 __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, float* out_u,
@@ -1066,7 +1091,7 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
   }
   if (lane < NX) sh.Qd[lane] = p.Q[(size_t)blockIdx.x * NX + lane];
   if (lane < NU) sh.Rd[lane] = p.R[(size_t)blockIdx.x * NU + lane];
-  __syncthreads();
+  wsync();
   const size_t s0 = (size_t)blockIdx.x * p.n_max;
   const int N = C.N;
 
@@ -1129,6 +1154,7 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
   }
 
   // outputs
+  gsync();
   for (int e = lane; e < C.n * NU; e += W64)
     out_u[ux + e] = (e < N * NU) ? (float)C.ru[e] : 0.f;
   for (int e = lane; e < (C.n + 1) * NX; e += W64)
