@@ -120,10 +120,11 @@ struct Workspace {
 // feedforward (12), inverse input Hessian (12x12), Hwx (12x13), inputs (12),
 // states ((n+1) x 13), costates (13), gradient (12), row multipliers, slacks,
 // interior-point multipliers and their steps (4 x 22 + 22), step du (12) and
-// dx ((n+1) x 13).
+// dx ((n+1) x 13), face tables (2 x 18) and interior-point row terms
+// (2 x 2 x 11).
 __host__ __device__ constexpr size_t refine_block_doubles(int n) {
   return (size_t)n * (NU * NX + NU + NU * NU + NU * NX + NU + NX + NU + 5 * 2 * NROW + NU) +
-         2 * (size_t)(n + 1) * NX;
+         2 * (size_t)(n + 1) * NX + (size_t)n * 2 * 18 + 2 * (size_t)n * 2 * NROW;
 }
 
 // Face code of one contact: bits 0..4 force rows active

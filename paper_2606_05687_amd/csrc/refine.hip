@@ -37,6 +37,10 @@ struct Ctx {
   const float *A, *B, *e, *x_ref, *u_ref, *x0;
   const uint8_t* contact;
   double *rK, *rkap, *rL, *rHwx, *ru, *rx, *rlam, *rg, *rmu, *rs, *rz, *rds, *rdz, *rdu, *rdx;
+  double* ftab;   // [n][2][18] face tables: force projector 3x3, force offset,
+                  // moment projector diagonal, moment offset
+  double* wrow;   // [n][2][11] interior-point row weights z / (s sc^2)
+  double* crow;   // [n][2][11] interior-point row coefficients of the linear term
   int32_t* faces;
 };
 
@@ -241,34 +245,88 @@ __device__ inline void load_AB(const Ctx& C, Sh& sh, int k) {
   for (int i = lane; i < NX * NU; i += W64) sh.B[i] = (double)B[i];
 }
 
-// Face projector/offset of stage k into sh.P, sh.c (lanes 0 and 1 build one
-// contact each).  newton: projector = stance mask, offset 0.
-__device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
+constexpr int FT = 18;   // doubles per contact in the face table
+
+// Face tables of every (stage, contact) of the problem, computed in parallel
+// over (stage, contact) once per equality-constrained pass.
+__device__ void build_face_table(const Ctx& C) {
   const int lane = threadIdx.x;
-  for (int i = lane; i < NU * NU; i += W64) sh.P[i] = 0.0;
-  wsync();
-  if (lane < 2) {
-    const int i = lane;
-    const bool st = C.contact[k * 2 + i] != 0;
-    if (st) {
-      if (newton) {
-        for (int a = 0; a < 6; ++a) {
-          sh.P[(6 * i + a) * NU + 6 * i + a] = 1.0;
-          sh.c[6 * i + a] = 0.0;
-        }
-      } else {
-        double P6[6][6], c6[6];
-        face_affine(C.faces[k * 2 + i], C.mu, C.fz, C.tm, P6, c6);
-        for (int a = 0; a < 6; ++a) {
-          sh.c[6 * i + a] = c6[a];
-          for (int bb = 0; bb < 6; ++bb) sh.P[(6 * i + a) * NU + 6 * i + bb] = P6[a][bb];
-        }
+  for (int e = lane; e < C.N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
+    double* t = C.ftab + (size_t)e * FT;
+    if (C.contact[k * 2 + i]) {
+      double P6[6][6], c6[6];
+      face_affine(C.faces[k * 2 + i], C.mu, C.fz, C.tm, P6, c6);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t[a * 3 + b] = P6[a][b];
+        t[9 + a] = c6[a];
+        t[12 + a] = P6[3 + a][3 + a];
+        t[15 + a] = c6[3 + a];
       }
     } else {
-      for (int a = 0; a < 6; ++a) sh.c[6 * i + a] = 0.0;
+#pragma unroll
+      for (int a = 0; a < FT; ++a) t[a] = 0.0;
     }
   }
+}
+
+// Face projector/offset of stage k into sh.P, sh.c, filled in parallel from
+// the face table (equality passes) or as the stance mask (Newton steps).
+__device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < NU * NU; e += W64) {
+    const int r = e / NU, c = e % NU;
+    const int i = r / 6;
+    double v = 0.0;
+    if (i == c / 6 && C.contact[k * 2 + i]) {
+      const int a = r % 6, b = c % 6;
+      if (newton) {
+        v = (a == b) ? 1.0 : 0.0;
+      } else {
+        const double* t = C.ftab + ((size_t)k * 2 + i) * FT;
+        if (a < 3 && b < 3) v = t[a * 3 + b];
+        else if (a == b) v = t[12 + a - 3];
+      }
+    }
+    sh.P[e] = v;
+  }
+  if (lane < NU) {
+    const int i = lane / 6, a = lane % 6;
+    double v = 0.0;
+    if (!newton && C.contact[k * 2 + i]) {
+      const double* t = C.ftab + ((size_t)k * 2 + i) * FT;
+      v = (a < 3) ? t[9 + a] : t[15 + a - 3];
+    }
+    sh.c[lane] = v;
+  }
   wsync();
+}
+
+// Interior-point row terms of every stance row, in parallel over rows:
+// the weight z / (s sc^2) of the input Hessian and the coefficient
+// z + (-rc + z rp) / s of the linear term (rows scaled by sc).
+__device__ void build_row_terms(const Ctx& C, const double* rcvec) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < C.N * 2 * NROW; e += W64) {
+    const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
+    if (!C.contact[k * 2 + i]) {
+      C.wrow[e] = 0.0;
+      C.crow[e] = 0.0;
+      continue;
+    }
+    double g[6], h;
+    wrench_row(r, C.mu, C.fz, C.tm, g, &h);
+    const double sc = (r < 5) ? C.mg : C.tm;
+    double gu = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) gu += g[t] * C.ru[k * NU + 6 * i + t];
+    const double s = C.rs[e], z = C.rz[e];
+    const double rp = (gu - h) / sc + s;
+    C.wrow[e] = z / s / (sc * sc);
+    C.crow[e] = (z + (-rcvec[e] + z * rp) / s) / sc;
+  }
 }
 
 // ------------------------------------------------------ Riccati recursion
@@ -289,30 +347,30 @@ __device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
 enum class Mode { EQ, NEWTON };
 
 __device__ void stage_rp(const Ctx& C, Sh& sh, int k, Mode mode) {
-  // R'_k into sh.Rp
+  // R'_k = R (+ sum over stance rows of w_r g_r g_r^T in Newton steps), in
+  // parallel over the entries of the two 6 x 6 contact blocks
   const int lane = threadIdx.x;
-  for (int i = lane; i < NU * NU; i += W64) sh.Rp[i] = (i % (NU + 1) == 0) ? C.R[i / NU] : 0.0;
-  wsync();
-  if (mode == Mode::NEWTON && lane < 2) {
-    const int i = lane;
-    if (C.contact[k * 2 + i]) {
-      const size_t rb = (k * 2 + i) * NROW;
-      for (int r = 0; r < NROW; ++r) {
+  for (int e = lane; e < NU * NU; e += W64) {
+    const int r = e / NU, c = e % NU;
+    double v = (r == c) ? C.R[r] : 0.0;
+    const int i = r / 6;
+    if (mode == Mode::NEWTON && i == c / 6 && C.contact[k * 2 + i]) {
+      const int a = r % 6, b = c % 6;
+      const double* w = C.wrow + ((size_t)k * 2 + i) * NROW;
+#pragma unroll
+      for (int row = 0; row < NROW; ++row) {
         double g[6], h;
-        wrench_row(r, C.mu, C.fz, C.tm, g, &h);
-        const double sc = (r < 5) ? C.mg : C.tm;
-        const double w = C.rz[rb + r] / C.rs[rb + r] / (sc * sc);
-        for (int a = 0; a < 6; ++a)
-          for (int bb = 0; bb < 6; ++bb)
-            sh.Rp[(6 * i + a) * NU + 6 * i + bb] += w * g[a] * g[bb];
+        wrench_row(row, C.mu, C.fz, C.tm, g, &h);
+        v += w[row] * g[a] * g[b];
       }
     }
+    sh.Rp[e] = v;
   }
   wsync();
 }
 
 // Linear input term rho_k of stage k into sh.rho.
-__device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode, const double* rcvec) {
+__device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode) {
   const int lane = threadIdx.x;
   if (lane < NU) {
     const int j = lane;
@@ -324,19 +382,12 @@ __device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode, const double* 
       r = C.R[j] * (C.ru[k * NU + j] - ur);
       const int i = j / 6, a = j % 6;
       if (C.contact[k * 2 + i]) {
-        const size_t rb = (k * 2 + i) * NROW;
+        const double* cr = C.crow + ((size_t)k * 2 + i) * NROW;
+#pragma unroll
         for (int row = 0; row < NROW; ++row) {
           double g[6], h;
           wrench_row(row, C.mu, C.fz, C.tm, g, &h);
-          if (g[a] == 0.0) continue;
-          const double sc = (row < 5) ? C.mg : C.tm;
-          const double s = C.rs[rb + row], z = C.rz[rb + row];
-          // rp = G~ u + s - h~ ; coefficient z + (-rc + z rp) / s
-          double gu = 0.0;
-          for (int t = 0; t < 6; ++t) gu += g[t] * C.ru[k * NU + 6 * i + t];
-          const double rp = (gu - h) / sc + s;
-          const double coef = z + (-rcvec[rb + row] + z * rp) / s;
-          r += g[a] / sc * coef;
+          r += g[a] * cr[row];
         }
       }
     }
@@ -345,6 +396,9 @@ __device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode, const double* 
 }
 
 __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const double* rcvec) {
+  gsync();
+  if (mode == Mode::EQ) build_face_table(C);
+  else build_row_terms(C, rcvec);
   gsync();
   const int lane = threadIdx.x;
   const int N = C.N;
@@ -356,7 +410,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const doub
     load_AB(C, sh, k);
     load_face(C, sh, k, mode == Mode::NEWTON);
     if (factor) stage_rp(C, sh, k, mode);
-    stage_rho(C, sh, k, mode, rcvec);
+    stage_rho(C, sh, k, mode);
     if (lane < NX) {
       const double r = (double)C.x_ref[st * NX + lane];
       double q;
@@ -1085,7 +1139,10 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
     C.rds = blk;                      blk += (size_t)n * 2 * NROW;
     C.rdz = blk;                      blk += (size_t)n * 2 * NROW;
     C.rdu = blk;                      blk += (size_t)n * NU;
-    C.rdx = blk;
+    C.rdx = blk;                      blk += (size_t)(n + 1) * NX;
+    C.ftab = blk;                     blk += (size_t)n * 2 * FT;
+    C.wrow = blk;                     blk += (size_t)n * 2 * NROW;
+    C.crow = blk;
     C.faces = ws.faces + s0 * 2;
   }
   }
