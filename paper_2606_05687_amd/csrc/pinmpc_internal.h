@@ -116,15 +116,17 @@ struct Workspace {
   float* warm_store;
 };
 
-// FP64 scratch of the refinement per problem with n stages: gains K (12x13),
-// feedforward (12), inverse input Hessian (12x12), Hwx (12x13), inputs (12),
-// states ((n+1) x 13), costates (13), gradient (12), row multipliers, slacks,
-// interior-point multipliers and their steps (4 x 22 + 22), step du (12) and
-// dx ((n+1) x 13), face tables (2 x 18) and interior-point row terms
-// (2 x 2 x 11).
+// FP64 scratch of the refinement per problem with n stages.  Four 16 x 16
+// tiles per stage come first, so every tile is 32-byte aligned: the stage's
+// input tile (face projector and offset, or the interior-point input Hessian
+// and linear term), the gain tile, the inverse input Hessian and Hwx.  Then
+// per stage: feedforward (12), inputs (12), costates (13), gradient (12), row
+// multipliers, slacks, interior-point multipliers and their steps (5 x 22)
+// and step du (12); and states x and dx ((n+1) x 13 each).
+constexpr int TILE = 256;
 __host__ __device__ constexpr size_t refine_block_doubles(int n) {
-  return (size_t)n * (NU * NX + NU + NU * NU + NU * NX + NU + NX + NU + 5 * 2 * NROW + NU) +
-         2 * (size_t)(n + 1) * NX + (size_t)n * 2 * 18 + 2 * (size_t)n * 2 * NROW;
+  return (((size_t)n * (4 * TILE + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
+           2 * (size_t)(n + 1) * NX) + 3) & ~(size_t)3;
 }
 
 // Face code of one contact: bits 0..4 force rows active

@@ -25,23 +25,28 @@ namespace pinmpc {
 namespace {
 
 constexpr int W64 = 64;
-constexpr int GJW = NU + NX + 1 + NU;   // 38 columns of the augmented system
+
+// Pointers with their address space spelled out: the context lives in LDS,
+// so the compiler cannot infer where its pointers point, and generic (flat)
+// accesses would make every wait on one load a wait on all memory in flight.
+#define GMEM __attribute__((address_space(1)))
+#define LMEM __attribute__((address_space(3)))
+typedef const GMEM float* gcf;
+typedef const GMEM double* gcd;
+typedef GMEM double* gd;
 
 // One problem's view: its inputs and its FP64 scratch block, all as
 // pointers to the problem's own first stage, so stage k is plain k.
 struct Ctx {
   int b, N, n;
   double mu, fz, tm, mg;
-  const double* Q;   // LDS copies of the diagonal weights
-  const double* R;
-  const float *A, *B, *e, *x_ref, *u_ref, *x0;
-  const uint8_t* contact;
-  double *rK, *rkap, *rL, *rHwx, *ru, *rx, *rlam, *rg, *rmu, *rs, *rz, *rds, *rdz, *rdu, *rdx;
-  double* ftab;   // [n][2][18] face tables: force projector 3x3, force offset,
-                  // moment projector diagonal, moment offset
-  double* wrow;   // [n][2][11] interior-point row weights z / (s sc^2)
-  double* crow;   // [n][2][11] interior-point row coefficients of the linear term
-  int32_t* faces;
+  const LMEM double* Q;   // LDS copies of the diagonal weights
+  const LMEM double* R;
+  gcf A, B, e, x_ref, u_ref, x0;
+  const GMEM uint8_t* contact;
+  gd rT, rK, rL, rHwx;   // per-stage 16 x 16 tiles (32-byte aligned)
+  gd rkap, ru, rx, rlam, rg, rmu, rs, rz, rds, rdz, rdu, rdx;
+  GMEM int32_t* faces;
 };
 
 // ------------------------------------------------------------ small helpers
@@ -223,109 +228,170 @@ __device__ inline int blk_len(int j) { return (j % 6 < 3) ? 3 : 1; }
 
 // --------------------------------------------------------------- LDS state
 
+// Hand-off buffers of the stage recursion; everything else of a stage lives
+// in registers as 16 x 16 tiles.
+constexpr int GS = NU + NX + 2;   // row stride of the Gauss-Jordan hand-off
 struct Sh {
-  double S[NX * NX], s[NX];           // value function of x_{k+1}
-  double A[NX * NX], B[NX * NU];
-  double W[NX * NX], WA[NX * NX];
-  double P[NU * NU], c[NU], Rp[NU * NU];
-  double Bp[NX * NU], WBp[NX * NU];
-  double Hwx[NU * NX], K[NU * NX];
-  double om[NX], d[NX], Wdo[NX], hw[NU], kap[NU], rho[NU], q[NX];
-  double xv[NX], wv[NU], uv[NU], xn[NX];
-  double G[NU * GJW];                 // Gauss-Jordan augmented [H | Hwx | hw | I]
-  double fac[16];
-  double Qd[NX], Rd[NU];              // diagonal weights of the problem
+  double G[NU * GS];     // [H | Hwx | hw] of the stage, row-major
+  double KK[NU * 16];    // [K | 0 | kap]: gains, feedforward in column 13
+  double HI[NU * 16];    // H^{-1} (Newton steps)
+  double ST[16 * 17];    // S of the stage, for its transpose
+  double xv[NX], xn[NX];
+  double Qd[NX], Rd[NU]; // diagonal weights of the problem
 };
 
-__device__ inline void load_AB(const Ctx& C, Sh& sh, int k) {
-  const int lane = threadIdx.x;
-  const float* A = C.A + k * NX * NX;
-  const float* B = C.B + k * NX * NU;
-  for (int i = lane; i < NX * NX; i += W64) sh.A[i] = (double)A[i];
-  for (int i = lane; i < NX * NU; i += W64) sh.B[i] = (double)B[i];
+// ------------------------------------------------------------ 16 x 16 tiles
+//
+// The stage recursion works on 16 x 16 FP64 tiles (13 states, 12 inputs, zero
+// padded) held in registers in the result layout of the FP64 matrix-core
+// product (16 x 16 x 4 per instruction): lane l = 16 g + j holds items
+// q = 0..3, item q being entry (4 q + g, j).  The same layout is the right
+// operand of the product chunk by chunk, and read as the left operand it is
+// the transposed tile.  So for tiles U, V in registers mmT(U, V) = U^T V takes
+// four instructions and leaves a tile again: products chain with no data
+// movement.  Vectors ride in column VC of a tile (lanes 13, 29, 45, 61).
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int VC = 13;
+
+__device__ inline d4 zero4() {
+  d4 z = {0.0, 0.0, 0.0, 0.0};
+  return z;
+}
+__device__ inline int tg() { return threadIdx.x >> 4; }
+__device__ inline int tj() { return threadIdx.x & 15; }
+
+// U^T V + acc, contracting over the first 4 NQ rows (NQ = 3: the input rows).
+template <int NQ>
+__device__ inline d4 mmT(d4 u, d4 v, d4 acc) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(u[q], v[q], acc, 0, 0, 0);
+  return acc;
 }
 
-constexpr int FT = 18;   // doubles per contact in the face table
+// Tile of the row-major rows x cols matrix M.
+__device__ inline d4 tile_of(gcf M, int rows, int cols) {
+  const int g = tg(), j = tj();
+  d4 t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    t[q] = (r < rows && j < cols) ? (double)M[r * cols + j] : 0.0;
+  }
+  return t;
+}
+// Tile of M^T.
+__device__ inline d4 tile_of_T(gcf M, int rows, int cols) {
+  const int g = tg(), j = tj();
+  d4 t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    t[q] = (j < rows && r < cols) ? (double)M[j * cols + r] : 0.0;
+  }
+  return t;
+}
+__device__ inline d4 ld_tile(gcd base) {
+  return reinterpret_cast<const GMEM d4*>(base)[threadIdx.x];
+}
+__device__ inline void st_tile(gd base, d4 t) { reinterpret_cast<GMEM d4*>(base)[threadIdx.x] = t; }
+// Column-VC vector of a tile to / from memory (len entries).
+__device__ inline void vec_store(gd v, int len, d4 t) {
+  if (tj() == VC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * q + tg() < len) v[4 * q + tg()] = t[q];
+  }
+}
+__device__ inline double readlane_d(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ inline d4 sel(bool c, d4 a) { return c ? a : zero4(); }
 
-// Face tables of every (stage, contact) of the problem, computed in parallel
-// over (stage, contact) once per equality-constrained pass.
-__device__ void build_face_table(const Ctx& C) {
+// Coefficient a (0..5) of wrench row `row` (the same rows as wrench_row).
+__device__ inline double wcoef(int row, int a, double mu) {
+  if (row < 4) {
+    if (a == 2) return -mu;
+    if (a == (row >> 1)) return (row & 1) ? -1.0 : 1.0;
+    return 0.0;
+  }
+  if (row == 4) return (a == 2) ? 1.0 : 0.0;
+  return (a == 3 + (row - 5) % 3) ? ((row < 8) ? 1.0 : -1.0) : 0.0;
+}
+
+// Address of entry (r, c) of a stage tile in memory: lane 16 (r % 4) + c
+// holds it as item r / 4.
+__device__ inline size_t tile_at(int r, int c) { return (size_t)4 * (16 * (r % 4) + c) + r / 4; }
+
+// Stage input tiles, written in parallel over (stage, contact): each lane
+// computes one contact's 6 x 6 diagonal block (columns 0..11) and its six
+// column-VC entries in registers and stores them into the stage's tile.  The
+// rest of every tile is zero (cleared once per launch).
+//   equality passes: the face projector P (block diagonal) and the face
+//                    offset c of the contact;
+//   Newton steps:    the input Hessian R + G^T diag(z/s) G and the linear term
+//                    R (u - u_ref) + G^T c_rows of a stance contact (zero
+//                    for a swing contact).
+// Interior-point rows are scaled by sc (mg force rows, tau_max moment rows):
+// row weight z / (s sc^2), linear coefficient (z + (-rc + z rp) / s) / sc with
+// rp = (g u - h) / sc + s.
+__device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec) {
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
-    double* t = C.ftab + (size_t)e * FT;
+    gd base = C.rT + (size_t)k * TILE;
+    double P6[6][6], c6[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      c6[a] = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) P6[a][b] = 0.0;
+    }
     if (C.contact[k * 2 + i]) {
-      double P6[6][6], c6[6];
-      face_affine(C.faces[k * 2 + i], C.mu, C.fz, C.tm, P6, c6);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) t[a * 3 + b] = P6[a][b];
-        t[9 + a] = c6[a];
-        t[12 + a] = P6[3 + a][3 + a];
-        t[15 + a] = c6[3 + a];
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < FT; ++a) t[a] = 0.0;
-    }
-  }
-}
-
-// Face projector/offset of stage k into sh.P, sh.c, filled in parallel from
-// the face table (equality passes) or as the stance mask (Newton steps).
-__device__ inline void load_face(const Ctx& C, Sh& sh, int k, bool newton) {
-  const int lane = threadIdx.x;
-  for (int e = lane; e < NU * NU; e += W64) {
-    const int r = e / NU, c = e % NU;
-    const int i = r / 6;
-    double v = 0.0;
-    if (i == c / 6 && C.contact[k * 2 + i]) {
-      const int a = r % 6, b = c % 6;
-      if (newton) {
-        v = (a == b) ? 1.0 : 0.0;
+      if (!newton) {
+        face_affine(C.faces[k * 2 + i], C.mu, C.fz, C.tm, P6, c6);
       } else {
-        const double* t = C.ftab + ((size_t)k * 2 + i) * FT;
-        if (a < 3 && b < 3) v = t[a * 3 + b];
-        else if (a == b) v = t[12 + a - 3];
+        double u[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const int jj = 6 * i + a;
+          u[a] = C.ru[k * NU + jj];
+          const double ur = C.u_ref ? (double)C.u_ref[k * NU + jj] : 0.0;
+          P6[a][a] = C.R[jj];
+          c6[a] = C.R[jj] * (u[a] - ur);
+        }
+        const size_t rb = (size_t)e * NROW;
+#pragma unroll
+        for (int row = 0; row < NROW; ++row) {
+          double gr[6], h;
+          wrench_row(row, C.mu, C.fz, C.tm, gr, &h);
+          const double sc = (row < 5) ? C.mg : C.tm;
+          double gu = 0.0;
+#pragma unroll
+          for (int a = 0; a < 6; ++a) gu += gr[a] * u[a];
+          const double s = C.rs[rb + row], z = C.rz[rb + row];
+          const double rp = (gu - h) / sc + s;
+          const double w = z / s / (sc * sc);
+          const double cr = (z + (-rcvec[rb + row] + z * rp) / s) / sc;
+#pragma unroll
+          for (int a = 0; a < 6; ++a) {
+            c6[a] += gr[a] * cr;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) P6[a][b] += w * gr[a] * gr[b];
+          }
+        }
       }
     }
-    sh.P[e] = v;
-  }
-  if (lane < NU) {
-    const int i = lane / 6, a = lane % 6;
-    double v = 0.0;
-    if (!newton && C.contact[k * 2 + i]) {
-      const double* t = C.ftab + ((size_t)k * 2 + i) * FT;
-      v = (a < 3) ? t[9 + a] : t[15 + a - 3];
-    }
-    sh.c[lane] = v;
-  }
-  wsync();
-}
-
-// Interior-point row terms of every stance row, in parallel over rows:
-// the weight z / (s sc^2) of the input Hessian and the coefficient
-// z + (-rc + z rp) / s of the linear term (rows scaled by sc).
-__device__ void build_row_terms(const Ctx& C, const double* rcvec) {
-  const int lane = threadIdx.x;
-  for (int e = lane; e < C.N * 2 * NROW; e += W64) {
-    const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-    if (!C.contact[k * 2 + i]) {
-      C.wrow[e] = 0.0;
-      C.crow[e] = 0.0;
-      continue;
-    }
-    double g[6], h;
-    wrench_row(r, C.mu, C.fz, C.tm, g, &h);
-    const double sc = (r < 5) ? C.mg : C.tm;
-    double gu = 0.0;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) gu += g[t] * C.ru[k * NU + 6 * i + t];
-    const double s = C.rs[e], z = C.rz[e];
-    const double rp = (gu - h) / sc + s;
-    C.wrow[e] = z / s / (sc * sc);
-    C.crow[e] = (z + (-rcvec[e] + z * rp) / s) / sc;
+    for (int a = 0; a < 6; ++a) {
+      const int r = 6 * i + a;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) base[tile_at(r, 6 * i + b)] = P6[a][b];
+      base[tile_at(r, VC)] = c6[a];
+    }
   }
 }
 
@@ -336,332 +402,392 @@ __device__ void build_row_terms(const Ctx& C, const double* rcvec) {
 //          s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,  u_k = c_k + P_k w_k
 // (P_k an orthogonal projector) by the backward recursion on the value
 // function V(x) = 1/2 x^T S x + s^T x and the forward rollout.
-//   newton = false: the equality-constrained tracking problem of the faces
-//                   (q = -Q r, rho = -R u_ref, R' = R, e from the data);
-//   newton = true:  the interior-point Newton step, x_0 = 0, e = 0,
-//                   q = Q (x_{k+1} - r), R' = R + G^T diag(z/s) G,
-//                   rho from ipm_rho (stage inputs), P = stance mask.
+//   EQ:     the equality-constrained tracking problem of the faces
+//           (q = -Q r, rho = -R u_ref, R' = R, e from the data);
+//   NEWTON: the interior-point Newton step, x_0 = 0, e = 0,
+//           q = Q (x_{k+1} - r), R' = R + G^T diag(z/s) G,
+//           rho from the stage tile, P = stance mask, c = 0.
+// Per stage, with W = S + Q, Bp = B P and d = B c + e:
+//   H = P R' P + Bp^T W Bp + (I - P),  Hwx = Bp^T W A,
+//   hw = P (R' c + rho) + Bp^T (W d + q + s),
+//   K = -H^{-1} Hwx, kap = -H^{-1} hw,
+//   S <- A^T W A + Hwx^T K,  s <- A^T (W d + q + s) + Hwx^T kap.
 // With factor = false only the linear part is recomputed from the stored
-// factors (second right-hand side of the same Newton matrix).
+// H^{-1}, Hwx and K (second right-hand side of the same Newton matrix).
 
 enum class Mode { EQ, NEWTON };
 
-__device__ void stage_rp(const Ctx& C, Sh& sh, int k, Mode mode) {
-  // R'_k = R (+ sum over stance rows of w_r g_r g_r^T in Newton steps), in
-  // parallel over the entries of the two 6 x 6 contact blocks
-  const int lane = threadIdx.x;
-  for (int e = lane; e < NU * NU; e += W64) {
-    const int r = e / NU, c = e % NU;
-    double v = (r == c) ? C.R[r] : 0.0;
-    const int i = r / 6;
-    if (mode == Mode::NEWTON && i == c / 6 && C.contact[k * 2 + i]) {
-      const int a = r % 6, b = c % 6;
-      const double* w = C.wrow + ((size_t)k * 2 + i) * NROW;
+// Raw stage data.  The stage loops fetch the next stage's data a whole stage
+// ahead; the fetch only gathers (addresses clamped into the stage's arrays)
+// and the conversion and masking happen when the stage is used.  Before the
+// next fetch and the deferred stores are issued, everything the stage uses is
+// pinned in registers, so no wait on memory falls inside a stage's compute
+// (loads and stores share one counter here: waiting for any access would
+// otherwise mean waiting for all of them).
+__device__ inline int clampi(int v, int hi) { return v < hi ? v : hi; }
+__device__ inline void gather(gcf M, bool transposed, int rows, int cols, float m[4]) {
+  const int g = tg(), j = tj();
 #pragma unroll
-      for (int row = 0; row < NROW; ++row) {
-        double g[6], h;
-        wrench_row(row, C.mu, C.fz, C.tm, g, &h);
-        v += w[row] * g[a] * g[b];
-      }
-    }
-    sh.Rp[e] = v;
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    m[q] = transposed ? M[clampi(j, rows - 1) * cols + clampi(r, cols - 1)]
+                      : M[clampi(r, rows - 1) * cols + clampi(j, cols - 1)];
   }
-  wsync();
+}
+__device__ inline void gatherv(gcf v, int len, float m[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) m[q] = v[clampi(4 * q + tg(), len - 1)];
+}
+__device__ inline d4 cook(const float m[4], bool transposed, int rows, int cols) {
+  const int g = tg(), j = tj();
+  d4 t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    const bool ok = transposed ? (j < rows && r < cols) : (r < rows && j < cols);
+    t[q] = ok ? (double)m[q] : 0.0;
+  }
+  return t;
+}
+__device__ inline void pin(const d4& t) {
+  asm volatile("" ::"v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]));
+}
+__device__ inline void pin_memory() { asm volatile("" ::: "memory"); }
+// A pointer read from the LDS context, made wave-uniform (scalar registers):
+// the stage loops then neither re-read the context after their LDS stores
+// nor hold its pointers in vector registers.
+template <class T>
+__device__ inline T uni(T p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (T)(((uint64_t)hi << 32) | lo);
 }
 
-// Linear input term rho_k of stage k into sh.rho.
-__device__ void stage_rho(const Ctx& C, Sh& sh, int k, Mode mode) {
-  const int lane = threadIdx.x;
-  if (lane < NU) {
-    const int j = lane;
-    const double ur = C.u_ref ? (double)C.u_ref[k * NU + j] : 0.0;
-    double r;
-    if (mode == Mode::EQ) {
-      r = -C.R[j] * ur;
+// Stance mask tile (identity on the inputs of stance contacts).
+__device__ inline d4 mask_tile(int stance) {
+  const int g = tg(), j = tj();
+  const double m = (j < NU && stance) ? 1.0 : 0.0;
+  d4 p;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) p[q] = (4 * q + g == j) ? m : 0.0;
+  return p;
+}
+
+struct BackRaw {
+  float a[4], bt[4], xr[4], ev[4], ur[4];
+  double xn[4];
+  d4 T, HI, HX;
+  int ct;
+};
+
+template <Mode mode, bool factor>
+__device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec) {
+  gsync();
+  build_tiles(C, mode == Mode::NEWTON, rcvec);
+  gsync();
+  const int lane = threadIdx.x, g = tg(), j = tj();
+  const int N = __builtin_amdgcn_readfirstlane(C.N);
+  constexpr bool newton = (mode == Mode::NEWTON);
+  const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pe = uni(C.e), pur = uni(C.u_ref);
+  const GMEM uint8_t* pct = uni(C.contact);
+  const gd prT = uni(C.rT), prK = uni(C.rK), prL = uni(C.rL), prH = uni(C.rHwx);
+  const gd prkap = uni(C.rkap), prx = uni(C.rx), pru = uni(C.ru), prdx = uni(C.rdx),
+           prdu = uni(C.rdu);
+  // the diagonal weights where this lane uses them
+  const double Qj = C.Q[clampi(j, NX - 1)];
+  d4 Qr, Rr;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Qr[q] = C.Q[clampi(4 * q + g, NX - 1)];
+    Rr[q] = C.R[clampi(4 * q + g, NU - 1)];
+  }
+  auto fetch = [&](int k, BackRaw& s) {
+    gather(pA + (size_t)k * NX * NX, false, NX, NX, s.a);
+    gather(pB + (size_t)k * NX * NU, true, NX, NU, s.bt);
+    gatherv(pxr + (size_t)k * NX, NX, s.xr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s.ev[q] = 0.f;
+      s.ur[q] = 0.f;
+      s.xn[q] = 0.0;
+    }
+    if (!newton && pe) gatherv(pe + (size_t)k * NX, NX, s.ev);
+    if (!newton && pur) gatherv(pur + (size_t)k * NU, NU, s.ur);
+    if (newton) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s.xn[q] = prx[(size_t)(k + 1) * NX + clampi(4 * q + g, NX - 1)];
+    }
+    s.T = ld_tile(prT + (size_t)k * TILE);
+    if (newton && !factor) {
+      s.HI = ld_tile(prL + (size_t)k * TILE);
+      s.HX = ld_tile(prH + (size_t)k * TILE);
     } else {
-      r = C.R[j] * (C.ru[k * NU + j] - ur);
-      const int i = j / 6, a = j % 6;
-      if (C.contact[k * 2 + i]) {
-        const double* cr = C.crow + ((size_t)k * 2 + i) * NROW;
-#pragma unroll
-        for (int row = 0; row < NROW; ++row) {
-          double g[6], h;
-          wrench_row(row, C.mu, C.fz, C.tm, g, &h);
-          r += g[a] * cr[row];
-        }
-      }
+      s.HI = s.HX = zero4();
     }
-    sh.rho[j] = r;
-  }
-}
+    s.ct = newton ? (int)pct[k * 2 + (j < NU ? j / 6 : 0)] : 0;
+  };
 
-__device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, const double* rcvec) {
-  gsync();
-  if (mode == Mode::EQ) build_face_table(C);
-  else build_row_terms(C, rcvec);
-  gsync();
-  const int lane = threadIdx.x;
-  const int N = C.N;
-  for (int i = lane; i < NX * NX; i += W64) sh.S[i] = 0.0;
-  if (lane < NX) sh.s[lane] = 0.0;
-  wsync();
+  d4 Ss = zero4();   // value function of x_{k+1}: S in columns 0..12, s in VC
+  BackRaw raw;
+  fetch(N > 0 ? N - 1 : 0, raw);
   for (int k = N - 1; k >= 0; --k) {
-    const int st = k;
-    load_AB(C, sh, k);
-    load_face(C, sh, k, mode == Mode::NEWTON);
-    if (factor) stage_rp(C, sh, k, mode);
-    stage_rho(C, sh, k, mode);
-    if (lane < NX) {
-      const double r = (double)C.x_ref[st * NX + lane];
-      double q;
-      if (mode == Mode::EQ) q = -C.Q[lane] * r;
-      else q = C.Q[lane] * (C.rx[(k + 1) * NX + lane] - r);
-      sh.om[lane] = q + sh.s[lane];
+    // this stage's data
+    const d4 At = cook(raw.a, false, NX, NX);
+    const d4 BT = cook(raw.bt, true, NX, NU);
+    const d4 T = raw.T, HIs = raw.HI, HXs = raw.HX;
+    d4 om, ev, ur;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * q + g;
+      const bool vr = (j == VC && r < NX);
+      const double xr = (double)raw.xr[q];
+      om[q] = vr ? (newton ? Qr[q] * (raw.xn[q] - xr) : -Qr[q] * xr) : 0.0;
+      ev[q] = vr ? (double)raw.ev[q] : 0.0;
+      ur[q] = (j == VC && r < NU) ? (double)raw.ur[q] : 0.0;
     }
-    wsync();
-    // Bp = B P ; d = B c + e
-    for (int e = lane; e < NX * NU; e += W64) {
-      const int i = e / NU, j = e % NU;
-      const int l0 = blk_start(j), l1 = l0 + blk_len(j);
-      double acc = 0.0;
-      for (int l = l0; l < l1; ++l) acc += sh.B[i * NU + l] * sh.P[l * NU + j];
-      sh.Bp[e] = acc;
-    }
-    if (lane < NX) {
-      double acc = 0.0;
-      if (mode == Mode::EQ) {
-        for (int l = 0; l < NU; ++l) acc += sh.B[lane * NU + l] * sh.c[l];
-        if (C.e) acc += (double)C.e[st * NX + lane];
+    const d4 Pt = newton ? mask_tile(raw.ct) : sel(j < NU, T);
+    pin(At); pin(BT); pin(T); pin(om); pin(ev); pin(ur); pin(Pt);
+    if (newton && !factor) { pin(HIs); pin(HXs); }
+    pin_memory();
+    if (k > 0) fetch(k - 1, raw);
+
+    // [Bp | 0 | d] = B [P | 0 | c] + [0 | 0 | e]
+    const d4 yc = (!newton && j == VC) ? T : Pt;
+    d4 D1 = mmT<3>(BT, yc, ev);
+    const d4 Bp = sel(j < NU, D1);
+    d4 Sn;
+    if (factor) {
+      d4 Wt;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        Wt[q] = (j < NX) ? Ss[q] + ((4 * q + g == j) ? Qj : 0.0) : 0.0;
+      const d4 yA = (j < NX) ? At : sel(j == VC, D1);
+      d4 D2 = mmT<4>(Wt, yA, zero4());      // [W A | W d]
+      if (j == VC) D2 += om + Ss;            // [W A | W d + q + s]
+      const d4 D3 = mmT<4>(Wt, Bp, zero4()); // W Bp
+      d4 D4 = mmT<4>(Bp, D3, zero4());       // Bp^T W Bp
+      const d4 D5 = mmT<4>(Bp, D2, zero4()); // [Hwx | Bp^T (W d + q + s)]
+      if (newton) {
+        // P R' P and P rho straight from the stage tile (P a mask there)
+        D4 += sel(j < NU || j == VC, T);
+      } else {
+        // P R P and P R (c - u_ref) = P (R c + rho)
+        d4 RP;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) RP[q] = (j < NU && 4 * q + g < NU) ? Rr[q] * T[q] : 0.0;
+        const d4 Py = (j < NU) ? T : sel(j == VC, T - ur);
+        D4 = mmT<3>(RP, Py, D4);
       }
-      sh.d[lane] = acc;
-    }
-    if (factor) {
-      for (int e = lane; e < NX * NX; e += W64)
-        sh.W[e] = sh.S[e] + ((e % (NX + 1) == 0) ? C.Q[e / NX] : 0.0);
-    }
-    wsync();
-    if (factor) {
-      // WA, WBp
-      for (int e = lane; e < NX * NX + NX * NU; e += W64) {
-        if (e < NX * NX) {
-          const int i = e / NX, j = e % NX;
-          double acc = 0.0;
-          for (int l = 0; l < NX; ++l) acc += sh.W[i * NX + l] * sh.A[l * NX + j];
-          sh.WA[e] = acc;
-        } else {
-          const int f = e - NX * NX, i = f / NU, j = f % NU;
-          double acc = 0.0;
-          for (int l = 0; l < NX; ++l) acc += sh.W[i * NX + l] * sh.Bp[l * NU + j];
-          sh.WBp[f] = acc;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int r = 4 * q + g;
+        if (j < NU) sh.G[r * GS + j] = D4[q] + ((r == j) ? 1.0 : 0.0) - Pt[q];
+        if (j < NX) sh.G[r * GS + NU + j] = D5[q];
+        if (j == VC) sh.G[r * GS + NU + NX] = D5[q] + D4[q];
+      }
+      wsync();
+      // Gauss-Jordan elimination (H is SPD: no pivoting) with lane c holding
+      // column c of [H | Hwx | hw | I]; the pivot column is broadcast from
+      // its lane.  Afterwards the lanes hold [I | H^-1 Hwx | H^-1 hw | H^-1].
+      constexpr int C0 = NU + NX + 1;
+      const int ncol = newton ? C0 + NU : C0;
+      double col[NU];
+#pragma unroll
+      for (int r = 0; r < NU; ++r)
+        col[r] = (lane < C0) ? sh.G[r * GS + lane] : ((lane < ncol && r == lane - C0) ? 1.0 : 0.0);
+#pragma unroll
+      for (int p = 0; p < NU; ++p) {
+        double pc[NU];
+#pragma unroll
+        for (int r = 0; r < NU; ++r) pc[r] = readlane_d(col[r], p);
+        const double t = col[p] / pc[p];
+#pragma unroll
+        for (int r = 0; r < NU; ++r)
+          if (r != p) col[r] -= pc[r] * t;
+        col[p] = t;
+      }
+      if (lane >= NU && lane < C0) {
+        const int c = (lane < NU + NX) ? lane - NU : VC;
+#pragma unroll
+        for (int r = 0; r < NU; ++r) sh.KK[r * 16 + c] = -col[r];
+      }
+      if (newton && lane >= C0 && lane < ncol) {
+#pragma unroll
+        for (int r = 0; r < NU; ++r) sh.HI[r * 16 + lane - C0] = col[r];
+      }
+      wsync();
+      d4 KK, KT;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g;
+        KK[q] = (r < NU && (j < NX || j == VC)) ? sh.KK[r * 16 + j] : 0.0;   // [K | kap]
+        KT[q] = (j < NU && r < NX) ? sh.KK[j * 16 + r] : 0.0;               // K^T
+      }
+      st_tile(prK + (size_t)k * TILE, KT);
+      vec_store(prkap + (size_t)k * NU, NU, KK);
+      if (newton) {
+        d4 HI;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 4 * q + g;
+          HI[q] = (r < NU && j < NU) ? sh.HI[r * 16 + j] : 0.0;
         }
+        st_tile(prL + (size_t)k * TILE, HI);
+        st_tile(prH + (size_t)k * TILE, sel(j < NX, D5));
       }
-    }
-    wsync();
-    if (lane < NX) {
-      // W d + omega (W = Q + S)
-      double acc = sh.om[lane];
-      if (mode == Mode::EQ)
-        for (int l = 0; l < NX; ++l)
-          acc += (sh.S[lane * NX + l] + (l == lane ? C.Q[lane] : 0.0)) * sh.d[l];
-      sh.Wdo[lane] = acc;
-    }
-    if (factor) {
-      // T = R' P, held in K until K itself is formed
-      for (int e = lane; e < NU * NU; e += W64) {
-        const int i = e / NU, j = e % NU;
-        const int l0 = blk_start(j), l1 = l0 + blk_len(j);
-        double acc = 0.0;
-        if (blk_start(i) == l0)
-          for (int l = l0; l < l1; ++l) acc += sh.Rp[i * NU + l] * sh.P[l * NU + j];
-        sh.K[e] = acc;   // scratch
+      // S = A^T W A + Hwx^T K, s = A^T (W d + q + s) + Hwx^T kap
+      Sn = mmT<4>(At, D2, zero4());
+      Sn = mmT<3>(sel(j < NX, D5), KK, Sn);
+      // keep S exactly symmetric: its rounding is not, and an asymmetric part
+      // is carried back through the open-loop A and grows along the horizon
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh.ST[(4 * q + g) * 17 + j] = Sn[q];
+      wsync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g;
+        if (r < NX && j < NX) Sn[q] = 0.5 * (Sn[q] + sh.ST[j * 17 + r]);
       }
-    }
-    wsync();
-    if (factor) {
-      // H = P R' P + Bp^T W Bp + (I - P) ; Hwx = Bp^T W A, straight into the
-      // augmented Gauss-Jordan system [H | Hwx | hw | I]
-      for (int e = lane; e < NU * NU + NU * NX; e += W64) {
-        if (e < NU * NU) {
-          const int i = e / NU, j = e % NU;
-          double acc = ((i == j) ? 1.0 : 0.0) - sh.P[i * NU + j];
-          const int l0 = blk_start(i), l1 = l0 + blk_len(i);
-          if (blk_start(j) == l0)
-            for (int l = l0; l < l1; ++l) acc += sh.P[l * NU + i] * sh.K[l * NU + j];
-          for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WBp[l * NU + j];
-          sh.G[i * GJW + j] = acc;
-          if (mode == Mode::NEWTON) sh.G[i * GJW + NU + NX + 1 + j] = (i == j) ? 1.0 : 0.0;
-        } else {
-          const int f = e - NU * NU, i = f / NX, j = f % NX;
-          double acc = 0.0;
-          for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + i] * sh.WA[l * NX + j];
-          sh.Hwx[f] = acc;
-          sh.G[i * GJW + NU + j] = acc;
-        }
-      }
+      wsync();
     } else {
-      for (int e = lane; e < NU * NX; e += W64) sh.Hwx[e] = C.rHwx[st * NU * NX + e];
+      // second right-hand side of the stored Newton matrix (d = 0, so
+      // W d + q + s = q + s)
+      const d4 wv = sel(j == VC, om + Ss);
+      d4 hw = mmT<4>(Bp, wv, zero4());
+      hw += sel(j == VC, T);
+      const d4 kap = -mmT<3>(HIs, hw, zero4());
+      vec_store(prkap + (size_t)k * NU, NU, kap);
+      Sn = mmT<4>(At, wv, zero4());
+      Sn = mmT<3>(HXs, kap, Sn);
     }
-    if (lane < NU) {
-      // hw = P (R' c + rho) + Bp^T (W d + omega)
-      double acc = 0.0;
-      const int l0 = blk_start(lane), l1 = l0 + blk_len(lane);
-      for (int l = l0; l < l1; ++l) {
-        double t = sh.rho[l];
-        if (mode == Mode::EQ)
-          for (int m = l0; m < l1; ++m) t += sh.Rp[l * NU + m] * sh.c[m];
-        acc += sh.P[lane * NU + l] * t;
-      }
-      for (int l = 0; l < NX; ++l) acc += sh.Bp[l * NU + lane] * sh.Wdo[l];
-      sh.hw[lane] = acc;
-      if (factor) sh.G[lane * GJW + NU + NX] = acc;
-    }
-    wsync();
-    if (factor) {
-      // Gauss-Jordan elimination (H is SPD: no pivoting) over all 64 lanes:
-      // afterwards G = [I | H^{-1} Hwx | H^{-1} hw | H^{-1}]; the equality
-      // pass needs no explicit inverse, so it stops at column 25.
-      const int gw = (mode == Mode::NEWTON) ? GJW : NU + NX + 1;
-      for (int j = 0; j < NU; ++j) {
-        const double piv = sh.G[j * GJW + j];
-        wsync();
-        for (int c = j + lane; c < gw; c += W64) sh.G[j * GJW + c] /= piv;
-        wsync();
-        if (lane < NU) sh.fac[lane] = sh.G[lane * GJW + j];
-        wsync();
-        for (int e = lane; e < NU * (gw - j - 1); e += W64) {
-          const int r = e / (gw - j - 1), c = j + 1 + e % (gw - j - 1);
-          if (r != j) sh.G[r * GJW + c] -= sh.fac[r] * sh.G[j * GJW + c];
-        }
-        wsync();
-      }
-      for (int e = lane; e < NU * NX; e += W64) {
-        const int i = e / NX, j = e % NX;
-        sh.K[e] = -sh.G[i * GJW + NU + j];
-      }
-      if (lane < NU) sh.kap[lane] = -sh.G[lane * GJW + NU + NX];
-      // keep H^{-1} and Hwx for a second right-hand side of the same matrix
-      if (mode == Mode::NEWTON) {
-        double* Hi = C.rL + st * NU * NU;
-        for (int e = lane; e < NU * NU; e += W64)
-          Hi[e] = sh.G[(e / NU) * GJW + NU + NX + 1 + e % NU];
-        for (int e = lane; e < NU * NX; e += W64) C.rHwx[st * NU * NX + e] = sh.Hwx[e];
-      }
-    } else {
-      const double* Hi = C.rL + st * NU * NU;
-      if (lane < NU) {
-        double acc = 0.0;
-        for (int l = 0; l < NU; ++l) acc += Hi[lane * NU + l] * sh.hw[l];
-        sh.kap[lane] = -acc;
-      }
-      for (int e = lane; e < NU * NX; e += W64) sh.K[e] = C.rK[st * NU * NX + e];
-    }
-    wsync();
-    if (factor)
-      for (int e = lane; e < NU * NX; e += W64) C.rK[st * NU * NX + e] = sh.K[e];
-    if (lane < NU) C.rkap[st * NU + lane] = sh.kap[lane];
-    // S = A^T W A + Hwx^T K ; s = A^T (W d + omega) + Hwx^T kap
-    if (factor) {
-      // upper triangle of the (symmetric) new S, mirrored below
-      for (int e = lane; e < NX * (NX + 1) / 2; e += W64) {
-        int i = 0, rem = e;
-        while (rem >= NX - i) { rem -= NX - i; ++i; }
-        const int j = i + rem;
-        double acc = 0.0;
-        for (int l = 0; l < NX; ++l) acc += sh.A[l * NX + i] * sh.WA[l * NX + j];
-        for (int l = 0; l < NU; ++l) acc += sh.Hwx[l * NX + i] * sh.K[l * NX + j];
-        sh.W[i * NX + j] = acc;    // new S, copied below
-      }
-    }
-    if (lane < NX) {
-      double acc = 0.0;
-      for (int l = 0; l < NX; ++l) acc += sh.A[l * NX + lane] * sh.Wdo[l];
-      for (int l = 0; l < NU; ++l) acc += sh.Hwx[l * NX + lane] * sh.kap[l];
-      sh.xn[lane] = acc;
-    }
-    wsync();
-    if (factor)
-      for (int e = lane; e < NX * NX; e += W64) {
-        const int i = e / NX, j = e % NX;
-        sh.S[e] = (i <= j) ? sh.W[i * NX + j] : sh.W[j * NX + i];
-      }
-    if (lane < NX) sh.s[lane] = sh.xn[lane];
-    wsync();
+    Ss = Sn;
   }
-  // forward rollout (reads the gains written by other lanes above)
-  gsync();
-  if (lane < NX) {
-    sh.xv[lane] = (mode == Mode::EQ) ? (double)C.x0[lane] : 0.0;
+
+  // forward rollout: w = K x + kap, u = P w + c, x' = A x + B u + e, all in
+  // column VC (each lane reads back only what it stored above)
+  gd xout = newton ? prdx : prx;
+  gd uout = newton ? prdu : pru;
+  struct FwdRaw {
+    float at[4], bt[4], ev[4];
+    double kap[4];
+    d4 KT, T;
+    int ct;
+  };
+  auto ffetch = [&](int k, FwdRaw& s) {
+    gather(pA + (size_t)k * NX * NX, true, NX, NX, s.at);
+    gather(pB + (size_t)k * NX * NU, true, NX, NU, s.bt);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s.ev[q] = 0.f;
+      s.kap[q] = prkap[(size_t)k * NU + clampi(4 * q + g, NU - 1)];
+    }
+    if (!newton && pe) gatherv(pe + (size_t)k * NX, NX, s.ev);
+    s.KT = ld_tile(prK + (size_t)k * TILE);
+    s.T = ld_tile(prT + (size_t)k * TILE);
+    s.ct = newton ? (int)pct[k * 2 + (j < NU ? j / 6 : 0)] : 0;
+  };
+  d4 xv = zero4();
+  if (j == VC && !newton) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * q + g < NX) xv[q] = (double)uni(C.x0)[4 * q + g];
   }
-  wsync();
-  double* xout = (mode == Mode::EQ) ? C.rx : C.rdx;
-  double* uout = (mode == Mode::EQ) ? C.ru : C.rdu;
-  if (lane < NX) xout[0 + lane] = sh.xv[lane];
+  vec_store(xout, NX, xv);
+  FwdRaw fr;
+  ffetch(0, fr);
+  d4 pu = zero4(), px = zero4();
+  int pf = -1;
   for (int k = 0; k < N; ++k) {
-    const int st = k;
-    load_AB(C, sh, k);
-    load_face(C, sh, k, mode == Mode::NEWTON);
-    if (lane < NU) {
-      double acc = C.rkap[st * NU + lane];
-      for (int l = 0; l < NX; ++l) acc += C.rK[st * NU * NX + lane * NX + l] * sh.xv[l];
-      sh.wv[lane] = acc;
+    const d4 AT = cook(fr.at, true, NX, NX);
+    const d4 BT = cook(fr.bt, true, NX, NU);
+    const d4 KT = fr.KT, T = fr.T;
+    d4 kap, ev;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * q + g;
+      kap[q] = (j == VC && r < NU) ? fr.kap[q] : 0.0;
+      ev[q] = (j == VC && r < NX) ? (double)fr.ev[q] : 0.0;
     }
-    wsync();
-    if (lane < NU) {
-      double acc = sh.c[lane];
-      for (int l = 0; l < NU; ++l) acc += sh.P[lane * NU + l] * sh.wv[l];
-      sh.uv[lane] = acc;
-      uout[st * NU + lane] = acc;
+    const d4 Pt = newton ? mask_tile(fr.ct) : sel(j < NU, T);
+    pin(AT); pin(BT); pin(KT); pin(T); pin(kap); pin(ev); pin(Pt);
+    pin_memory();
+    if (pf >= 0) {
+      vec_store(uout + (size_t)pf * NU, NU, pu);
+      vec_store(xout + (size_t)(pf + 1) * NX, NX, px);
     }
-    wsync();
-    if (lane < NX) {
-      double acc = 0.0;
-      for (int l = 0; l < NX; ++l) acc += sh.A[lane * NX + l] * sh.xv[l];
-      for (int l = 0; l < NU; ++l) acc += sh.B[lane * NU + l] * sh.uv[l];
-      if (mode == Mode::EQ && C.e) acc += (double)C.e[st * NX + lane];
-      sh.xn[lane] = acc;
-    }
-    wsync();
-    if (lane < NX) {
-      sh.xv[lane] = sh.xn[lane];
-      xout[(k + 1) * NX + lane] = sh.xn[lane];
-    }
-    wsync();
+    if (k + 1 < N) ffetch(k + 1, fr);
+    const d4 w = mmT<4>(KT, xv, kap);
+    d4 u = mmT<3>(Pt, w, zero4());
+    if (!newton) u += sel(j == VC, T);
+    d4 xn = mmT<4>(AT, xv, ev);
+    xn = mmT<3>(BT, u, xn);
+    pu = u;
+    px = xn;
+    pf = k;
+    xv = xn;
+  }
+  if (pf >= 0) {
+    vec_store(uout + (size_t)pf * NU, NU, pu);
+    vec_store(xout + (size_t)(pf + 1) * NX, NX, px);
   }
   gsync();
 }
 
-// Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
-// gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
+__device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec) {
+  if (mode == Mode::EQ) riccati_t<Mode::EQ, true>(C, sh, rcvec);
+  else if (factor) riccati_t<Mode::NEWTON, true>(C, sh, rcvec);
+  else riccati_t<Mode::NEWTON, false>(C, sh, rcvec);
+}
+
+// Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} (column VC of a
+// tile) and the reduced gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
 __device__ void costates_grad(const Ctx& C, Sh& sh) {
   gsync();
-  const int lane = threadIdx.x;
-  for (int k = C.N - 1; k >= 0; --k) {
-    const int st = k;
-    if (lane < NX) {
-      const double x = C.rx[(k + 1) * NX + lane];
-      double acc = C.Q[lane] * (x - (double)C.x_ref[st * NX + lane]);
-      if (k + 1 < C.N) {
-        const float* A1 = C.A + (st + 1) * NX * NX;
-        for (int l = 0; l < NX; ++l) acc += (double)A1[l * NX + lane] * sh.xn[l];
-      }
-      sh.om[lane] = acc;
-    }
-    wsync();
-    if (lane < NX) {
-      sh.xn[lane] = sh.om[lane];
-      C.rlam[st * NX + lane] = sh.om[lane];
-    }
-    wsync();
+  const int lane = threadIdx.x, g = tg(), j = tj();
+  const int N = __builtin_amdgcn_readfirstlane(C.N);
+  const gcf pA = uni(C.A), pxr = uni(C.x_ref);
+  const gd prx = uni(C.rx), prlam = uni(C.rlam);
+  d4 Qr;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Qr[q] = C.Q[clampi(4 * q + g, NX - 1)];
+  struct CoRaw {
+    float a[4], xr[4];
+    double x[4];
+  };
+  auto cfetch = [&](int k, CoRaw& s) {
+    gather(pA + (size_t)clampi(k + 1, N - 1) * NX * NX, false, NX, NX, s.a);
+    gatherv(pxr + (size_t)k * NX, NX, s.xr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s.x[q] = prx[(size_t)(k + 1) * NX + clampi(4 * q + g, NX - 1)];
+  };
+  CoRaw cr;
+  cfetch(N > 0 ? N - 1 : 0, cr);
+  d4 p = zero4(), pp = zero4();
+  int pk = -1;
+  for (int k = N - 1; k >= 0; --k) {
+    const d4 A1 = cook(cr.a, false, NX, NX);
+    d4 qx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      qx[q] = (j == VC && 4 * q + g < NX) ? Qr[q] * (cr.x[q] - (double)cr.xr[q]) : 0.0;
+    pin(A1); pin(qx);
+    pin_memory();
+    if (pk >= 0) vec_store(prlam + (size_t)pk * NX, NX, pp);
+    if (k > 0) cfetch(k - 1, cr);
+    p = (k + 1 < N) ? mmT<4>(A1, p, qx) : qx;
+    pp = p;
+    pk = k;
   }
+  if (pk >= 0) vec_store(prlam + (size_t)pk * NX, NX, pp);
   gsync();
-  for (int e = lane; e < C.N * NU; e += W64) {
-    const int k = e / NU, j = e % NU;
-    const int st = k;
-    const float* B = C.B + st * NX * NU;
-    const double ur = C.u_ref ? (double)C.u_ref[st * NU + j] : 0.0;
-    double acc = C.R[j] * (C.ru[st * NU + j] - ur);
-    for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + j] * C.rlam[st * NX + l];
-    C.rg[st * NU + j] = acc;
+  for (int e = lane; e < N * NU; e += W64) {
+    const int k = e / NU, jj = e % NU;
+    gcf B = C.B + k * NX * NU;
+    const double ur = C.u_ref ? (double)C.u_ref[k * NU + jj] : 0.0;
+    double acc = C.R[jj] * (C.ru[k * NU + jj] - ur);
+    for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + jj] * C.rlam[k * NX + l];
+    C.rg[k * NU + jj] = acc;
   }
   gsync();
 }
@@ -675,9 +801,9 @@ __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     const int st = k;
-    const double* u = C.ru + st * NU + 6 * i;
-    const double* g = C.rg + st * NU + 6 * i;
-    double* mu = C.rmu + (st * 2 + i) * NROW;
+    gcd u = C.ru + st * NU + 6 * i;
+    gcd g = C.rg + st * NU + 6 * i;
+    gd mu = C.rmu + (st * 2 + i) * NROW;
     for (int r = 0; r < NROW; ++r) mu[r] = 0.0;
     if (!C.contact[st * 2 + i]) {
       for (int a = 0; a < 6; ++a) r_ineq = fmax(r_ineq, fabs(u[a]) / C.mg);
@@ -794,9 +920,9 @@ __device__ double dyn_residual(const Ctx& C) {
   for (int e = lane; e < C.N * NX; e += W64) {
     const int k = e / NX, i = e % NX;
     const int st = k;
-    const double* x = C.rx + k * NX;
-    const float* A = C.A + st * NX * NX + i * NX;
-    const float* B = C.B + st * NX * NU + i * NU;
+    gcd x = C.rx + k * NX;
+    gcf A = C.A + st * NX * NX + i * NX;
+    gcf B = C.B + st * NX * NU + i * NU;
     double ax = 0.0, bu = 0.0;
     for (int l = 0; l < NX; ++l) ax += (double)A[l] * x[l];
     for (int l = 0; l < NU; ++l) bu += (double)B[l] * C.ru[st * NU + l];
@@ -819,8 +945,8 @@ __device__ uint64_t pdas_update(const Ctx& C) {
     const int st = k;
     int code = 0;
     if (C.contact[st * 2 + i]) {
-      const double* u = C.ru + st * NU + 6 * i;
-      const double* mu = C.rmu + (st * 2 + i) * NROW;
+      gcd u = C.ru + st * NU + 6 * i;
+      gcd mu = C.rmu + (st * 2 + i) * NROW;
       for (int r = 0; r < NROW; ++r) {
         double gg[6], hh;
         wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
@@ -844,7 +970,7 @@ __device__ uint64_t pdas_update(const Ctx& C) {
 }
 
 // Faces from slack: rows whose slack is below tol * row scale.
-__device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
+__device__ void faces_from_u(const Ctx& C, gcd u_src, double tol) {
   gsync();
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * 2; e += W64) {
@@ -852,7 +978,7 @@ __device__ void faces_from_u(const Ctx& C, const double* u_src, double tol) {
     const int st = k;
     int code = 0;
     if (C.contact[st * 2 + i]) {
-      const double* u = u_src + st * NU + 6 * i;
+      gcd u = u_src + st * NU + 6 * i;
       for (int r = 0; r < NROW; ++r) {
         double gg[6], hh;
         wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
@@ -905,7 +1031,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     C.rz[rb] = 1.0;
   }
   wsync();
-  double* rc = C.rdz;   // reuse: complementarity target, then dz
+  gd rc = C.rdz;   // reuse: complementarity target, then dz
   int it = 0;
   for (; it < maxit; ++it) {
     // residuals rp and mu
@@ -1080,7 +1206,7 @@ __device__ void rollout_ru(const Ctx& C, Sh& sh) {
 }
 
 // The ADMM's input iterate, unscaled, into ru (swing inputs exactly 0).
-__device__ void admm_point(const Ctx& C, const float* zsrc, const float* sf, float tsc) {
+__device__ void admm_point(const Ctx& C, gcf zsrc, gcf sf, float tsc) {
   gsync();
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * NU; e += W64) {
@@ -1113,24 +1239,24 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
   C.fz = p.fz_max[C.b];
   C.tm = p.tau_max[C.b];
   C.mg = weight_of(p, C.b);
-  C.Q = sh.Qd;
-  C.R = sh.Rd;
-  C.A = p.A + s0 * NX * NX;
-  C.B = p.B + s0 * NX * NU;
-  C.e = p.e ? p.e + s0 * NX : nullptr;
-  C.x_ref = p.x_ref + s0 * NX;
-  C.u_ref = p.u_ref ? p.u_ref + s0 * NU : nullptr;
-  C.x0 = p.x0 + (size_t)C.b * NX;
-  C.contact = p.contact + s0 * 2;
+  C.Q = (const LMEM double*)sh.Qd;
+  C.R = (const LMEM double*)sh.Rd;
+  C.A = (gcf)(p.A + s0 * NX * NX);
+  C.B = (gcf)(p.B + s0 * NX * NU);
+  C.e = p.e ? (gcf)(p.e + s0 * NX) : nullptr;
+  C.x_ref = (gcf)(p.x_ref + s0 * NX);
+  C.u_ref = p.u_ref ? (gcf)(p.u_ref + s0 * NU) : nullptr;
+  C.x0 = (gcf)(p.x0 + (size_t)C.b * NX);
+  C.contact = (const GMEM uint8_t*)(p.contact + s0 * 2);
   {
     const int n = C.n;
-    double* blk = ws.rblk + (size_t)C.b * refine_block_doubles(n);
-    C.rK = blk;                       blk += (size_t)n * NU * NX;
+    gd blk = (gd)(ws.rblk + (size_t)C.b * refine_block_doubles(n));
+    C.rT = blk;                       blk += (size_t)n * TILE;
+    C.rK = blk;                       blk += (size_t)n * TILE;
+    C.rL = blk;                       blk += (size_t)n * TILE;
+    C.rHwx = blk;                     blk += (size_t)n * TILE;
     C.rkap = blk;                     blk += (size_t)n * NU;
-    C.rL = blk;                       blk += (size_t)n * NU * NU;
-    C.rHwx = blk;                     blk += (size_t)n * NU * NX;
     C.ru = blk;                       blk += (size_t)n * NU;
-    C.rx = blk;                       blk += (size_t)(n + 1) * NX;
     C.rlam = blk;                     blk += (size_t)n * NX;
     C.rg = blk;                       blk += (size_t)n * NU;
     C.rmu = blk;                      blk += (size_t)n * 2 * NROW;
@@ -1139,11 +1265,9 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
     C.rds = blk;                      blk += (size_t)n * 2 * NROW;
     C.rdz = blk;                      blk += (size_t)n * 2 * NROW;
     C.rdu = blk;                      blk += (size_t)n * NU;
-    C.rdx = blk;                      blk += (size_t)(n + 1) * NX;
-    C.ftab = blk;                     blk += (size_t)n * 2 * FT;
-    C.wrow = blk;                     blk += (size_t)n * 2 * NROW;
-    C.crow = blk;
-    C.faces = ws.faces + s0 * 2;
+    C.rx = blk;                       blk += (size_t)(n + 1) * NX;
+    C.rdx = blk;
+    C.faces = (GMEM int32_t*)(ws.faces + s0 * 2);
   }
   }
   if (lane < NX) sh.Qd[lane] = p.Q[(size_t)blockIdx.x * NX + lane];
@@ -1181,8 +1305,11 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
     return;
   }
 
-  const float* zsrc = (accel ? ws.cur : ws.hat) + s0 * NSTATE * NL;
-  const float* sf = ws.sf + s0;
+  // stage input tiles: everything outside the contacts' diagonal blocks and
+  // offset column stays zero
+  for (int k = 0; k < N; ++k) st_tile(C.rT + (size_t)k * TILE, zero4());
+  gcf zsrc = (gcf)((accel ? ws.cur : ws.hat) + s0 * NSTATE * NL);
+  gcf sf = (gcf)(ws.sf + s0);
   const float tsc = ws.tsc[C.b];
   admm_point(C, zsrc, sf, tsc);
 
