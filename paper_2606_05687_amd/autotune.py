@@ -37,9 +37,9 @@ def _key(dev, allow_bf16):
 
 def candidates(n_max, allow_bf16=False):
     forms = [1] if n_max <= 40 else [-1]
-    iters = [50, 100, 200, 400]
+    iters = [10, 20, 30, 50, 100, 200]
     rhos = [10.0, 30.0]
-    passes = [3, 5, 8]
+    passes = [5, 8, 12, 16]
     precs = [0, 1] if allow_bf16 else [0]
     for f, k, r, pa, p in itertools.product(forms, iters, rhos, passes, precs):
         yield dict(form=f, iters=k, rho=r, refine_passes=pa, precision=p)

@@ -172,7 +172,7 @@ __device__ void face_affine(int code, double mu, double fz, double tm, double P[
     for (int i = 0; i < 5; ++i) y[i] = ((mask >> i) & 1) && i == 4 ? fz : 0.0;
     // columns of (G G^T)^{-1} G, one solve per coordinate, and the point c
     double Gi[5][3];
-#pragma unroll
+#pragma unroll 1
     for (int col = 0; col < 3; ++col) {
       double Mc[5][5], r[5];
 #pragma unroll
@@ -742,7 +742,7 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec)
 
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} (column VC of a
 // tile) and the reduced gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
-__device__ void costates_grad(const Ctx& C, Sh& sh) {
+__device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
   gsync();
   const int lane = threadIdx.x, g = tg(), j = tj();
   const int N = __builtin_amdgcn_readfirstlane(C.N);
@@ -794,7 +794,7 @@ __device__ void costates_grad(const Ctx& C, Sh& sh) {
 
 // Row multipliers of each stance contact from its face and the gradient, and
 // the normalised KKT residuals of the current (u, x, p, mu).  Returns KKT.
-__device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
+__device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
   gsync();
   const int lane = threadIdx.x;
   double r_ineq = 0.0, stat = 0.0, term = 0.0, comp = 0.0, mumax = 0.0, neg = 0.0;
@@ -822,7 +822,7 @@ __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
     // normal cone of the apex)
     if (face_apex(code)) {
       double best = -1e300, bm[5] = {0, 0, 0, 0, 0};
-#pragma unroll
+#pragma unroll 1
       for (int drop = 0; drop < 4; ++drop) {
         const int mask = 15 & ~(1 << drop);
         double M[5][5], r[5];
@@ -913,7 +913,7 @@ __device__ double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
 }
 
 // Dynamics residual of the FP64 trajectory (rx, ru).
-__device__ double dyn_residual(const Ctx& C) {
+__device__ __attribute__((noinline)) double dyn_residual(const Ctx& C) {
   gsync();
   const int lane = threadIdx.x;
   double r = 0.0;
@@ -936,7 +936,7 @@ __device__ double dyn_residual(const Ctx& C) {
 
 // Primal-dual active-set update of the faces; returns an order-independent
 // hash of the new face set.
-__device__ uint64_t pdas_update(const Ctx& C) {
+__device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C) {
   gsync();
   const int lane = threadIdx.x;
   uint64_t hsh = 0;
@@ -970,7 +970,7 @@ __device__ uint64_t pdas_update(const Ctx& C) {
 }
 
 // Faces from slack: rows whose slack is below tol * row scale.
-__device__ void faces_from_u(const Ctx& C, gcd u_src, double tol) {
+__device__ __attribute__((noinline)) void faces_from_u(const Ctx& C, gcd u_src, double tol) {
   gsync();
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * 2; e += W64) {
@@ -996,7 +996,7 @@ __device__ void faces_from_u(const Ctx& C, gcd u_src, double tol) {
 
 // One active-set pass: equality-constrained solve on the current faces,
 // costates, multipliers and residuals.
-__device__ double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
+__device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
   riccati(C, sh, Mode::EQ, true, nullptr);
   costates_grad(C, sh);
   const double kkt = multipliers_kkt(C, res);
@@ -1004,9 +1004,43 @@ __device__ double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
   return fmax(kkt, res[0]);
 }
 
+// Faces from the interior-point iterate (row active where z > s); returns an
+// order-independent hash of the face set.
+__device__ __attribute__((noinline)) uint64_t faces_from_zs(const Ctx& C) {
+  gsync();
+  const int lane = threadIdx.x;
+  uint64_t hsh = 0;
+  for (int e = lane; e < C.N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
+    int code = 0;
+    if (C.contact[k * 2 + i]) {
+      const size_t rb = (size_t)(k * 2 + i) * NROW;
+      for (int r = 0; r < NROW; ++r)
+        if (C.rz[rb + r] > C.rs[rb + r]) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
+      if (face_apex(code)) code = (code & ~31) | FACE_APEX;
+      for (int a = 0; a < 3; ++a)
+        if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
+    }
+    C.faces[k * 2 + i] = code;
+    uint64_t v = (uint64_t)(code + 1) * 0x9E3779B97F4A7C15ull ^ ((uint64_t)(e + 1) * 0xC2B2AE3D27D4EB4Full);
+    v ^= v >> 29;
+    v *= 0xBF58476D1CE4E5B9ull;
+    hsh ^= v;
+  }
+  wsync();
+  return wave_xor(hsh);
+}
+
 // Interior-point fallback.  Rows scaled by mg (force rows) and tau_max
-// (moment rows).  Leaves faces from z > s.
-__device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
+// (moment rows).  Crossover: once the face guess z > s is the same after two
+// consecutive iterations, one equality-constrained pass on those faces is
+// tried (the iterate is kept aside and restored if it does not certify).
+// Returns the number of iterations; *certified tells whether a crossover pass
+// certified (then ru, rx, res and *kkt are that pass's), else the faces from
+// z > s are left for the polish passes.
+__device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, double tol, int* passes,
+                   double res[PINMPC_NRES], double* kkt_out, bool* certified) {
+  *certified = false;
   gsync();
   const int lane = threadIdx.x;
   const int N = C.N;
@@ -1033,6 +1067,7 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
   wsync();
   gd rc = C.rdz;   // reuse: complementarity target, then dz
   int it = 0;
+  uint64_t hprev = 0;
   for (; it < maxit; ++it) {
     // residuals rp and mu
     double smz = 0.0, rpn = 0.0;
@@ -1140,24 +1175,27 @@ __device__ int ipm(const Ctx& C, Sh& sh, int maxit) {
     for (int e = lane; e < (N + 1) * NX; e += W64)
       C.rx[e] += a * C.rdx[e];
     wsync();
-  }
-  // faces from z > s (rows were updated by other lanes)
-  gsync();
-  for (int e = lane; e < N * 2; e += W64) {
-    const int k = e >> 1, i = e & 1;
-    const int st = k;
-    int code = 0;
-    if (C.contact[st * 2 + i]) {
-      const size_t rb = (st * 2 + i) * NROW;
-      for (int r = 0; r < NROW; ++r)
-        if (C.rz[rb + r] > C.rs[rb + r]) code |= (r < 5) ? (1 << r) : (1 << (8 + (r - 5)));
-      if (face_apex(code)) code = (code & ~31) | FACE_APEX;
-      for (int a = 0; a < 3; ++a)
-        if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
+    const uint64_t h = faces_from_zs(C);
+    if (it >= 1 && h == hprev) {
+      // the step buffers are free between iterations: keep the iterate there
+      gsync();
+      for (int e = lane; e < N * NU; e += W64) C.rdu[e] = C.ru[e];
+      for (int e = lane; e < (N + 1) * NX; e += W64) C.rdx[e] = C.rx[e];
+      const double kkt = eq_pass(C, sh, res);
+      ++*passes;
+      if (kkt <= tol) {
+        *kkt_out = kkt;
+        *certified = true;
+        return it + 1;
+      }
+      gsync();
+      for (int e = lane; e < N * NU; e += W64) C.ru[e] = C.rdu[e];
+      for (int e = lane; e < (N + 1) * NX; e += W64) C.rx[e] = C.rdx[e];
+      wsync();
     }
-    C.faces[st * 2 + i] = code;
+    hprev = h;
   }
-  wsync();
+  faces_from_zs(C);
   return it;
 }
 
@@ -1182,7 +1220,7 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int*
   return false;
 }
 
-__device__ void rollout_ru(const Ctx& C, Sh& sh) {
+__device__ __attribute__((noinline)) void rollout_ru(const Ctx& C, Sh& sh) {
   gsync();
   // x = rollout of ru from x0, in FP64, into rx
   const int lane = threadIdx.x;
@@ -1206,7 +1244,7 @@ __device__ void rollout_ru(const Ctx& C, Sh& sh) {
 }
 
 // The ADMM's input iterate, unscaled, into ru (swing inputs exactly 0).
-__device__ void admm_point(const Ctx& C, gcf zsrc, gcf sf, float tsc) {
+__device__ __attribute__((noinline)) void admm_point(const Ctx& C, gcf zsrc, gcf sf, float tsc) {
   gsync();
   const int lane = threadIdx.x;
   for (int e = lane; e < C.N * NU; e += W64) {
@@ -1219,7 +1257,7 @@ __device__ void admm_point(const Ctx& C, gcf zsrc, gcf sf, float tsc) {
   wsync();
 }
 
-__global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, float* out_u,
+__global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, float* out_u,
                                                     float* out_x, float* out_res,
                                                     int32_t* out_iters, int32_t* out_status,
                                                     int admm_iters, int accel, int refine,
@@ -1324,9 +1362,9 @@ __global__ void __launch_bounds__(64) refine_kernel(Problem p, Workspace ws, flo
       // interior point from the ADMM point (ru was overwritten by the passes)
       admm_point(C, zsrc, sf, tsc);
       rollout_ru(C, sh);
-      const int its = ipm(C, sh, ipm_max);
+      const int its = ipm(C, sh, ipm_max, tol, &passes, res, &kkt, &ok);
       passes += its;
-      ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
+      if (!ok) ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
     }
   } else {
     // the ADMM point as it is: rollout, faces from slack, residuals

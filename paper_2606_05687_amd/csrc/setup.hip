@@ -24,27 +24,30 @@ __device__ inline double scale_of(const Problem& p, int b, int k, int j, bool sc
   return (j % 6) < 3 ? sf : (double)p.tau_max[b];
 }
 
-// In-place Gauss-Jordan inverse of an SPD n x n matrix held in LDS as the
-// augmented [n][2n] array [M | I]; on return the right half is M^{-1}.
-// SPD matrices need no pivoting.  n <= 32.
-__device__ void gj_inverse(double* aug, int n) {
-  __shared__ double fac[32];
-  const int lane = threadIdx.x;
-  const int w = 2 * n;
-  for (int j = 0; j < n; ++j) {
-    __syncthreads();
-    const double piv = aug[j * w + j];
-    __syncthreads();
-    for (int c = lane; c < w; c += 64) aug[j * w + c] /= piv;
-    __syncthreads();
-    if (lane < n) fac[lane] = aug[lane * w + j];
-    __syncthreads();
-    for (int e = lane; e < n * w; e += 64) {
-      const int r = e / w, c = e % w;
-      if (r != j) aug[r * w + c] -= fac[r] * aug[j * w + c];
-    }
+__device__ inline double readlane_d(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Gauss-Jordan inverse of an SPD n x n matrix (no pivoting needed) with lane
+// c holding column c of the augmented [M | I] in registers (lanes 0..n-1 the
+// matrix, lanes n..2n-1 the identity); the pivot column is broadcast from its
+// lane.  Afterwards lanes n..2n-1 hold the columns of M^{-1}.
+template <int n>
+__device__ inline void gj_columns(double (&col)[n]) {
+#pragma unroll
+  for (int p = 0; p < n; ++p) {
+    double pc[n];
+#pragma unroll
+    for (int r = 0; r < n; ++r) pc[r] = readlane_d(col[r], p);
+    const double t = col[p] / pc[p];
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+      if (r != p) col[r] -= pc[r] * t;
+    col[p] = t;
   }
-  __syncthreads();
 }
 
 __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, float rho,
@@ -53,11 +56,8 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
   const int b = s / p.n_max, k = s % p.n_max;
   const int lane = threadIdx.x;
   const int N = horizon(p, b);
-  __shared__ double sA1[NX * NX];              // A_{k+1}
+  __shared__ double sTop[NX * NL];             // [A_{k+1} | Bt_{k+1}], 13 x 25
   __shared__ double sBt[NX * NU];              // Bt_k
-  __shared__ double sBt1[NX * NU];             // Bt_{k+1}
-  __shared__ double augM[NU * 2 * NU];
-  __shared__ double augH[NL * 2 * NL];
   const bool sc = scaling != 0;
 
   if (k >= N) {   // padding stage: benign values, never read by the sweep
@@ -74,76 +74,100 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
     const double v = (double)Bk[i] * scale_of(p, b, k, j, sc);
     sBt[i] = v;
     ws.Bt[(size_t)s * NX * NU + i] = (float)v;
+    if (bf16) ws.Btbf[(size_t)s * NX * NU + i] = to_bf16((float)v);
   }
   const bool has_next = (k + 1 < N);
   if (has_next) {
     const float* A1 = p.A + (size_t)(s + 1) * NX * NX;
     const float* B1 = p.B + (size_t)(s + 1) * NX * NU;
-    for (int i = lane; i < NX * NX; i += 64) sA1[i] = (double)A1[i];
-    for (int i = lane; i < NX * NU; i += 64) sBt1[i] = (double)B1[i] * scale_of(p, b, k + 1, i % NU, sc);
+    for (int e = lane; e < NX * NL; e += 64) {
+      const int i = e / NL, c = e % NL;
+      sTop[e] = (c < NX) ? (double)A1[i * NX + c]
+                         : (double)B1[i * NU + c - NX] * scale_of(p, b, k + 1, c - NX, sc);
+    }
   }
   if (lane == 0) {
     ws.sf[s] = (float)scale_of(p, b, k, 0, sc);
     if (k == 0) ws.tsc[b] = sc ? p.tau_max[b] : 1.f;
   }
-  __syncthreads();
-
-  // M_k: [Bt^T Bt + I | I]
-  for (int e = lane; e < NU * NU; e += 64) {
-    const int r = e / NU, c = e % NU;
-    double acc = (r == c) ? 1.0 : 0.0;
-    for (int i = 0; i < NX; ++i) acc += sBt[i * NU + r] * sBt[i * NU + c];
-    augM[r * 2 * NU + c] = acc;
-    augM[r * 2 * NU + NU + c] = (r == c) ? 1.0 : 0.0;
-  }
-  // H_k^{-1}: diag(Q, R S^2) + rho I + [has_next] rho Abar_{k+1}^T Abar_{k+1}
-  for (int e = lane; e < NL * NL; e += 64) {
-    const int r = e / NL, c = e % NL;
-    double acc = 0.0;
-    if (r == c) {
-      if (r < NX) acc = (double)p.Q[(size_t)b * NX + r];
-      else {
-        const double sj = scale_of(p, b, k, r - NX, sc);
-        acc = (double)p.R[(size_t)b * NU + r - NX] * sj * sj;
-      }
-      acc += rho;
-    }
-    if (has_next) {
-      double g = 0.0;
-      // Abar_{k+1} columns: c < 13 -> (A col c; 0), c >= 13 -> (Bt col c-13; e_{c-13})
-      for (int i = 0; i < NX; ++i) {
-        const double ar = r < NX ? sA1[i * NX + r] : sBt1[i * NU + (r - NX)];
-        const double ac = c < NX ? sA1[i * NX + c] : sBt1[i * NU + (c - NX)];
-        g += ar * ac;
-      }
-      if (r >= NX && r == c) g += 1.0;
-      acc += rho * g;
-    }
-    augH[r * 2 * NL + c] = acc;
-    augH[r * 2 * NL + NL + c] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  gj_inverse(augM, NU);
-  gj_inverse(augH, NL);
-  for (int r = 0; r < NU; ++r)
-    for (int c = r + lane; c < NU; c += 64)
-      ws.Mp[(size_t)s * NM + pk(r, c, NU)] =
-          (float)(0.5 * (augM[r * 2 * NU + NU + c] + augM[c * 2 * NU + NU + r]));
-  for (int r = 0; r < NL; ++r)
-    for (int c = r + lane; c < NL; c += 64)
-      ws.Hp[(size_t)s * NH + pk(r, c, NL)] =
-          (float)(0.5 * (augH[r * 2 * NL + NL + c] + augH[c * 2 * NL + NL + r]));
   if (bf16) {
     const float* A = p.A + (size_t)s * NX * NX;
     for (int i = lane; i < NX * NX; i += 64) ws.Abf[(size_t)s * NX * NX + i] = to_bf16(A[i]);
-    for (int i = lane; i < NX * NU; i += 64)
-      ws.Btbf[(size_t)s * NX * NU + i] = to_bf16((float)sBt[i]);
-    for (int r = 0; r < NU; ++r)
-      for (int c = r + lane; c < NU; c += 64)
-        ws.Mbf[(size_t)s * NM + pk(r, c, NU)] = to_bf16(ws.Mp[(size_t)s * NM + pk(r, c, NU)]);
-    for (int r = 0; r < NL; ++r)
-      for (int c = r + lane; c < NL; c += 64)
-        ws.Hbf[(size_t)s * NH + pk(r, c, NL)] = to_bf16(ws.Hp[(size_t)s * NH + pk(r, c, NL)]);
+  }
+  __syncthreads();
+
+  // H_k^{-1} = diag(Q, R S^2) + rho I + [has_next] rho Abar_{k+1}^T Abar_{k+1},
+  // with Abar_{k+1} = [[A, Bt], [0, I]]: lane c < 25 forms its column c
+  {
+    double col[NL];
+    if (lane < NL) {
+      double top[NX];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) top[i] = has_next ? sTop[i * NL + lane] : 0.0;
+      double dg;
+      if (lane < NX) {
+        dg = (double)p.Q[(size_t)b * NX + lane];
+      } else {
+        const double sj = scale_of(p, b, k, lane - NX, sc);
+        dg = (double)p.R[(size_t)b * NU + lane - NX] * sj * sj;
+      }
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        double g = 0.0;
+        if (has_next) {
+#pragma unroll
+          for (int i = 0; i < NX; ++i) g += sTop[i * NL + r] * top[i];
+          if (r >= NX && r == lane) g += 1.0;
+        }
+        col[r] = rho * g + ((r == lane) ? dg + rho : 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NL; ++r) col[r] = (r == lane - NL) ? 1.0 : 0.0;
+    }
+    gj_columns<NL>(col);
+    if (lane >= NL && lane < 2 * NL) {
+      const int c = lane - NL;
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        if (r <= c) {
+          const float v = (float)col[r];
+          ws.Hp[(size_t)s * NH + pk(r, c, NL)] = v;
+          if (bf16) ws.Hbf[(size_t)s * NH + pk(r, c, NL)] = to_bf16(v);
+        }
+      }
+    }
+  }
+  // M_k = (Bt^T Bt + I)^{-1}: lane c < 12 forms column c
+  {
+    double col[NU];
+    if (lane < NU) {
+      double bc[NX];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * NU + lane];
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        double g = (r == lane) ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) g += sBt[i * NU + r] * bc[i];
+        col[r] = g;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NU; ++r) col[r] = (r == lane - NU) ? 1.0 : 0.0;
+    }
+    gj_columns<NU>(col);
+    if (lane >= NU && lane < 2 * NU) {
+      const int c = lane - NU;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        if (r <= c) {
+          const float v = (float)col[r];
+          ws.Mp[(size_t)s * NM + pk(r, c, NU)] = v;
+          if (bf16) ws.Mbf[(size_t)s * NM + pk(r, c, NU)] = to_bf16(v);
+        }
+      }
+    }
   }
   if (lane < NL) {
     double q;
