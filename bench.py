@@ -38,6 +38,15 @@ SWEEP_BYTES_PER_STAGE = 3070 + 2000
 # vector ops + projection 150), block 3 and the restart test 200
 SWEEP_FLOPS_PER_STAGE = 338 + 312 + 288 + 1250 + 100 + 650 + 312 + 150 + 200
 FP32_PEAK_TFLOPS = 157.3
+# Algorithmic FP64 flops of one refinement pass per stage (an active-set pass
+# or an interior-point iteration; dense 13-state / 12-input shapes, 2 flops per
+# multiply-add): Bp = B P 3744, d = B c + e 312, W A 4394, W d 338, W Bp 4056,
+# Bp^T W Bp 3744, Bp^T [W A | W d] 4368, P R P and P R c 3744, Gauss-Jordan on
+# [H | Hwx | hw] 5904, S and s 9100, forward rollout 1250, costates and gradient
+# 650, multipliers and residuals 500
+REFINE_FLOPS_PER_PASS_STAGE = (3744 + 312 + 4394 + 338 + 4056 + 3744 + 4368 + 3744 + 5904 +
+                               9100 + 1250 + 650 + 500)
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -48,12 +57,21 @@ def parse():
     ap.add_argument("--iters", type=int, default=100, help="ADMM sweeps per solve")
     ap.add_argument("--form", type=int, default=0, help="0 plain, 1 fused, -1 packed")
     ap.add_argument("--rho", type=float, default=10.0)
+    ap.add_argument("--refine-passes", type=int, default=8,
+                    help="active-set passes before the interior-point fallback")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: choose form/K/rho with the autotuner on a held-out batch "
                          "(problems 4096..8191 of the same generator) before timing")
-    ap.add_argument("--cpu-sample", type=int, default=256,
-                    help="problems in the oracle CPU-baseline sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="problems in the oracle CPU-baseline sample (0: skip); the default "
+                         "is the whole batch, about 20 core-seconds of oracle work")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a plain streaming kernel over this many bytes (read once, "
+                         "written once), to scale the HBM byte counters")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: time captured-graph replays (phase times then come from a "
+                         "second, uncaptured loop)")
     return ap.parse_args()
 
 
@@ -106,15 +124,16 @@ def _kernel_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_src, launches_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current source of the kernel; else None."""
+def measured_traffic(kernel_src, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
+    if it was taken on the current source of the kernel; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        t = json.load(f)
-    if t.get("source_sha") != _kernel_sha(kernel_src):
+        t = json.load(f).get(kernel)
+    if not t or t.get("source_sha") != _kernel_sha(kernel_src):
         return None
     return t.get("bytes_per_launch")
 
@@ -129,11 +148,24 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_kernel": "elementwise multiply by 1", "bytes_read": n * 4,
+                          "bytes_written": n * 4, "reps": 3}), flush=True)
+        return
+
     import mpcgen
     from paper_2606_05687_amd import binding
 
     torch.cuda.set_device(0)
-    settings = dict(iters=args.iters, form=args.form, rho=args.rho)
+    settings = dict(iters=args.iters, form=args.form, rho=args.rho,
+                    refine_passes=args.refine_passes)
     tuned = None
     if args.autotune:
         from paper_2606_05687_amd import autotune
@@ -148,12 +180,8 @@ def main():
     stages = int(batch["N"].sum())
     dev = binding.to_device(batch, "cuda:0")
     solver = binding.Solver(0, **settings)
-    # phase split (setup / sweeps / refinement) from an uncaptured solve
-    solver.set(graph=0)
+    solver.set(graph=int(args.graph))
     out = solver.alloc_out(dev)
-    solver.solve(dev, out)
-    phase_split = solver.stats()
-    solver.set(graph=1)
     bstruct = binding.make_batch_struct(dev)
     stream = torch.cuda.current_stream()
 
@@ -161,9 +189,10 @@ def main():
         solver.solve(dev, out, stream=stream, batch_struct=bstruct)
     torch.cuda.synchronize()
 
-    # timed region: K solves enqueued back to back on one stream (graph
-    # replays), bracketed by device synchronisation; per-solve latency from
-    # HIP events recorded around each solve on the same stream
+    # timed region: K solves enqueued back to back on one stream, bracketed by
+    # device synchronisation; per-solve latency from HIP events recorded
+    # around each solve on that stream, per-kernel times from the library's
+    # own HIP events on the same stream (kept for the last STATS_RING solves)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -183,32 +212,64 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = certified / elapsed
 
-    admm_ms = phase_split["admm_ms"]
-    refine_ms = phase_split["refine_ms"]
-    setup_ms = phase_split["setup_ms"]
+    if args.graph:
+        # graph replays report totals only: per-kernel times from an
+        # uncaptured loop of the same length right after
+        solver.set(graph=0)
+        for _ in range(args.steps):
+            solver.solve(dev, out, stream=stream, batch_struct=bstruct)
+        torch.cuda.synchronize()
+    nk = min(args.steps, binding.STATS_RING)
+    phases = [solver.stats(back=i) for i in range(nk)]
+    setup_ms = float(np.mean([ph["setup_ms"] for ph in phases]))
+    admm_ms = float(np.mean([ph["admm_ms"] for ph in phases]))
+    refine_ms = float(np.mean([ph["refine_ms"] for ph in phases]))
     K = settings["iters"]
-    sweep_ms = admm_ms / max(1, K)
-    sweep_bytes = stages * SWEEP_BYTES_PER_STAGE
-    # dominant phase: ADMM sweeps (HBM-bound) or the FP64 refinement
-    if admm_ms >= refine_ms and settings["form"] == 0:
-        achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    iters_out = out["iters"].cpu().numpy().astype(np.int64)
+    passes = iters_out - K
+    N_b = batch["N"].astype(np.int64)
+    kernels = {
+        "setup_kernel": {"ms": setup_ms},
+        "admm": {"ms": admm_ms, "form": {0: "plain", 1: "fused", -1: "packed"}[settings["form"]]},
+        "refine_kernel": {"ms": refine_ms},
+    }
+    # algorithmic work of each phase per launch
+    refine_flops = float((N_b * passes).sum()) * REFINE_FLOPS_PER_PASS_STAGE
+    kernels["refine_kernel"]["tflops"] = refine_flops / (refine_ms * 1e-3) / 1e12
+    if settings["form"] == 0:
+        sweep_bytes = stages * SWEEP_BYTES_PER_STAGE
+        kernels["admm"]["gbs"] = sweep_bytes * K / (admm_ms * 1e-3) / 1e9
+    else:
+        kernels["admm"]["tflops"] = stages * SWEEP_FLOPS_PER_STAGE * K / (admm_ms * 1e-3) / 1e12
+    dominant = max(kernels, key=lambda k: kernels[k]["ms"])
+    if dominant == "refine_kernel":
+        src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "refine.hip")
+        achieved = kernels["refine_kernel"]["tflops"]
+        roof = {"kernel": "refine_kernel", "bound": "mfma", "achieved": achieved,
+                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                "traffic": measured_traffic(src, "refine_kernel"),
+                "launch_ms": refine_ms, "flops_per_launch": refine_flops, "dtype": "f64"}
+    elif dominant == "admm" and settings["form"] == 0:
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_plain.hip")
+        achieved = kernels["admm"]["gbs"]
         roof = {"kernel": "admm_sweep_kernel", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(src, sweep_bytes),
-                "launch_ms": sweep_ms, "bytes_per_launch": sweep_bytes}
-    elif admm_ms >= refine_ms:
-        flops = stages * SWEEP_FLOPS_PER_STAGE * K
-        achieved = flops / (admm_ms * 1e-3) / 1e12
+                "traffic": measured_traffic(src, "admm_sweep_kernel"),
+                "launch_ms": admm_ms / max(1, K), "bytes_per_launch": stages * SWEEP_BYTES_PER_STAGE}
+    elif dominant == "admm":
+        src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_fused.hip")
+        achieved = kernels["admm"]["tflops"]
         roof = {"kernel": "admm_fused_kernel", "bound": "alu", "achieved": achieved,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": None, "launch_ms": admm_ms, "flops_per_launch": flops}
+                "traffic": measured_traffic(src, "admm_fused_kernel"), "launch_ms": admm_ms,
+                "flops_per_launch": stages * SWEEP_FLOPS_PER_STAGE * K}
     else:
-        roof = {"kernel": "refine_kernel", "bound": "fp64", "achieved": None,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "launch_ms": refine_ms}
+        src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "setup.hip")
+        roof = {"kernel": "setup_kernel", "bound": "mfma", "achieved": None,
+                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": measured_traffic(src, "setup_kernel"), "launch_ms": setup_ms}
     status = out["status"].cpu().numpy()
-    passes = out["iters"].cpu().numpy() - K
     line = {
         "metric": METRIC,
         "value": value,
@@ -235,6 +296,8 @@ def main():
         "refine_passes": {"mean": float(passes.mean()), "p99": float(np.percentile(passes, 99)),
                           "max": int(passes.max())},
         "phase_ms": {"setup": setup_ms, "admm": admm_ms, "refine": refine_ms},
+        "kernels": kernels,
+        "timed_graph": bool(args.graph),
         "roofline": roof,
     }
     solver.close()

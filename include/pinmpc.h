@@ -150,10 +150,22 @@ int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out,
 int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters,
                 float* z_out, void* hip_stream);
 
-/* Time of the last solve's phases in ms (host pointers; any may be NULL).
- * Blocks until the last solve finished.  setup+admm+refine = total. */
+/* Time of the last solve's phases in ms (host pointers; any may be NULL),
+ * measured with HIP events on the solve's stream.  Blocks until the last
+ * solve finished.  setup + admm + refine = total.  A solve replayed from a
+ * captured graph reports only its total (setup, admm, refine = -1).
+ * PINMPC_EINVAL if the context has made no solve. */
 int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms,
                  double* admm_ms, double* refine_ms);
+
+/* The same for an earlier solve: back = 0 is the last solve, 1 the one
+ * before, up to PINMPC_STATS_RING - 1 (a context keeps the events of its last
+ * PINMPC_STATS_RING solves, so back-to-back solves can be timed without a
+ * synchronisation between them).  PINMPC_EINVAL if back is out of that range
+ * or fewer than back + 1 solves were made. */
+#define PINMPC_STATS_RING 64
+int pinmpc_stats_back(pinmpc_ctx c, int32_t back, double* total_ms, double* setup_ms,
+                      double* admm_ms, double* refine_ms);
 
 int pinmpc_destroy(pinmpc_ctx c);
 

@@ -81,6 +81,8 @@ EXPORTS = {
     "pinmpc_admm": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "pinmpc_stats": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 4),
+    "pinmpc_stats_back": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32] +
+                          [ctypes.POINTER(ctypes.c_double)] * 4),
     "pinmpc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pinmpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pinmpc_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
@@ -97,6 +99,9 @@ EXPORTS = {
 }
 
 _lib = None
+
+
+STATS_RING = 64   # PINMPC_STATS_RING
 
 
 def load(path: str = LIB_PATH):
@@ -235,9 +240,11 @@ class Solver:
                                   ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
         return z
 
-    def stats(self):
+    def stats(self, back: int = 0):
+        """Phase times (ms) of the last solve, or of the solve `back` solves
+        before it (up to STATS_RING - 1)."""
         vals = [ctypes.c_double() for _ in range(4)]
-        _check(load().pinmpc_stats(self._h, *[ctypes.byref(v) for v in vals]))
+        _check(load().pinmpc_stats_back(self._h, int(back), *[ctypes.byref(v) for v in vals]))
         return dict(zip(("total_ms", "setup_ms", "admm_ms", "refine_ms"), [v.value for v in vals]))
 
 

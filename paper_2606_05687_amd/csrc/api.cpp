@@ -39,9 +39,13 @@ struct pinmpc_ctx_s {
   pinmpc_settings s{};
   void* mem = nullptr;
   size_t mem_bytes = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // phase events of the last PINMPC_STATS_RING solves (start, after setup,
+  // after the sweeps, end); ev points at the current solve's set
+  hipEvent_t ring[PINMPC_STATS_RING][4] = {};
+  bool ring_graph[PINMPC_STATS_RING] = {};   // that solve replayed a graph
+  int64_t nsolves = 0;
+  hipEvent_t* ev = ring[0];
   bool have_timing = false;
-  bool last_graph = false;      // last solve replayed a graph (no phase split)
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey{};
 };
@@ -233,8 +237,9 @@ int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)64 << 30;
   c->s = *s;
   c->have_timing = true;
-  for (auto& e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) c->have_timing = false;
+  for (auto& set : c->ring)
+    for (auto& e : set)
+      if (hipEventCreate(&e) != hipSuccess) c->have_timing = false;
   *out = c;
   return PINMPC_OK;
 }
@@ -314,13 +319,18 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_i
       if (crc) return crc;
       std::memcpy(&c->gkey, &key, sizeof(key));
     }
+    const int slot = (int)(c->nsolves % PINMPC_STATS_RING);
+    c->ev = c->ring[slot];
+    c->ring_graph[slot] = true;
     if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
     if (hipGraphLaunch(c->gexec, st) != hipSuccess) return PINMPC_EDEVICE;
     if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
-    c->last_graph = true;
+    ++c->nsolves;
     return PINMPC_OK;
   }
-  c->last_graph = false;
+  const int slot = (int)(c->nsolves % PINMPC_STATS_RING);
+  c->ev = c->ring[slot];
+  c->ring_graph[slot] = false;
   if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
   rc = run_admm(c, p, w, c->s.iters, st);
   if (rc) return rc;
@@ -328,6 +338,7 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_i
   if (c->have_timing) (void)hipEventRecord(c->ev[2], st);
   if (launch_refine(p, w, c->s, *out, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
+  ++c->nsolves;
   return PINMPC_OK;
 }
 
@@ -367,13 +378,16 @@ int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters, float* z_ou
   return PINMPC_OK;
 }
 
-int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_ms,
-                 double* refine_ms) {
-  if (!c || !c->have_timing) return PINMPC_EINVAL;
-  if (hipEventSynchronize(c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
-  if (c->last_graph) {
+int pinmpc_stats_back(pinmpc_ctx c, int32_t back, double* total_ms, double* setup_ms,
+                      double* admm_ms, double* refine_ms) {
+  if (!c || !c->have_timing || back < 0 || back >= PINMPC_STATS_RING || back >= c->nsolves)
+    return PINMPC_EINVAL;
+  const int slot = (int)((c->nsolves - 1 - back) % PINMPC_STATS_RING);
+  hipEvent_t* ev = c->ring[slot];
+  if (hipEventSynchronize(ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  if (c->ring_graph[slot]) {
     float t = 0;
-    if (hipEventElapsedTime(&t, c->ev[0], c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+    if (hipEventElapsedTime(&t, ev[0], ev[3]) != hipSuccess) return PINMPC_EDEVICE;
     if (total_ms) *total_ms = t;
     if (setup_ms) *setup_ms = -1.0;
     if (admm_ms) *admm_ms = -1.0;
@@ -381,14 +395,19 @@ int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_
     return PINMPC_OK;
   }
   float t01 = 0, t12 = 0, t23 = 0;
-  if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) != hipSuccess) return PINMPC_EDEVICE;
-  if (hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) != hipSuccess) return PINMPC_EDEVICE;
-  if (hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  if (hipEventElapsedTime(&t01, ev[0], ev[1]) != hipSuccess) return PINMPC_EDEVICE;
+  if (hipEventElapsedTime(&t12, ev[1], ev[2]) != hipSuccess) return PINMPC_EDEVICE;
+  if (hipEventElapsedTime(&t23, ev[2], ev[3]) != hipSuccess) return PINMPC_EDEVICE;
   if (setup_ms) *setup_ms = t01;
   if (admm_ms) *admm_ms = t12;
   if (refine_ms) *refine_ms = t23;
   if (total_ms) *total_ms = (double)t01 + t12 + t23;
   return PINMPC_OK;
+}
+
+int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_ms,
+                 double* refine_ms) {
+  return pinmpc_stats_back(c, 0, total_ms, setup_ms, admm_ms, refine_ms);
 }
 
 int pinmpc_destroy(pinmpc_ctx c) {
@@ -397,8 +416,9 @@ int pinmpc_destroy(pinmpc_ctx c) {
   (void)hipDeviceSynchronize();
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->mem) (void)hipFree(c->mem);
-  for (auto& e : c->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& set : c->ring)
+    for (auto& e : set)
+      if (e) (void)hipEventDestroy(e);
   delete c;
   return PINMPC_OK;
 }

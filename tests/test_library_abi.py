@@ -48,3 +48,14 @@ def test_default_settings_and_errors():
     h = ctypes.c_void_p()
     bad = binding.default_settings(rho=-1.0)
     assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1
+
+
+def test_stats_ring_matches_header_and_rejects_bad_calls():
+    text = open(os.path.join(ROOT, "include", "pinmpc.h")).read()
+    ring = int(re.search(r"#define PINMPC_STATS_RING (\d+)", text).group(1))
+    assert ring == binding.STATS_RING
+    lib = binding.load()
+    d = [ctypes.c_double() for _ in range(4)]
+    refs = [ctypes.byref(v) for v in d]
+    assert lib.pinmpc_stats_back(None, 0, *refs) == -1
+    assert lib.pinmpc_stats(None, *refs) == -1
