@@ -69,6 +69,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain streaming kernel over this many bytes (read once, "
                          "written once), to scale the HBM byte counters")
+    ap.add_argument("--pmc-summary", default="",
+                    help="only summarise rocprofv3 --pmc runs found under this folder "
+                         "(pmc_fetch, pmc_write, pmc_copy_fetch, pmc_copy_write) into "
+                         "profiles/traffic.json")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: time captured-graph replays (phase times then come from a "
                          "second, uncaptured loop)")
@@ -119,9 +123,89 @@ def cpu_baseline(sample, workers):
     }
 
 
+KERNEL_SOURCES = {
+    "refine_kernel": "refine.hip",
+    "setup_kernel": "setup.hip",
+    "admm_fused_kernel": "admm_fused.hip",
+    "admm_sweep_kernel": "admm_plain.hip",
+}
+
+
 def _kernel_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of a kernel's source together with the shared internal header."""
+    h = hashlib.sha256()
+    for f in (path, os.path.join(os.path.dirname(path), "pinmpc_internal.h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(run_dir):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(run_dir, "*counter_collection.csv")):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+TUNED = "--autotune 0 --form 1 --iters 10 --rho 30 --refine-passes 12 --cpu-sample 0"
+PMC_COMMANDS = [
+    f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
+    f"python3 bench.py {TUNED} --steps 2 --warmup 1",
+    f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o w --output-format csv -- "
+    f"python3 bench.py {TUNED} --steps 2 --warmup 1",
+    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_copy_fetch -o cf --output-format csv -- "
+    "python3 bench.py --copy-calibration 1073741824",
+    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_copy_write -o cw --output-format csv -- "
+    "python3 bench.py --copy-calibration 1073741824",
+    "python3 bench.py --pmc-summary gpurun_out",
+]
+
+
+def pmc_summary(prof_dir, command):
+    """HBM bytes per launch of the library's kernels from two rocprofv3 --pmc
+    runs of the benchmark (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
+    scaled by what the same counter reads for the --copy-calibration kernel,
+    whose bytes are known.  Writes profiles/traffic.json; returns a text
+    summary."""
+    cal = {}
+    for counter, sub in (("FETCH_SIZE", "pmc_copy_fetch"), ("WRITE_SIZE", "pmc_copy_write")):
+        vals = [float(r["Counter_Value"]) for r in _counter_rows(os.path.join(prof_dir, sub))
+                if r["Counter_Name"] == counter and "AUnaryFunctor" in r["Kernel_Name"]]
+        known_kib = 1073741824 / 1024.0
+        cal[counter] = {"dispatches": len(vals), "mean_kib": sum(vals) / len(vals),
+                        "scale": known_kib / (sum(vals) / len(vals))}
+    out = {"calibration": {"kernel": "elementwise multiply by 1 over 1 GiB (read 1 GiB, write 1 GiB)",
+                           "FETCH_SIZE": cal["FETCH_SIZE"], "WRITE_SIZE": cal["WRITE_SIZE"]},
+           "commands": PMC_COMMANDS}
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes per launch |",
+             "|---|---|---|---|---|"]
+    for kernel, src in KERNEL_SOURCES.items():
+        per = {}
+        for counter, sub in (("FETCH_SIZE", "pmc_fetch"), ("WRITE_SIZE", "pmc_write")):
+            vals = [float(r["Counter_Value"]) for r in _counter_rows(os.path.join(prof_dir, sub))
+                    if r["Counter_Name"] == counter and
+                    ("::" + kernel + "(" in r["Kernel_Name"] or "::" + kernel + "<" in r["Kernel_Name"])]
+            if vals:
+                per[counter] = (len(vals), sum(vals) / len(vals))
+        if len(per) < 2:
+            continue
+        nb = per["FETCH_SIZE"][1] * 1024 * cal["FETCH_SIZE"]["scale"] + \
+            per["WRITE_SIZE"][1] * 1024 * cal["WRITE_SIZE"]["scale"]
+        out[kernel] = {"source_sha": _kernel_sha(os.path.join(ROOT, "paper_2606_05687_amd", "csrc", src)),
+                       "fetch_kib": per["FETCH_SIZE"][1], "write_kib": per["WRITE_SIZE"][1],
+                       "bytes_per_launch": nb}
+        lines.append(f"| {kernel} | {per['FETCH_SIZE'][0]} | {per['FETCH_SIZE'][1]:.0f} | "
+                     f"{per['WRITE_SIZE'][1]:.0f} | {nb / 1e9:.3f} GB |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    lines += ["", f"FETCH_SIZE scale {cal['FETCH_SIZE']['scale']:.4f} "
+              f"(calibration kernel reads {cal['FETCH_SIZE']['mean_kib']:.0f} KiB for 1 GiB read), "
+              f"WRITE_SIZE scale {cal['WRITE_SIZE']['scale']:.4f} "
+              f"({cal['WRITE_SIZE']['mean_kib']:.0f} KiB for 1 GiB written)"]
+    return "\n".join(lines)
 
 
 def measured_traffic(kernel_src, kernel):
@@ -140,6 +224,9 @@ def measured_traffic(kernel_src, kernel):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary, " ".join(sys.argv[1:])))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the batch shards across GPUs with no communication, see DESIGN.md",
