@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--rho", type=float, default=10.0)
     ap.add_argument("--refine-passes", type=int, default=8,
                     help="active-set passes before the interior-point fallback")
+    ap.add_argument("--first-passes", type=int, default=4,
+                    help="active-set passes every problem runs in the first refinement launch")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: choose form/K/rho with the autotuner on a held-out batch "
                          "(problems 4096..8191 of the same generator) before timing")
@@ -252,7 +254,7 @@ def main():
 
     torch.cuda.set_device(0)
     settings = dict(iters=args.iters, form=args.form, rho=args.rho,
-                    refine_passes=args.refine_passes)
+                    refine_passes=args.refine_passes, first_passes=args.first_passes)
     tuned = None
     if args.autotune:
         from paper_2606_05687_amd import autotune
@@ -375,6 +377,7 @@ def main():
                    "form": {0: "plain", 1: "fused", -1: "packed"}[settings["form"]],
                    "precision": "bf16" if settings.get("precision") else "fp32",
                    "refine_passes": int(settings.get("refine_passes", 8)),
+                   "first_passes": int(settings.get("first_passes", 4)),
                    "autotuned": bool(tuned)},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),

@@ -90,6 +90,12 @@ typedef struct {
   int32_t graph;           /* 1: capture the whole solve as a hipGraph on first
                               use and replay it while the batch shape, buffers
                               and settings are unchanged; default 1 */
+  int32_t first_passes;    /* active-set passes run for every problem in the
+                              first refinement launch; a problem they do not
+                              certify continues (remaining passes, then the
+                              interior point) in a second launch with the
+                              other uncertified problems.  0: all passes in
+                              the first launch; default 4 */
 } pinmpc_settings;
 
 typedef struct pinmpc_ctx_s* pinmpc_ctx;

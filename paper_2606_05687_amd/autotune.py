@@ -3,7 +3,9 @@
 Chooses, by measurement on a sample of the workload, the sweep form (one
 launch per sweep, fused, or horizon-class packed), the number of ADMM sweeps
 K (more sweeps cost sweep time but give the FP64 refinement a better active
-set and fewer passes), the penalty rho and the operator precision.  The score
+set and fewer passes), the penalty rho, the active-set pass budget and how
+many of those passes run for every problem before the uncertified ones are
+handed to the second refinement launch, and the operator precision.  The score
 is certified solves per second: problems whose status is certified and whose
 reported KKT residuals are all <= the bar, divided by the measured solve time;
 a candidate that certifies fewer than ``min_certified`` of the sample is
@@ -37,12 +39,13 @@ def _key(dev, allow_bf16):
 
 def candidates(n_max, allow_bf16=False):
     forms = [1] if n_max <= 40 else [-1]
-    iters = [10, 20, 30, 50, 100, 200]
+    iters = [10, 20, 50]
     rhos = [10.0, 30.0]
-    passes = [5, 8, 12, 16]
+    passes = [8, 12, 16]
+    firsts = [2, 4, 0]
     precs = [0, 1] if allow_bf16 else [0]
-    for f, k, r, pa, p in itertools.product(forms, iters, rhos, passes, precs):
-        yield dict(form=f, iters=k, rho=r, refine_passes=pa, precision=p)
+    for f, k, r, pa, p1, p in itertools.product(forms, iters, rhos, passes, firsts, precs):
+        yield dict(form=f, iters=k, rho=r, refine_passes=pa, first_passes=p1, precision=p)
 
 
 def measure(solver, dev, out, bs, settings, reps=3, kkt_bar=1e-5):

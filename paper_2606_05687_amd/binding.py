@@ -34,6 +34,7 @@ class Settings(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("form", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("first_passes", ctypes.c_int32),
     ]
 
 

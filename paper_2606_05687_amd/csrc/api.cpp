@@ -24,7 +24,8 @@ static bool same_settings(const pinmpc_settings& a, const pinmpc_settings& b) {
          a.restart_eta == b.restart_eta && a.scaling == b.scaling && a.refine == b.refine &&
          a.refine_passes == b.refine_passes && a.ipm_iters == b.ipm_iters &&
          a.polish_passes == b.polish_passes && a.kkt_tol == b.kkt_tol &&
-         a.precision == b.precision && a.form == b.form && a.graph == b.graph;
+         a.precision == b.precision && a.form == b.form && a.graph == b.graph &&
+         a.first_passes == b.first_passes;
 }
 
 static bool same_key(const GraphKey& a, const GraphKey& b) {
@@ -88,6 +89,9 @@ size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.faces = (int32_t*)take(S * 2 * 4);
   t.order = (int32_t*)take(Bn * 3 * 4);
   t.counts = (int32_t*)take(4 * 4);
+  t.rlist = (int32_t*)take(Bn * 4);
+  t.rcount = (int32_t*)take(4);
+  t.rpass = (int32_t*)take(Bn * 4);
   t.bytes = off;
   if (w) *w = t;
   return off;
@@ -103,6 +107,7 @@ int check_settings(const pinmpc_settings* s) {
   if (s->precision < 0 || s->precision > 1) return PINMPC_EINVAL;
   if (s->form < -1 || s->form > 1) return PINMPC_EINVAL;
   if (s->graph < 0 || s->graph > 1) return PINMPC_EINVAL;
+  if (s->first_passes < 0) return PINMPC_EINVAL;
   return PINMPC_OK;
 }
 
@@ -216,6 +221,7 @@ void pinmpc_default_settings(pinmpc_settings* s) {
   s->precision = 0;
   s->form = 0;
   s->graph = 1;
+  s->first_passes = 4;
 }
 
 int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,

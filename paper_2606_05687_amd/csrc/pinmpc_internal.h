@@ -109,6 +109,12 @@ struct Workspace {
   int32_t* faces;   // [s][2] face code per contact
   int32_t* order;   // [3][b] problems of each horizon class (packing)
   int32_t* counts;  // [4] problems per class
+  // refinement hand-off: problems the active-set passes did not certify
+  // (second launch: interior point and polish), their count, and the passes
+  // each used in the first launch
+  int32_t* rlist;   // [b]
+  int32_t* rcount;  // [1]
+  int32_t* rpass;   // [b]
   size_t bytes;
   // warm start (serving): per problem slot index into a device store of
   // iterates [slot][PINMPC_NMAX][5][25]; null / negative index = cold start

@@ -236,6 +236,7 @@ struct Sh {
   double KK[NU * 16];    // [K | 0 | kap]: gains, feedforward in column 13
   double HI[NU * 16];    // H^{-1} (Newton steps)
   double ST[16 * 17];    // S of the stage, for its transpose
+  double PV[PINMPC_NMAX * 16];  // costate recursion: Q (x_{k+1} - r_k), then p_{k+1}
   double xv[NX], xn[NX];
   double Qd[NX], Rd[NU]; // diagonal weights of the problem
 };
@@ -555,6 +556,14 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     // [Bp | 0 | d] = B [P | 0 | c] + [0 | 0 | e]
     const d4 yc = (!newton && j == VC) ? T : Pt;
     d4 D1 = mmT<3>(BT, yc, ev);
+    d4 PRP = zero4();
+    if (!newton && factor) {
+      d4 RP;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) RP[q] = (j < NU && 4 * q + g < NU) ? Rr[q] * T[q] : 0.0;
+      const d4 Py = (j < NU) ? T : sel(j == VC, T - ur);
+      PRP = mmT<3>(RP, Py, zero4());
+    }
     const d4 Bp = sel(j < NU, D1);
     d4 Sn;
     if (factor) {
@@ -572,13 +581,13 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         // P R' P and P rho straight from the stage tile (P a mask there)
         D4 += sel(j < NU || j == VC, T);
       } else {
-        // P R P and P R (c - u_ref) = P (R c + rho)
-        d4 RP;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) RP[q] = (j < NU && 4 * q + g < NU) ? Rr[q] * T[q] : 0.0;
-        const d4 Py = (j < NU) ? T : sel(j == VC, T - ur);
-        D4 = mmT<3>(RP, Py, D4);
+        // P R P and P R (c - u_ref) = P (R c + rho), independent of the chain
+        // above (its instructions overlap it)
+        D4 += PRP;
       }
+      // A^T [W A | W d + q + s]: the part of S that needs no gains, issued
+      // before the elimination
+      const d4 SA = mmT<4>(At, D2, zero4());
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const int r = 4 * q + g;
@@ -637,8 +646,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         st_tile(prH + (size_t)k * TILE, sel(j < NX, D5));
       }
       // S = A^T W A + Hwx^T K, s = A^T (W d + q + s) + Hwx^T kap
-      Sn = mmT<4>(At, D2, zero4());
-      Sn = mmT<3>(sel(j < NX, D5), KK, Sn);
+      Sn = mmT<3>(sel(j < NX, D5), KK, SA);
       // keep S exactly symmetric: its rounding is not, and an asymmetric part
       // is carried back through the open-loop A and grows along the horizon
 #pragma unroll
@@ -742,44 +750,50 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec)
 
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} (column VC of a
 // tile) and the reduced gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
+// The state terms of every stage are formed first, in parallel, into LDS;
+// the recursion then fetches only the A tiles, two stages ahead (it issues
+// no global store, so waiting for one fetch does not wait for the next), and
+// leaves p in LDS until it is done.
 __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
   gsync();
   const int lane = threadIdx.x, g = tg(), j = tj();
   const int N = __builtin_amdgcn_readfirstlane(C.N);
   const gcf pA = uni(C.A), pxr = uni(C.x_ref);
   const gd prx = uni(C.rx), prlam = uni(C.rlam);
-  d4 Qr;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) Qr[q] = C.Q[clampi(4 * q + g, NX - 1)];
-  struct CoRaw {
-    float a[4], xr[4];
-    double x[4];
+  for (int e = lane; e < N * NX; e += W64) {
+    const int k = e / NX, i = e % NX;
+    sh.PV[k * 16 + i] = C.Q[i] * (prx[(size_t)(k + 1) * NX + i] - (double)pxr[(size_t)k * NX + i]);
+  }
+  wsync();
+  auto cfetch = [&](int k, float a[4]) {
+    gather(pA + (size_t)clampi(k + 1, N - 1) * NX * NX, false, NX, NX, a);
   };
-  auto cfetch = [&](int k, CoRaw& s) {
-    gather(pA + (size_t)clampi(k + 1, N - 1) * NX * NX, false, NX, NX, s.a);
-    gatherv(pxr + (size_t)k * NX, NX, s.xr);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) s.x[q] = prx[(size_t)(k + 1) * NX + clampi(4 * q + g, NX - 1)];
-  };
-  CoRaw cr;
-  cfetch(N > 0 ? N - 1 : 0, cr);
-  d4 p = zero4(), pp = zero4();
-  int pk = -1;
-  for (int k = N - 1; k >= 0; --k) {
-    const d4 A1 = cook(cr.a, false, NX, NX);
+  d4 p = zero4();
+  auto step = [&](int k, const float a[4]) {
+    const d4 A1 = cook(a, false, NX, NX);
     d4 qx;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      qx[q] = (j == VC && 4 * q + g < NX) ? Qr[q] * (cr.x[q] - (double)cr.xr[q]) : 0.0;
-    pin(A1); pin(qx);
-    pin_memory();
-    if (pk >= 0) vec_store(prlam + (size_t)pk * NX, NX, pp);
-    if (k > 0) cfetch(k - 1, cr);
+      qx[q] = (j == VC && 4 * q + g < NX) ? sh.PV[k * 16 + 4 * q + g] : 0.0;
     p = (k + 1 < N) ? mmT<4>(A1, p, qx) : qx;
-    pp = p;
-    pk = k;
+    if (j == VC) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * q + g < NX) sh.PV[k * 16 + 4 * q + g] = p[q];
+    }
+  };
+  float fa[4], fb[4];
+  cfetch(N > 0 ? N - 1 : 0, fa);
+  cfetch(N > 1 ? N - 2 : 0, fb);
+  for (int k = N - 1; k >= 0; k -= 2) {
+    step(k, fa);
+    if (k - 2 >= 0) cfetch(k - 2, fa);
+    if (k - 1 < 0) break;
+    step(k - 1, fb);
+    if (k - 3 >= 0) cfetch(k - 3, fb);
   }
-  if (pk >= 0) vec_store(prlam + (size_t)pk * NX, NX, pp);
+  wsync();
+  for (int e = lane; e < N * NX; e += W64) prlam[e] = sh.PV[(e / NX) * 16 + e % NX];
   gsync();
   for (int e = lane; e < N * NU; e += W64) {
     const int k = e / NU, jj = e % NU;
@@ -996,12 +1010,12 @@ __device__ __attribute__((noinline)) void faces_from_u(const Ctx& C, gcd u_src, 
 
 // One active-set pass: equality-constrained solve on the current faces,
 // costates, multipliers and residuals.
+// The pass's x is the FP64 rollout of its u, so its dynamics residual is
+// rounding only: it is checked once, on the final trajectory, by the caller.
 __device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
   riccati(C, sh, Mode::EQ, true, nullptr);
   costates_grad(C, sh);
-  const double kkt = multipliers_kkt(C, res);
-  res[0] = dyn_residual(C);
-  return fmax(kkt, res[0]);
+  return multipliers_kkt(C, res);
 }
 
 // Faces from the interior-point iterate (row active where z > s); returns an
@@ -1050,16 +1064,18 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
     if (C.contact[(e >> 1) * 2 + (e & 1)]) mloc += NROW;
   const double m = wave_sum((double)mloc);
   if (m == 0.0) return 0;
-  // initial point: the current ru (feasible ADMM point), its rollout in rx
+  // initial point: the current ru (the ADMM point) and its rollout in rx,
+  // slacks at least 1, multipliers 1 (a start from the last active-set pass,
+  // its slacks and multipliers floored at 1e-1 .. 1e-3, took as long or
+  // longer: the early steps near the boundary are short)
   for (int e = lane; e < N * 2 * NROW; e += W64) {
     const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-    const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
-    if (!C.contact[st * 2 + i]) continue;
+    const size_t rb = ((size_t)k * 2 + i) * NROW + r;
+    if (!C.contact[k * 2 + i]) continue;
     double gg[6], hh;
     wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
     double gu = 0.0;
-    for (int a = 0; a < 6; ++a) gu += gg[a] * C.ru[st * NU + 6 * i + a];
+    for (int a = 0; a < 6; ++a) gu += gg[a] * C.ru[k * NU + 6 * i + a];
     const double sc = (r < 5) ? C.mg : C.tm;
     C.rs[rb] = fmax((hh - gu) / sc, 1.0);
     C.rz[rb] = 1.0;
@@ -1201,7 +1217,9 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
 
 // Active-set loop; returns true if certified.  passes accumulates.
 __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int* passes,
-                                double res[PINMPC_NRES], double* kkt_out) {
+                                double res[PINMPC_NRES], double* kkt_out,
+                                bool* cycled = nullptr) {
+  if (cycled) *cycled = false;
   uint64_t hist[8];
   for (int i = 0; i < 8; ++i) hist[i] = 0;
   int nh = 0;
@@ -1213,7 +1231,10 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int*
     const uint64_t h = pdas_update(C);
     bool seen = false;
     for (int i = 0; i < 8; ++i) seen |= (hist[i] == h) && (i < nh || nh >= 8);
-    if (seen) return false;
+    if (seen) {
+      if (cycled) *cycled = true;
+      return false;
+    }
     hist[nh & 7] = h;
     ++nh;
   }
@@ -1257,19 +1278,30 @@ __device__ __attribute__((noinline)) void admm_point(const Ctx& C, gcf zsrc, gcf
   wsync();
 }
 
+// PHASE 1 runs every problem's active-set passes; a problem they do not
+// certify (with the interior point enabled) is appended to ws.rlist and left
+// to PHASE 2, which runs the interior point and the polish passes for the
+// listed problems only (surplus blocks exit).  The slow problems thus start
+// together instead of behind a second round of easy ones.
+template <int PHASE>
 __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, float* out_u,
                                                     float* out_x, float* out_res,
                                                     int32_t* out_iters, int32_t* out_status,
                                                     int admm_iters, int accel, int refine,
                                                     int pass_a, int ipm_max, int pass_c,
-                                                    double tol) {
+                                                    double tol, int pass_1) {
   __shared__ Sh sh;
   // the problem context lives in LDS: its pointers are loaded where they are
   // used instead of being held in registers across the whole kernel
   __shared__ Ctx C;
   const int lane = threadIdx.x;
+  int pb = blockIdx.x;
+  if (PHASE == 2) {
+    if ((int)blockIdx.x >= ws.rcount[0]) return;
+    pb = ws.rlist[blockIdx.x];
+  }
   if (lane == 0) {
-  C.b = blockIdx.x;
+  C.b = pb;
   C.n = p.n_max;
   C.N = horizon(p, C.b);
   const size_t s0 = (size_t)C.b * C.n;
@@ -1308,10 +1340,10 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     C.faces = (GMEM int32_t*)(ws.faces + s0 * 2);
   }
   }
-  if (lane < NX) sh.Qd[lane] = p.Q[(size_t)blockIdx.x * NX + lane];
-  if (lane < NU) sh.Rd[lane] = p.R[(size_t)blockIdx.x * NU + lane];
+  if (lane < NX) sh.Qd[lane] = p.Q[(size_t)pb * NX + lane];
+  if (lane < NU) sh.Rd[lane] = p.R[(size_t)pb * NU + lane];
   wsync();
-  const size_t s0 = (size_t)blockIdx.x * p.n_max;
+  const size_t s0 = (size_t)pb * p.n_max;
   const int N = C.N;
 
   // input checks: bounds, then finiteness of this problem's data
@@ -1349,23 +1381,49 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
   gcf zsrc = (gcf)((accel ? ws.cur : ws.hat) + s0 * NSTATE * NL);
   gcf sf = (gcf)(ws.sf + s0);
   const float tsc = ws.tsc[C.b];
-  admm_point(C, zsrc, sf, tsc);
+  if (PHASE == 1) admm_point(C, zsrc, sf, tsc);
 
   double res[PINMPC_NRES] = {0, 0, 0, 0, 0};
   double kkt = 1e300;
   int passes = 0;
   bool ok = false;
   if (refine) {
-    faces_from_u(C, C.ru, 1e-5);
-    ok = active_set_loop(C, sh, pass_a, tol, &passes, res, &kkt);
-    if (!ok && ipm_max > 0) {
-      // interior point from the ADMM point (ru was overwritten by the passes)
-      admm_point(C, zsrc, sf, tsc);
-      rollout_ru(C, sh);
-      const int its = ipm(C, sh, ipm_max, tol, &passes, res, &kkt, &ok);
-      passes += its;
-      if (!ok) ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
+    // first launch: pass_1 passes (all pass_a when pass_1 is 0); the rest of
+    // the passes, the interior point and the polish in the second launch
+    const int p1 = (pass_1 > 0 && pass_1 < pass_a) ? pass_1 : pass_a;
+    if (PHASE == 1) {
+      faces_from_u(C, C.ru, 1e-5);
+      bool cycled = false;
+      ok = active_set_loop(C, sh, p1, tol, &passes, res, &kkt, &cycled);
+      const bool more = !cycled && p1 < pass_a;
+      if (!ok && (more || ipm_max > 0)) {
+        if (lane == 0) {
+          const int slot = atomicAdd(ws.rcount, 1);
+          ws.rlist[slot] = C.b;
+          ws.rpass[C.b] = passes | (more ? (1 << 20) : 0);
+        }
+        return;
+      }
+    } else {
+      const int rp = ws.rpass[C.b];
+      passes = rp & ((1 << 20) - 1);
+      if (rp >> 20) {
+        // resume the active-set passes from the faces the first launch left
+        ok = active_set_loop(C, sh, pass_a - passes, tol, &passes, res, &kkt);
+      }
+      if (!ok && ipm_max > 0) {
+        // interior point from the ADMM point
+        admm_point(C, zsrc, sf, tsc);
+        rollout_ru(C, sh);
+        const int its = ipm(C, sh, ipm_max, tol, &passes, res, &kkt, &ok);
+        passes += its;
+        if (!ok) ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
+      }
     }
+    // the dynamics residual of the returned trajectory, checked independently
+    // of the rollout that produced it
+    res[0] = dyn_residual(C);
+    ok = ok && res[0] <= tol;
   } else {
     // the ADMM point as it is: rollout, faces from slack, residuals
     faces_from_u(C, C.ru, 1e-5);
@@ -1397,9 +1455,20 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
 hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                          const pinmpc_out& out, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
-  hipLaunchKernelGGL(refine_kernel, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x, out.res,
-                     out.iters, out.status, s.iters, s.accel, s.refine, s.refine_passes,
-                     s.ipm_iters, s.polish_passes, s.kkt_tol);
+  const bool second =
+      s.refine && (s.ipm_iters > 0 || (s.first_passes > 0 && s.first_passes < s.refine_passes));
+  if (second) {
+    // the hand-off counter starts at zero (a fill kernel: graph-safe)
+    const hipError_t e = launch_fill_i32(w.rcount, 1, 0, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(refine_kernel<1>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
+                     out.res, out.iters, out.status, s.iters, s.accel, s.refine,
+                     s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes);
+  if (second)
+    hipLaunchKernelGGL(refine_kernel<2>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
+                       out.res, out.iters, out.status, s.iters, s.accel, s.refine,
+                       s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes);
   return hipGetLastError();
 }
 
