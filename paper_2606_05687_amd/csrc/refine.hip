@@ -311,6 +311,16 @@ __device__ inline double readlane_d(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 __device__ inline d4 sel(bool c, d4 a) { return c ? a : zero4(); }
+// 1/a from the hardware estimate refined by two Newton steps (the pivots of
+// SPD eliminations: finite and positive); within about an ulp of the quotient.
+__device__ inline double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
 
 // Coefficient a (0..5) of wrench row `row` (the same rows as wrench_row).
 __device__ inline double wcoef(int row, int a, double mu) {
@@ -610,7 +620,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         double pc[NU];
 #pragma unroll
         for (int r = 0; r < NU; ++r) pc[r] = readlane_d(col[r], p);
-        const double t = col[p] / pc[p];
+        const double t = col[p] * recip(pc[p]);
 #pragma unroll
         for (int r = 0; r < NU; ++r)
           if (r != p) col[r] -= pc[r] * t;
@@ -1052,6 +1062,43 @@ __device__ __attribute__((noinline)) uint64_t faces_from_zs(const Ctx& C) {
 // Returns the number of iterations; *certified tells whether a crossover pass
 // certified (then ru, rx, res and *kkt are that pass's), else the faces from
 // z > s are left for the polish passes.
+// Row data of one stance contact-stage (k, i) in registers: a lane owns a
+// contact-stage and its 11 rows, so each row pass over the horizon issues its
+// loads together and stores once (no store-then-load chains between rows).
+__device__ inline void load_u6(gcd v, int k, int i, double x[6]) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) x[a] = v[k * NU + 6 * i + a];
+}
+__device__ inline void load_r(gcd v, size_t rb, double x[NROW]) {
+#pragma unroll
+  for (int r = 0; r < NROW; ++r) x[r] = v[rb + r];
+}
+__device__ inline void store_r(gd v, size_t rb, const double x[NROW]) {
+#pragma unroll
+  for (int r = 0; r < NROW; ++r) v[rb + r] = x[r];
+}
+// g_r u, h_r and the row scale of the contact's 11 rows
+__device__ inline void rows_of(const Ctx& C, const double u[6], double gu[NROW], double hh[NROW],
+                               double sc[NROW]) {
+#pragma unroll
+  for (int r = 0; r < NROW; ++r) {
+    double g[6];
+    wrench_row(r, C.mu, C.fz, C.tm, g, &hh[r]);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc += g[a] * u[a];
+    gu[r] = acc;
+    sc[r] = (r < 5) ? C.mg : C.tm;
+  }
+}
+
+// Interior-point fallback.  Rows scaled by mg (force rows) and tau_max
+// (moment rows).  Crossover: once the face guess z > s is the same after two
+// consecutive iterations, one equality-constrained pass on those faces is
+// tried (the iterate is kept aside and restored if it does not certify).
+// Returns the number of iterations; *certified tells whether a crossover pass
+// certified (then ru, rx, res and *kkt are that pass's), else the faces from
+// z > s are left for the polish passes.
 __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, double tol, int* passes,
                    double res[PINMPC_NRES], double* kkt_out, bool* certified) {
   *certified = false;
@@ -1064,132 +1111,172 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
     if (C.contact[(e >> 1) * 2 + (e & 1)]) mloc += NROW;
   const double m = wave_sum((double)mloc);
   if (m == 0.0) return 0;
+  gd rc = C.rdz;   // complementarity target
   // initial point: the current ru (the ADMM point) and its rollout in rx,
   // slacks at least 1, multipliers 1 (a start from the last active-set pass,
   // its slacks and multipliers floored at 1e-1 .. 1e-3, took as long or
-  // longer: the early steps near the boundary are short)
-  for (int e = lane; e < N * 2 * NROW; e += W64) {
-    const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-    const size_t rb = ((size_t)k * 2 + i) * NROW + r;
+  // longer: the early steps near the boundary are short); and the residuals
+  // of that point
+  double smz = 0.0, rpn = 0.0;
+  for (int e = lane; e < N * 2; e += W64) {
+    const int k = e >> 1, i = e & 1;
     if (!C.contact[k * 2 + i]) continue;
-    double gg[6], hh;
-    wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
-    double gu = 0.0;
-    for (int a = 0; a < 6; ++a) gu += gg[a] * C.ru[k * NU + 6 * i + a];
-    const double sc = (r < 5) ? C.mg : C.tm;
-    C.rs[rb] = fmax((hh - gu) / sc, 1.0);
-    C.rz[rb] = 1.0;
+    const size_t rb = (size_t)e * NROW;
+    double u[6], gu[NROW], hh[NROW], sc[NROW], sv[NROW], zv[NROW], cv[NROW];
+    load_u6(C.ru, k, i, u);
+    rows_of(C, u, gu, hh, sc);
+#pragma unroll
+    for (int r = 0; r < NROW; ++r) {
+      sv[r] = fmax((hh[r] - gu[r]) / sc[r], 1.0);
+      zv[r] = 1.0;
+      rpn = fmax(rpn, fabs((gu[r] - hh[r]) / sc[r] + sv[r]));
+      smz += sv[r] * zv[r];
+      cv[r] = sv[r] * zv[r];
+    }
+    store_r(C.rs, rb, sv);
+    store_r(C.rz, rb, zv);
+    store_r(rc, rb, cv);
   }
-  wsync();
-  gd rc = C.rdz;   // reuse: complementarity target, then dz
   int it = 0;
   uint64_t hprev = 0;
   for (; it < maxit; ++it) {
-    // residuals rp and mu
-    double smz = 0.0, rpn = 0.0;
-    for (int e = lane; e < N * 2 * NROW; e += W64) {
-      const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-      const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
-      if (!C.contact[st * 2 + i]) continue;
-      double gg[6], hh;
-      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
-      double gu = 0.0;
-      for (int a = 0; a < 6; ++a) gu += gg[a] * C.ru[st * NU + 6 * i + a];
-      const double sc = (r < 5) ? C.mg : C.tm;
-      const double rp = (gu - hh) / sc + C.rs[rb];
-      smz += C.rs[rb] * C.rz[rb];
-      rpn = fmax(rpn, fabs(rp));
-      rc[rb] = C.rs[rb] * C.rz[rb];     // affine (predictor) target
-    }
     const double muv = wave_sum(smz) / m;
     rpn = wave_max(rpn);
-    wsync();
     if (muv <= 1e-10 && rpn <= 1e-9) break;
-    // predictor
+    // predictor (affine target rc = s z)
     riccati(C, sh, Mode::NEWTON, true, rc);
     double amax_s = 1.0, amax_z = 1.0;
-    for (int e = lane; e < N * 2 * NROW; e += W64) {
-      const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-      const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
-      if (!C.contact[st * 2 + i]) continue;
-      double gg[6], hh;
-      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
-      double gu = 0.0, gdu = 0.0;
-      for (int a = 0; a < 6; ++a) {
-        gu += gg[a] * C.ru[st * NU + 6 * i + a];
-        gdu += gg[a] * C.rdu[st * NU + 6 * i + a];
+    for (int e = lane; e < N * 2; e += W64) {
+      const int k = e >> 1, i = e & 1;
+      if (!C.contact[k * 2 + i]) continue;
+      const size_t rb = (size_t)e * NROW;
+      double u[6], du[6], gu[NROW], gdu[NROW], hh[NROW], sc[NROW], sv[NROW], zv[NROW];
+      load_u6(C.ru, k, i, u);
+      load_u6(C.rdu, k, i, du);
+      load_r(C.rs, rb, sv);
+      load_r(C.rz, rb, zv);
+      rows_of(C, u, gu, hh, sc);
+      rows_of(C, du, gdu, hh, sc);
+      double dsv[NROW], dzv[NROW];
+#pragma unroll
+      for (int r = 0; r < NROW; ++r) {
+        const double rp = (gu[r] - hh[r]) / sc[r] + sv[r];
+        dsv[r] = -rp - gdu[r] / sc[r];
+        dzv[r] = (-sv[r] * zv[r] - zv[r] * dsv[r]) / sv[r];
+        if (dsv[r] < 0) amax_s = fmin(amax_s, -sv[r] / dsv[r]);
+        if (dzv[r] < 0) amax_z = fmin(amax_z, -zv[r] / dzv[r]);
       }
-      const double sc = (r < 5) ? C.mg : C.tm;
-      const double s = C.rs[rb], z = C.rz[rb];
-      const double rp = (gu - hh) / sc + s;
-      const double ds = -rp - gdu / sc;
-      const double dz = (-s * z - z * ds) / s;
-      C.rds[rb] = ds;
-      C.rmu[rb] = dz;     // affine dz kept in rmu scratch
-      if (ds < 0) amax_s = fmin(amax_s, -s / ds);
-      if (dz < 0) amax_z = fmin(amax_z, -z / dz);
+      store_r(C.rds, rb, dsv);
+      store_r(C.rmu, rb, dzv);    // affine dz kept in rmu scratch
     }
     const double aa = fmin(wave_min(amax_s), wave_min(amax_z));
     double sm = 0.0;
-    for (int e = lane; e < N * 2 * NROW; e += W64) {
-      const int k = e / (2 * NROW), i = (e / NROW) & 1;
-      const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + e % NROW;
-      if (!C.contact[st * 2 + i]) continue;
-      sm += (C.rs[rb] + aa * C.rds[rb]) * (C.rz[rb] + aa * C.rmu[rb]);
+    for (int e = lane; e < N * 2; e += W64) {
+      const int k = e >> 1, i = e & 1;
+      if (!C.contact[k * 2 + i]) continue;
+      const size_t rb = (size_t)e * NROW;
+      double sv[NROW], zv[NROW], dsv[NROW], dzv[NROW];
+      load_r(C.rs, rb, sv);
+      load_r(C.rz, rb, zv);
+      load_r(C.rds, rb, dsv);
+      load_r(C.rmu, rb, dzv);
+#pragma unroll
+      for (int r = 0; r < NROW; ++r) sm += (sv[r] + aa * dsv[r]) * (zv[r] + aa * dzv[r]);
     }
     const double mu_aff = wave_sum(sm) / m;
     const double sigma = pow(mu_aff / muv, 3.0);
-    wsync();
-    for (int e = lane; e < N * 2 * NROW; e += W64) {
-      const int k = e / (2 * NROW), i = (e / NROW) & 1;
-      const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + e % NROW;
-      if (!C.contact[st * 2 + i]) continue;
-      rc[rb] = C.rs[rb] * C.rz[rb] + C.rds[rb] * C.rmu[rb] - sigma * muv;
+    // corrector target: s z + ds_aff dz_aff - sigma mu
+    for (int e = lane; e < N * 2; e += W64) {
+      const int k = e >> 1, i = e & 1;
+      if (!C.contact[k * 2 + i]) continue;
+      const size_t rb = (size_t)e * NROW;
+      double sv[NROW], zv[NROW], dsv[NROW], dzv[NROW], cv[NROW];
+      load_r(C.rs, rb, sv);
+      load_r(C.rz, rb, zv);
+      load_r(C.rds, rb, dsv);
+      load_r(C.rmu, rb, dzv);
+#pragma unroll
+      for (int r = 0; r < NROW; ++r) cv[r] = sv[r] * zv[r] + dsv[r] * dzv[r] - sigma * muv;
+      store_r(rc, rb, cv);
     }
-    wsync();
     // corrector: same matrix, new right-hand side
     riccati(C, sh, Mode::NEWTON, false, rc);
     amax_s = 1.0;
     amax_z = 1.0;
-    for (int e = lane; e < N * 2 * NROW; e += W64) {
-      const int k = e / (2 * NROW), i = (e / NROW) & 1, r = e % NROW;
-      const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + r;
-      if (!C.contact[st * 2 + i]) continue;
-      double gg[6], hh;
-      wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
-      double gu = 0.0, gdu = 0.0;
-      for (int a = 0; a < 6; ++a) {
-        gu += gg[a] * C.ru[st * NU + 6 * i + a];
-        gdu += gg[a] * C.rdu[st * NU + 6 * i + a];
+    for (int e = lane; e < N * 2; e += W64) {
+      const int k = e >> 1, i = e & 1;
+      if (!C.contact[k * 2 + i]) continue;
+      const size_t rb = (size_t)e * NROW;
+      double u[6], du[6], gu[NROW], gdu[NROW], hh[NROW], sc[NROW], sv[NROW], zv[NROW], cv[NROW];
+      load_u6(C.ru, k, i, u);
+      load_u6(C.rdu, k, i, du);
+      load_r(C.rs, rb, sv);
+      load_r(C.rz, rb, zv);
+      load_r(rc, rb, cv);
+      rows_of(C, u, gu, hh, sc);
+      rows_of(C, du, gdu, hh, sc);
+      double dsv[NROW], dzv[NROW];
+#pragma unroll
+      for (int r = 0; r < NROW; ++r) {
+        const double rp = (gu[r] - hh[r]) / sc[r] + sv[r];
+        dsv[r] = -rp - gdu[r] / sc[r];
+        dzv[r] = (-cv[r] - zv[r] * dsv[r]) / sv[r];
+        if (dsv[r] < 0) amax_s = fmin(amax_s, -sv[r] / dsv[r]);
+        if (dzv[r] < 0) amax_z = fmin(amax_z, -zv[r] / dzv[r]);
       }
-      const double sc = (r < 5) ? C.mg : C.tm;
-      const double s = C.rs[rb], z = C.rz[rb];
-      const double rp = (gu - hh) / sc + s;
-      const double ds = -rp - gdu / sc;
-      const double dz = (-rc[rb] - z * ds) / s;
-      C.rds[rb] = ds;
-      C.rmu[rb] = dz;
-      if (ds < 0) amax_s = fmin(amax_s, -s / ds);
-      if (dz < 0) amax_z = fmin(amax_z, -z / dz);
+      store_r(C.rds, rb, dsv);
+      store_r(C.rmu, rb, dzv);
     }
     const double a = fmin(1.0, 0.99 * fmin(wave_min(amax_s), wave_min(amax_z)));
-    wsync();
-    for (int e = lane; e < N * 2 * NROW; e += W64) {
-      const int k = e / (2 * NROW), i = (e / NROW) & 1;
-      const int st = k;
-      const size_t rb = ((size_t)st * 2 + i) * NROW + e % NROW;
-      if (!C.contact[st * 2 + i]) continue;
-      C.rs[rb] += a * C.rds[rb];
-      C.rz[rb] += a * C.rmu[rb];
+    // step, and the residuals and affine target of the new point; a lane
+    // updates the inputs of its own contact-stage (swing inputs stay 0)
+    smz = 0.0;
+    rpn = 0.0;
+    for (int e = lane; e < N * 2; e += W64) {
+      const int k = e >> 1, i = e & 1;
+      if (!C.contact[k * 2 + i]) continue;
+      const size_t rb = (size_t)e * NROW;
+      double u[6], du[6], gu[NROW], hh[NROW], sc[NROW], sv[NROW], zv[NROW], dsv[NROW], dzv[NROW],
+          cv[NROW];
+      load_u6(C.ru, k, i, u);
+      load_u6(C.rdu, k, i, du);
+      load_r(C.rs, rb, sv);
+      load_r(C.rz, rb, zv);
+      load_r(C.rds, rb, dsv);
+      load_r(C.rmu, rb, dzv);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        u[t] += a * du[t];
+        C.ru[k * NU + 6 * i + t] = u[t];
+      }
+      rows_of(C, u, gu, hh, sc);
+#pragma unroll
+      for (int r = 0; r < NROW; ++r) {
+        sv[r] += a * dsv[r];
+        zv[r] += a * dzv[r];
+        rpn = fmax(rpn, fabs((gu[r] - hh[r]) / sc[r] + sv[r]));
+        smz += sv[r] * zv[r];
+        cv[r] = sv[r] * zv[r];
+      }
+      store_r(C.rs, rb, sv);
+      store_r(C.rz, rb, zv);
+      store_r(rc, rb, cv);
     }
-    for (int e = lane; e < N * NU; e += W64) C.ru[e] += a * C.rdu[e];
-    for (int e = lane; e < (N + 1) * NX; e += W64)
-      C.rx[e] += a * C.rdx[e];
+    // states: loads of a group first, then its stores
+    for (int e0 = lane; e0 < (N + 1) * NX; e0 += 4 * W64) {
+      double xv[4], dv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = e0 + t * W64;
+        xv[t] = (e < (N + 1) * NX) ? C.rx[e] : 0.0;
+        dv[t] = (e < (N + 1) * NX) ? C.rdx[e] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = e0 + t * W64;
+        if (e < (N + 1) * NX) C.rx[e] = xv[t] + a * dv[t];
+      }
+    }
     wsync();
     const uint64_t h = faces_from_zs(C);
     if (it >= 1 && h == hprev) {

@@ -31,6 +31,16 @@ __device__ inline double readlane_d(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// 1/a from the hardware estimate refined by two Newton steps (the pivots of
+// SPD eliminations: finite and positive); within about an ulp of the quotient.
+__device__ inline double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Gauss-Jordan inverse of an SPD n x n matrix (no pivoting needed) with lane
 // c holding column c of the augmented [M | I] in registers (lanes 0..n-1 the
 // matrix, lanes n..2n-1 the identity); the pivot column is broadcast from its
@@ -42,7 +52,7 @@ __device__ inline void gj_columns(double (&col)[n]) {
     double pc[n];
 #pragma unroll
     for (int r = 0; r < n; ++r) pc[r] = readlane_d(col[r], p);
-    const double t = col[p] / pc[p];
+    const double t = col[p] * recip(pc[p]);
 #pragma unroll
     for (int r = 0; r < n; ++r)
       if (r != p) col[r] -= pc[r] * t;
