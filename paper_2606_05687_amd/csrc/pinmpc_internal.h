@@ -135,6 +135,44 @@ __host__ __device__ constexpr size_t refine_block_doubles(int n) {
            2 * (size_t)(n + 1) * NX) + 3) & ~(size_t)3;
 }
 
+// 1/a from the hardware estimate refined by two Newton steps (the pivots of
+// SPD eliminations: finite and positive); within about an ulp of the quotient.
+__device__ inline double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Gauss-Jordan elimination without pivoting (SPD systems) on a matrix whose
+// column c is held in registers by lane c of a 64-lane wave: col[r] is row r.
+// The pivot column is broadcast from its lane with readlane (a broadcast
+// through LDS was slower: each pivot then waits for an LDS round trip).
+// Afterwards each lane holds its column of M^{-1} [rest] where M is the
+// leading n x n block (lanes 0..n-1 end with the identity).
+template <int n>
+__device__ inline void gj_columns(double (&col)[n]) {
+#pragma unroll
+  for (int p = 0; p < n; ++p) {
+    double pc[n];
+#pragma unroll
+    for (int r = 0; r < n; ++r) pc[r] = readlane_d(col[r], p);
+    const double t = col[p] * recip(pc[p]);
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+      if (r != p) col[r] -= pc[r] * t;
+    col[p] = t;
+  }
+}
+
 // Face code of one contact: bits 0..4 force rows active
 //   (0: f_x - mu f_z <= 0, 1: -f_x - mu f_z <= 0, 2: f_y - mu f_z <= 0,
 //    3: -f_y - mu f_z <= 0, 4: f_z <= fz_max),

@@ -232,11 +232,20 @@ __device__ inline int blk_len(int j) { return (j % 6 < 3) ? 3 : 1; }
 // in registers as 16 x 16 tiles.
 constexpr int GS = NU + NX + 2;   // row stride of the Gauss-Jordan hand-off
 struct Sh {
-  double G[NU * GS];     // [H | Hwx | hw] of the stage, row-major
-  double KK[NU * 16];    // [K | 0 | kap]: gains, feedforward in column 13
-  double HI[NU * 16];    // H^{-1} (Newton steps)
-  double ST[16 * 17];    // S of the stage, for its transpose
-  double PV[PINMPC_NMAX * 16];  // costate recursion: Q (x_{k+1} - r_k), then p_{k+1}
+  // the Riccati recursion's hand-off buffers and the costate recursion's
+  // stage vectors share storage: the two never run at the same time
+  union {
+    struct {
+      double G[NU * GS];     // [H | Hwx | hw] of the stage, row-major
+      double KK[NU * 16];    // [K | 0 | kap]: gains, feedforward in column 13
+      double HI[NU * 16];    // H^{-1} (Newton steps)
+      double ST[16 * 17];    // S of the stage, for its transpose
+    } r;
+    struct {
+      double PV[PINMPC_NMAX * 16];   // Q (x_{k+1} - r_k), then p_{k+1}
+      double GV[PINMPC_NMAX * 16];   // R (u_k - u_ref_k), then g_k
+    } c;
+  };
   double xv[NX], xn[NX];
   double Qd[NX], Rd[NU]; // diagonal weights of the problem
 };
@@ -304,24 +313,7 @@ __device__ inline void vec_store(gd v, int len, d4 t) {
       if (4 * q + tg() < len) v[4 * q + tg()] = t[q];
   }
 }
-__device__ inline double readlane_d(double v, int l) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 __device__ inline d4 sel(bool c, d4 a) { return c ? a : zero4(); }
-// 1/a from the hardware estimate refined by two Newton steps (the pivots of
-// SPD eliminations: finite and positive); within about an ulp of the quotient.
-__device__ inline double recip(double a) {
-  double r = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-a, r, 1.0);
-  return fma(r, e, r);
-}
-
-
 // Coefficient a (0..5) of wrench row `row` (the same rows as wrench_row).
 __device__ inline double wcoef(int row, int a, double mu) {
   if (row < 4) {
@@ -601,47 +593,37 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const int r = 4 * q + g;
-        if (j < NU) sh.G[r * GS + j] = D4[q] + ((r == j) ? 1.0 : 0.0) - Pt[q];
-        if (j < NX) sh.G[r * GS + NU + j] = D5[q];
-        if (j == VC) sh.G[r * GS + NU + NX] = D5[q] + D4[q];
+        if (j < NU) sh.r.G[r * GS + j] = D4[q] + ((r == j) ? 1.0 : 0.0) - Pt[q];
+        if (j < NX) sh.r.G[r * GS + NU + j] = D5[q];
+        if (j == VC) sh.r.G[r * GS + NU + NX] = D5[q] + D4[q];
       }
       wsync();
       // Gauss-Jordan elimination (H is SPD: no pivoting) with lane c holding
-      // column c of [H | Hwx | hw | I]; the pivot column is broadcast from
-      // its lane.  Afterwards the lanes hold [I | H^-1 Hwx | H^-1 hw | H^-1].
+      // column c of [H | Hwx | hw | I]; afterwards the lanes hold
+      // [I | H^-1 Hwx | H^-1 hw | H^-1].
       constexpr int C0 = NU + NX + 1;
       const int ncol = newton ? C0 + NU : C0;
       double col[NU];
 #pragma unroll
       for (int r = 0; r < NU; ++r)
-        col[r] = (lane < C0) ? sh.G[r * GS + lane] : ((lane < ncol && r == lane - C0) ? 1.0 : 0.0);
-#pragma unroll
-      for (int p = 0; p < NU; ++p) {
-        double pc[NU];
-#pragma unroll
-        for (int r = 0; r < NU; ++r) pc[r] = readlane_d(col[r], p);
-        const double t = col[p] * recip(pc[p]);
-#pragma unroll
-        for (int r = 0; r < NU; ++r)
-          if (r != p) col[r] -= pc[r] * t;
-        col[p] = t;
-      }
+        col[r] = (lane < C0) ? sh.r.G[r * GS + lane] : ((lane < ncol && r == lane - C0) ? 1.0 : 0.0);
+      gj_columns<NU>(col);
       if (lane >= NU && lane < C0) {
         const int c = (lane < NU + NX) ? lane - NU : VC;
 #pragma unroll
-        for (int r = 0; r < NU; ++r) sh.KK[r * 16 + c] = -col[r];
+        for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + c] = -col[r];
       }
       if (newton && lane >= C0 && lane < ncol) {
 #pragma unroll
-        for (int r = 0; r < NU; ++r) sh.HI[r * 16 + lane - C0] = col[r];
+        for (int r = 0; r < NU; ++r) sh.r.HI[r * 16 + lane - C0] = col[r];
       }
       wsync();
       d4 KK, KT;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = 4 * q + g;
-        KK[q] = (r < NU && (j < NX || j == VC)) ? sh.KK[r * 16 + j] : 0.0;   // [K | kap]
-        KT[q] = (j < NU && r < NX) ? sh.KK[j * 16 + r] : 0.0;               // K^T
+        KK[q] = (r < NU && (j < NX || j == VC)) ? sh.r.KK[r * 16 + j] : 0.0;   // [K | kap]
+        KT[q] = (j < NU && r < NX) ? sh.r.KK[j * 16 + r] : 0.0;               // K^T
       }
       st_tile(prK + (size_t)k * TILE, KT);
       vec_store(prkap + (size_t)k * NU, NU, KK);
@@ -650,7 +632,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = 4 * q + g;
-          HI[q] = (r < NU && j < NU) ? sh.HI[r * 16 + j] : 0.0;
+          HI[q] = (r < NU && j < NU) ? sh.r.HI[r * 16 + j] : 0.0;
         }
         st_tile(prL + (size_t)k * TILE, HI);
         st_tile(prH + (size_t)k * TILE, sel(j < NX, D5));
@@ -660,12 +642,12 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
       // keep S exactly symmetric: its rounding is not, and an asymmetric part
       // is carried back through the open-loop A and grows along the horizon
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sh.ST[(4 * q + g) * 17 + j] = Sn[q];
+      for (int q = 0; q < 4; ++q) sh.r.ST[(4 * q + g) * 17 + j] = Sn[q];
       wsync();
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = 4 * q + g;
-        if (r < NX && j < NX) Sn[q] = 0.5 * (Sn[q] + sh.ST[j * 17 + r]);
+        if (r < NX && j < NX) Sn[q] = 0.5 * (Sn[q] + sh.r.ST[j * 17 + r]);
       }
       wsync();
     } else {
@@ -758,62 +740,99 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec)
   else riccati_t<Mode::NEWTON, false>(C, sh, rcvec);
 }
 
-// Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} (column VC of a
-// tile) and the reduced gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.
-// The state terms of every stage are formed first, in parallel, into LDS;
-// the recursion then fetches only the A tiles, two stages ahead (it issues
-// no global store, so waiting for one fetch does not wait for the next), and
-// leaves p in LDS until it is done.
+// Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
+// gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}, both in column VC of a
+// tile.  The terms that need no costate are formed first, in parallel, into
+// LDS; the recursion then fetches only the A and B tiles, two stages ahead
+// (it issues no global store, so waiting for one fetch does not wait for the
+// next), and leaves p and g in LDS until it is done.
 __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
   gsync();
   const int lane = threadIdx.x, g = tg(), j = tj();
   const int N = __builtin_amdgcn_readfirstlane(C.N);
-  const gcf pA = uni(C.A), pxr = uni(C.x_ref);
-  const gd prx = uni(C.rx), prlam = uni(C.rlam);
+  const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pur = uni(C.u_ref);
+  const gd prx = uni(C.rx), pru = uni(C.ru), prlam = uni(C.rlam), prg = uni(C.rg);
   for (int e = lane; e < N * NX; e += W64) {
     const int k = e / NX, i = e % NX;
-    sh.PV[k * 16 + i] = C.Q[i] * (prx[(size_t)(k + 1) * NX + i] - (double)pxr[(size_t)k * NX + i]);
+    sh.c.PV[k * 16 + i] = C.Q[i] * (prx[(size_t)(k + 1) * NX + i] - (double)pxr[(size_t)k * NX + i]);
+  }
+  for (int e = lane; e < N * NU; e += W64) {
+    const int k = e / NU, i = e % NU;
+    const double ur = pur ? (double)pur[(size_t)k * NU + i] : 0.0;
+    sh.c.GV[k * 16 + i] = C.R[i] * (pru[(size_t)k * NU + i] - ur);
   }
   wsync();
-  auto cfetch = [&](int k, float a[4]) {
+  // stage k needs A_{k+1} (for p_{k+1}) and B_k (for g_k)
+  auto cfetch = [&](int k, float a[4], float b[4]) {
     gather(pA + (size_t)clampi(k + 1, N - 1) * NX * NX, false, NX, NX, a);
+    gather(pB + (size_t)k * NX * NU, false, NX, NU, b);
   };
   d4 p = zero4();
-  auto step = [&](int k, const float a[4]) {
+  auto step = [&](int k, const float a[4], const float b[4]) {
     const d4 A1 = cook(a, false, NX, NX);
-    d4 qx;
+    const d4 Bk = cook(b, false, NX, NU);
+    d4 qx, rg;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      qx[q] = (j == VC && 4 * q + g < NX) ? sh.PV[k * 16 + 4 * q + g] : 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * q + g;
+      qx[q] = (j == VC && r < NX) ? sh.c.PV[k * 16 + r] : 0.0;
+      rg[q] = (j == VC && r < NU) ? sh.c.GV[k * 16 + r] : 0.0;
+    }
     p = (k + 1 < N) ? mmT<4>(A1, p, qx) : qx;
+    const d4 gk = mmT<4>(Bk, p, rg);
     if (j == VC) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (4 * q + g < NX) sh.PV[k * 16 + 4 * q + g] = p[q];
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g;
+        if (r < NX) sh.c.PV[k * 16 + r] = p[q];
+        if (r < NU) sh.c.GV[k * 16 + r] = gk[q];
+      }
     }
   };
-  float fa[4], fb[4];
-  cfetch(N > 0 ? N - 1 : 0, fa);
-  cfetch(N > 1 ? N - 2 : 0, fb);
+  float fa[4], fb[4], ga[4], gb[4];
+  cfetch(N > 0 ? N - 1 : 0, fa, fb);
+  cfetch(N > 1 ? N - 2 : 0, ga, gb);
   for (int k = N - 1; k >= 0; k -= 2) {
-    step(k, fa);
-    if (k - 2 >= 0) cfetch(k - 2, fa);
+    step(k, fa, fb);
+    if (k - 2 >= 0) cfetch(k - 2, fa, fb);
     if (k - 1 < 0) break;
-    step(k - 1, fb);
-    if (k - 3 >= 0) cfetch(k - 3, fb);
+    step(k - 1, ga, gb);
+    if (k - 3 >= 0) cfetch(k - 3, ga, gb);
   }
   wsync();
-  for (int e = lane; e < N * NX; e += W64) prlam[e] = sh.PV[(e / NX) * 16 + e % NX];
+  for (int e = lane; e < N * NX; e += W64) prlam[e] = sh.c.PV[(e / NX) * 16 + e % NX];
+  for (int e = lane; e < N * NU; e += W64) prg[e] = sh.c.GV[(e / NU) * 16 + e % NU];
   gsync();
-  for (int e = lane; e < N * NU; e += W64) {
-    const int k = e / NU, jj = e % NU;
-    gcf B = C.B + k * NX * NU;
-    const double ur = C.u_ref ? (double)C.u_ref[k * NU + jj] : 0.0;
-    double acc = C.R[jj] * (C.ru[k * NU + jj] - ur);
-    for (int l = 0; l < NX; ++l) acc += (double)B[l * NU + jj] * C.rlam[k * NX + l];
-    C.rg[k * NU + jj] = acc;
+}
+
+// Row data of one stance contact-stage (k, i) in registers: a lane owns a
+// contact-stage and its 11 rows, so each row pass over the horizon issues its
+// loads together and stores once (no store-then-load chains between rows).
+__device__ inline void load_u6(gcd v, int k, int i, double x[6]) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) x[a] = v[k * NU + 6 * i + a];
+}
+__device__ inline void load_r(gcd v, size_t rb, double x[NROW]) {
+#pragma unroll
+  for (int r = 0; r < NROW; ++r) x[r] = v[rb + r];
+}
+__device__ inline void store_r(gd v, size_t rb, const double x[NROW]) {
+#pragma unroll
+  for (int r = 0; r < NROW; ++r) v[rb + r] = x[r];
+}
+// g_r u, h_r and the row scale of the contact's 11 rows
+__device__ inline void rows_of(const Ctx& C, const double u[6], double gu[NROW], double hh[NROW],
+                               double sc[NROW]) {
+#pragma unroll
+  for (int r = 0; r < NROW; ++r) {
+    double g[6];
+    wrench_row(r, C.mu, C.fz, C.tm, g, &hh[r]);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc += g[a] * u[a];
+    gu[r] = acc;
+    sc[r] = (r < 5) ? C.mg : C.tm;
   }
-  gsync();
 }
 
 // Row multipliers of each stance contact from its face and the gradient, and
@@ -825,12 +844,16 @@ __device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     const int st = k;
-    gcd u = C.ru + st * NU + 6 * i;
-    gcd g = C.rg + st * NU + 6 * i;
-    gd mu = C.rmu + (st * 2 + i) * NROW;
+    // the contact-stage's inputs, gradient and multipliers in registers
+    double u[6], g[6], mu[NROW];
+    load_u6(C.ru, st, i, u);
+    load_u6(C.rg, st, i, g);
+#pragma unroll
     for (int r = 0; r < NROW; ++r) mu[r] = 0.0;
+    gd mu_out = C.rmu + (st * 2 + i) * NROW;
     if (!C.contact[st * 2 + i]) {
       for (int a = 0; a < 6; ++a) r_ineq = fmax(r_ineq, fabs(u[a]) / C.mg);
+      store_r(mu_out, 0, mu);
       continue;
     }
     const int code = C.faces[st * 2 + i];
@@ -887,16 +910,20 @@ __device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double
           if ((mask >> i) & 1) mu[i] = r[i];
       }
     }
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (code >> (8 + a) & 1) mu[5 + a] = -g[3 + a];
       else if (code >> (11 + a) & 1) mu[8 + a] = g[3 + a];
     }
+    store_r(mu_out, 0, mu);
     // residual pieces
     double gm[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
     for (int r = 0; r < NROW; ++r) {
       double gg[6], hh;
       wrench_row(r, C.mu, C.fz, C.tm, gg, &hh);
       double gu = 0.0;
+#pragma unroll
       for (int a = 0; a < 6; ++a) {
         gu += gg[a] * u[a];
         gm[a] += gg[a] * mu[r];
@@ -1053,43 +1080,6 @@ __device__ __attribute__((noinline)) uint64_t faces_from_zs(const Ctx& C) {
   }
   wsync();
   return wave_xor(hsh);
-}
-
-// Interior-point fallback.  Rows scaled by mg (force rows) and tau_max
-// (moment rows).  Crossover: once the face guess z > s is the same after two
-// consecutive iterations, one equality-constrained pass on those faces is
-// tried (the iterate is kept aside and restored if it does not certify).
-// Returns the number of iterations; *certified tells whether a crossover pass
-// certified (then ru, rx, res and *kkt are that pass's), else the faces from
-// z > s are left for the polish passes.
-// Row data of one stance contact-stage (k, i) in registers: a lane owns a
-// contact-stage and its 11 rows, so each row pass over the horizon issues its
-// loads together and stores once (no store-then-load chains between rows).
-__device__ inline void load_u6(gcd v, int k, int i, double x[6]) {
-#pragma unroll
-  for (int a = 0; a < 6; ++a) x[a] = v[k * NU + 6 * i + a];
-}
-__device__ inline void load_r(gcd v, size_t rb, double x[NROW]) {
-#pragma unroll
-  for (int r = 0; r < NROW; ++r) x[r] = v[rb + r];
-}
-__device__ inline void store_r(gd v, size_t rb, const double x[NROW]) {
-#pragma unroll
-  for (int r = 0; r < NROW; ++r) v[rb + r] = x[r];
-}
-// g_r u, h_r and the row scale of the contact's 11 rows
-__device__ inline void rows_of(const Ctx& C, const double u[6], double gu[NROW], double hh[NROW],
-                               double sc[NROW]) {
-#pragma unroll
-  for (int r = 0; r < NROW; ++r) {
-    double g[6];
-    wrench_row(r, C.mu, C.fz, C.tm, g, &hh[r]);
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) acc += g[a] * u[a];
-    gu[r] = acc;
-    sc[r] = (r < 5) ? C.mg : C.tm;
-  }
 }
 
 // Interior-point fallback.  Rows scaled by mg (force rows) and tau_max

@@ -24,42 +24,6 @@ __device__ inline double scale_of(const Problem& p, int b, int k, int j, bool sc
   return (j % 6) < 3 ? sf : (double)p.tau_max[b];
 }
 
-__device__ inline double readlane_d(double v, int l) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// 1/a from the hardware estimate refined by two Newton steps (the pivots of
-// SPD eliminations: finite and positive); within about an ulp of the quotient.
-__device__ inline double recip(double a) {
-  double r = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-a, r, 1.0);
-  return fma(r, e, r);
-}
-
-// Gauss-Jordan inverse of an SPD n x n matrix (no pivoting needed) with lane
-// c holding column c of the augmented [M | I] in registers (lanes 0..n-1 the
-// matrix, lanes n..2n-1 the identity); the pivot column is broadcast from its
-// lane.  Afterwards lanes n..2n-1 hold the columns of M^{-1}.
-template <int n>
-__device__ inline void gj_columns(double (&col)[n]) {
-#pragma unroll
-  for (int p = 0; p < n; ++p) {
-    double pc[n];
-#pragma unroll
-    for (int r = 0; r < n; ++r) pc[r] = readlane_d(col[r], p);
-    const double t = col[p] * recip(pc[p]);
-#pragma unroll
-    for (int r = 0; r < n; ++r)
-      if (r != p) col[r] -= pc[r] * t;
-    col[p] = t;
-  }
-}
-
 __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, float rho,
                                                    int scaling, int bf16) {
   const int s = blockIdx.x;                    // stage index b * n_max + k
