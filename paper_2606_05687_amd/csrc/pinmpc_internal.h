@@ -157,11 +157,15 @@ __device__ inline double readlane_d(double v, int l) {
 // The pivot column is broadcast from its lane with readlane (a broadcast
 // through LDS was slower: each pivot then waits for an LDS round trip).
 // Afterwards each lane holds its column of M^{-1} [rest] where M is the
-// leading n x n block (lanes 0..n-1 end with the identity).
+// leading n x n block (lanes 0..n-1 end with the identity).  Bit p of the
+// wave-uniform `unit` marks a pivot whose row and column of the whole system
+// are exactly the unit vector e_p: its elimination step changes nothing and
+// is skipped (bitwise the same result).
 template <int n>
-__device__ inline void gj_columns(double (&col)[n]) {
+__device__ inline void gj_columns(double (&col)[n], uint32_t unit = 0) {
 #pragma unroll
   for (int p = 0; p < n; ++p) {
+    if ((unit >> p) & 1u) continue;
     double pc[n];
 #pragma unroll
     for (int r = 0; r < n; ++r) pc[r] = readlane_d(col[r], p);

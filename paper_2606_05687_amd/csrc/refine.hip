@@ -482,7 +482,29 @@ struct BackRaw {
   double xn[4];
   d4 T, HI, HX;
   int ct;
+  int c0, c1, f0, f1;   // the stage's contact flags and face codes (uniform)
 };
+
+// Inputs of a stage that the projector P_k removes exactly (P_k's column is
+// zero): every input of a swing contact; on an equality pass also the force of
+// an apex face and each moment component fixed at its bound.  For those, the
+// stage system [H | Hwx | hw] has exactly e_j as row and column j.
+__device__ inline uint32_t null_inputs(int c0, int c1, int f0, int f1, bool newton) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int c = i ? c1 : c0, f = i ? f1 : f0;
+    if (!c) {
+      m |= 0x3Fu << (6 * i);
+    } else if (!newton) {
+      if ((f & 31) == FACE_APEX) m |= 7u << (6 * i);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (((f >> (8 + a)) & 1) || ((f >> (11 + a)) & 1)) m |= 1u << (6 * i + 3 + a);
+    }
+  }
+  return m;
+}
 
 template <Mode mode, bool factor>
 __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec) {
@@ -494,6 +516,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   constexpr bool newton = (mode == Mode::NEWTON);
   const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pe = uni(C.e), pur = uni(C.u_ref);
   const GMEM uint8_t* pct = uni(C.contact);
+  const GMEM int32_t* pfc = uni(C.faces);
   const gd prT = uni(C.rT), prK = uni(C.rK), prL = uni(C.rL), prH = uni(C.rHwx);
   const gd prkap = uni(C.rkap), prx = uni(C.rx), pru = uni(C.ru), prdx = uni(C.rdx),
            prdu = uni(C.rdu);
@@ -529,6 +552,10 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
       s.HI = s.HX = zero4();
     }
     s.ct = newton ? (int)pct[k * 2 + (j < NU ? j / 6 : 0)] : 0;
+    s.c0 = __builtin_amdgcn_readfirstlane((int)pct[k * 2]);
+    s.c1 = __builtin_amdgcn_readfirstlane((int)pct[k * 2 + 1]);
+    s.f0 = newton ? 0 : __builtin_amdgcn_readfirstlane(pfc[k * 2]);
+    s.f1 = newton ? 0 : __builtin_amdgcn_readfirstlane(pfc[k * 2 + 1]);
   };
 
   d4 Ss = zero4();   // value function of x_{k+1}: S in columns 0..12, s in VC
@@ -550,6 +577,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
       ur[q] = (j == VC && r < NU) ? (double)raw.ur[q] : 0.0;
     }
     const d4 Pt = newton ? mask_tile(raw.ct) : sel(j < NU, T);
+    const uint32_t unit = null_inputs(raw.c0, raw.c1, raw.f0, raw.f1, newton);
     pin(At); pin(BT); pin(T); pin(om); pin(ev); pin(ur); pin(Pt);
     if (newton && !factor) { pin(HIs); pin(HXs); }
     pin_memory();
@@ -607,7 +635,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
 #pragma unroll
       for (int r = 0; r < NU; ++r)
         col[r] = (lane < C0) ? sh.r.G[r * GS + lane] : ((lane < ncol && r == lane - C0) ? 1.0 : 0.0);
-      gj_columns<NU>(col);
+      gj_columns<NU>(col, unit);
       if (lane >= NU && lane < C0) {
         const int c = (lane < NU + NX) ? lane - NU : VC;
 #pragma unroll
