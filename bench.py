@@ -88,6 +88,10 @@ def parse():
     ap.add_argument("--serving-ticks", type=int, default=3)
     ap.add_argument("--lanes", type=int, default=3)
     ap.add_argument("--lane-capacity", type=int, default=4096)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="solves in flight: S library contexts on S streams (default "
+                         "priority) take the timed solves round robin, so one solve's "
+                         "refinement tail overlaps the next solve's setup and sweeps")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: time captured-graph replays (phase times then come from a "
                          "second, uncaptured loop)")
@@ -166,7 +170,7 @@ def _counter_rows(run_dir):
     return rows
 
 
-TUNED = "--autotune 0 --form 1 --iters 10 --rho 10 --refine-passes 12 --first-passes 0 --cpu-sample 0"
+TUNED = "--autotune 0 --form 1 --iters 10 --rho 10 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
 PMC_COMMANDS = [
     f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
     f"python3 bench.py {TUNED} --steps 2 --warmup 1",
@@ -372,43 +376,51 @@ def main():
         held = mpcgen.make_batch(args.workload, indices=range(nb, 2 * nb))
         hdev = binding.to_device(held, "cuda:0")
         tuned = autotune.tune(hdev, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
-                              force=True)
+                              force=True, in_flight=max(1, args.streams))
         settings.update(tuned)
         del hdev
     batch = mpcgen.make_batch(args.workload)
     Bn, n = batch["A"].shape[0], batch["A"].shape[1]
     stages = int(batch["N"].sum())
     dev = binding.to_device(batch, "cuda:0")
-    solver = binding.Solver(0, **settings)
-    solver.set(graph=int(args.graph))
-    out = solver.alloc_out(dev)
+    nst = max(1, args.streams)
+    solvers = [binding.Solver(0, **settings) for _ in range(nst)]
+    for sv in solvers:
+        sv.set(graph=int(args.graph))
+    outs = [sv.alloc_out(dev) for sv in solvers]
     bstruct = binding.make_batch_struct(dev)
-    stream = torch.cuda.current_stream()
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(nst - 1)]
+    solver, out, stream = solvers[0], outs[0], streams[0]
 
     for _ in range(args.warmup):
-        solver.solve(dev, out, stream=stream, batch_struct=bstruct)
+        for sv, o, st in zip(solvers, outs, streams):
+            sv.solve(dev, o, stream=st, batch_struct=bstruct)
     torch.cuda.synchronize()
 
-    # timed region: K solves enqueued back to back on one stream, bracketed by
-    # device synchronisation; per-solve latency from HIP events recorded
-    # around each solve on that stream, per-kernel times from the library's
-    # own HIP events on the same stream (kept for the last STATS_RING solves)
+    # timed region: K solves enqueued back to back (round robin over the
+    # streams when more than one solve is in flight), bracketed by device
+    # synchronisation; per-solve latency from HIP events recorded around each
+    # solve on its stream, per-kernel times from the library's own HIP events
+    # on the same stream (kept for the last STATS_RING solves)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        evs[i][0].record(stream)
-        solver.solve(dev, out, stream=stream, batch_struct=bstruct)
-        evs[i][1].record(stream)
+        sv, o, st = solvers[i % nst], outs[i % nst], streams[i % nst]
+        evs[i][0].record(st)
+        sv.solve(dev, o, stream=st, batch_struct=bstruct)
+        evs[i][1].record(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms = [a.elapsed_time(b) for a, b in evs]
     # every step solves the same batch deterministically: the last outputs
     # are every step's outputs
-    res = out["res"]
-    ok = (out["status"] == 0) & (res.max(dim=1).values <= KKT_BAR)
-    certified = int(ok.sum().item()) * args.steps
+    certified = 0
+    for i in range(args.steps):
+        o = outs[i % nst]
+        ok = (o["status"] == 0) & (o["res"].max(dim=1).values <= KKT_BAR)
+        certified += int(ok.sum().item())
     ms_per_step = elapsed * 1e3 / args.steps
     value = certified / elapsed
 
@@ -419,11 +431,40 @@ def main():
         for _ in range(args.steps):
             solver.solve(dev, out, stream=stream, batch_struct=bstruct)
         torch.cuda.synchronize()
-    nk = min(args.steps, binding.STATS_RING)
+    nk = min((args.steps + nst - 1) // nst, binding.STATS_RING)
     phases = [solver.stats(back=i) for i in range(nk)]
     setup_ms = float(np.mean([ph["setup_ms"] for ph in phases]))
     admm_ms = float(np.mean([ph["admm_ms"] for ph in phases]))
     refine_ms = float(np.mean([ph["refine_ms"] for ph in phases]))
+
+    single = None
+    if nst > 1:
+        # the same solves one at a time on one stream, for comparison
+        evs1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            evs1[i][0].record(stream)
+            solver.solve(dev, out, stream=stream, batch_struct=bstruct)
+            evs1[i][1].record(stream)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t1
+        ms1 = [a.elapsed_time(b) for a, b in evs1]
+        ok1 = (out["status"] == 0) & (out["res"].max(dim=1).values <= KKT_BAR)
+        single = {"value": int(ok1.sum().item()) * args.steps / el1,
+                  "ms_per_step": el1 * 1e3 / args.steps,
+                  "p50_ms": float(np.percentile(ms1, 50)), "p99_ms": float(np.percentile(ms1, 99))}
+        # kernel durations for the roofline: from these solves, where no other
+        # solve shares the GPU (with solves in flight, the stream events of a
+        # phase also count time its kernels wait for the other stream's)
+        single["kernel_ms_in_flight"] = {"setup": setup_ms, "admm": admm_ms, "refine": refine_ms}
+        nk1 = min(args.steps, binding.STATS_RING)
+        ph1 = [solver.stats(back=i) for i in range(nk1)]
+        setup_ms = float(np.mean([ph["setup_ms"] for ph in ph1]))
+        admm_ms = float(np.mean([ph["admm_ms"] for ph in ph1]))
+        refine_ms = float(np.mean([ph["refine_ms"] for ph in ph1]))
+
     K = settings["iters"]
     iters_out = out["iters"].cpu().numpy().astype(np.int64)
     passes = iters_out - K
@@ -500,9 +541,12 @@ def main():
         "phase_ms": {"setup": setup_ms, "admm": admm_ms, "refine": refine_ms},
         "kernels": kernels,
         "timed_graph": bool(args.graph),
+        "solves_in_flight": nst,
+        "one_in_flight": single,
         "roofline": roof,
     }
-    solver.close()
+    for sv in solvers:
+        sv.close()
     if args.cpu_sample > 0 and args.workload == WORKLOAD:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_workers)
     print(json.dumps(line), flush=True)

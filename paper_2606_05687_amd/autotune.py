@@ -48,45 +48,56 @@ def candidates(n_max, allow_bf16=False):
         yield dict(form=f, iters=k, rho=r, refine_passes=pa, first_passes=p1, precision=p)
 
 
-def measure(solver, dev, out, bs, settings, reps=3, kkt_bar=1e-5):
+def measure(solvers, streams, dev, outs, bs, settings, reps=4, kkt_bar=1e-5):
+    """Seconds per solve with len(solvers) solves in flight (round robin over
+    the streams), and the certified fraction."""
     import torch
-    solver.set(**settings)
-    solver.solve(dev, out, batch_struct=bs)        # warm-up (and graph capture)
+    for sv in solvers:
+        sv.set(**settings)
+    for sv, o, st in zip(solvers, outs, streams):
+        sv.solve(dev, o, stream=st, batch_struct=bs)   # warm-up (and graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        solver.solve(dev, out, batch_struct=bs)
+    for i in range(reps):
+        k = i % len(solvers)
+        solvers[k].solve(dev, outs[k], stream=streams[k], batch_struct=bs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    out = outs[0]
     ok = (out["status"] == 0) & (out["res"].max(dim=1).values <= kkt_bar)
     frac = float(ok.float().mean().item())
     return dt, frac
 
 
 def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, verbose=False,
-         force=False):
-    """Best settings (dict) for batches shaped like ``dev``; cached."""
-    key = _key(dev, allow_bf16)
+         force=False, in_flight=1):
+    """Best settings (dict) for batches shaped like ``dev``, measured with
+    `in_flight` solves on as many streams; cached."""
+    import torch
+    key = _key(dev, allow_bf16) + f"|inflight{int(in_flight)}"
     cache = {}
     if os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
     if key in cache and not force:
         return cache[key]["settings"]
-    solver = binding.Solver(0)
-    out = solver.alloc_out(dev)
+    n = max(1, int(in_flight))
+    solvers = [binding.Solver(0) for _ in range(n)]
+    outs = [sv.alloc_out(dev) for sv in solvers]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n - 1)]
     bs = binding.make_batch_struct(dev)
     Bn = int(dev["A"].shape[0])
     best, best_score, log = None, -1.0, []
     for cand in candidates(int(dev["A"].shape[1]), allow_bf16):
-        dt, frac = measure(solver, dev, out, bs, cand)
+        dt, frac = measure(solvers, streams, dev, outs, bs, cand)
         score = frac * Bn / dt if frac >= min_certified else 0.0
         log.append(dict(cand, ms=dt * 1e3, certified=frac, score=score))
         if verbose:
             print(f"  {cand} {dt * 1e3:.2f} ms certified {frac:.4f} -> {score:.0f}/s", flush=True)
         if score > best_score:
             best, best_score = cand, score
-    solver.close()
+    for sv in solvers:
+        sv.close()
     cache[key] = {"settings": best, "score": best_score, "log": log}
     os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
     with open(cache_path, "w") as f:
