@@ -303,3 +303,49 @@ def test_two_launch_refinement_matches_one_launch(solver):
     print("max rel |u_two - u_one|", du.max())
     assert du.max() <= 1e-4
     assert np.all(two["res"] <= TOL_KKT)
+
+
+def test_two_solves_in_flight_equal_one_at_a_time():
+    """Two library contexts solving on two streams at once (the benchmark's
+    solves in flight) give bitwise the results of solving one after the other."""
+    import torch
+    from paper_2606_05687_amd import binding
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(1024))
+    dev = binding.to_device(batch)
+    cfg = dict(graph=0, form=1, iters=10, rho=10.0, refine_passes=12, first_passes=0)
+    a, b = binding.Solver(0, **cfg), binding.Solver(0, **cfg)
+    ref = a.solve(dev)
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().numpy() for k, v in ref.items()}
+    s1, s2 = torch.cuda.current_stream(), torch.cuda.Stream()
+    o1, o2 = a.alloc_out(dev), b.alloc_out(dev)
+    for _ in range(3):
+        a.solve(dev, o1, stream=s1)
+        b.solve(dev, o2, stream=s2)
+    torch.cuda.synchronize()
+    for o in (o1, o2):
+        for k, v in o.items():
+            assert np.array_equal(v.cpu().numpy(), ref[k]), k
+    assert (ref["status"] == 0).all()
+    a.close()
+    b.close()
+
+
+def test_second_launch_resumes_active_set_passes_without_interior_point():
+    """With the interior point off, the second refinement launch only resumes
+    the active-set passes from the faces the first launch left: the problems
+    certified either way have the same optimum, and none is lost."""
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(512))
+    from paper_2606_05687_amd import binding
+    s = binding.Solver(0)
+    one = _solve(s, batch, iters=10, refine_passes=12, first_passes=0, ipm_iters=0)
+    two = _solve(s, batch, iters=10, refine_passes=12, first_passes=3, ipm_iters=0)
+    s.close()
+    c1, c2 = one["status"] == 0, two["status"] == 0
+    print("certified", c1.mean(), c2.mean())
+    assert c2.sum() >= c1.sum() - 2
+    both = c1 & c2
+    scale = np.maximum(np.abs(one["u"][both]).max(axis=(1, 2)), 1.0)
+    du = np.abs(two["u"][both] - one["u"][both]).max(axis=(1, 2)) / scale
+    assert du.max() <= 1e-4
+    assert set(np.unique(two["status"])) <= {0, 2}
