@@ -131,7 +131,7 @@ struct Workspace {
 // and step du (12); and states x and dx ((n+1) x 13 each).
 constexpr int TILE = 256;
 __host__ __device__ constexpr size_t refine_block_doubles(int n) {
-  return (((size_t)n * (4 * TILE + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
+  return (((size_t)n * (5 * TILE + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
            2 * (size_t)(n + 1) * NX) + 3) & ~(size_t)3;
 }
 
@@ -174,6 +174,37 @@ __device__ inline void gj_columns(double (&col)[n], uint32_t unit = 0) {
     for (int r = 0; r < n; ++r)
       if (r != p) col[r] -= pc[r] * t;
     col[p] = t;
+  }
+}
+
+// Lane P of each 16-lane row of the wave, to every lane of that row (a DPP
+// row broadcast of the 64-bit value).
+template <int P>
+__device__ inline double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + P, 0xF, 0xF, true);
+}
+
+// The same elimination as gj_columns (same operations, same order), for a
+// system whose leading n x n block (n <= 16) sits in lanes 0..n-1 of every
+// 16-lane row of the wave (column c in lane c of each row, the rows
+// identical) and whose other columns occupy the remaining lanes of the rows:
+// each pivot column entry then reaches its row's lanes by one row broadcast
+// instead of two lane reads.
+template <int n, int p = 0>
+__device__ inline void gj_rows(double (&col)[n], uint32_t unit = 0) {
+  static_assert(n <= 16, "pivot columns must fit a 16-lane row");
+  if constexpr (p < n) {
+    if (!((unit >> p) & 1u)) {
+      double pc[n];
+#pragma unroll
+      for (int r = 0; r < n; ++r) pc[r] = row_bcast<p>(col[r]);
+      const double t = col[p] * recip(pc[p]);
+#pragma unroll
+      for (int r = 0; r < n; ++r)
+        if (r != p) col[r] -= pc[r] * t;
+      col[p] = t;
+    }
+    gj_rows<n, p + 1>(col, unit);
   }
 }
 

@@ -44,7 +44,7 @@ struct Ctx {
   const LMEM double* R;
   gcf A, B, e, x_ref, u_ref, x0;
   const GMEM uint8_t* contact;
-  gd rT, rK, rL, rHwx;   // per-stage 16 x 16 tiles (32-byte aligned)
+  gd rT, rK, rL, rHwx, rS;   // per-stage 16 x 16 tiles (32-byte aligned)
   gd rkap, ru, rx, rlam, rg, rmu, rs, rz, rds, rdz, rdu, rdx;
   GMEM int32_t* faces;
 };
@@ -341,9 +341,9 @@ __device__ inline size_t tile_at(int r, int c) { return (size_t)4 * (16 * (r % 4
 // Interior-point rows are scaled by sc (mg force rows, tau_max moment rows):
 // row weight z / (s sc^2), linear coefficient (z + (-rc + z rp) / s) / sc with
 // rp = (g u - h) / sc + s.
-__device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec) {
+__device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec, int kn) {
   const int lane = threadIdx.x;
-  for (int e = lane; e < C.N * 2; e += W64) {
+  for (int e = lane; e < kn * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     gd base = C.rT + (size_t)k * TILE;
     double P6[6][6], c6[6];
@@ -417,6 +417,12 @@ __device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec) {
 //   S <- A^T W A + Hwx^T K,  s <- A^T (W d + q + s) + Hwx^T kap.
 // With factor = false only the linear part is recomputed from the stored
 // H^{-1}, Hwx and K (second right-hand side of the same Newton matrix).
+// EQ keeps each stage's value function [S_k | s_k] (symmetrised, as used);
+// stage k's factors depend on the faces of stages k..N-1 only, so a pass
+// whose faces differ from the previous pass's only before stage ktop
+// rebuilds the tiles and reruns the backward recursion for stages
+// 0..ktop-1 only, starting from the kept [S_ktop | s_ktop]; the result is
+// bitwise that of the whole recursion.
 
 enum class Mode { EQ, NEWTON };
 
@@ -507,17 +513,18 @@ __device__ inline uint32_t null_inputs(int c0, int c1, int f0, int f1, bool newt
 }
 
 template <Mode mode, bool factor>
-__device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec) {
+__device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec, int ktop) {
+  const int N = __builtin_amdgcn_readfirstlane(C.N);
+  ktop = (mode == Mode::EQ) ? __builtin_amdgcn_readfirstlane(ktop < N ? ktop : N) : N;
   gsync();
-  build_tiles(C, mode == Mode::NEWTON, rcvec);
+  build_tiles(C, mode == Mode::NEWTON, rcvec, ktop);
   gsync();
   const int lane = threadIdx.x, g = tg(), j = tj();
-  const int N = __builtin_amdgcn_readfirstlane(C.N);
   constexpr bool newton = (mode == Mode::NEWTON);
   const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pe = uni(C.e), pur = uni(C.u_ref);
   const GMEM uint8_t* pct = uni(C.contact);
   const GMEM int32_t* pfc = uni(C.faces);
-  const gd prT = uni(C.rT), prK = uni(C.rK), prL = uni(C.rL), prH = uni(C.rHwx);
+  const gd prT = uni(C.rT), prK = uni(C.rK), prL = uni(C.rL), prH = uni(C.rHwx), prS = uni(C.rS);
   const gd prkap = uni(C.rkap), prx = uni(C.rx), pru = uni(C.ru), prdx = uni(C.rdx),
            prdu = uni(C.rdu);
   // the diagonal weights where this lane uses them
@@ -558,10 +565,11 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     s.f1 = newton ? 0 : __builtin_amdgcn_readfirstlane(pfc[k * 2 + 1]);
   };
 
-  d4 Ss = zero4();   // value function of x_{k+1}: S in columns 0..12, s in VC
+  // value function of x_{k+1}: S in columns 0..12, s in VC
+  d4 Ss = (ktop < N) ? ld_tile(prS + (size_t)ktop * TILE) : zero4();
   BackRaw raw;
-  fetch(N > 0 ? N - 1 : 0, raw);
-  for (int k = N - 1; k >= 0; --k) {
+  fetch(ktop > 0 ? ktop - 1 : 0, raw);
+  for (int k = ktop - 1; k >= 0; --k) {
     // this stage's data
     const d4 At = cook(raw.a, false, NX, NX);
     const d4 BT = cook(raw.bt, true, NX, NU);
@@ -626,24 +634,42 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         if (j == VC) sh.r.G[r * GS + NU + NX] = D5[q] + D4[q];
       }
       wsync();
-      // Gauss-Jordan elimination (H is SPD: no pivoting) with lane c holding
-      // column c of [H | Hwx | hw | I]; afterwards the lanes hold
-      // [I | H^-1 Hwx | H^-1 hw | H^-1].
-      constexpr int C0 = NU + NX + 1;
-      const int ncol = newton ? C0 + NU : C0;
-      double col[NU];
+      // Gauss-Jordan elimination (H is SPD: no pivoting).
+      if constexpr (!newton) {
+        // [H | Hwx | hw]: lane 16 R + c holds column c of H (c < NU, the same
+        // in every row R) or right-hand side 4 R + c - NU (Hwx columns 0..12,
+        // hw as 13 = VC); afterwards the right-hand sides are H^-1 Hwx and
+        // H^-1 hw.
+        const int hc = lane & 15, rhs = 4 * (lane >> 4) + hc - NU;
+        const bool is_h = hc < NU;
+        double col[NU];
 #pragma unroll
-      for (int r = 0; r < NU; ++r)
-        col[r] = (lane < C0) ? sh.r.G[r * GS + lane] : ((lane < ncol && r == lane - C0) ? 1.0 : 0.0);
-      gj_columns<NU>(col, unit);
-      if (lane >= NU && lane < C0) {
-        const int c = (lane < NU + NX) ? lane - NU : VC;
+        for (int r = 0; r < NU; ++r)
+          col[r] = (is_h || rhs <= NX) ? sh.r.G[r * GS + (is_h ? hc : NU + rhs)] : 0.0;
+        gj_rows<NU>(col, unit);
+        if (!is_h && rhs <= NX) {
 #pragma unroll
-        for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + c] = -col[r];
-      }
-      if (newton && lane >= C0 && lane < ncol) {
+          for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + rhs] = -col[r];
+        }
+      } else {
+        // [H | Hwx | hw | I] with lane c holding column c (38 columns: more
+        // than a row's free lanes); afterwards [I | H^-1 Hwx | H^-1 hw | H^-1].
+        constexpr int C0 = NU + NX + 1;
+        double col[NU];
 #pragma unroll
-        for (int r = 0; r < NU; ++r) sh.r.HI[r * 16 + lane - C0] = col[r];
+        for (int r = 0; r < NU; ++r)
+          col[r] = (lane < C0) ? sh.r.G[r * GS + lane]
+                               : ((lane < C0 + NU && r == lane - C0) ? 1.0 : 0.0);
+        gj_columns<NU>(col, unit);
+        if (lane >= NU && lane < C0) {
+          const int c = (lane < NU + NX) ? lane - NU : VC;
+#pragma unroll
+          for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + c] = -col[r];
+        }
+        if (lane >= C0 && lane < C0 + NU) {
+#pragma unroll
+          for (int r = 0; r < NU; ++r) sh.r.HI[r * 16 + lane - C0] = col[r];
+        }
       }
       wsync();
       d4 KK, KT;
@@ -677,6 +703,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         const int r = 4 * q + g;
         if (r < NX && j < NX) Sn[q] = 0.5 * (Sn[q] + sh.r.ST[j * 17 + r]);
       }
+      if (mode == Mode::EQ) st_tile(prS + (size_t)k * TILE, Sn);
       wsync();
     } else {
       // second right-hand side of the stored Newton matrix (d = 0, so
@@ -762,10 +789,10 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   gsync();
 }
 
-__device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec) {
-  if (mode == Mode::EQ) riccati_t<Mode::EQ, true>(C, sh, rcvec);
-  else if (factor) riccati_t<Mode::NEWTON, true>(C, sh, rcvec);
-  else riccati_t<Mode::NEWTON, false>(C, sh, rcvec);
+__device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec, int ktop) {
+  if (mode == Mode::EQ) riccati_t<Mode::EQ, true>(C, sh, rcvec, ktop);
+  else if (factor) riccati_t<Mode::NEWTON, true>(C, sh, rcvec, ktop);
+  else riccati_t<Mode::NEWTON, false>(C, sh, rcvec, ktop);
 }
 
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
@@ -817,16 +844,27 @@ __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
       }
     }
   };
-  float fa[4], fb[4], ga[4], gb[4];
-  cfetch(N > 0 ? N - 1 : 0, fa, fb);
-  cfetch(N > 1 ? N - 2 : 0, ga, gb);
-  for (int k = N - 1; k >= 0; k -= 2) {
-    step(k, fa, fb);
-    if (k - 2 >= 0) cfetch(k - 2, fa, fb);
-    if (k - 1 < 0) break;
-    step(k - 1, ga, gb);
-    if (k - 3 >= 0) cfetch(k - 3, ga, gb);
+  // ring of CD stages in flight (the chain's work per stage is short next to
+  // a load's latency)
+  constexpr int CD = 4;
+  float ra[CD][4], rb[CD][4];
+#pragma unroll
+  for (int d = 0; d < CD; ++d) {
+    cfetch(N - 1 - d >= 0 ? N - 1 - d : 0, ra[d], rb[d]);
+    pin_memory();   // issued in ring order, as the loop issues them
   }
+  // Every path back to the loop head has issued the same fetches in ring
+  // order (the fetch is unconditional, clamped, and the exit leaves the
+  // whole loop), so each stage waits for its own loads only.
+  for (int k = N - 1;;) {
+#pragma unroll
+    for (int d = 0; d < CD; ++d, --k) {
+      if (k < 0) goto chain_done;
+      step(k, ra[d], rb[d]);
+      cfetch(k - CD >= 0 ? k - CD : 0, ra[d], rb[d]);
+    }
+  }
+chain_done:
   wsync();
   for (int e = lane; e < N * NX; e += W64) prlam[e] = sh.c.PV[(e / NX) * 16 + e % NX];
   for (int e = lane; e < N * NU; e += W64) prg[e] = sh.c.GV[(e / NU) * 16 + e % NU];
@@ -1014,11 +1052,13 @@ __device__ __attribute__((noinline)) double dyn_residual(const Ctx& C) {
 }
 
 // Primal-dual active-set update of the faces; returns an order-independent
-// hash of the new face set.
-__device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C) {
+// hash of the new face set and, in *ktop, one past the last stage whose face
+// changed (0: none did).
+__device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C, int* ktop) {
   gsync();
   const int lane = threadIdx.x;
   uint64_t hsh = 0;
+  int kch = 0;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     const int st = k;
@@ -1038,6 +1078,7 @@ __device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C) {
       for (int a = 0; a < 3; ++a)
         if ((code >> (8 + a) & 1) && (code >> (11 + a) & 1)) code &= ~(1 << (11 + a));
     }
+    if (C.faces[st * 2 + i] != code) kch = k + 1;
     C.faces[st * 2 + i] = code;
     uint64_t v = (uint64_t)(code + 1) * 0x9E3779B97F4A7C15ull ^ ((uint64_t)(e + 1) * 0xC2B2AE3D27D4EB4Full);
     v ^= v >> 29;
@@ -1045,6 +1086,7 @@ __device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C) {
     hsh ^= v;
   }
   wsync();
+  *ktop = (int)wave_max((double)kch);
   return wave_xor(hsh);
 }
 
@@ -1074,11 +1116,14 @@ __device__ __attribute__((noinline)) void faces_from_u(const Ctx& C, gcd u_src, 
 }
 
 // One active-set pass: equality-constrained solve on the current faces,
-// costates, multipliers and residuals.
+// costates, multipliers and residuals.  `ktop` < N: the faces of stages
+// ktop..N-1 are those of the previous equality-constrained solve, whose tiles
+// and factors are still in the scratch block.
 // The pass's x is the FP64 rollout of its u, so its dynamics residual is
 // rounding only: it is checked once, on the final trajectory, by the caller.
-__device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES]) {
-  riccati(C, sh, Mode::EQ, true, nullptr);
+__device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES],
+                                                   int ktop) {
+  riccati(C, sh, Mode::EQ, true, nullptr, ktop);
   costates_grad(C, sh);
   return multipliers_kkt(C, res);
 }
@@ -1162,7 +1207,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
     rpn = wave_max(rpn);
     if (muv <= 1e-10 && rpn <= 1e-9) break;
     // predictor (affine target rc = s z)
-    riccati(C, sh, Mode::NEWTON, true, rc);
+    riccati(C, sh, Mode::NEWTON, true, rc, C.N);
     double amax_s = 1.0, amax_z = 1.0;
     for (int e = lane; e < N * 2; e += W64) {
       const int k = e >> 1, i = e & 1;
@@ -1218,7 +1263,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
       store_r(rc, rb, cv);
     }
     // corrector: same matrix, new right-hand side
-    riccati(C, sh, Mode::NEWTON, false, rc);
+    riccati(C, sh, Mode::NEWTON, false, rc, C.N);
     amax_s = 1.0;
     amax_z = 1.0;
     for (int e = lane; e < N * 2; e += W64) {
@@ -1302,7 +1347,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
       gsync();
       for (int e = lane; e < N * NU; e += W64) C.rdu[e] = C.ru[e];
       for (int e = lane; e < (N + 1) * NX; e += W64) C.rdx[e] = C.rx[e];
-      const double kkt = eq_pass(C, sh, res);
+      const double kkt = eq_pass(C, sh, res, N);
       ++*passes;
       if (kkt <= tol) {
         *kkt_out = kkt;
@@ -1328,12 +1373,13 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int*
   uint64_t hist[8];
   for (int i = 0; i < 8; ++i) hist[i] = 0;
   int nh = 0;
+  int ktop = C.N;   // the first pass solves the whole horizon
   for (int it = 0; it < maxp; ++it) {
-    const double kkt = eq_pass(C, sh, res);
+    const double kkt = eq_pass(C, sh, res, ktop);
     ++*passes;
     *kkt_out = kkt;
     if (kkt <= tol) return true;
-    const uint64_t h = pdas_update(C);
+    const uint64_t h = pdas_update(C, &ktop);
     bool seen = false;
     for (int i = 0; i < 8; ++i) seen |= (hist[i] == h) && (i < nh || nh >= 8);
     if (seen) {
@@ -1430,6 +1476,7 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     C.rK = blk;                       blk += (size_t)n * TILE;
     C.rL = blk;                       blk += (size_t)n * TILE;
     C.rHwx = blk;                     blk += (size_t)n * TILE;
+    C.rS = blk;                       blk += (size_t)n * TILE;
     C.rkap = blk;                     blk += (size_t)n * NU;
     C.ru = blk;                       blk += (size_t)n * NU;
     C.rlam = blk;                     blk += (size_t)n * NX;
