@@ -184,27 +184,39 @@ __device__ inline double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(v, v, 0x150 + P, 0xF, 0xF, true);
 }
 
-// The same elimination as gj_columns (same operations, same order), for a
-// system whose leading n x n block (n <= 16) sits in lanes 0..n-1 of every
-// 16-lane row of the wave (column c in lane c of each row, the rows
+// c[r] += (c[r] of lane P of this 16-lane row) * s for r = 0..11, as one
+// block of DPP fused multiply-adds.  Each instruction reads its own register
+// from lane P before writing it, so every lane sees lane P's values from
+// before the block.  The leading two wait states separate the block's DPP
+// reads from a vector write just before it.
+template <int P>
+__device__ inline void fmac_row_bcast12(double (&c)[12], double s) {
+#define PINMPC_FMAC(i) \
+  "v_fmac_f64_dpp %" #i ", %" #i ", %12 row_newbcast:%13 row_mask:0xf bank_mask:0xf bound_ctrl:1\n"
+  asm volatile("s_nop 1\n" PINMPC_FMAC(0) PINMPC_FMAC(1) PINMPC_FMAC(2) PINMPC_FMAC(3)
+               PINMPC_FMAC(4) PINMPC_FMAC(5) PINMPC_FMAC(6) PINMPC_FMAC(7) PINMPC_FMAC(8)
+               PINMPC_FMAC(9) PINMPC_FMAC(10) PINMPC_FMAC(11)
+               : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]),
+                 "+v"(c[6]), "+v"(c[7]), "+v"(c[8]), "+v"(c[9]), "+v"(c[10]), "+v"(c[11])
+               : "v"(s), "i"(P));
+#undef PINMPC_FMAC
+}
+
+// The same elimination as gj_columns (the same roundings in the same order),
+// for a 12-row system whose leading 12 x 12 block sits in lanes 0..11 of
+// every 16-lane row of the wave (column c in lane c of each row, the rows
 // identical) and whose other columns occupy the remaining lanes of the rows:
-// each pivot column entry then reaches its row's lanes by one row broadcast
-// instead of two lane reads.
-template <int n, int p = 0>
-__device__ inline void gj_rows(double (&col)[n], uint32_t unit = 0) {
-  static_assert(n <= 16, "pivot columns must fit a 16-lane row");
-  if constexpr (p < n) {
+// the pivot column reaches its row's lanes through the DPP row broadcast of
+// the update instructions themselves.
+template <int p = 0>
+__device__ inline void gj_rows(double (&col)[12], uint32_t unit = 0) {
+  if constexpr (p < 12) {
     if (!((unit >> p) & 1u)) {
-      double pc[n];
-#pragma unroll
-      for (int r = 0; r < n; ++r) pc[r] = row_bcast<p>(col[r]);
-      const double t = col[p] * recip(pc[p]);
-#pragma unroll
-      for (int r = 0; r < n; ++r)
-        if (r != p) col[r] -= pc[r] * t;
+      const double t = col[p] * recip(row_bcast<p>(col[p]));
+      fmac_row_bcast12<p>(col, -t);   // col[r] - pc[r] t; col[p] is replaced next
       col[p] = t;
     }
-    gj_rows<n, p + 1>(col, unit);
+    gj_rows<p + 1>(col, unit);
   }
 }
 

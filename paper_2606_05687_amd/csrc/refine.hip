@@ -646,7 +646,8 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
 #pragma unroll
         for (int r = 0; r < NU; ++r)
           col[r] = (is_h || rhs <= NX) ? sh.r.G[r * GS + (is_h ? hc : NU + rhs)] : 0.0;
-        gj_rows<NU>(col, unit);
+        static_assert(NU == 12, "row elimination is written for 12 inputs");
+        gj_rows(col, unit);
         if (!is_h && rhs <= NX) {
 #pragma unroll
           for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + rhs] = -col[r];
@@ -720,7 +721,12 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   }
 
   // forward rollout: w = K x + kap, u = P w + c, x' = A x + B u + e, all in
-  // column VC (each lane reads back only what it stored above)
+  // column VC (each lane uses only what it stored above).  The stage data is
+  // fetched FD stages ahead, unconditionally (stage index clamped) and with
+  // the loop left as a whole, so every path back to the loop head has issued
+  // the same loads and each stage waits for its own loads only; u_k and
+  // x_{k+1} collect in LDS (the costate buffers, free here) and are copied
+  // out after the loop.
   gd xout = newton ? prdx : prx;
   gd uout = newton ? prdu : pru;
   struct FwdRaw {
@@ -749,43 +755,51 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
       if (4 * q + g < NX) xv[q] = (double)uni(C.x0)[4 * q + g];
   }
   vec_store(xout, NX, xv);
-  FwdRaw fr;
-  ffetch(0, fr);
-  d4 pu = zero4(), px = zero4();
-  int pf = -1;
-  for (int k = 0; k < N; ++k) {
-    const d4 AT = cook(fr.at, true, NX, NX);
-    const d4 BT = cook(fr.bt, true, NX, NU);
-    const d4 KT = fr.KT, T = fr.T;
-    d4 kap, ev;
+  constexpr int FD = 2;
+  FwdRaw ring[FD];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = 4 * q + g;
-      kap[q] = (j == VC && r < NU) ? fr.kap[q] : 0.0;
-      ev[q] = (j == VC && r < NX) ? (double)fr.ev[q] : 0.0;
-    }
-    const d4 Pt = newton ? mask_tile(fr.ct) : sel(j < NU, T);
-    pin(AT); pin(BT); pin(KT); pin(T); pin(kap); pin(ev); pin(Pt);
-    pin_memory();
-    if (pf >= 0) {
-      vec_store(uout + (size_t)pf * NU, NU, pu);
-      vec_store(xout + (size_t)(pf + 1) * NX, NX, px);
-    }
-    if (k + 1 < N) ffetch(k + 1, fr);
-    const d4 w = mmT<4>(KT, xv, kap);
-    d4 u = mmT<3>(Pt, w, zero4());
-    if (!newton) u += sel(j == VC, T);
-    d4 xn = mmT<4>(AT, xv, ev);
-    xn = mmT<3>(BT, u, xn);
-    pu = u;
-    px = xn;
-    pf = k;
-    xv = xn;
+  for (int d = 0; d < FD; ++d) {
+    ffetch(d < N ? d : (N > 0 ? N - 1 : 0), ring[d]);
+    pin_memory();   // issued in ring order, as the loop issues them
   }
-  if (pf >= 0) {
-    vec_store(uout + (size_t)pf * NU, NU, pu);
-    vec_store(xout + (size_t)(pf + 1) * NX, NX, px);
+  for (int k = 0;;) {
+#pragma unroll
+    for (int d = 0; d < FD; ++d, ++k) {
+      if (k >= N) goto rollout_done;
+      const d4 AT = cook(ring[d].at, true, NX, NX);
+      const d4 BT = cook(ring[d].bt, true, NX, NU);
+      const d4 KT = ring[d].KT, T = ring[d].T;
+      d4 kap, ev;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g;
+        kap[q] = (j == VC && r < NU) ? ring[d].kap[q] : 0.0;
+        ev[q] = (j == VC && r < NX) ? (double)ring[d].ev[q] : 0.0;
+      }
+      const d4 Pt = newton ? mask_tile(ring[d].ct) : sel(j < NU, T);
+      pin(AT); pin(BT); pin(KT); pin(T); pin(kap); pin(ev); pin(Pt);
+      pin_memory();
+      ffetch(k + FD < N ? k + FD : N - 1, ring[d]);
+      const d4 w = mmT<4>(KT, xv, kap);
+      d4 u = mmT<3>(Pt, w, zero4());
+      if (!newton) u += sel(j == VC, T);
+      d4 xn = mmT<4>(AT, xv, ev);
+      xn = mmT<3>(BT, u, xn);
+      if (j == VC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 4 * q + g;
+          if (r < NU) sh.c.GV[k * 16 + r] = u[q];
+          if (r < NX) sh.c.PV[k * 16 + r] = xn[q];
+        }
+      }
+      xv = xn;
+    }
   }
+rollout_done:
+  wsync();
+  for (int e = lane; e < N * NU; e += W64) uout[e] = sh.c.GV[(e / NU) * 16 + e % NU];
+  for (int e = lane; e < N * NX; e += W64) xout[NX + e] = sh.c.PV[(e / NX) * 16 + e % NX];
   gsync();
 }
 
