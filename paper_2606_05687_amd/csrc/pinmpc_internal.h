@@ -220,6 +220,23 @@ __device__ inline void gj_rows(double (&col)[12], uint32_t unit = 0) {
   }
 }
 
+// gj_rows on two systems with the same leading block (so the same pivots):
+// one reciprocal per pivot, two independent update blocks.
+template <int p = 0>
+__device__ inline void gj_rows2(double (&a)[12], double (&b)[12], uint32_t unit = 0) {
+  if constexpr (p < 12) {
+    if (!((unit >> p) & 1u)) {
+      const double rp = recip(row_bcast<p>(a[p]));
+      const double ta = a[p] * rp, tb = b[p] * rp;
+      fmac_row_bcast12<p>(a, -ta);
+      fmac_row_bcast12<p>(b, -tb);
+      a[p] = ta;
+      b[p] = tb;
+    }
+    gj_rows2<p + 1>(a, b, unit);
+  }
+}
+
 // Face code of one contact: bits 0..4 force rows active
 //   (0: f_x - mu f_z <= 0, 1: -f_x - mu f_z <= 0, 2: f_y - mu f_z <= 0,
 //    3: -f_y - mu f_z <= 0, 4: f_z <= fz_max),

@@ -634,43 +634,34 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         if (j == VC) sh.r.G[r * GS + NU + NX] = D5[q] + D4[q];
       }
       wsync();
-      // Gauss-Jordan elimination (H is SPD: no pivoting).
+      // Gauss-Jordan elimination (H is SPD: no pivoting) of [H | Hwx | hw]
+      // (and, for Newton steps, which keep H^-1, of [H | I] beside it): lane
+      // 16 R + c holds column c of H (c < NU, the same in every row R) or
+      // right-hand side 4 R + c - NU (Hwx columns 0..12, hw as 13 = VC;
+      // identity columns 0..11); afterwards the right-hand sides are
+      // H^-1 Hwx, H^-1 hw (and H^-1).
+      static_assert(NU == 12, "row elimination is written for 12 inputs");
+      const int hc = lane & 15, rhs = 4 * (lane >> 4) + hc - NU;
+      const bool is_h = hc < NU;
+      double col[NU];
+#pragma unroll
+      for (int r = 0; r < NU; ++r)
+        col[r] = (is_h || rhs <= NX) ? sh.r.G[r * GS + (is_h ? hc : NU + rhs)] : 0.0;
       if constexpr (!newton) {
-        // [H | Hwx | hw]: lane 16 R + c holds column c of H (c < NU, the same
-        // in every row R) or right-hand side 4 R + c - NU (Hwx columns 0..12,
-        // hw as 13 = VC); afterwards the right-hand sides are H^-1 Hwx and
-        // H^-1 hw.
-        const int hc = lane & 15, rhs = 4 * (lane >> 4) + hc - NU;
-        const bool is_h = hc < NU;
-        double col[NU];
-#pragma unroll
-        for (int r = 0; r < NU; ++r)
-          col[r] = (is_h || rhs <= NX) ? sh.r.G[r * GS + (is_h ? hc : NU + rhs)] : 0.0;
-        static_assert(NU == 12, "row elimination is written for 12 inputs");
         gj_rows(col, unit);
-        if (!is_h && rhs <= NX) {
-#pragma unroll
-          for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + rhs] = -col[r];
-        }
       } else {
-        // [H | Hwx | hw | I] with lane c holding column c (38 columns: more
-        // than a row's free lanes); afterwards [I | H^-1 Hwx | H^-1 hw | H^-1].
-        constexpr int C0 = NU + NX + 1;
-        double col[NU];
+        double icol[NU];
 #pragma unroll
-        for (int r = 0; r < NU; ++r)
-          col[r] = (lane < C0) ? sh.r.G[r * GS + lane]
-                               : ((lane < C0 + NU && r == lane - C0) ? 1.0 : 0.0);
-        gj_columns<NU>(col, unit);
-        if (lane >= NU && lane < C0) {
-          const int c = (lane < NU + NX) ? lane - NU : VC;
+        for (int r = 0; r < NU; ++r) icol[r] = is_h ? col[r] : ((r == rhs) ? 1.0 : 0.0);
+        gj_rows2(col, icol, unit);
+        if (!is_h && rhs < NU) {
 #pragma unroll
-          for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + c] = -col[r];
+          for (int r = 0; r < NU; ++r) sh.r.HI[r * 16 + rhs] = icol[r];
         }
-        if (lane >= C0 && lane < C0 + NU) {
+      }
+      if (!is_h && rhs <= NX) {
 #pragma unroll
-          for (int r = 0; r < NU; ++r) sh.r.HI[r * 16 + lane - C0] = col[r];
-        }
+        for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + rhs] = -col[r];
       }
       wsync();
       d4 KK, KT;
