@@ -461,6 +461,7 @@ __device__ inline d4 cook(const float m[4], bool transposed, int rows, int cols)
 __device__ inline void pin(const d4& t) {
   asm volatile("" ::"v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]));
 }
+__device__ inline void pin(double t) { asm volatile("" ::"v"(t)); }
 __device__ inline void pin_memory() { asm volatile("" ::: "memory"); }
 // A pointer read from the LDS context, made wave-uniform (scalar registers):
 // the stage loops then neither re-read the context after their LDS stores
@@ -800,15 +801,41 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec,
   else riccati_t<Mode::NEWTON, false>(C, sh, rcvec, ktop);
 }
 
+// s + sum_r (v of lane r of this 16-lane row) * a[r], r = 0..12, over four
+// interleaved accumulators: the DPP row broadcast of v rides in each fused
+// multiply-add.  The leading two wait states separate the block's DPP reads
+// of v from a vector write of v just before it.
+__device__ inline double dot_row_bcast13(double v, const double (&a)[13], double s) {
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#define PINMPC_DOT(acc, r, ai) \
+  "v_fmac_f64_dpp %" #acc ", %4, %" #ai " row_newbcast:" #r " row_mask:0xf bank_mask:0xf bound_ctrl:1\n"
+  asm volatile("s_nop 1\n"
+               PINMPC_DOT(0, 0, 5) PINMPC_DOT(1, 1, 6) PINMPC_DOT(2, 2, 7) PINMPC_DOT(3, 3, 8)
+               PINMPC_DOT(0, 4, 9) PINMPC_DOT(1, 5, 10) PINMPC_DOT(2, 6, 11) PINMPC_DOT(3, 7, 12)
+               PINMPC_DOT(0, 8, 13) PINMPC_DOT(1, 9, 14) PINMPC_DOT(2, 10, 15)
+               PINMPC_DOT(3, 11, 16) PINMPC_DOT(0, 12, 17)
+               : "+v"(s), "+v"(s1), "+v"(s2), "+v"(s3)
+               : "v"(v), "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
+                 "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11]),
+                 "v"(a[12]));
+#undef PINMPC_DOT
+  return (s + s1) + (s2 + s3);
+}
+
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
-// gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}, both in column VC of a
-// tile.  The terms that need no costate are formed first, in parallel, into
-// LDS; the recursion then fetches only the A and B tiles, two stages ahead
-// (it issues no global store, so waiting for one fetch does not wait for the
-// next), and leaves p and g in LDS until it is done.
+// gradient g_k = R (u_k - u_ref_k) + B_k^T p_{k+1}.  The terms that need no
+// costate are formed first, in parallel, into LDS.  The recursion is a chain
+// of 13-vector products, so it runs on the vector units rather than the
+// matrix cores (where a 16 x 16 tile product per stage would carry one useful
+// column): lane i of every 16-lane row holds entry i of p (the rows
+// identical) and column i of A_{k+1} and B_k, and each product is 13 fused
+// multiply-adds whose other factor, p_r, arrives by row broadcast.  Columns
+// are fetched two stages ahead (unconditionally, stage index clamped, loop
+// left as a whole, no global store inside: each stage waits for its own
+// loads only); p and g stay in LDS until the chain is done.
 __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
   gsync();
-  const int lane = threadIdx.x, g = tg(), j = tj();
+  const int lane = threadIdx.x;
   const int N = __builtin_amdgcn_readfirstlane(C.N);
   const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pur = uni(C.u_ref);
   const gd prx = uni(C.rx), pru = uni(C.ru), prlam = uni(C.rlam), prg = uni(C.rg);
@@ -822,51 +849,53 @@ __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
     sh.c.GV[k * 16 + i] = C.R[i] * (pru[(size_t)k * NU + i] - ur);
   }
   wsync();
-  // stage k needs A_{k+1} (for p_{k+1}) and B_k (for g_k)
-  auto cfetch = [&](int k, float a[4], float b[4]) {
-    gather(pA + (size_t)clampi(k + 1, N - 1) * NX * NX, false, NX, NX, a);
-    gather(pB + (size_t)k * NX * NU, false, NX, NU, b);
+  const int i = lane & 15;
+  const int ia = clampi(i, NX - 1), ib = clampi(i, NU - 1);
+  struct ColRaw {
+    float a[NX], b[NX];   // A_{k+1}[r][i], B_k[r][i]
   };
-  d4 p = zero4();
-  auto step = [&](int k, const float a[4], const float b[4]) {
-    const d4 A1 = cook(a, false, NX, NX);
-    const d4 Bk = cook(b, false, NX, NU);
-    d4 qx, rg;
+  // stage k needs A_{k+1} (for p_{k+1}) and B_k (for g_k); at k = N - 1 the
+  // clamped A_N multiplies p_{N+1} = 0
+  auto cfetch = [&](int k, ColRaw& s) {
+    const gcf Ak = pA + (size_t)clampi(k + 1, N - 1) * NX * NX;
+    const gcf Bk = pB + (size_t)k * NX * NU;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = 4 * q + g;
-      qx[q] = (j == VC && r < NX) ? sh.c.PV[k * 16 + r] : 0.0;
-      rg[q] = (j == VC && r < NU) ? sh.c.GV[k * 16 + r] : 0.0;
-    }
-    p = (k + 1 < N) ? mmT<4>(A1, p, qx) : qx;
-    const d4 gk = mmT<4>(Bk, p, rg);
-    if (j == VC) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 4 * q + g;
-        if (r < NX) sh.c.PV[k * 16 + r] = p[q];
-        if (r < NU) sh.c.GV[k * 16 + r] = gk[q];
-      }
+    for (int r = 0; r < NX; ++r) {
+      s.a[r] = Ak[r * NX + ia];
+      s.b[r] = Bk[r * NU + ib];
     }
   };
-  // ring of CD stages in flight (the chain's work per stage is short next to
-  // a load's latency)
-  constexpr int CD = 4;
-  float ra[CD][4], rb[CD][4];
+  constexpr int CD = 2;
+  ColRaw ring[CD];
 #pragma unroll
   for (int d = 0; d < CD; ++d) {
-    cfetch(N - 1 - d >= 0 ? N - 1 - d : 0, ra[d], rb[d]);
+    cfetch(N - 1 - d >= 0 ? N - 1 - d : 0, ring[d]);
     pin_memory();   // issued in ring order, as the loop issues them
   }
-  // Every path back to the loop head has issued the same fetches in ring
-  // order (the fetch is unconditional, clamped, and the exit leaves the
-  // whole loop), so each stage waits for its own loads only.
+  double p = 0.0;   // p_{k+2}, entry i
   for (int k = N - 1;;) {
 #pragma unroll
     for (int d = 0; d < CD; ++d, --k) {
       if (k < 0) goto chain_done;
-      step(k, ra[d], rb[d]);
-      cfetch(k - CD >= 0 ? k - CD : 0, ra[d], rb[d]);
+      double a[NX], b[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        a[r] = (double)ring[d].a[r];
+        b[r] = (double)ring[d].b[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        pin(a[r]);
+        pin(b[r]);
+      }
+      pin_memory();
+      cfetch(k - CD >= 0 ? k - CD : 0, ring[d]);
+      const double qx = (i < NX) ? sh.c.PV[k * 16 + i] : 0.0;
+      const double rg = (i < NU) ? sh.c.GV[k * 16 + i] : 0.0;
+      p = dot_row_bcast13(p, a, qx);          // p_{k+1}
+      const double gk = dot_row_bcast13(p, b, rg);
+      if (lane < NX) sh.c.PV[k * 16 + i] = p;
+      if (lane < NU) sh.c.GV[k * 16 + i] = gk;
     }
   }
 chain_done:
