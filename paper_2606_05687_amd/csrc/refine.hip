@@ -513,6 +513,44 @@ __device__ inline uint32_t null_inputs(int c0, int c1, int f0, int f1, bool newt
   return m;
 }
 
+// s + sum_r (v of lane r of this 16-lane row) * a[r], r = 0..12, over four
+// interleaved accumulators: the DPP row broadcast of v rides in each fused
+// multiply-add.  The leading two wait states separate the block's DPP reads
+// of v from a vector write of v just before it.
+__device__ inline double dot_row_bcast13(double v, const double (&a)[13], double s) {
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#define PINMPC_DOT(acc, r, ai) \
+  "v_fmac_f64_dpp %" #acc ", %4, %" #ai " row_newbcast:" #r " row_mask:0xf bank_mask:0xf bound_ctrl:1\n"
+  asm volatile("s_nop 1\n"
+               PINMPC_DOT(0, 0, 5) PINMPC_DOT(1, 1, 6) PINMPC_DOT(2, 2, 7) PINMPC_DOT(3, 3, 8)
+               PINMPC_DOT(0, 4, 9) PINMPC_DOT(1, 5, 10) PINMPC_DOT(2, 6, 11) PINMPC_DOT(3, 7, 12)
+               PINMPC_DOT(0, 8, 13) PINMPC_DOT(1, 9, 14) PINMPC_DOT(2, 10, 15)
+               PINMPC_DOT(3, 11, 16) PINMPC_DOT(0, 12, 17)
+               : "+v"(s), "+v"(s1), "+v"(s2), "+v"(s3)
+               : "v"(v), "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
+                 "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11]),
+                 "v"(a[12]));
+#undef PINMPC_DOT
+  return (s + s1) + (s2 + s3);
+}
+
+// s + sum_r (v of lane r of this 16-lane row) * a[r], r = 0..11, likewise.
+__device__ inline double dot_row_bcast12(double v, const double (&a)[12], double s) {
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#define PINMPC_DOT(acc, r, ai) \
+  "v_fmac_f64_dpp %" #acc ", %4, %" #ai " row_newbcast:" #r " row_mask:0xf bank_mask:0xf bound_ctrl:1\n"
+  asm volatile("s_nop 1\n"
+               PINMPC_DOT(0, 0, 5) PINMPC_DOT(1, 1, 6) PINMPC_DOT(2, 2, 7) PINMPC_DOT(3, 3, 8)
+               PINMPC_DOT(0, 4, 9) PINMPC_DOT(1, 5, 10) PINMPC_DOT(2, 6, 11) PINMPC_DOT(3, 7, 12)
+               PINMPC_DOT(0, 8, 13) PINMPC_DOT(1, 9, 14) PINMPC_DOT(2, 10, 15)
+               PINMPC_DOT(3, 11, 16)
+               : "+v"(s), "+v"(s1), "+v"(s2), "+v"(s3)
+               : "v"(v), "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
+                 "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11]));
+#undef PINMPC_DOT
+  return (s + s1) + (s2 + s3);
+}
+
 template <Mode mode, bool factor>
 __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec, int ktop) {
   const int N = __builtin_amdgcn_readfirstlane(C.N);
@@ -665,14 +703,16 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         for (int r = 0; r < NU; ++r) sh.r.KK[r * 16 + rhs] = -col[r];
       }
       wsync();
-      d4 KK, KT;
+      d4 KK;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = 4 * q + g;
         KK[q] = (r < NU && (j < NX || j == VC)) ? sh.r.KK[r * 16 + j] : 0.0;   // [K | kap]
-        KT[q] = (j < NU && r < NX) ? sh.r.KK[j * 16 + r] : 0.0;               // K^T
       }
-      st_tile(prK + (size_t)k * TILE, KT);
+      // [K | kap] row-major (row r at 16 r) for the rollout; rows 4q + g, q < 3,
+      // are the 12 input rows
+#pragma unroll
+      for (int q = 0; q < 3; ++q) prK[(size_t)k * TILE + (4 * q + g) * 16 + j] = KK[q];
       vec_store(prkap + (size_t)k * NU, NU, KK);
       if (newton) {
         d4 HI;
@@ -712,84 +752,89 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     Ss = Sn;
   }
 
-  // forward rollout: w = K x + kap, u = P w + c, x' = A x + B u + e, all in
-  // column VC (each lane uses only what it stored above).  The stage data is
-  // fetched FD stages ahead, unconditionally (stage index clamped) and with
-  // the loop left as a whole, so every path back to the loop head has issued
-  // the same loads and each stage waits for its own loads only; u_k and
-  // x_{k+1} collect in LDS (the costate buffers, free here) and are copied
-  // out after the loop.
+  // forward rollout: w = K x + kap, u = P^T w + c (P from the stage tile;
+  // the stance mask for Newton steps), x' = A x + B u + e.  It is a chain of
+  // 13-vector products, so it runs on the vector units: lane i of every
+  // 16-lane row holds x_i, w_i, u_i (the rows identical) with row i of K, A,
+  // B and column i of P, and each product is a block of fused multiply-adds
+  // whose vector factor arrives by DPP row broadcast.  The stage data is
+  // fetched a stage ahead (unconditionally, so every path back to the loop
+  // head has issued the same loads); u_k and x_{k+1} collect in LDS (the
+  // costate buffers, free here) and are copied out after the loop.
   gd xout = newton ? prdx : prx;
   gd uout = newton ? prdu : pru;
+  const int fi = lane & 15;
+  const int ix = clampi(fi, NX - 1), iu = clampi(fi, NU - 1);
+  const gcf pev = pe ? pe : pA;   // a valid address when there is no e
   struct FwdRaw {
-    float at[4], bt[4], ev[4];
-    double kap[4];
-    d4 KT, T;
+    double kr[NX];   // K[i][0..12]
+    double pc[NU];   // P[0..11][i] (equality passes)
+    double c, kap;
+    float a[NX], b[NU], e;
     int ct;
   };
   auto ffetch = [&](int k, FwdRaw& s) {
-    gather(pA + (size_t)k * NX * NX, true, NX, NX, s.at);
-    gather(pB + (size_t)k * NX * NU, true, NX, NU, s.bt);
+    const gcd kr = prK + (size_t)k * TILE + iu * 16;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      s.ev[q] = 0.f;
-      s.kap[q] = prkap[(size_t)k * NU + clampi(4 * q + g, NU - 1)];
+    for (int r = 0; r < NX; ++r) s.kr[r] = kr[r];
+    s.kap = prkap[(size_t)k * NU + iu];
+    if (!newton) {
+      const gcd tt = prT + (size_t)k * TILE;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) s.pc[r] = tt[tile_at(r, iu)];
+      s.c = tt[tile_at(iu, VC)];
     }
-    if (!newton && pe) gatherv(pe + (size_t)k * NX, NX, s.ev);
-    s.KT = ld_tile(prK + (size_t)k * TILE);
-    s.T = ld_tile(prT + (size_t)k * TILE);
-    s.ct = newton ? (int)pct[k * 2 + (j < NU ? j / 6 : 0)] : 0;
+    const gcf ar = pA + (size_t)k * NX * NX + ix * NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s.a[r] = ar[r];
+    const gcf br = pB + (size_t)k * NX * NU + ix * NU;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) s.b[r] = br[r];
+    s.e = pev[pe ? (size_t)k * NX + ix : 0];
+    s.ct = newton ? (int)pct[k * 2 + iu / 6] : 0;
   };
-  d4 xv = zero4();
-  if (j == VC && !newton) {
+  double xv = 0.0;   // x_k, entry fi
+  if (!newton) xv = (double)uni(C.x0)[ix];
+  FwdRaw fr;
+  ffetch(0, fr);
+  pin_memory();
+  for (int k = 0; k < N; ++k) {
+    double kr[NX], pc[NU], a[NX], b[NU];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (4 * q + g < NX) xv[q] = (double)uni(C.x0)[4 * q + g];
-  }
-  vec_store(xout, NX, xv);
-  constexpr int FD = 2;
-  FwdRaw ring[FD];
-#pragma unroll
-  for (int d = 0; d < FD; ++d) {
-    ffetch(d < N ? d : (N > 0 ? N - 1 : 0), ring[d]);
-    pin_memory();   // issued in ring order, as the loop issues them
-  }
-  for (int k = 0;;) {
-#pragma unroll
-    for (int d = 0; d < FD; ++d, ++k) {
-      if (k >= N) goto rollout_done;
-      const d4 AT = cook(ring[d].at, true, NX, NX);
-      const d4 BT = cook(ring[d].bt, true, NX, NU);
-      const d4 KT = ring[d].KT, T = ring[d].T;
-      d4 kap, ev;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 4 * q + g;
-        kap[q] = (j == VC && r < NU) ? ring[d].kap[q] : 0.0;
-        ev[q] = (j == VC && r < NX) ? (double)ring[d].ev[q] : 0.0;
-      }
-      const d4 Pt = newton ? mask_tile(ring[d].ct) : sel(j < NU, T);
-      pin(AT); pin(BT); pin(KT); pin(T); pin(kap); pin(ev); pin(Pt);
-      pin_memory();
-      ffetch(k + FD < N ? k + FD : N - 1, ring[d]);
-      const d4 w = mmT<4>(KT, xv, kap);
-      d4 u = mmT<3>(Pt, w, zero4());
-      if (!newton) u += sel(j == VC, T);
-      d4 xn = mmT<4>(AT, xv, ev);
-      xn = mmT<3>(BT, u, xn);
-      if (j == VC) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = 4 * q + g;
-          if (r < NU) sh.c.GV[k * 16 + r] = u[q];
-          if (r < NX) sh.c.PV[k * 16 + r] = xn[q];
-        }
-      }
-      xv = xn;
+    for (int r = 0; r < NX; ++r) {
+      kr[r] = fr.kr[r];
+      a[r] = (double)fr.a[r];
     }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      pc[r] = newton ? 0.0 : fr.pc[r];
+      b[r] = (double)fr.b[r];
+    }
+    const double kap = fr.kap, cc = newton ? 0.0 : fr.c;
+    const double ee = (!newton && pe) ? (double)fr.e : 0.0;
+    const bool stance = fr.ct != 0;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      pin(kr[r]);
+      pin(a[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      pin(pc[r]);
+      pin(b[r]);
+    }
+    pin_memory();
+    ffetch(k + 1 < N ? k + 1 : k, fr);
+    const double w = dot_row_bcast13(xv, kr, kap);
+    const double u = newton ? (stance ? w : 0.0) : dot_row_bcast12(w, pc, cc);
+    double xn = dot_row_bcast13(xv, a, ee);
+    xn = dot_row_bcast12(u, b, xn);
+    if (lane < NU) sh.c.GV[k * 16 + fi] = u;
+    if (lane < NX) sh.c.PV[k * 16 + fi] = xn;
+    xv = xn;
   }
-rollout_done:
   wsync();
+  if (lane < NX) xout[lane] = newton ? 0.0 : (double)uni(C.x0)[lane];
   for (int e = lane; e < N * NU; e += W64) uout[e] = sh.c.GV[(e / NU) * 16 + e % NU];
   for (int e = lane; e < N * NX; e += W64) xout[NX + e] = sh.c.PV[(e / NX) * 16 + e % NX];
   gsync();
@@ -799,27 +844,6 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec,
   if (mode == Mode::EQ) riccati_t<Mode::EQ, true>(C, sh, rcvec, ktop);
   else if (factor) riccati_t<Mode::NEWTON, true>(C, sh, rcvec, ktop);
   else riccati_t<Mode::NEWTON, false>(C, sh, rcvec, ktop);
-}
-
-// s + sum_r (v of lane r of this 16-lane row) * a[r], r = 0..12, over four
-// interleaved accumulators: the DPP row broadcast of v rides in each fused
-// multiply-add.  The leading two wait states separate the block's DPP reads
-// of v from a vector write of v just before it.
-__device__ inline double dot_row_bcast13(double v, const double (&a)[13], double s) {
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#define PINMPC_DOT(acc, r, ai) \
-  "v_fmac_f64_dpp %" #acc ", %4, %" #ai " row_newbcast:" #r " row_mask:0xf bank_mask:0xf bound_ctrl:1\n"
-  asm volatile("s_nop 1\n"
-               PINMPC_DOT(0, 0, 5) PINMPC_DOT(1, 1, 6) PINMPC_DOT(2, 2, 7) PINMPC_DOT(3, 3, 8)
-               PINMPC_DOT(0, 4, 9) PINMPC_DOT(1, 5, 10) PINMPC_DOT(2, 6, 11) PINMPC_DOT(3, 7, 12)
-               PINMPC_DOT(0, 8, 13) PINMPC_DOT(1, 9, 14) PINMPC_DOT(2, 10, 15)
-               PINMPC_DOT(3, 11, 16) PINMPC_DOT(0, 12, 17)
-               : "+v"(s), "+v"(s1), "+v"(s2), "+v"(s3)
-               : "v"(v), "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
-                 "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11]),
-                 "v"(a[12]));
-#undef PINMPC_DOT
-  return (s + s1) + (s2 + s3);
 }
 
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
