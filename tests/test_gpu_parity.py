@@ -111,6 +111,22 @@ def test_parity_uneven_horizons(solver):
     _check_invariants(batch, out, range(96))
 
 
+def test_parity_maximum_horizon(solver):
+    """Horizons at the library's maximum of 64 stages (the per-stage LDS
+    buffers of the costate chain and the rollout full), with shorter
+    horizons padded to it beside them."""
+    cfg = dict(mpcgen.CONFIGS["uneven_b16384"], horizons=(64,), batch=8)
+    full = mpcgen.make_batch(cfg, indices=range(6), n_max=64)
+    mixed = mpcgen.make_batch("uneven_b16384", indices=range(6), n_max=64)
+    batch = {k: (np.concatenate([full[k], mixed[k]]) if hasattr(full[k], "shape") and full[k].ndim
+                 else full[k]) for k in full}
+    assert batch["A"].shape[1] == 64 and (batch["N"][:6] == 64).all()
+    out = _solve(solver, batch)
+    assert (out["status"] == 0).all(), out["status"]
+    _compare(batch, out, [0, 1, 2, 6, 7])
+    _check_invariants(batch, out, range(12))
+
+
 def test_edge_cases(solver):
     import torch
     from paper_2606_05687_amd import binding
