@@ -219,13 +219,6 @@ __device__ void face_affine(int code, double mu, double fz, double tm, double P[
   }
 }
 
-// Input blocks: force triples (3 x 3) and single moment components.  Face
-// projectors P_k and the interior-point input Hessian R' are block diagonal
-// in these blocks, so products with them only run over the block of the
-// column (exact, not an approximation).
-__device__ inline int blk_start(int j) { return (j % 6 < 3) ? j - j % 6 : j; }
-__device__ inline int blk_len(int j) { return (j % 6 < 3) ? 3 : 1; }
-
 // --------------------------------------------------------------- LDS state
 
 // Hand-off buffers of the stage recursion; everything else of a stage lives
@@ -279,28 +272,6 @@ __device__ inline d4 mmT(d4 u, d4 v, d4 acc) {
   return acc;
 }
 
-// Tile of the row-major rows x cols matrix M.
-__device__ inline d4 tile_of(gcf M, int rows, int cols) {
-  const int g = tg(), j = tj();
-  d4 t;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = 4 * q + g;
-    t[q] = (r < rows && j < cols) ? (double)M[r * cols + j] : 0.0;
-  }
-  return t;
-}
-// Tile of M^T.
-__device__ inline d4 tile_of_T(gcf M, int rows, int cols) {
-  const int g = tg(), j = tj();
-  d4 t;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = 4 * q + g;
-    t[q] = (j < rows && r < cols) ? (double)M[j * cols + r] : 0.0;
-  }
-  return t;
-}
 __device__ inline d4 ld_tile(gcd base) {
   return reinterpret_cast<const GMEM d4*>(base)[threadIdx.x];
 }
@@ -314,16 +285,6 @@ __device__ inline void vec_store(gd v, int len, d4 t) {
   }
 }
 __device__ inline d4 sel(bool c, d4 a) { return c ? a : zero4(); }
-// Coefficient a (0..5) of wrench row `row` (the same rows as wrench_row).
-__device__ inline double wcoef(int row, int a, double mu) {
-  if (row < 4) {
-    if (a == 2) return -mu;
-    if (a == (row >> 1)) return (row & 1) ? -1.0 : 1.0;
-    return 0.0;
-  }
-  if (row == 4) return (a == 2) ? 1.0 : 0.0;
-  return (a == 3 + (row - 5) % 3) ? ((row < 8) ? 1.0 : -1.0) : 0.0;
-}
 
 // Address of entry (r, c) of a stage tile in memory: lane 16 (r % 4) + c
 // holds it as item r / 4.
