@@ -112,27 +112,31 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
       }
     }
   }
-  // M_k = (Bt^T Bt + I)^{-1}: lane c < 12 forms column c
+  // M_k = (Bt^T Bt + I)^{-1}: Gauss-Jordan on [Bt^T Bt + I | I] with lane
+  // 16 R + c holding column c of the matrix (c < 12, the same in every row R)
+  // or identity column 4 R + c - 12; pivot columns by DPP row broadcast
   {
+    static_assert(NU == 12, "row elimination is written for 12 inputs");
+    const int hc = lane & 15, rhs = 4 * (lane >> 4) + hc - NU;
     double col[NU];
-    if (lane < NU) {
+    if (hc < NU) {
       double bc[NX];
 #pragma unroll
-      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * NU + lane];
+      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * NU + hc];
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
-        double g = (r == lane) ? 1.0 : 0.0;
+        double g = (r == hc) ? 1.0 : 0.0;
 #pragma unroll
         for (int i = 0; i < NX; ++i) g += sBt[i * NU + r] * bc[i];
         col[r] = g;
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < NU; ++r) col[r] = (r == lane - NU) ? 1.0 : 0.0;
+      for (int r = 0; r < NU; ++r) col[r] = (r == rhs) ? 1.0 : 0.0;
     }
-    gj_columns<NU>(col);
-    if (lane >= NU && lane < 2 * NU) {
-      const int c = lane - NU;
+    gj_rows(col);
+    if (hc >= NU && rhs < NU) {
+      const int c = rhs;
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
         if (r <= c) {
