@@ -817,8 +817,10 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec,
 // multiply-adds whose other factor, p_r, arrives by row broadcast.  Columns
 // are fetched two stages ahead (unconditionally, stage index clamped, loop
 // left as a whole, no global store inside: each stage waits for its own
-// loads only); p and g stay in LDS until the chain is done.
-__device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
+// loads only); p and g stay in LDS until the chain is done.  Returns the
+// state-side magnitude max |Q (x_{k+1} - r_k)|, |p|, |p - Q (x_{k+1} - r_k)|
+// (= |A^T p_{k+2}|) over all stages, which the KKT scaling needs.
+__device__ __attribute__((noinline)) double costates_grad(const Ctx& C, Sh& sh) {
   gsync();
   const int lane = threadIdx.x;
   const int N = __builtin_amdgcn_readfirstlane(C.N);
@@ -858,6 +860,7 @@ __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
     pin_memory();   // issued in ring order, as the loop issues them
   }
   double p = 0.0;   // p_{k+2}, entry i
+  double tstate = 0.0;
   for (int k = N - 1;;) {
 #pragma unroll
     for (int d = 0; d < CD; ++d, --k) {
@@ -879,6 +882,7 @@ __device__ __attribute__((noinline)) void costates_grad(const Ctx& C, Sh& sh) {
       const double rg = (i < NU) ? sh.c.GV[k * 16 + i] : 0.0;
       p = dot_row_bcast13(p, a, qx);          // p_{k+1}
       const double gk = dot_row_bcast13(p, b, rg);
+      if (i < NX) tstate = fmax(tstate, fmax(fabs(qx), fmax(fabs(p), fabs(p - qx))));
       if (lane < NX) sh.c.PV[k * 16 + i] = p;
       if (lane < NU) sh.c.GV[k * 16 + i] = gk;
     }
@@ -888,6 +892,7 @@ chain_done:
   for (int e = lane; e < N * NX; e += W64) prlam[e] = sh.c.PV[(e / NX) * 16 + e % NX];
   for (int e = lane; e < N * NU; e += W64) prg[e] = sh.c.GV[(e / NU) * 16 + e % NU];
   gsync();
+  return wave_max(tstate);
 }
 
 // Row data of one stance contact-stage (k, i) in registers: a lane owns a
@@ -922,10 +927,11 @@ __device__ inline void rows_of(const Ctx& C, const double u[6], double gu[NROW],
 
 // Row multipliers of each stance contact from its face and the gradient, and
 // the normalised KKT residuals of the current (u, x, p, mu).  Returns KKT.
-__device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES]) {
+__device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES],
+                                                           double term_state) {
   gsync();
   const int lane = threadIdx.x;
-  double r_ineq = 0.0, stat = 0.0, term = 0.0, comp = 0.0, mumax = 0.0, neg = 0.0;
+  double r_ineq = 0.0, stat = 0.0, term = term_state, comp = 0.0, mumax = 0.0, neg = 0.0;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     const int st = k;
@@ -1023,15 +1029,8 @@ __device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double
       stat = fmax(stat, fabs(g[a] + gm[a]));
     }
   }
-  // state-side term norms: |Q (x - r)|, |p|, |A^T p| = |p_k - Q(x_{k+1} - r_k)|
-  for (int e = lane; e < C.N * NX; e += W64) {
-    const int k = e / NX, j = e % NX;
-    const int st = k;
-    const double x = C.rx[(k + 1) * NX + j];
-    const double qx = C.Q[j] * (x - (double)C.x_ref[st * NX + j]);
-    const double lam = C.rlam[st * NX + j];
-    term = fmax(term, fmax(fabs(qx), fmax(fabs(lam), fabs(lam - qx))));
-  }
+  // the state-side term norms (|Q (x - r)|, |p|, |A^T p|) come in as
+  // term_state from the costate recursion, which holds them
   r_ineq = wave_max(r_ineq);
   stat = wave_max(stat);
   term = wave_max(term);
@@ -1143,8 +1142,8 @@ __device__ __attribute__((noinline)) void faces_from_u(const Ctx& C, gcd u_src, 
 __device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES],
                                                    int ktop) {
   riccati(C, sh, Mode::EQ, true, nullptr, ktop);
-  costates_grad(C, sh);
-  return multipliers_kkt(C, res);
+  const double ts = costates_grad(C, sh);
+  return multipliers_kkt(C, res, ts);
 }
 
 // Faces from the interior-point iterate (row active where z > s); returns an
@@ -1599,8 +1598,8 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     // the ADMM point as it is: rollout, faces from slack, residuals
     faces_from_u(C, C.ru, 1e-5);
     rollout_ru(C, sh);
-    costates_grad(C, sh);
-    kkt = multipliers_kkt(C, res);
+    const double ts = costates_grad(C, sh);
+    kkt = multipliers_kkt(C, res, ts);
     res[0] = dyn_residual(C);
   }
 
