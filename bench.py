@@ -170,7 +170,7 @@ def _counter_rows(run_dir):
     return rows
 
 
-TUNED = "--autotune 0 --form 1 --iters 10 --rho 10 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
+TUNED = "--autotune 0 --form 1 --iters 3 --rho 10 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
 PMC_COMMANDS = [
     f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
     f"python3 bench.py {TUNED} --steps 2 --warmup 1",

@@ -39,7 +39,7 @@ def _key(dev, allow_bf16):
 
 def candidates(n_max, allow_bf16=False):
     forms = [1] if n_max <= 40 else [-1]
-    iters = [10, 20, 50]
+    iters = [3, 5, 10, 20, 50]
     rhos = [10.0, 30.0]
     passes = [8, 12, 16]
     firsts = [2, 4, 0]
