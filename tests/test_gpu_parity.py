@@ -365,3 +365,33 @@ def test_second_launch_resumes_active_set_passes_without_interior_point():
     du = np.abs(two["u"][both] - one["u"][both]).max(axis=(1, 2)) / scale
     assert du.max() <= 1e-4
     assert set(np.unique(two["status"])) <= {0, 2}
+
+
+def test_autotuner_picks_a_certifying_schedule(tmp_path):
+    """The autotuner measures its candidate grid on a batch, keeps a schedule
+    that certifies, caches it, and answers the second call from the cache."""
+    import json
+    import torch
+    from paper_2606_05687_amd import autotune, binding
+    batch = mpcgen.make_batch("small_b64_n10")
+    dev = binding.to_device(batch)
+    cache = tmp_path / "tune.json"
+    best = autotune.tune(dev, cache_path=str(cache), in_flight=1)
+    assert best["iters"] in (3, 5, 10, 20, 50) and best["form"] == 1
+    rec = json.loads(cache.read_text())
+    (key, entry), = rec.items()
+    assert entry["settings"] == best and entry["score"] > 0
+    assert len(entry["log"]) == len(list(autotune.candidates(10)))
+    again = autotune.tune(dev, cache_path=str(cache), in_flight=1)
+    assert again == best
+    s = binding.Solver(0, **best)
+    try:
+        out = s.solve(dev)
+        torch.cuda.synchronize()
+        st = out["status"].cpu().numpy()
+        res = out["res"].cpu().numpy()
+    finally:
+        s.close()
+    assert (st == 0).all(), st
+    assert (res <= TOL_KKT).all()
+
