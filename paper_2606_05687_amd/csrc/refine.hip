@@ -959,31 +959,40 @@ __device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double
     // nonnegative (some subset is nonnegative exactly when -g_f lies in the
     // normal cone of the apex)
     if (face_apex(code)) {
-      double best = -1e300, bm[5] = {0, 0, 0, 0, 0};
-#pragma unroll 1
-      for (int drop = 0; drop < 4; ++drop) {
-        const int mask = 15 & ~(1 << drop);
-        double M[5][5], r[5];
-        gram5(mask, C.mu, M);
+      // the four side rows are [+-1, 0, -mu] and [0, +-1, -mu]: with b = -g_f
+      // and S = -b_z / mu the three-row systems are
+      //   mu0 - mu1 = b_x,  mu2 - mu3 = b_y,  mu0 + mu1 + mu2 + mu3 = S
+      // with the dropped multiplier zero, solved in closed form
+      const double bx = -g[0], by = -g[1], S = g[2] / C.mu;
+      double cand[4][4];
+      cand[0][0] = 0.0;                    cand[0][1] = -bx;
+      cand[0][2] = 0.5 * (S + bx + by);    cand[0][3] = 0.5 * (S + bx - by);
+      cand[1][0] = bx;                     cand[1][1] = 0.0;
+      cand[1][2] = 0.5 * (S - bx + by);    cand[1][3] = 0.5 * (S - bx - by);
+      cand[2][0] = 0.5 * (S + by + bx);    cand[2][1] = 0.5 * (S + by - bx);
+      cand[2][2] = 0.0;                    cand[2][3] = -by;
+      cand[3][0] = 0.5 * (S - by + bx);    cand[3][1] = 0.5 * (S - by - bx);
+      cand[3][2] = by;                     cand[3][3] = 0.0;
+      double best = -1e300;
+      int pick = 0;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          double gi[3];
-          force_row(i, C.mu, gi);
-          r[i] = ((mask >> i) & 1) ? -(gi[0] * g[0] + gi[1] * g[1] + gi[2] * g[2]) : 0.0;
-        }
-        solve5(M, r);
+      for (int drop = 0; drop < 4; ++drop) {
         double mn = 1e300;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if ((mask >> i) & 1) mn = fmin(mn, r[i]);
+          if (i != drop) mn = fmin(mn, cand[drop][i]);
         if (mn > best) {
           best = mn;
-#pragma unroll
-          for (int i = 0; i < 5; ++i) bm[i] = ((mask >> i) & 1) ? r[i] : 0.0;
+          pick = drop;
         }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) mu[i] = bm[i];
+      for (int i = 0; i < 4; ++i) {
+        double v = cand[0][i];
+#pragma unroll
+        for (int d = 1; d < 4; ++d) v = (pick == d) ? cand[d][i] : v;
+        mu[i] = v;
+      }
     } else {
       const int mask = code & 31;
       if (mask) {
