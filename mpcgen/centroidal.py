@@ -106,13 +106,43 @@ def _skew(r):
     return S
 
 
+def _draw_offsets(seed, idx, n, N, mass):
+    """Nonzero affine terms of one problem, from a substream of its own (so the
+    draws of ``_draw`` and every workload without offsets are unchanged):
+
+      e_k     per-stage disturbance of the dynamics, different at every stage
+              (angles and positions N(0, 2e-3), angular and linear velocity
+              N(0, 0.02), gravity state N(0, 1e-3))
+      u_ref   input reference: each contact's force (N(0, 20), N(0, 20),
+              m g / 2 + N(0, 30)) and moment N(0, 5)^3, at every stage
+              (swing stages included: their inputs are fixed to 0 anyway)
+      u_prev  input before stage 0: forces N(0, 50), moments N(0, 5)
+    """
+    rng = np.random.default_rng([int(seed), int(idx), 7])
+    sd = np.array([2e-3] * 6 + [0.02] * 6 + [1e-3])
+    e = rng.normal(0.0, 1.0, (n, NX)) * sd
+    ur = np.zeros((n, NU))
+    up = np.zeros(NU)
+    for i in range(NC):
+        ur[:, 6 * i:6 * i + 3] = rng.normal(0.0, 1.0, (n, 3)) * np.array([20.0, 20.0, 30.0])
+        ur[:, 6 * i + 2] += 0.5 * mass * GRAVITY
+        ur[:, 6 * i + 3:6 * i + 6] = rng.normal(0.0, 5.0, (n, 3))
+        up[6 * i:6 * i + 3] = rng.normal(0.0, 50.0, 3)
+        up[6 * i + 3:6 * i + 6] = rng.normal(0.0, 5.0, 3)
+    e[N:] = 0.0
+    ur[N:] = 0.0
+    return e, ur, up
+
+
 def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
-               dt=None, as_float32=True):
+               dt=None, as_float32=True, offsets=False):
     """Build a batch of problems.
 
     config   name in CONFIGS or a dict with the same keys
     indices  problem indices to draw (default range(batch))
     n_max    padded horizon (default: the largest drawn horizon)
+    offsets  draw nonzero e_k, u_ref and u_prev (``_draw_offsets``); without
+             it all three are zero, as in the paper's workloads
 
     Returns a dict of arrays (float32 unless ``as_float32`` is False):
       N [B] int32, A [B,n,13,13], B [B,n,13,12], e [B,n,13], x0 [B,13],
@@ -223,6 +253,12 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
         "tau_max": np.full(Bn, 50.0),
         "weight": mass * GRAVITY,
     }
+    if offsets:
+        for j, idx in enumerate(indices):
+            e, ur, up = _draw_offsets(seed, idx, n, int(Nh[j]), mass[j])
+            out["e"][j] = e
+            out["u_ref"][j] = ur
+            out["u_prev"][j] = up
     if as_float32:
         for k, v in out.items():
             if v.dtype == np.float64:

@@ -17,11 +17,21 @@ from oracle import admm, kkt, projection, qp
 NX, NU = 13, 12
 
 
-def _prob(config="small_b64_n10", b=0, **over):
-    batch = mpcgen.make_batch(config, indices=[b])
+def _prob(config="small_b64_n10", b=0, offsets=False, **over):
+    """Problem b of a workload; with ``offsets`` its e_k, u_ref and u_prev are
+    random and nonzero (e_k different at every stage), so that the affine terms
+    of the velocity-form lifting and of the cost enter every pin."""
+    batch = mpcgen.make_batch(config, indices=[b], offsets=offsets)
     p = mpcgen.problem_fp64(batch, 0)
+    if offsets:
+        assert np.all(np.abs(p["e"]) > 0) and np.all(np.abs(p["u_ref"]) > 0)
+        assert np.all(np.abs(p["u_prev"]) > 0)
+        assert not np.allclose(p["e"][1:], p["e"][:-1])
     p.update(over)
     return p
+
+
+OFFSETS = [pytest.param(False, id="zero-affine"), pytest.param(True, id="offsets")]
 
 
 # --------------------------------------------------------------- projection
@@ -99,10 +109,11 @@ def _loose(p):
     return q
 
 
+@pytest.mark.parametrize("offsets", OFFSETS)
 @pytest.mark.parametrize("config,b", [("small_b64_n10", 0), ("small_b64_n10", 3),
                                       ("plain_b4096_n20", 1)])
-def test_unconstrained_equals_riccati(config, b):
-    p = _loose(_prob(config, b))
+def test_unconstrained_equals_riccati(config, b, offsets):
+    p = _loose(_prob(config, b, offsets))
     u_ric = _riccati_lq(p)
     Gc, hc = projection.wrench_rows(p["mu"], p["fz_max"], p["tau_max"])
     slack = min(np.min(hc - Gc @ u_ric[k, 6 * i:6 * i + 6]) for k in range(p["N"]) for i in range(2))
@@ -115,8 +126,9 @@ def test_unconstrained_equals_riccati(config, b):
     assert np.max(np.abs(U - u_ric.reshape(-1)[free])) <= 1e-8 * np.max(np.abs(u_ric))
 
 
-def test_single_stage_closed_form():
-    p = _loose(_prob("small_b64_n10", 5))
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_single_stage_closed_form(offsets):
+    p = _loose(_prob("small_b64_n10", 5, offsets))
     p["N"] = 1
     for key in ("A", "B", "e", "x_ref", "u_ref", "contact"):
         p[key] = p[key][:1]
@@ -236,9 +248,10 @@ def _trim(p, N, contact, **over):
     return q
 
 
+@pytest.mark.parametrize("offsets", OFFSETS)
 @pytest.mark.parametrize("b", [0, 2])
-def test_bruteforce_one_stage_full_wrench(b):
-    p = _prob("small_b64_n10", b)
+def test_bruteforce_one_stage_full_wrench(b, offsets):
+    p = _prob("small_b64_n10", b, offsets)
     p = _trim(p, 1, [[True, False]], tau_max=2.0, fz_max=0.45 * p["weight"])
     U, stance, nact = _brute_force(p, with_moments=True)
     assert nact >= 1
@@ -247,8 +260,9 @@ def test_bruteforce_one_stage_full_wrench(b):
     assert np.max(np.abs(sol["u"] - u_bf)) <= 1e-6 * p["weight"]
 
 
-def test_bruteforce_three_stages_forces():
-    p = _prob("small_b64_n10", 1)
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_bruteforce_three_stages_forces(offsets):
+    p = _prob("small_b64_n10", 1, offsets)
     p = _trim(p, 3, [[True, False], [True, False], [False, True]], tau_max=1e6,
               fz_max=0.8 * p["weight"], mu=0.35)
     U, stance, nact = _brute_force(p, with_moments=False)
@@ -257,8 +271,9 @@ def test_bruteforce_three_stages_forces():
     assert np.max(np.abs(sol["u"] - _to_u(U, stance, 3))) <= 1e-6 * p["weight"]
 
 
-def test_bruteforce_double_support_forces():
-    p = _prob("plain_b4096_n20", 4)
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_bruteforce_double_support_forces(offsets):
+    p = _prob("plain_b4096_n20", 4, offsets)
     p = _trim(p, 1, [[True, True]], tau_max=1e6, fz_max=0.4 * p["weight"], mu=0.3)
     U, stance, nact = _brute_force(p, with_moments=False)
     assert nact >= 1
@@ -268,10 +283,13 @@ def test_bruteforce_double_support_forces():
 
 # -------------------------------------------------------------- certificate
 
-@pytest.mark.parametrize("config,count", [("small_b64_n10", 6), ("plain_b4096_n20", 3),
-                                          ("uneven_b16384", 2)])
-def test_oracle_kkt_certificate(config, count):
-    batch = mpcgen.make_batch(config, indices=range(count))
+@pytest.mark.parametrize("config,count,offsets", [("small_b64_n10", 6, False),
+                                                  ("plain_b4096_n20", 3, False),
+                                                  ("uneven_b16384", 2, False),
+                                                  ("small_b64_n10", 4, True),
+                                                  ("plain_b4096_n20", 3, True)])
+def test_oracle_kkt_certificate(config, count, offsets):
+    batch = mpcgen.make_batch(config, indices=range(count), offsets=offsets)
     for b in range(count):
         p = mpcgen.problem_fp64(batch, b)
         sol = qp.solve(p)
@@ -299,6 +317,37 @@ def test_kkt_measure_detects_planted_errors():
     assert kkt.residuals(p, u2, qp.rollout(p, u2))["r_ineq"] > 1e-3
     eu, ex = kkt.rel_err(u, sol["u"], sol["x"], sol["x"], p["weight"])
     assert eu > 1e-3 and ex == 0
+
+
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_kkt_measure_detects_planted_complementarity_error(offsets):
+    """Multipliers on both rows of a moment axis whose bound is slack on both
+    sides cancel in G^T mu (rows +e and -e), so stationarity, multiplier signs,
+    feasibility and the dynamics all still hold exactly; only complementarity
+    (a positive multiplier on a row with positive slack) is violated, by an
+    amount fixed by the planted multiplier and the row slacks."""
+    p = _prob("small_b64_n10", 2, offsets)
+    sol = qp.solve(p)
+    base = kkt.residuals(p, sol["u"], sol["x"], sol["lam"], sol["mu"])
+    assert base["kkt"] <= 1e-10
+    tm = p["tau_max"]
+    cand = [(k, i, a) for k in range(p["N"]) for i in range(2) for a in range(3)
+            if p["contact"][k][i] and abs(sol["u"][k, 6 * i + 3 + a]) < 0.5 * tm]
+    assert cand
+    k, i, a = cand[0]
+    mu = sol["mu"].copy()
+    delta = 2.0
+    mu[k, i, 5 + a] += delta          # tau_a <= tau_max
+    mu[k, i, 8 + a] += delta          # -tau_a <= tau_max
+    r = kkt.residuals(p, sol["u"], sol["x"], sol["lam"], mu)
+    for key in ("r_dyn", "r_ineq", "r_stat", "r_sign"):
+        assert r[key] <= 1e-10, (key, r)
+    tau = sol["u"][k, 6 * i + 3 + a]
+    slack = min(tm - tau, tm + tau)
+    mg = float(p["weight"])
+    # the violation is at least the planted product over the normalisation
+    assert r["r_comp"] >= 0.99 * delta * slack / (1.0 + np.max(mu) * mg)
+    assert r["r_comp"] > 1e-6 and r["kkt"] == r["r_comp"]
 
 
 def test_kkt_measure_rejects_wrong_face_with_negative_multiplier():
@@ -385,8 +434,9 @@ def _random_state(p, seed):
             for k in ("z", "v", "th", "be", "la")}
 
 
-def test_admm_block1_is_exact_minimiser():
-    p = _prob("small_b64_n10", 6)
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_admm_block1_is_exact_minimiser(offsets):
+    p = _prob("small_b64_n10", 6, offsets)
     p["N"] = 4
     for key in ("A", "B", "e", "x_ref", "u_ref", "contact"):
         p[key] = p[key][:4]
@@ -403,20 +453,22 @@ def test_admm_block1_is_exact_minimiser():
 
     du, xi = aux["du"], aux["xi"]
     base = L(du, xi)
+    # L is quadratic, so the central difference is its exact partial
+    # derivative up to the rounding of L itself (about 1e-16 |L| / h); every
+    # component of both blocks is checked
+    h = 1e-2
+    tol = 1e-12 * (1 + abs(base)) / h
     for arr, name in ((du, "du"), (xi, "xi")):
-        for idx in [(0, 0), (1, 5), (3, 11), (2, 3)] + ([(0, 20), (3, 24)] if name == "xi" else []):
-            h = 1e-2
+        for idx in np.ndindex(arr.shape):
             a1 = arr.copy()
             a1[idx] += h
             a2 = arr.copy()
             a2[idx] -= h
             if name == "du":
                 grad = (L(a1, xi) - L(a2, xi)) / (2 * h)
-                curv = (L(a1, xi) - 2 * base + L(a2, xi)) / h ** 2
             else:
                 grad = (L(du, a1) - L(du, a2)) / (2 * h)
-                curv = (L(du, a1) - 2 * base + L(du, a2)) / h ** 2
-            assert abs(grad) <= 1e-6 * (1 + abs(base)) ** 0.5 * max(curv, 1), (name, idx, grad)
+            assert abs(grad) <= tol, (name, idx, grad, tol)
 
 
 def _sample_feasible(rng, p, k):
@@ -433,8 +485,9 @@ def _sample_feasible(rng, p, k):
     return np.concatenate([w, u])
 
 
-def test_admm_block2_is_minimiser_over_set():
-    p = _prob("small_b64_n10", 7)
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_admm_block2_is_minimiser_over_set(offsets):
+    p = _prob("small_b64_n10", 7, offsets)
     rho = 1.3
     st = _random_state(p, 5)
     c = admm.setup(p, rho, scaling=False)
@@ -462,14 +515,15 @@ def test_admm_block2_is_minimiser_over_set():
             assert phi(zt, vt) >= best - 1e-9 * (1 + best)
 
 
-def test_admm_fixed_point_is_the_qp_optimum():
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_admm_fixed_point_is_the_qp_optimum(offsets):
     """At an ADMM fixed point the KKT conditions hold (Sec. III updates), so
     the iterates converge to the oracle optimum, whatever u_prev is."""
-    p = _prob("small_b64_n10", 8)
+    p = _prob("small_b64_n10", 8, offsets)
     p = _trim(p, 4, [[True, False], [True, False], [True, True], [False, True]],
               R=np.full(NU, 2e-3))
     ref = qp.solve(p)
-    for u_prev in (np.zeros(NU), np.linspace(-50, 50, NU)):
+    for u_prev in (np.zeros(NU), np.linspace(-50, 50, NU)) + ((p["u_prev"],) if offsets else ()):
         p["u_prev"] = u_prev
         out = admm.solve(p, iters=2500, rho=10.0, scaling=True, accel=True)
         eu, ex = kkt.rel_err(out["u"], ref["u"], out["x"], ref["x"], p["weight"])
