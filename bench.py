@@ -38,15 +38,24 @@ SWEEP_BYTES_PER_STAGE = 3070 + 2000
 # vector ops + projection 150), block 3 and the restart test 200
 SWEEP_FLOPS_PER_STAGE = 338 + 312 + 288 + 1250 + 100 + 650 + 312 + 150 + 200
 FP32_PEAK_TFLOPS = 157.3
-# Algorithmic FP64 flops of one refinement pass per stage (an active-set pass
-# or an interior-point iteration; dense 13-state / 12-input shapes, 2 flops per
-# multiply-add): Bp = B P 3744, d = B c + e 312, W A 4394, W d 338, W Bp 4056,
-# Bp^T W Bp 3744, Bp^T [W A | W d] 4368, P R P and P R c 3744, Gauss-Jordan on
-# [H | Hwx | hw] 5904, S and s 9100, forward rollout 1250, costates and gradient
-# 650, multipliers and residuals 500
-REFINE_FLOPS_PER_PASS_STAGE = (3744 + 312 + 4394 + 338 + 4056 + 3744 + 4368 + 3744 + 5904 +
-                               9100 + 1250 + 650 + 500)
-FP64_MFMA_PEAK_TFLOPS = 78.6
+# Algorithmic work of the FP64 refinement per pass-stage (one stage of one
+# equality-constrained pass or of one interior-point iteration): about 30 kflop
+# and 4.5 KB of stage data (the survey's per-unit figures for this step)
+REFINE_FLOPS_PER_PASS_STAGE = 30_000
+REFINE_BYTES_PER_PASS_STAGE = 4_500
+# the same pass-stage counted densely from the kernel's own products (13-state,
+# 12-input shapes, 2 flops per multiply-add): backward recursion Bp = B P 3744,
+# d = B c + e 312, W A 4394, W d 338, W Bp 4056, Bp^T W Bp 3744,
+# Bp^T [W A | W d] 4368, P R P and P R c 3744, Gauss-Jordan on [H | Hwx | hw]
+# 5904, S and s 9100 (39 704 per factored stage); forward rollout 1250,
+# costates and gradient 650, multipliers and residuals 500 (2 400 per stage of
+# every pass)
+REFINE_DENSE_BACKWARD = 3744 + 312 + 4394 + 338 + 4056 + 3744 + 4368 + 3744 + 5904 + 9100
+REFINE_DENSE_FORWARD = 1250 + 650 + 500
+# setup, once per stage: operators read, H, M, qbar and the scaled B written
+SETUP_BYTES_PER_STAGE = 3_200
+# FP64 peak of the chip: vector FMA units and matrix cores have the same rate
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -109,9 +118,36 @@ def _oracle_chunk(idx):
     return time.perf_counter() - t
 
 
-def cpu_baseline(sample, workers):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _admm_chunk(args):
+    idx, K, rho = args
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import mpcgen
+    from oracle import admm
+    batch = mpcgen.make_batch(WORKLOAD, indices=idx)
+    t = time.perf_counter()
+    for b in range(len(idx)):
+        admm.solve(mpcgen.problem_fp64(batch, b), iters=K, rho=rho, scaling=True, accel=True)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(sample, workers, admm_k=None, rho=10.0):
     """The FP64 oracle on the host cores: `sample` problems of the workload,
-    one process per worker, BLAS single-threaded per process."""
+    one process per worker, BLAS single-threaded per process.  The worker
+    count is capped at 16, the host-core share of one GPU on the GPU machine.
+    With admm_k, also the FP64 ADMM reference (the same algorithm as the GPU's
+    sweeps, no refinement, not certified) at the GPU's sweep count on the
+    same sample."""
     import multiprocessing as mp
     if workers <= 0:
         workers = min(16, os.cpu_count() or 1)
@@ -125,7 +161,16 @@ def cpu_baseline(sample, workers):
     t0 = time.perf_counter()
     with ctx.Pool(len(chunks)) as pool:
         busy = pool.map(_oracle_chunk, chunks)
-    wall = time.perf_counter() - t0
+        wall = time.perf_counter() - t0
+        admm_rec = None
+        if admm_k:
+            t1 = time.perf_counter()
+            busy2 = pool.map(_admm_chunk, [(c, admm_k, rho) for c in chunks])
+            wall2 = time.perf_counter() - t1
+            admm_rec = {"value": sample / wall2, "unit": "solves/s", "cores": len(chunks),
+                        "kind": "oracle ADMM reference (same algorithm, FP64, not certified)",
+                        "sweeps": admm_k,
+                        "sample": f"{sample} problems of {WORKLOAD}, {sum(busy2):.1f} core-s"}
     for k, v in saved.items():
         if v is None:
             os.environ.pop(k, None)
@@ -135,7 +180,11 @@ def cpu_baseline(sample, workers):
         "value": sample / wall,
         "unit": "solves/s",
         "cores": len(chunks),
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "worker_cap": "16 processes: the host-core share of one GPU on the GPU box",
         "kind": "oracle",
+        "same_algorithm_admm": admm_rec,
         "sample": f"{sample} problems of {WORKLOAD} (problem indices 0..{sample - 1}), "
                   f"dense-condensed FP64 interior point + certified active-set polish, "
                   f"{sum(busy):.1f} core-s",
@@ -469,14 +518,32 @@ def main():
     iters_out = out["iters"].cpu().numpy().astype(np.int64)
     passes = iters_out - K
     N_b = batch["N"].astype(np.int64)
+    det = out["detail"].cpu().numpy().astype(np.int64)
+    eq_p, ipm_p, stf = det[:, 0], det[:, 1], det[:, 2]
+    # pass-stages: one stage of one equality-constrained pass or interior-point
+    # iteration, the unit of the refinement's algorithmic work
+    pass_stages = int((N_b * (eq_p + ipm_p)).sum())
+    dense_flops = float(stf.sum() * REFINE_DENSE_BACKWARD +
+                        (N_b * eq_p).sum() * REFINE_DENSE_FORWARD +
+                        (N_b * ipm_p).sum() * (REFINE_DENSE_BACKWARD + 2 * REFINE_DENSE_FORWARD))
+    work = {"pass_stages": pass_stages,
+            "equality_passes_mean": float(eq_p.mean()),
+            "interior_point_iters_mean": float(ipm_p.mean()),
+            "frac_reaching_interior_point": float((ipm_p > 0).mean()),
+            "frac_finished_in_second_launch": float((det[:, 3] == 2).mean()),
+            "stages_factored_per_equality_pass": float(stf.sum() / max(1, eq_p.sum())),
+            "dense_flops_per_solve": dense_flops}
     kernels = {
         "setup_kernel": {"ms": setup_ms},
         "admm": {"ms": admm_ms, "form": {0: "plain", 1: "fused", -1: "packed"}[settings["form"]]},
         "refine_kernel": {"ms": refine_ms},
     }
     # algorithmic work of each phase per launch
-    refine_flops = float((N_b * passes).sum()) * REFINE_FLOPS_PER_PASS_STAGE
+    refine_flops = float(pass_stages) * REFINE_FLOPS_PER_PASS_STAGE
+    refine_bytes = float(pass_stages) * REFINE_BYTES_PER_PASS_STAGE
     kernels["refine_kernel"]["tflops"] = refine_flops / (refine_ms * 1e-3) / 1e12
+    kernels["refine_kernel"]["gbs"] = refine_bytes / (refine_ms * 1e-3) / 1e9
+    kernels["refine_kernel"]["dense_tflops"] = dense_flops / (refine_ms * 1e-3) / 1e12
     if settings["form"] == 0:
         sweep_bytes = stages * SWEEP_BYTES_PER_STAGE
         kernels["admm"]["gbs"] = sweep_bytes * K / (admm_ms * 1e-3) / 1e9
@@ -486,11 +553,17 @@ def main():
     if dominant == "refine_kernel":
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "refine.hip")
         achieved = kernels["refine_kernel"]["tflops"]
-        roof = {"kernel": "refine_kernel<1>+<2>", "bound": "mfma", "achieved": achieved,
-                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+        # FP64 arithmetic on the vector units and matrix cores (the same FP64
+        # peak on this chip); the HBM fraction of the same launch beside it
+        roof = {"kernel": "refine_kernel<1>+<2>", "bound": "alu", "achieved": achieved,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS,
                 "traffic": measured_traffic(src, "refine_kernel"),
-                "launch_ms": refine_ms, "flops_per_launch": refine_flops, "dtype": "f64"}
+                "launch_ms": refine_ms, "flops_per_launch": refine_flops,
+                "pass_stages": pass_stages, "flops_per_pass_stage": REFINE_FLOPS_PER_PASS_STAGE,
+                "hbm_gbs": kernels["refine_kernel"]["gbs"],
+                "hbm_frac": kernels["refine_kernel"]["gbs"] / HBM_PEAK_GBS,
+                "bytes_per_pass_stage": REFINE_BYTES_PER_PASS_STAGE, "dtype": "f64"}
     elif dominant == "admm" and settings["form"] == 0:
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_plain.hip")
         achieved = kernels["admm"]["gbs"]
@@ -507,9 +580,21 @@ def main():
                 "flops_per_launch": stages * SWEEP_FLOPS_PER_STAGE * K}
     else:
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "setup.hip")
-        roof = {"kernel": "setup_kernel", "bound": "mfma", "achieved": None,
-                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+        roof = {"kernel": "setup_kernel", "bound": "alu", "achieved": None,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": measured_traffic(src, "setup_kernel"), "launch_ms": setup_ms}
+    # the whole solve against HBM: setup once per stage, K sweeps of operators
+    # and iterates, the refinement's pass-stages, over the throughput interval
+    # (solves in flight) and over one uncontended solve
+    solve_bytes = float(stages * (SETUP_BYTES_PER_STAGE + K * SWEEP_BYTES_PER_STAGE) + refine_bytes)
+    whole = {"bytes_per_solve": solve_bytes,
+             "interval_ms": ms_per_step,
+             "gbs": solve_bytes / (ms_per_step * 1e-3) / 1e9,
+             "frac": solve_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if single is not None:
+        whole["one_in_flight_ms"] = single["ms_per_step"]
+        whole["one_in_flight_frac"] = (solve_bytes / (single["ms_per_step"] * 1e-3) / 1e9 /
+                                       HBM_PEAK_GBS)
     status = out["status"].cpu().numpy()
     line = {
         "metric": METRIC if args.workload == WORKLOAD else
@@ -538,6 +623,8 @@ def main():
         "status_counts": {str(k): int((status == k).sum()) for k in range(5)},
         "refine_passes": {"mean": float(passes.mean()), "p99": float(np.percentile(passes, 99)),
                           "max": int(passes.max())},
+        "refine_work": work,
+        "whole_solve_hbm": whole,
         "phase_ms": {"setup": setup_ms, "admm": admm_ms, "refine": refine_ms},
         "kernels": kernels,
         "timed_graph": bool(args.graph),
@@ -548,7 +635,8 @@ def main():
     for sv in solvers:
         sv.close()
     if args.cpu_sample > 0 and args.workload == WORKLOAD:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_workers)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_workers,
+                                            admm_k=K, rho=float(settings["rho"]))
     print(json.dumps(line), flush=True)
 
 

@@ -66,8 +66,11 @@ enum {
   PINMPC_ST_OK = 0,          /* certified: every KKT residual <= kkt_tol */
   PINMPC_ST_MAXITER = 1,     /* refinement disabled; ADMM iterate returned */
   PINMPC_ST_UNPOLISHED = 2,  /* refinement ran out of passes; best iterate */
-  PINMPC_ST_NONFINITE = 3,   /* NaN/Inf in this problem's data */
-  PINMPC_ST_BADINPUT = 4     /* malformed bounds (mu < 0, fz_max < 0, ...) */
+  PINMPC_ST_NONFINITE = 3,   /* NaN/Inf in this problem's data (stage arrays,
+                                x0, u_prev, u_ref, weights or bounds) */
+  PINMPC_ST_BADINPUT = 4     /* malformed bounds or horizon (mu <= 0,
+                                fz_max < 0, tau_max < 0, weight <= 0,
+                                Q or R not positive, N outside 1..n_max) */
 };
 
 /* Solver settings.  pinmpc_default_settings fills the defaults. */
@@ -80,7 +83,9 @@ typedef struct {
   int32_t refine;          /* 1: FP64 refinement and certificate; default 1 */
   int32_t refine_passes;   /* active-set passes from the ADMM faces; 8 */
   int32_t ipm_iters;       /* interior-point fallback iterations cap; 40 */
-  int32_t polish_passes;   /* active-set passes after the fallback; 6 */
+  int32_t polish_passes;   /* active-set passes after the fallback; 6
+                              (each of the three in 0..1000; with refine = 1,
+                              refine_passes and ipm_iters not both 0) */
   double kkt_tol;          /* certification threshold; default 1e-9 */
   int32_t precision;       /* 0: FP32 operators; 1: BF16 operators */
   int32_t form;            /* 0: plain (one launch per sweep);
@@ -130,6 +135,14 @@ typedef struct {
                               normalised as documented in DESIGN; may be NULL */
   int32_t* iters;          /* [B] ADMM sweeps + refinement passes; may be NULL */
   int32_t* status;         /* [B] PINMPC_ST_*; may be NULL */
+  int32_t* detail;         /* [B][4] work of the FP64 refinement, may be NULL:
+                              equality-constrained passes (active-set,
+                              crossover and polish), interior-point
+                              iterations, stages whose backward recursion the
+                              equality passes factored (a pass restarted at
+                              stage k factors k stages), and the refinement
+                              launch (1 or 2) that finished the problem;
+                              0 0 0 0 for a problem with bad input */
 } pinmpc_out;
 
 /* Fill *s with the defaults listed above. */
@@ -198,7 +211,10 @@ int pinmpc_server_create(pinmpc_server* out, int device, const pinmpc_settings* 
                          int n_lanes, int32_t lane_capacity, int32_t warm_slots,
                          size_t hbm_budget_bytes);
 
-/* Queue one request; *ticket identifies it.  Thread-safe. */
+/* Queue one request; *ticket identifies it.  Thread-safe.  PINMPC_EBUSY if
+ * the request's warm-slot range [warm_base, warm_base + batch) overlaps the
+ * range of a request that is not done yet (a slot is read and rewritten by
+ * its solve, so it serves one request at a time). */
 int pinmpc_submit(pinmpc_server s, const pinmpc_batch* req, const pinmpc_out* out,
                   int32_t warm_base, int64_t* ticket);
 

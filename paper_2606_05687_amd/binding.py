@@ -67,6 +67,7 @@ class Out(ctypes.Structure):
         ("res", ctypes.c_void_p),
         ("iters", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
+        ("detail", ctypes.c_void_p),
     ]
 
 
@@ -213,6 +214,7 @@ class Solver:
             "res": torch.empty((Bn, NRES), dtype=torch.float32, device=d),
             "iters": torch.empty((Bn,), dtype=torch.int32, device=d),
             "status": torch.empty((Bn,), dtype=torch.int32, device=d),
+            "detail": torch.empty((Bn, 4), dtype=torch.int32, device=d),
         }
 
     def solve(self, dev: dict, out: dict | None = None, stream=None, batch_struct=None):
@@ -221,10 +223,7 @@ class Solver:
         if out is None:
             out = self.alloc_out(dev)
         b = batch_struct if batch_struct is not None else make_batch_struct(dev)
-        o = Out(out["u"].data_ptr(), out["x"].data_ptr(),
-                None if out.get("res") is None else out["res"].data_ptr(),
-                None if out.get("iters") is None else out["iters"].data_ptr(),
-                None if out.get("status") is None else out["status"].data_ptr())
+        o = _out_struct(out)
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(load().pinmpc_solve(self._h, ctypes.byref(b), ctypes.byref(o),
                                    ctypes.c_void_p(st.cuda_stream)))
@@ -250,10 +249,10 @@ class Solver:
 
 
 def _out_struct(out):
-    return Out(out["u"].data_ptr(), out["x"].data_ptr(),
-               None if out.get("res") is None else out["res"].data_ptr(),
-               None if out.get("iters") is None else out["iters"].data_ptr(),
-               None if out.get("status") is None else out["status"].data_ptr())
+    def opt(k):
+        return None if out.get(k) is None else out[k].data_ptr()
+    return Out(out["u"].data_ptr(), out["x"].data_ptr(), opt("res"), opt("iters"),
+               opt("status"), opt("detail"))
 
 
 class Server:

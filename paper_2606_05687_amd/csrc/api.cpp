@@ -57,8 +57,12 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+}  // namespace
+
+namespace pinmpc {
+
 // Carve (or size, when base == nullptr) the workspace for batch x n.
-size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
+size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w) {
   const size_t S = (size_t)batch * n;        // stages
   const size_t Bn = (size_t)batch;
   const size_t X = (size_t)batch * (n + 1);  // state slots
@@ -93,6 +97,8 @@ size_t carve(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.rcount = (int32_t*)take(4);
   t.rpass = (int32_t*)take(Bn * 4);
   t.bytes = off;
+  t.warm_idx = nullptr;
+  t.warm_store = nullptr;
   if (w) *w = t;
   return off;
 }
@@ -103,11 +109,16 @@ int check_settings(const pinmpc_settings* s) {
   if (s->iters < 0 || s->iters > 1000000) return PINMPC_EINVAL;
   if (!(s->restart_eta > 0.f && s->restart_eta <= 1.f)) return PINMPC_EINVAL;
   if (s->refine_passes < 0 || s->ipm_iters < 0 || s->polish_passes < 0) return PINMPC_EINVAL;
+  if (s->refine_passes > 1000 || s->ipm_iters > 1000 || s->polish_passes > 1000)
+    return PINMPC_EINVAL;
   if (!(s->kkt_tol > 0.0)) return PINMPC_EINVAL;
   if (s->precision < 0 || s->precision > 1) return PINMPC_EINVAL;
   if (s->form < -1 || s->form > 1) return PINMPC_EINVAL;
   if (s->graph < 0 || s->graph > 1) return PINMPC_EINVAL;
   if (s->first_passes < 0) return PINMPC_EINVAL;
+  // a refinement needs at least one pass or interior-point iteration: the
+  // outputs are the last pass's solution
+  if (s->refine && s->refine_passes == 0 && s->ipm_iters == 0) return PINMPC_EINVAL;
   return PINMPC_OK;
 }
 
@@ -143,8 +154,42 @@ Problem to_problem(const pinmpc_batch* in) {
   return p;
 }
 
+// The fused kernel holds one problem per workgroup with one thread per
+// (stage, lifted row): horizons up to 1024 / 25 = 40 stages.
+static bool use_fused(const pinmpc_settings& s, int n_max) {
+  const bool fits = NL * n_max <= 1024;
+  if (s.form == 1) return fits;
+  if (s.form == -1) return fits;
+  return false;
+}
+
+// The ADMM sweeps in the form the settings ask for.
+int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
+                      hipStream_t st) {
+  if (s.form == -1 && p.n_max > CLASS_N[0] && iters > 0) {
+    // pack problems by horizon class: fused kernels sized for each class,
+    // one-launch-per-sweep for the longest horizons
+    if (launch_classify(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
+    for (int cls = 0; cls < 2; ++cls)
+      if (launch_admm_fused_class(p, w, s, iters, cls, st) != hipSuccess) return PINMPC_EDEVICE;
+    if (p.n_max > CLASS_N[1])
+      for (int it = 0; it < iters; ++it)
+        if (launch_admm_sweep_class(p, w, s, 2, st) != hipSuccess) return PINMPC_EDEVICE;
+  } else if (use_fused(s, p.n_max)) {
+    if (launch_admm_fused(p, w, s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
+  } else {
+    for (int it = 0; it < iters; ++it)
+      if (launch_admm_sweep(p, w, s, st) != hipSuccess) return PINMPC_EDEVICE;
+  }
+  return PINMPC_OK;
+}
+
+}  // namespace pinmpc
+
+namespace {
+
 int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Workspace* w) {
-  const size_t need = carve(nullptr, batch, n, nullptr);
+  const size_t need = carve_workspace(nullptr, batch, n, nullptr);
   if (need > c->budget) return PINMPC_EBUDGET;
   if (need > c->mem_bytes) {
     if (c->mem) {
@@ -163,42 +208,15 @@ int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Wor
     }
     c->mem_bytes = need;
   }
-  carve((char*)c->mem, batch, n, w);
-  w->warm_idx = nullptr;
-  w->warm_store = nullptr;
+  carve_workspace((char*)c->mem, batch, n, w);
   return PINMPC_OK;
-}
-
-// The fused kernel holds one problem per workgroup with one thread per
-// (stage, lifted row): horizons up to 1024 / 25 = 40 stages.
-bool use_fused(const pinmpc_settings& s, int n_max) {
-  const bool fits = NL * n_max <= 1024;
-  if (s.form == 1) return fits;
-  if (s.form == -1) return fits;
-  return false;
 }
 
 int run_admm(pinmpc_ctx c, const Problem& p, const Workspace& w, int iters, hipStream_t st) {
   if (launch_setup(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
   if (launch_admm_init(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[1], st);
-  if (c->s.form == -1 && p.n_max > CLASS_N[0] && iters > 0) {
-    // pack problems by horizon class: fused kernels sized for each class,
-    // one-launch-per-sweep for the longest horizons
-    if (launch_classify(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
-    for (int cls = 0; cls < 2; ++cls)
-      if (launch_admm_fused_class(p, w, c->s, iters, cls, st) != hipSuccess)
-        return PINMPC_EDEVICE;
-    if (p.n_max > CLASS_N[1])
-      for (int it = 0; it < iters; ++it)
-        if (launch_admm_sweep_class(p, w, c->s, 2, st) != hipSuccess) return PINMPC_EDEVICE;
-  } else if (use_fused(c->s, p.n_max)) {
-    if (launch_admm_fused(p, w, c->s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
-  } else {
-    for (int it = 0; it < iters; ++it)
-      if (launch_admm_sweep(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
-  }
-  return PINMPC_OK;
+  return launch_admm_phase(c->s, p, w, iters, st);
 }
 
 }  // namespace
@@ -262,7 +280,7 @@ int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_ma
                            size_t* bytes) {
   if (!bytes || batch < 0 || n_max < 1 || n_max > PINMPC_NMAX) return PINMPC_EINVAL;
   (void)s;
-  *bytes = carve(nullptr, batch, n_max, nullptr);
+  *bytes = carve_workspace(nullptr, batch, n_max, nullptr);
   return PINMPC_OK;
 }
 

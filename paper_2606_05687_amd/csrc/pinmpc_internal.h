@@ -320,6 +320,18 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out,
 // Allocate the context's workspace for batch x n ahead of the first solve.
 int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n);
 
+// Host-side pieces of a solve shared by the entry points (api.cpp): carve the
+// workspace for batch x n out of `base` (or only size it when base is null;
+// returns the bytes), validate settings and a batch, view a batch as the
+// kernels' Problem, and enqueue the ADMM sweeps in the form the settings ask
+// for.
+size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w);
+int check_settings(const pinmpc_settings* s);
+int check_batch(const pinmpc_batch* in);
+Problem to_problem(const pinmpc_batch* in);
+int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
+                      hipStream_t st);
+
 // Kernel launchers (defined in the .hip units).
 hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                         hipStream_t st);

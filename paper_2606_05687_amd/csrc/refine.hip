@@ -1182,6 +1182,14 @@ __device__ __attribute__((noinline)) uint64_t faces_from_zs(const Ctx& C) {
   return wave_xor(hsh);
 }
 
+// Work done by the refinement of one problem: equality-constrained passes
+// (active-set, crossover and polish passes), interior-point iterations, and
+// the stages whose backward recursion an equality pass factored (a pass that
+// restarts at stage ktop factors ktop stages).
+struct Counts {
+  int eq, ipm, stf;
+};
+
 // Interior-point fallback.  Rows scaled by mg (force rows) and tau_max
 // (moment rows).  Crossover: once the face guess z > s is the same after two
 // consecutive iterations, one equality-constrained pass on those faces is
@@ -1189,7 +1197,7 @@ __device__ __attribute__((noinline)) uint64_t faces_from_zs(const Ctx& C) {
 // Returns the number of iterations; *certified tells whether a crossover pass
 // certified (then ru, rx, res and *kkt are that pass's), else the faces from
 // z > s are left for the polish passes.
-__device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, double tol, int* passes,
+__device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, double tol, Counts* cnt,
                    double res[PINMPC_NRES], double* kkt_out, bool* certified) {
   *certified = false;
   gsync();
@@ -1375,7 +1383,8 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
       for (int e = lane; e < N * NU; e += W64) C.rdu[e] = C.ru[e];
       for (int e = lane; e < (N + 1) * NX; e += W64) C.rdx[e] = C.rx[e];
       const double kkt = eq_pass(C, sh, res, N);
-      ++*passes;
+      ++cnt->eq;
+      cnt->stf += N;
       if (kkt <= tol) {
         *kkt_out = kkt;
         *certified = true;
@@ -1392,8 +1401,8 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
   return it;
 }
 
-// Active-set loop; returns true if certified.  passes accumulates.
-__device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int* passes,
+// Active-set loop; returns true if certified.  cnt accumulates.
+__device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, Counts* cnt,
                                 double res[PINMPC_NRES], double* kkt_out,
                                 bool* cycled = nullptr) {
   if (cycled) *cycled = false;
@@ -1403,7 +1412,8 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, int*
   int ktop = C.N;   // the first pass solves the whole horizon
   for (int it = 0; it < maxp; ++it) {
     const double kkt = eq_pass(C, sh, res, ktop);
-    ++*passes;
+    ++cnt->eq;
+    cnt->stf += ktop < C.N ? ktop : C.N;
     *kkt_out = kkt;
     if (kkt <= tol) return true;
     const uint64_t h = pdas_update(C, &ktop);
@@ -1465,6 +1475,7 @@ template <int PHASE>
 __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, float* out_u,
                                                     float* out_x, float* out_res,
                                                     int32_t* out_iters, int32_t* out_status,
+                                                    int32_t* out_detail,
                                                     int admm_iters, int accel, int refine,
                                                     int pass_a, int ipm_max, int pass_c,
                                                     double tol, int pass_1) {
@@ -1525,23 +1536,35 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
   const size_t s0 = (size_t)pb * p.n_max;
   const int N = C.N;
 
-  // input checks: bounds, then finiteness of this problem's data
+  // input checks: finiteness of the scalars and weights, then the bounds
+  // (a friction coefficient must be positive: mu = 0 leaves the pyramid
+  // without f_z >= 0 and its apex multipliers undefined), then finiteness of
+  // this problem's stage data
   const int Nraw = horizon_raw(p, C.b);
-  int bad = !(C.mu >= 0.0) || !(C.fz >= 0.0) || !(C.tm >= 0.0) || !(C.mg > 0.0) ||
-            Nraw < 1 || Nraw > C.n;
-  for (int j = 0; j < NX; ++j) bad |= !(C.Q[j] > 0.0);
-  for (int j = 0; j < NU; ++j) bad |= !(C.R[j] > 0.0);
-  int nonfinite = 0;
-  if (!bad) {
-    for (int e = lane; e < N * NX * NX; e += W64) nonfinite |= !isfinite(C.A[e]);
-    for (int e = lane; e < N * NX * NU; e += W64) nonfinite |= !isfinite(C.B[e]);
-    for (int e = lane; e < N * NX; e += W64) {
-      nonfinite |= !isfinite(C.x_ref[e]);
-      if (C.e) nonfinite |= !isfinite(C.e[e]);
-    }
-    if (lane < NX) nonfinite |= !isfinite(C.x0[lane]);
+  int nonfinite = !isfinite(C.mu) || !isfinite(C.fz) || !isfinite(C.tm) || !isfinite(C.mg);
+  for (int j = 0; j < NX; ++j) nonfinite |= !isfinite(C.Q[j]);
+  for (int j = 0; j < NU; ++j) nonfinite |= !isfinite(C.R[j]);
+  int bad = 0;
+  if (!nonfinite) {
+    bad = !(C.mu > 0.0) || !(C.fz >= 0.0) || !(C.tm >= 0.0) || !(C.mg > 0.0) || Nraw < 1 ||
+          Nraw > C.n;
+    for (int j = 0; j < NX; ++j) bad |= !(C.Q[j] > 0.0);
+    for (int j = 0; j < NU; ++j) bad |= !(C.R[j] > 0.0);
   }
-  nonfinite = wave_max((double)nonfinite) > 0.0;
+  if (!bad && !nonfinite) {
+    int nf = 0;
+    for (int e = lane; e < N * NX * NX; e += W64) nf |= !isfinite(C.A[e]);
+    for (int e = lane; e < N * NX * NU; e += W64) nf |= !isfinite(C.B[e]);
+    for (int e = lane; e < N * NX; e += W64) {
+      nf |= !isfinite(C.x_ref[e]);
+      if (C.e) nf |= !isfinite(C.e[e]);
+    }
+    if (C.u_ref)
+      for (int e = lane; e < N * NU; e += W64) nf |= !isfinite(C.u_ref[e]);
+    if (lane < NX) nf |= !isfinite(C.x0[lane]);
+    if (p.u_prev && lane < NU) nf |= !isfinite(p.u_prev[(size_t)C.b * NU + lane]);
+    nonfinite = wave_max((double)nf) > 0.0;
+  }
   const size_t ux = (size_t)C.b * C.n * NU, xx = (size_t)C.b * (C.n + 1) * NX;
   if (bad || nonfinite) {
     for (int e = lane; e < C.n * NU; e += W64) out_u[ux + e] = 0.f;
@@ -1550,6 +1573,7 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
       if (out_status) out_status[C.b] = bad ? PINMPC_ST_BADINPUT : PINMPC_ST_NONFINITE;
       if (out_iters) out_iters[C.b] = 0;
     }
+    if (out_detail && lane < 4) out_detail[(size_t)C.b * 4 + lane] = 0;
     if (out_res && lane < PINMPC_NRES) out_res[(size_t)C.b * PINMPC_NRES + lane] = __builtin_nanf("");
     return;
   }
@@ -1564,7 +1588,7 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
 
   double res[PINMPC_NRES] = {0, 0, 0, 0, 0};
   double kkt = 1e300;
-  int passes = 0;
+  Counts cnt = {0, 0, 0};
   bool ok = false;
   if (refine) {
     // first launch: pass_1 passes (all pass_a when pass_1 is 0); the rest of
@@ -1573,30 +1597,32 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     if (PHASE == 1) {
       faces_from_u(C, C.ru, 1e-5);
       bool cycled = false;
-      ok = active_set_loop(C, sh, p1, tol, &passes, res, &kkt, &cycled);
+      ok = active_set_loop(C, sh, p1, tol, &cnt, res, &kkt, &cycled);
       const bool more = !cycled && p1 < pass_a;
       if (!ok && (more || ipm_max > 0)) {
         if (lane == 0) {
           const int slot = atomicAdd(ws.rcount, 1);
           ws.rlist[slot] = C.b;
-          ws.rpass[C.b] = passes | (more ? (1 << 20) : 0);
+          // passes (< 2^10, settings are capped at 1000) and stages factored
+          // (< 2^20) so far, and whether active-set passes remain
+          ws.rpass[C.b] = cnt.eq | (cnt.stf << 10) | (more ? (1 << 30) : 0);
         }
         return;
       }
     } else {
       const int rp = ws.rpass[C.b];
-      passes = rp & ((1 << 20) - 1);
-      if (rp >> 20) {
+      cnt.eq = rp & 1023;
+      cnt.stf = (rp >> 10) & ((1 << 20) - 1);
+      if ((rp >> 30) & 1) {
         // resume the active-set passes from the faces the first launch left
-        ok = active_set_loop(C, sh, pass_a - passes, tol, &passes, res, &kkt);
+        ok = active_set_loop(C, sh, pass_a - cnt.eq, tol, &cnt, res, &kkt);
       }
       if (!ok && ipm_max > 0) {
         // interior point from the ADMM point
         admm_point(C, zsrc, sf, tsc);
         rollout_ru(C, sh);
-        const int its = ipm(C, sh, ipm_max, tol, &passes, res, &kkt, &ok);
-        passes += its;
-        if (!ok) ok = active_set_loop(C, sh, pass_c, tol, &passes, res, &kkt);
+        cnt.ipm = ipm(C, sh, ipm_max, tol, &cnt, res, &kkt, &ok);
+        if (!ok) ok = active_set_loop(C, sh, pass_c, tol, &cnt, res, &kkt);
       }
     }
     // the dynamics residual of the returned trajectory, checked independently
@@ -1621,7 +1647,11 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
   if (lane == 0) {
     if (out_status)
       out_status[C.b] = refine ? (ok ? PINMPC_ST_OK : PINMPC_ST_UNPOLISHED) : PINMPC_ST_MAXITER;
-    if (out_iters) out_iters[C.b] = admm_iters + passes;
+    if (out_iters) out_iters[C.b] = admm_iters + cnt.eq + cnt.ipm;
+  }
+  if (out_detail && lane < 4) {
+    const int v = lane == 0 ? cnt.eq : lane == 1 ? cnt.ipm : lane == 2 ? cnt.stf : PHASE;
+    out_detail[(size_t)C.b * 4 + lane] = v;
   }
   if (out_res) {
     for (int i = 0; i < PINMPC_NRES; ++i)
@@ -1642,11 +1672,11 @@ hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_sett
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(refine_kernel<1>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
-                     out.res, out.iters, out.status, s.iters, s.accel, s.refine,
+                     out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
                      s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes);
   if (second)
     hipLaunchKernelGGL(refine_kernel<2>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
-                       out.res, out.iters, out.status, s.iters, s.accel, s.refine,
+                       out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
                        s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes);
   return hipGetLastError();
 }

@@ -60,7 +60,7 @@ struct Lane {
   uint8_t* contact;
   int32_t *N, *warm_idx;
   float *u, *x, *res;
-  int32_t *iters, *status;
+  int32_t *iters, *status, *detail;
   std::vector<Request*> inflight;
   bool busy = false;      // owns requests (set by the scheduler before enqueueing)
   bool launched = false;  // its event was recorded after the last enqueued work
@@ -77,7 +77,7 @@ size_t staging_bytes(int cap) {
   add((size_t)cap * NU * 4); add((size_t)cap * 4); add((size_t)cap * 4); add((size_t)cap * 4);
   add((size_t)cap * 4); add(S * 2); add((size_t)cap * 4); add((size_t)cap * 4);
   add(S * NU * 4); add((size_t)cap * (PINMPC_NMAX + 1) * NX * 4); add((size_t)cap * PINMPC_NRES * 4);
-  add((size_t)cap * 4); add((size_t)cap * 4);
+  add((size_t)cap * 4); add((size_t)cap * 4); add((size_t)cap * 4 * 4);
   return b;
 }
 
@@ -106,6 +106,7 @@ void carve_lane(Lane& L, int cap) {
   L.res = (float*)take((size_t)cap * PINMPC_NRES * 4);
   L.iters = (int32_t*)take((size_t)cap * 4);
   L.status = (int32_t*)take((size_t)cap * 4);
+  L.detail = (int32_t*)take((size_t)cap * 4 * 4);
 }
 
 // Pitched device-to-device copy of [rows][spitch] -> [rows][dpitch] (bytes).
@@ -208,7 +209,7 @@ int pinmpc_server_s::launch(Lane& L, std::vector<Request*>& rq) {
   sb.fz_max = L.fz;
   sb.tau_max = L.tau;
   sb.weight = has_w ? L.weight : nullptr;
-  pinmpc_out so{L.u, L.x, L.res, L.iters, L.status};
+  pinmpc_out so{L.u, L.x, L.res, L.iters, L.status, L.detail};
   int rc = solve_internal(L.ctx, &sb, &so, st, warm ? L.warm_idx : nullptr, warm_store);
   if (rc) return rc;
   off = 0;
@@ -226,6 +227,8 @@ int pinmpc_server_s::launch(Lane& L, std::vector<Request*>& rq) {
       e = e ? e : hipMemcpyAsync(d.iters, L.iters + o, nb * 4, hipMemcpyDeviceToDevice, st);
     if (d.status)
       e = e ? e : hipMemcpyAsync(d.status, L.status + o, nb * 4, hipMemcpyDeviceToDevice, st);
+    if (d.detail)
+      e = e ? e : hipMemcpyAsync(d.detail, L.detail + o * 4, nb * 16, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return PINMPC_EDEVICE;
     off += r->in.batch;
   }
@@ -391,6 +394,17 @@ int pinmpc_submit(pinmpc_server s, const pinmpc_batch* req, const pinmpc_out* ou
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(s->m);
   if (s->stop) return PINMPC_EBUSY;
+  if (warm_base >= 0) {
+    // a warm slot belongs to one request at a time: the solve reads the slot
+    // and writes it back, so two requests in flight on one slot would race
+    const int64_t lo = warm_base, hi = (int64_t)warm_base + req->batch;
+    for (const auto& kv : s->reqs) {
+      const Request& o = *kv.second;
+      if (o.done || o.warm_base < 0) continue;
+      if (lo < (int64_t)o.warm_base + o.in.batch && (int64_t)o.warm_base < hi)
+        return PINMPC_EBUSY;
+    }
+  }
   r->ticket = s->next_ticket++;
   *ticket = r->ticket;
   s->queue.push_back(r.get());

@@ -15,3 +15,13 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def repo_root():
     return ROOT
+
+
+@pytest.fixture(scope="module")
+def solver():
+    """One library context on cuda:0 for a test module (GPU tests only)."""
+    import torch  # noqa: F401
+    from paper_2606_05687_amd import binding
+    s = binding.Solver(0)
+    yield s
+    s.close()

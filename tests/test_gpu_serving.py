@@ -87,3 +87,39 @@ def test_warm_start_round_trip():
         a = outs[0][i]["u"].cpu().numpy()
         c = outs[2][i]["u"].cpu().numpy()
         assert np.max(np.abs(a - c)) <= 1e-4 * np.max(np.abs(a))
+
+
+def test_overlapping_warm_slots_rejected_while_in_flight():
+    """A warm slot serves one request at a time: a second request whose slot
+    range overlaps a request still in flight is refused with PINMPC_EBUSY,
+    a disjoint range is accepted, and the overlapping range is accepted again
+    once the first request is done."""
+    import ctypes
+    from paper_2606_05687_amd import binding
+    big = mpcgen.make_batch("uneven_b16384", indices=range(2048), n_max=60)
+    small = mpcgen.make_batch("uneven_b16384", indices=range(64), n_max=60)
+    dbig, dsmall = binding.to_device(big), binding.to_device(small)
+    srv = binding.Server(0, lanes=2, capacity=2048, warm_slots=4096)
+    lib = binding.load()
+    obig = binding.Solver.alloc_out(None, dbig)
+    osm = [binding.Solver.alloc_out(None, dsmall) for _ in range(2)]
+    t = ctypes.c_int64()
+    bbig, bsm = binding.make_batch_struct(dbig), binding.make_batch_struct(dsmall)
+    assert lib.pinmpc_submit(srv._h, ctypes.byref(bbig), ctypes.byref(binding._out_struct(obig)),
+                             0, ctypes.byref(t)) == 0
+    first = t.value
+    rc = lib.pinmpc_submit(srv._h, ctypes.byref(bsm), ctypes.byref(binding._out_struct(osm[0])),
+                           2000, ctypes.byref(t))
+    assert rc == -5, rc                              # overlaps slots 2000..2047
+    assert lib.pinmpc_submit(srv._h, ctypes.byref(bsm), ctypes.byref(binding._out_struct(osm[0])),
+                             2048, ctypes.byref(t)) == 0   # disjoint
+    second = t.value
+    srv.wait(first)
+    assert lib.pinmpc_submit(srv._h, ctypes.byref(bsm), ctypes.byref(binding._out_struct(osm[1])),
+                             2000, ctypes.byref(t)) == 0
+    srv.wait(second)
+    srv.wait(t.value)
+    srv.close()
+    assert (obig["status"].cpu().numpy() == 0).all()
+    for o in osm:
+        assert (o["status"].cpu().numpy() == 0).all()

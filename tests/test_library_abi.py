@@ -29,7 +29,7 @@ def test_struct_layouts_match_header():
     # field order and C types as declared in include/pinmpc.h
     assert ctypes.sizeof(binding.Settings) == 64
     assert ctypes.sizeof(binding.Batch) == 8 + 15 * 8
-    assert ctypes.sizeof(binding.Out) == 5 * 8
+    assert ctypes.sizeof(binding.Out) == 6 * 8
 
 
 def test_default_settings_and_errors():
@@ -48,6 +48,12 @@ def test_default_settings_and_errors():
     h = ctypes.c_void_p()
     bad = binding.default_settings(rho=-1.0)
     assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1
+    # settings are validated before any device call
+    for over in (dict(refine_passes=0, ipm_iters=0), dict(refine_passes=1001),
+                 dict(ipm_iters=-1), dict(form=2), dict(precision=3), dict(kkt_tol=0.0)):
+        bad = binding.default_settings(**over)
+        assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1, over
+        assert lib.pinmpc_workspace_bytes(ctypes.byref(bad), 16, 10, ctypes.byref(nb)) in (0, -1)
 
 
 def test_stats_ring_matches_header_and_rejects_bad_calls():
