@@ -58,7 +58,9 @@ enum {
   PINMPC_ENOMEM = -2,   /* device allocation failed */
   PINMPC_EBUDGET = -3,  /* workspace would exceed hbm_budget_bytes */
   PINMPC_EDEVICE = -4,  /* HIP runtime or launch error */
-  PINMPC_EBUSY = -5     /* server: no free slot / request still running */
+  PINMPC_EBUSY = -5,   /* server: no free slot / request still running */
+  PINMPC_ETOOBIG = -6   /* batch needs more workspace than the static scratch
+                           of pinmpc_solve_noalloc holds */
 };
 
 /* Per-problem status written to pinmpc_out.status. */
@@ -163,6 +165,26 @@ int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_ma
 /* Solve every problem of `in`; results into `out`.  Stream-ordered. */
 int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out,
                  void* hip_stream);
+
+/* pinmpc_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results as pinmpc_solve with the context's
+ * settings, launched eagerly on `hip_stream` (never captured or replayed as a
+ * graph by the library), with the workspace taken from a file-scope device
+ * array of PINMPC_NOALLOC_SCRATCH_BYTES per GPU instead of the context's
+ * allocation.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); its first call on a device resolves that
+ * device's copy of the array once.  Each GPU that runs it holds the array
+ * until the process ends.  A batch whose workspace (pinmpc_workspace_bytes)
+ * exceeds the array returns PINMPC_ETOOBIG before any GPU work: at 16.6 KB
+ * per stage that is about 16 000 stages, e.g. 800 problems at N = 20 or 268
+ * at N = 60.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind (the kernels initialise everything they read): calls that
+ * overlap on one GPU (two streams, two host threads, two contexts) race and
+ * must be serialised by the caller. */
+#define PINMPC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int pinmpc_solve_noalloc(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out,
+                         void* hip_stream);
 
 /* ADMM only, no refinement, into caller buffers: for iterate-level checks.
  * z_out: [B][n_max][25] final z iterates (lifted (x_{k+1}, u_k), unscaled u). */

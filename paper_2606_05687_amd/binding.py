@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libpinmpc.so")
 
 NX, NU, NRES = 13, 12, 5
 ST_OK, ST_MAXITER, ST_UNPOLISHED, ST_NONFINITE, ST_BADINPUT = range(5)
+E_TOOBIG = -6                  # PINMPC_ETOOBIG
+NOALLOC_SCRATCH_BYTES = 256 << 20   # PINMPC_NOALLOC_SCRATCH_BYTES
 
 
 class Settings(ctypes.Structure):
@@ -80,6 +82,8 @@ EXPORTS = {
                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "pinmpc_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Out),
                                     ctypes.c_void_p]),
+    "pinmpc_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch),
+                                            ctypes.POINTER(Out), ctypes.c_void_p]),
     "pinmpc_admm": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "pinmpc_stats": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 4),
@@ -126,12 +130,14 @@ def load(path: str = LIB_PATH):
 
 
 class PinmpcError(RuntimeError):
-    pass
+    def __init__(self, code: int, msg: str):
+        super().__init__(msg)
+        self.code = code
 
 
 def _check(rc):
     if rc != 0:
-        raise PinmpcError(f"pinmpc error {rc}: {load().pinmpc_strerror(rc).decode()}")
+        raise PinmpcError(rc, f"pinmpc error {rc}: {load().pinmpc_strerror(rc).decode()}")
 
 
 def default_settings(**over) -> Settings:
@@ -227,6 +233,18 @@ class Solver:
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(load().pinmpc_solve(self._h, ctypes.byref(b), ctypes.byref(o),
                                    ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def solve_noalloc(self, dev: dict, out: dict, stream=None):
+        """pinmpc_solve_noalloc: the same solve with the library's static
+        device scratch as workspace (no device allocation by the library);
+        `out` must be preallocated."""
+        import torch
+        b = make_batch_struct(dev)
+        o = _out_struct(out)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().pinmpc_solve_noalloc(self._h, ctypes.byref(b), ctypes.byref(o),
+                                           ctypes.c_void_p(st.cuda_stream)))
         return out
 
     def admm(self, dev: dict, iters: int, stream=None):

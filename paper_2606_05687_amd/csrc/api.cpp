@@ -366,6 +366,35 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_i
   return PINMPC_OK;
 }
 
+int solve_in_buffer(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_in,
+                    hipStream_t st, void* base, size_t capacity) {
+  if (!c || !out_in) return PINMPC_EINVAL;
+  const pinmpc_out& out = *out_in;
+  int rc = check_batch(in);
+  if (rc) return rc;
+  if (in->batch > 0 && (!out.u || !out.x)) return PINMPC_EINVAL;
+  if (carve_workspace(nullptr, in->batch, in->n_max, nullptr) > capacity) return PINMPC_ETOOBIG;
+  if (in->batch == 0) return PINMPC_OK;
+  if (!base) return PINMPC_EINVAL;
+  Workspace w;
+  carve_workspace((char*)base, in->batch, in->n_max, &w);
+  const Problem p = to_problem(in);
+  // eager launches only: instantiating a graph would allocate
+  const int slot = (int)(c->nsolves % PINMPC_STATS_RING);
+  c->ev = c->ring[slot];
+  c->ring_graph[slot] = false;
+  if (c->have_timing) (void)hipEventRecord(c->ev[0], st);
+  rc = run_admm(c, p, w, c->s.iters, st);
+  if (rc) return rc;
+  if (c->have_timing) (void)hipEventRecord(c->ev[2], st);
+  if (launch_refine(p, w, c->s, out, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
+  ++c->nsolves;
+  return PINMPC_OK;
+}
+
+int context_device(pinmpc_ctx c) { return c ? c->device : -1; }
+
 int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n) {
   if (!c) return PINMPC_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
@@ -455,6 +484,7 @@ const char* pinmpc_strerror(int code) {
     case PINMPC_EBUDGET: return "workspace exceeds the HBM budget";
     case PINMPC_EDEVICE: return "HIP runtime or launch error";
     case PINMPC_EBUSY: return "busy";
+    case PINMPC_ETOOBIG: return "batch needs more workspace than the static scratch holds";
     default: return "unknown error";
   }
 }

@@ -317,6 +317,15 @@ __device__ inline float stage_ordered_sum(const float* cp, float* ss, int N) {
 int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out,
                    hipStream_t st, const int32_t* warm_idx, float* warm_store);
 
+// Eager solve (no graph) whose workspace is carved from caller-provided device
+// memory `base` of `capacity` bytes; PINMPC_ETOOBIG when the batch needs more.
+// Allocates nothing.  Defined in api.cpp.
+int solve_in_buffer(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out,
+                    hipStream_t st, void* base, size_t capacity);
+
+// The HIP device a context solves on (-1 for a null context).
+int context_device(pinmpc_ctx c);
+
 // Allocate the context's workspace for batch x n ahead of the first solve.
 int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n);
 

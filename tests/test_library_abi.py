@@ -65,3 +65,13 @@ def test_stats_ring_matches_header_and_rejects_bad_calls():
     refs = [ctypes.byref(v) for v in d]
     assert lib.pinmpc_stats_back(None, 0, *refs) == -1
     assert lib.pinmpc_stats(None, *refs) == -1
+
+
+def test_noalloc_constants_match_header_and_null_calls_rejected():
+    text = open(os.path.join(ROOT, "include", "pinmpc.h")).read()
+    m = re.search(r"#define PINMPC_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == binding.NOALLOC_SCRATCH_BYTES
+    assert int(re.search(r"PINMPC_ETOOBIG = (-\d+)", text).group(1)) == binding.E_TOOBIG
+    lib = binding.load()
+    assert lib.pinmpc_solve_noalloc(None, None, None, None) == -1
+    assert b"static scratch" in lib.pinmpc_strerror(binding.E_TOOBIG)

@@ -1,0 +1,65 @@
+"""pinmpc_solve_noalloc (the entry point for callers that cannot allocate)
+against pinmpc_solve through the C ABI: two calls in a row, the second on a
+smaller batch, each output equal to the allocating solve's; a batch beyond the
+static scratch is refused before any GPU work."""
+import numpy as np
+import pytest
+
+import mpcgen
+from gpu_common import _compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(solver, dev, noalloc):
+    import torch
+    out = solver.alloc_out(dev)
+    for t in out.values():
+        t.fill_(-7)                     # stale values must be overwritten
+    if noalloc:
+        solver.solve_noalloc(dev, out)
+    else:
+        solver.solve(dev, out)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_noalloc_matches_solve_twice_then_smaller():
+    import torch
+    from paper_2606_05687_amd import binding
+    big = mpcgen.make_batch("uneven_b16384", indices=range(96), n_max=60)
+    small = mpcgen.make_batch("plain_b4096_n20", indices=range(40))
+    solver = binding.Solver(0, iters=3, refine_passes=12, first_passes=4, graph=0)
+    try:
+        for batch in (big, small):
+            dev = binding.to_device(batch)
+            ref = _run(solver, dev, noalloc=False)
+            got = _run(solver, dev, noalloc=True)
+            for k in ref:
+                assert np.array_equal(got[k], ref[k]), k
+            assert (got["status"] == binding.ST_OK).all()
+        _compare(small, got, range(0, 40, 5))
+        # the second call reused the scratch the first call left behind
+        torch.cuda.synchronize()
+    finally:
+        solver.close()
+
+
+def test_noalloc_rejects_batch_beyond_scratch():
+    import ctypes
+    from paper_2606_05687_amd import binding
+    lib = binding.load()
+    s = binding.default_settings()
+    nb = ctypes.c_size_t()
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 4096, 20, ctypes.byref(nb)) == 0
+    assert nb.value > binding.NOALLOC_SCRATCH_BYTES
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(4096))
+    dev = binding.to_device(batch)
+    solver = binding.Solver(0, iters=3)
+    try:
+        out = solver.alloc_out(dev)
+        with pytest.raises(binding.PinmpcError) as e:
+            solver.solve_noalloc(dev, out)
+        assert e.value.code == binding.E_TOOBIG
+    finally:
+        solver.close()
