@@ -148,7 +148,9 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
       N [B] int32, A [B,n,13,13], B [B,n,13,12], e [B,n,13], x0 [B,13],
       u_prev [B,12], x_ref [B,n,13] (reference for x_{k+1}), u_ref [B,n,12],
       Q [B,13], R [B,12] (diagonals), contact [B,n,2] uint8 (1 = stance),
-      mu [B], fz_max [B], tau_max [B], weight [B] (m g, the force scale).
+      mu [B], fz_max [B], tau_max [B], weight [B] (m g, the force scale),
+      and the compact physics of A and B: yaw_k [B,n], c_ref [B,n,3], feet
+      [B,n,2,3], mass [B], inertia [B,3], dt [B].
     Stages k >= N[b] are padding: A = I, B = 0, e = 0, references 0, swing.
     """
     cfg = _cfg(config)
@@ -252,6 +254,15 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
         "fz_max": np.full(Bn, 1000.0),
         "tau_max": np.full(Bn, 50.0),
         "weight": mass * GRAVITY,
+        # the compact physics the matrices above are built from (the input of
+        # an on-device construction): yaw, reference CoM and contact positions
+        # per stage (zero on padding), mass, principal moments, time step
+        "yaw_k": np.where(valid, yaw[:, None], 0.0),
+        "c_ref": np.where(valid[:, :, None], c_ref[:, :n, :], 0.0),
+        "feet": np.where(valid[:, :, None, None], feet[:, None, :, :], 0.0),
+        "mass": mass,
+        "inertia": inertia,
+        "dt": np.full(Bn, float(dt)),
     }
     if offsets:
         for j, idx in enumerate(indices):
@@ -278,7 +289,9 @@ def _empty(n):
         "Q": np.zeros((0, NX), f), "R": np.zeros((0, NU), f),
         "contact": np.zeros((0, n, NC), np.uint8), "mu": np.zeros(0, f),
         "fz_max": np.zeros(0, f), "tau_max": np.zeros(0, f),
-        "weight": np.zeros(0, f),
+        "weight": np.zeros(0, f), "yaw_k": np.zeros((0, n), f),
+        "c_ref": np.zeros((0, n, 3), f), "feet": np.zeros((0, n, NC, 3), f),
+        "mass": np.zeros(0, f), "inertia": np.zeros((0, 3), f), "dt": np.zeros(0, f),
     }
 
 

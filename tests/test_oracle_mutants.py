@@ -10,7 +10,11 @@ that zero e_k, u_ref and u_prev could not reveal:
     ebar_{k+1};
   * the sign of the R r^u term of the condensed linear cost flipped;
   * the e_k term dropped from the condensed state trajectory;
-  * complementarity measured without the row multiplier.
+  * complementarity measured without the row multiplier;
+
+and, in the stage matrices built from compact physics (Sec. II-A), the
+world-frame inertia rotated the wrong way, the lever-arm cross product
+reversed, and the angle rates taken through R_z instead of R_z^T.
 """
 import os
 import shutil
@@ -38,6 +42,18 @@ MUTANTS = [
      "r_comp = max(r_comp, (mu[k, i] * slack).max() / (1.0 + mu_max * mg))",
      "r_comp = max(r_comp, (0.0 * mu[k, i] * slack).max() / (1.0 + mu_max * mg))",
      "complementarity"),
+    ("dyn-inertia-rotation", "oracle/dynamics.py",
+     "Iw = Rz @ np.diag(inertia) @ Rz.T",
+     "Iw = Rz.T @ np.diag(inertia) @ Rz",
+     "tests/test_oracle_dynamics.py"),
+    ("dyn-cross-order", "oracle/dynamics.py",
+     "wrench_moment += np.cross(feet[i] - c_ref, f) + tau",
+     "wrench_moment += np.cross(f, feet[i] - c_ref) + tau",
+     "tests/test_oracle_dynamics.py"),
+    ("dyn-angle-rate-rotation", "oracle/dynamics.py",
+     "d[0:3] = Rz.T @ omega",
+     "d[0:3] = Rz @ omega",
+     "tests/test_oracle_dynamics.py"),
 ]
 
 
@@ -50,8 +66,11 @@ def test_planted_oracle_mistake_fails_a_pin(tmp_path, name, path, old, new, sele
     src = (tmp_path / path).read_text()
     assert src.count(old) == 1, f"mutation site of {name} not found"
     (tmp_path / path).write_text(src.replace(old, new))
-    cmd = [sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
-           "tests/test_oracle_pins.py", "-k", select]
+    if select.startswith("tests/"):
+        target = [select]                 # a whole pin file
+    else:
+        target = ["tests/test_oracle_pins.py", "-k", select]
+    cmd = [sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", *target]
     r = subprocess.run(cmd, cwd=tmp_path, capture_output=True, text=True, timeout=600)
     tail = r.stdout[-2000:]
     assert "passed" in tail or "failed" in tail, tail + r.stderr[-2000:]
