@@ -197,6 +197,7 @@ KERNEL_SOURCES = {
     "setup_kernel": "setup.hip",
     "admm_fused_kernel": "admm_fused.hip",
     "admm_sweep_kernel": "admm_plain.hip",
+    "dynamics_kernel": "dynamics.hip",
 }
 
 
@@ -219,7 +220,7 @@ def _counter_rows(run_dir):
     return rows
 
 
-TUNED = "--autotune 0 --form 1 --iters 3 --rho 10 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
+TUNED = "--autotune 0 --form 1 --iters 3 --rho 30 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
 PMC_COMMANDS = [
     f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
     f"python3 bench.py {TUNED} --steps 2 --warmup 1",
@@ -383,6 +384,61 @@ def serving(args, settings):
     }
 
 
+# Algorithmic bytes of the step before the solve (stage matrices from compact
+# physics) per stage: A and B written (169 + 156 floats), yaw, reference CoM
+# and two contact positions read (1 + 3 + 6 floats); per problem mass,
+# principal moments, dt and horizon (6 words)
+DYN_BYTES_PER_STAGE = (169 + 156) * 4 + (1 + 3 + 6) * 4
+DYN_BYTES_PER_PROBLEM = 6 * 4
+
+
+def before_after(batch, reps=20):
+    """The steps before and after the solve on the metric workload, timed
+    with HIP events on the current stream: the stage matrices of all 4096 x 20
+    stages built from compact physics, and one landmark push (5 landmarks)
+    plus one reward evaluation for 4096 environments."""
+    import numpy as np
+    import torch
+    from paper_2606_05687_amd import binding
+    keys = ("N", "yaw_k", "c_ref", "feet", "mass", "inertia", "dt")
+    phys = {k: torch.from_numpy(np.ascontiguousarray(batch[k])).cuda() for k in keys}
+    Bn, n = batch["yaw_k"].shape
+    A = torch.empty((Bn, n, 13, 13), dtype=torch.float32, device="cuda")
+    B = torch.empty((Bn, n, 13, 12), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        binding.build_dynamics(phys, A, B)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        binding.build_dynamics(phys, A, B)
+    ev[1].record()
+    torch.cuda.synchronize()
+    dyn_ms = ev[0].elapsed_time(ev[1]) / reps
+    dyn_bytes = Bn * n * DYN_BYTES_PER_STAGE + Bn * DYN_BYTES_PER_PROBLEM
+    ring = binding.LandmarkRing(Bn, 5, n + 1)
+    ring.clear()
+    x = torch.zeros((Bn, n + 1, 13), dtype=torch.float32, device="cuda")
+    Nd = phys["N"]
+    com = torch.zeros((Bn, 3), dtype=torch.float32, device="cuda")
+    alpha = torch.tensor([0.5, 0.25, 0.15, 0.07, 0.03], dtype=torch.float32, device="cuda")
+    qc = torch.ones(3, dtype=torch.float32, device="cuda")
+    for t in range(3):
+        ring.push(x, Nd, t)
+        ring.reward(com, t, alpha, qc, 0.1)
+    ev[0].record()
+    for t in range(3, 3 + reps):
+        ring.push(x, Nd, t)
+        ring.reward(com, t, alpha, qc, 0.1)
+    ev[1].record()
+    torch.cuda.synchronize()
+    lm_ms = ev[0].elapsed_time(ev[1]) / reps
+    return {"dynamics": {"ms": dyn_ms, "bytes": dyn_bytes,
+                         "gbs": dyn_bytes / (dyn_ms * 1e-3) / 1e9,
+                         "hbm_frac": dyn_bytes / (dyn_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "stages": int(Bn * n)},
+            "landmark_push_and_reward_ms": lm_ms, "envs": int(Bn), "landmarks": 5}
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -419,6 +475,7 @@ def main():
         print(json.dumps(serving(args, settings)), flush=True)
         return
     tuned = None
+    tune_curve = None
     if args.autotune:
         from paper_2606_05687_amd import autotune
         nb = mpcgen.CONFIGS[args.workload]["batch"]
@@ -427,6 +484,11 @@ def main():
         tuned = autotune.tune(hdev, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
                               force=True, in_flight=max(1, args.streams))
         settings.update(tuned)
+        tune_curve = [{k: r[k] for k in ("iters", "rho", "ms", "certified", "eq_passes",
+                                          "ipm_iters")}
+                      for r in autotune.LAST_LOG
+                      if r["rho"] == tuned["rho"] and r["refine_passes"] == 12
+                      and r["first_passes"] == 0 and r["precision"] == tuned["precision"]]
         del hdev
     batch = mpcgen.make_batch(args.workload)
     Bn, n = batch["A"].shape[0], batch["A"].shape[1]
@@ -634,6 +696,12 @@ def main():
     }
     for sv in solvers:
         sv.close()
+    if tune_curve:
+        # the autotuner's measurements at the chosen rho: sweep count K against
+        # solve time and the refinement's mean passes (held-out batch)
+        line["passes_vs_sweeps"] = tune_curve
+    if args.workload == WORKLOAD:
+        line["steps_before_after"] = before_after(batch)
     if args.cpu_sample > 0 and args.workload == WORKLOAD:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_workers,
                                             admm_k=K, rho=float(settings["rho"]))

@@ -135,7 +135,7 @@ def _draw_offsets(seed, idx, n, N, mass):
 
 
 def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
-               dt=None, as_float32=True, offsets=False):
+               dt=None, as_float32=True, offsets=False, model="srb"):
     """Build a batch of problems.
 
     config   name in CONFIGS or a dict with the same keys
@@ -143,6 +143,13 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
     n_max    padded horizon (default: the largest drawn horizon)
     offsets  draw nonzero e_k, u_ref and u_prev (``_draw_offsets``); without
              it all three are zero, as in the paper's workloads
+    model    "srb": the 13-state single-rigid-body form above; "momentum": the
+             paper's 9-state centroidal model (CoM, linear momentum, angular
+             momentum about the CoM; Sec. II-A) in slots 0..8 of the same
+             13-slot layout, slots 9..12 inert (A = I, B = 0, e = 0, x0 = 0,
+             reference 0, weight 1), gravity in e_k = (0, dt m g, 0); the same
+             draws, the weights carried over (Q_v / m^2 on l, Q_omega / I^2 on
+             k), the lever arm at the reference CoM
 
     Returns a dict of arrays (float32 unless ``as_float32`` is False):
       N [B] int32, A [B,n,13,13], B [B,n,13,12], e [B,n,13], x0 [B,13],
@@ -264,6 +271,36 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
         "inertia": inertia,
         "dt": np.full(Bn, float(dt)),
     }
+    if model == "momentum":
+        if offsets:
+            raise ValueError("offsets are drawn for the single-rigid-body layout only")
+        Am = np.tile(np.eye(NX), (Bn, n, 1, 1))
+        Am[:, :, 0:3, 3:6] = (dt / mass)[:, None, None, None] * np.eye(3)
+        Bq = np.zeros((Bn, n, NX, NU))
+        for i in range(NC):
+            r = feet[:, None, i, :] - c_ref[:, :n, :]
+            Bq[:, :, 3:6, 6 * i:6 * i + 3] = dt * np.eye(3)
+            Bq[:, :, 6:9, 6 * i:6 * i + 3] = dt * _skew(r)
+            Bq[:, :, 6:9, 6 * i + 3:6 * i + 6] = dt * np.eye(3)
+        eq = np.zeros((Bn, n, NX))
+        eq[:, :, 5] = -dt * mass[:, None] * GRAVITY
+        Am[~valid] = np.eye(NX)
+        Bq[~valid] = 0.0
+        eq[~valid] = 0.0
+        xq0 = np.zeros((Bn, NX))
+        xq0[:, 0:3] = out["x0"][:, 3:6]
+        xq0[:, 3:6] = mass[:, None] * out["x0"][:, 9:12]
+        xqr = np.zeros((Bn, n, NX))
+        xqr[:, :, 0:3] = out["x_ref"][:, :, 3:6]
+        xqr[:, :, 3:6] = mass[:, None, None] * out["x_ref"][:, :, 9:12]
+        xqr[~valid] = 0.0
+        qq = np.ones((Bn, NX))
+        qq[:, 0:3] = q[:, 3:6]
+        qq[:, 3:6] = q[:, 9:12] / mass[:, None] ** 2
+        qq[:, 6:9] = q[:, 6:9] / inertia.mean(axis=1)[:, None] ** 2
+        out.update(A=Am, B=Bq, e=eq, x0=xq0, x_ref=xqr, Q=qq)
+    elif model != "srb":
+        raise ValueError(f"unknown model {model!r}")
     if offsets:
         for j, idx in enumerate(indices):
             e, ur, up = _draw_offsets(seed, idx, n, int(Nh[j]), mass[j])

@@ -19,8 +19,10 @@ Modules
   projection  Euclidean projection onto the stage wrench set.
   kkt         the accuracy measures (solution error, normalised KKT
               residuals) applied to any candidate solution.
+  landmarks   the landmark guidance reward of Sec. II-C (landmark offsets, the
+              store of predicted CoM landmarks, the reward).
   dynamics    the stage matrices A_k, B_k of the centroidal model (Sec. II-A)
               from compact physics (yaw, reference CoM, contact positions,
               mass, inertia, time step), each column from its definition.
 """
-from . import projection, qp, admm, kkt, dynamics  # noqa: F401
+from . import projection, qp, admm, kkt, dynamics, landmarks  # noqa: F401

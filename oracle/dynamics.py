@@ -95,3 +95,68 @@ def horizon_matrices(yaw, c_ref, feet, mass, inertia, dt, N):
                                     np.asarray(feet[k], float), float(mass),
                                     np.asarray(inertia, float), float(dt))
     return A, B
+
+
+# --------------------------------------------------------------------------
+# The paper's own model: 9 centroidal states (CoM c, linear momentum l_G,
+# angular momentum about the CoM k_G), Sec. II-A, its three discrete updates
+#   c_{k+1}   = c_k + dt l_k / m
+#   l_{k+1}   = l_k + dt (m g + sum_i f_i)
+#   k_{k+1}   = k_k + dt sum_i ((p_{i,k} - c_k) x f_i + tau_i)
+# with the lever arm taken at the reference CoM (the bilinear c_k x f_i
+# linearised at c_ref,k).  Gravity enters through the affine term e_k.  The
+# 13-slot state layout of the solver holds (c, l_G, k_G) in slots 0..8; slots
+# 9..12 are inert (A = I, B = 0, e = 0), so with zero initial value, zero
+# reference and any positive weight they add nothing to the cost and the
+# optimum of the 9-state problem is unchanged.
+
+GRAV = np.array([0.0, 0.0, -9.81])
+
+
+def momentum_next(x, u, c_ref, feet, mass, dt):
+    """x_{k+1} of the paper's discrete centroidal dynamics (embedded layout)."""
+    c, l, kg = x[0:3], x[3:6], x[6:9]
+    force = np.zeros(3)
+    moment = np.zeros(3)
+    for i in range(NC):
+        f = u[6 * i:6 * i + 3]
+        tau = u[6 * i + 3:6 * i + 6]
+        force += f
+        moment += np.cross(feet[i] - c_ref, f) + tau
+    out = np.array(x, dtype=np.float64)
+    out[0:3] = c + dt * l / mass
+    out[3:6] = l + dt * (mass * GRAV + force)
+    out[6:9] = kg + dt * moment
+    return out
+
+
+def momentum_stage_matrices(c_ref, feet, mass, dt):
+    """A_k, B_k, e_k of one stage: e = the image of the zero state and input,
+    each column of A and B the image of one unit state or input minus e."""
+    zx, zu = np.zeros(NX), np.zeros(NU)
+    e = momentum_next(zx, zu, c_ref, feet, mass, dt)
+    A = np.zeros((NX, NX))
+    B = np.zeros((NX, NU))
+    for j in range(NX):
+        ej = np.zeros(NX)
+        ej[j] = 1.0
+        A[:, j] = momentum_next(ej, zu, c_ref, feet, mass, dt) - e
+    for j in range(NU):
+        ej = np.zeros(NU)
+        ej[j] = 1.0
+        B[:, j] = momentum_next(zx, ej, c_ref, feet, mass, dt) - e
+    return A, B, e
+
+
+def momentum_horizon_matrices(c_ref, feet, mass, dt, N):
+    """A [n][13][13], B [n][13][12], e [n][13] of the momentum model; padding
+    stages k >= N get A = I, B = 0, e = 0."""
+    n = len(c_ref)
+    A = np.tile(np.eye(NX), (n, 1, 1))
+    B = np.zeros((n, NX, NU))
+    e = np.zeros((n, NX))
+    for k in range(N):
+        A[k], B[k], e[k] = momentum_stage_matrices(np.asarray(c_ref[k], float),
+                                                   np.asarray(feet[k], float), float(mass),
+                                                   float(dt))
+    return A, B, e

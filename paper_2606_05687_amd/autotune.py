@@ -1,11 +1,14 @@
 """Autotuner for the solve schedule (driver over the C ABI).
 
-Chooses, by measurement on a sample of the workload, the sweep form (one
-launch per sweep, fused, or horizon-class packed), the number of ADMM sweeps
-K (more sweeps cost sweep time but give the FP64 refinement a better active
-set and fewer passes), the penalty rho, the active-set pass budget and how
-many of those passes run for every problem before the uncertified ones are
-handed to the second refinement launch, and the operator precision.  The score
+Chooses, by measurement on a sample of the workload, the number of ADMM
+sweeps K (from one to 200: more sweeps cost sweep time but may give the FP64
+refinement a better active set and fewer passes), the penalty rho (1 to 30),
+the operator precision, then, at the best of those, the active-set pass budget
+and how many of those passes run for every problem before the uncertified
+ones are handed to the second refinement launch.  The sweep form follows the
+horizon (fused up to 40 stages, packed by horizon class beyond).  Every
+candidate's mean refinement work is logged beside its time, which gives the
+refinement-passes-versus-K curve of the workload.  The score
 is certified solves per second: problems whose status is certified and whose
 reported KKT residuals are all <= the bar, divided by the measured solve time;
 a candidate that certifies fewer than ``min_certified`` of the sample is
@@ -25,6 +28,7 @@ import numpy as np
 from . import binding
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pinmpc_tune.json")
+LAST_LOG: list = []   # measurements of the last tune() (or its cache entry)
 
 
 def _key(dev, allow_bf16):
@@ -37,20 +41,52 @@ def _key(dev, allow_bf16):
     return f"{arch}|B{int(dev['A'].shape[0])}|n{int(dev['A'].shape[1])}|mix{mix}|bf16{int(allow_bf16)}"
 
 
-def candidates(n_max, allow_bf16=False):
-    forms = [1] if n_max <= 40 else [-1]
-    iters = [3, 5, 10, 20, 50]
-    rhos = [10.0, 30.0]
-    passes = [8, 12, 16]
-    firsts = [2, 4, 0]
+RHOS = (1.0, 3.0, 10.0, 30.0)
+ITERS = (1, 2, 3, 5, 10, 20, 50, 100, 200)
+PASSES = (8, 12, 16)
+FIRSTS = (0, 2, 4)
+BASE_PASSES, BASE_FIRST = 12, 0
+
+
+def form_for(n_max):
+    """Fused sweeps up to 40 stages, horizon-class packing beyond."""
+    return 1 if n_max <= 40 else -1
+
+
+def stage_a(n_max, allow_bf16=False):
+    """First stage of the search: the ADMM schedule (penalty rho and sweep
+    count K, from a single sweep up to 200) under the base refinement budget."""
     precs = [0, 1] if allow_bf16 else [0]
-    for f, k, r, pa, p1, p in itertools.product(forms, iters, rhos, passes, firsts, precs):
-        yield dict(form=f, iters=k, rho=r, refine_passes=pa, first_passes=p1, precision=p)
+    for r, k, p in itertools.product(RHOS, ITERS, precs):
+        yield dict(form=form_for(n_max), iters=k, rho=r, refine_passes=BASE_PASSES,
+                   first_passes=BASE_FIRST, precision=p)
+
+
+def stage_b(best):
+    """Second stage: the refinement's pass budget and launch split at the best
+    ADMM schedule of the first stage."""
+    for pa, p1 in itertools.product(PASSES, FIRSTS):
+        if (pa, p1) == (best["refine_passes"], best["first_passes"]):
+            continue
+        yield dict(best, refine_passes=pa, first_passes=p1)
+
+
+def candidates(n_max, allow_bf16=False):
+    """Every candidate the search can measure (both stages over all first-stage
+    winners); the search itself measures stage_a, then stage_b of its best."""
+    seen = set()
+    for a in stage_a(n_max, allow_bf16):
+        for c in [a, *stage_b(a)]:
+            key = tuple(sorted(c.items()))
+            if key not in seen:
+                seen.add(key)
+                yield c
 
 
 def measure(solvers, streams, dev, outs, bs, settings, reps=4, kkt_bar=1e-5):
     """Seconds per solve with len(solvers) solves in flight (round robin over
-    the streams), and the certified fraction."""
+    the streams), the certified fraction, and the mean refinement work per
+    problem (equality-constrained passes, interior-point iterations)."""
     import torch
     for sv in solvers:
         sv.set(**settings)
@@ -66,7 +102,8 @@ def measure(solvers, streams, dev, outs, bs, settings, reps=4, kkt_bar=1e-5):
     out = outs[0]
     ok = (out["status"] == 0) & (out["res"].max(dim=1).values <= kkt_bar)
     frac = float(ok.float().mean().item())
-    return dt, frac
+    det = out["detail"].float()
+    return dt, frac, float(det[:, 0].mean().item()), float(det[:, 1].mean().item())
 
 
 def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, verbose=False,
@@ -79,7 +116,9 @@ def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, v
     if os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
+    global LAST_LOG
     if key in cache and not force:
+        LAST_LOG = cache[key].get("log", [])
         return cache[key]["settings"]
     n = max(1, int(in_flight))
     solvers = [binding.Solver(0) for _ in range(n)]
@@ -88,16 +127,26 @@ def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, v
     bs = binding.make_batch_struct(dev)
     Bn = int(dev["A"].shape[0])
     best, best_score, log = None, -1.0, []
-    for cand in candidates(int(dev["A"].shape[1]), allow_bf16):
-        dt, frac = measure(solvers, streams, dev, outs, bs, cand)
-        score = frac * Bn / dt if frac >= min_certified else 0.0
-        log.append(dict(cand, ms=dt * 1e3, certified=frac, score=score))
-        if verbose:
-            print(f"  {cand} {dt * 1e3:.2f} ms certified {frac:.4f} -> {score:.0f}/s", flush=True)
-        if score > best_score:
-            best, best_score = cand, score
+
+    def run(cands):
+        nonlocal best, best_score
+        for cand in cands:
+            dt, frac, eq, ipm = measure(solvers, streams, dev, outs, bs, cand)
+            score = frac * Bn / dt if frac >= min_certified else 0.0
+            log.append(dict(cand, ms=dt * 1e3, certified=frac, score=score, eq_passes=eq,
+                            ipm_iters=ipm))
+            if verbose:
+                print(f"  {cand} {dt * 1e3:.2f} ms certified {frac:.4f} passes {eq:.2f}+{ipm:.2f}"
+                      f" -> {score:.0f}/s", flush=True)
+            if score > best_score:
+                best, best_score = cand, score
+
+    run(stage_a(int(dev["A"].shape[1]), allow_bf16))
+    if best is not None:
+        run(list(stage_b(best)))
     for sv in solvers:
         sv.close()
+    LAST_LOG = log
     cache[key] = {"settings": best, "score": best_score, "log": log}
     os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
     with open(cache_path, "w") as f:

@@ -73,6 +73,32 @@ class Out(ctypes.Structure):
     ]
 
 
+class Physics(ctypes.Structure):
+    _fields_ = [
+        ("batch", ctypes.c_int32),
+        ("n_max", ctypes.c_int32),
+        ("model", ctypes.c_int32),
+        ("N", ctypes.c_void_p),
+        ("yaw", ctypes.c_void_p),
+        ("c_ref", ctypes.c_void_p),
+        ("feet", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+        ("inertia", ctypes.c_void_p),
+        ("dt", ctypes.c_void_p),
+    ]
+
+
+class Landmarks(ctypes.Structure):
+    _fields_ = [
+        ("envs", ctypes.c_int32),
+        ("n_landmarks", ctypes.c_int32),
+        ("ring", ctypes.c_int32),
+        ("ticks_per_step", ctypes.c_int32),
+        ("com", ctypes.c_void_p),
+        ("tag", ctypes.c_void_p),
+    ]
+
+
 EXPORTS = {
     "pinmpc_default_settings": (None, [ctypes.POINTER(Settings)]),
     "pinmpc_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
@@ -89,6 +115,23 @@ EXPORTS = {
     "pinmpc_stats": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 4),
     "pinmpc_stats_back": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32] +
                           [ctypes.POINTER(ctypes.c_double)] * 4),
+    "pinmpc_stats_traffic": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "pinmpc_build_dynamics": (ctypes.c_int, [ctypes.POINTER(Physics), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pinmpc_server_export_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_void_p, ctypes.c_size_t]),
+    "pinmpc_server_import_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_void_p, ctypes.c_size_t]),
+    "pinmpc_landmarks_clear": (ctypes.c_int, [ctypes.POINTER(Landmarks), ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "pinmpc_landmarks_push": (ctypes.c_int, [ctypes.POINTER(Landmarks), ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_void_p]),
+    "pinmpc_landmark_reward": (ctypes.c_int, [ctypes.POINTER(Landmarks), ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "pinmpc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pinmpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pinmpc_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
@@ -108,6 +151,14 @@ _lib = None
 
 
 STATS_RING = 64   # PINMPC_STATS_RING
+NMAX = 64         # PINMPC_NMAX
+WARM_SLOT_BYTES = NMAX * 5 * 25 * 4   # PINMPC_WARM_SLOT_BYTES
+E_BUSY = -5       # PINMPC_EBUSY
+
+
+def warm_image_bytes(count: int) -> int:
+    """PINMPC_WARM_IMAGE_BYTES(count)."""
+    return 16 + count * WARM_SLOT_BYTES
 
 
 def load(path: str = LIB_PATH):
@@ -258,6 +309,12 @@ class Solver:
                                   ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
         return z
 
+    def traffic(self):
+        """Algorithmic HBM bytes of the last solve and their rate (GB/s)."""
+        b, g = ctypes.c_double(), ctypes.c_double()
+        _check(load().pinmpc_stats_traffic(self._h, ctypes.byref(b), ctypes.byref(g)))
+        return {"bytes": b.value, "gbs": g.value}
+
     def stats(self, back: int = 0):
         """Phase times (ms) of the last solve, or of the solve `back` solves
         before it (up to STATS_RING - 1)."""
@@ -312,6 +369,19 @@ class Server:
         self._keep.pop(ticket, None)
         return lat.value
 
+    def export_state(self, slot_base: int, count: int) -> bytes:
+        """Host image of warm slots [slot_base, slot_base + count)."""
+        buf = ctypes.create_string_buffer(warm_image_bytes(count))
+        _check(load().pinmpc_server_export_state(self._h, int(slot_base), int(count), buf,
+                                                 len(buf)))
+        return buf.raw
+
+    def import_state(self, slot_base: int, count: int, image: bytes):
+        """Write a host image back into warm slots [slot_base, slot_base + count)."""
+        buf = ctypes.create_string_buffer(bytes(image), len(image))
+        _check(load().pinmpc_server_import_state(self._h, int(slot_base), int(count), buf,
+                                                 len(image)))
+
     def stats(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(load().pinmpc_server_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
@@ -328,3 +398,73 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+PHYSICS_FIELDS = ("N", "yaw_k", "c_ref", "feet", "mass", "inertia", "dt")
+MODELS = {"srb": 0, "momentum": 1}
+
+
+def build_dynamics(phys: dict, A=None, B=None, e=None, model="srb", stream=None):
+    """pinmpc_build_dynamics: stage matrices [B][n][13][13], [B][n][13][12]
+    and affine terms [B][n][13] from compact physics held in device tensors
+    (keys of PHYSICS_FIELDS); model "srb" (13-state single rigid body) or
+    "momentum" (the 9-state momentum model, e required)."""
+    import torch
+    ref = phys["c_ref"]
+    assert ref.dtype == torch.float32 and ref.is_contiguous()
+    Bn, n = int(ref.shape[0]), int(ref.shape[1])
+    if A is None:
+        A = torch.empty((Bn, n, NX, NX), dtype=torch.float32, device=ref.device)
+    if B is None:
+        B = torch.empty((Bn, n, NX, NU), dtype=torch.float32, device=ref.device)
+    if e is None and model == "momentum":
+        e = torch.empty((Bn, n, NX), dtype=torch.float32, device=ref.device)
+    ph = Physics()
+    ph.batch, ph.n_max, ph.model = Bn, n, MODELS[model]
+    for f, k in (("N", "N"), ("yaw", "yaw_k"), ("c_ref", "c_ref"), ("feet", "feet"),
+                 ("mass", "mass"), ("inertia", "inertia"), ("dt", "dt")):
+        t = phys.get(k)
+        if t is not None:
+            assert t.is_contiguous() and t.shape[0] == Bn, k
+        setattr(ph, f, None if t is None else t.data_ptr())
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().pinmpc_build_dynamics(ctypes.byref(ph), ctypes.c_void_p(A.data_ptr()),
+                                        ctypes.c_void_p(B.data_ptr()), _ptr(e),
+                                        ctypes.c_void_p(st.cuda_stream)))
+    return A, B, e
+
+
+class LandmarkRing:
+    """Device landmark store of Sec. II-C's guidance reward (pinmpc_landmarks_*)."""
+
+    def __init__(self, envs, n_landmarks, ring, ticks_per_step=1, device="cuda"):
+        import torch
+        self.com = torch.zeros((envs, ring, n_landmarks, 3), dtype=torch.float32, device=device)
+        self.tag = torch.full((envs, ring, n_landmarks), -1, dtype=torch.int32, device=device)
+        self.st = Landmarks(int(envs), int(n_landmarks), int(ring), int(ticks_per_step),
+                            self.com.data_ptr(), self.tag.data_ptr())
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(st.cuda_stream)
+
+    def clear(self, env_mask=None, stream=None):
+        _check(load().pinmpc_landmarks_clear(ctypes.byref(self.st), _ptr(env_mask),
+                                             self._stream(stream)))
+
+    def push(self, x, N, tick, stream=None):
+        n_max = int(x.shape[1]) - 1
+        _check(load().pinmpc_landmarks_push(ctypes.byref(self.st), n_max, _ptr(N), _ptr(x),
+                                            int(tick), self._stream(stream)))
+
+    def reward(self, com, tick, alpha, qc, sigma, stream=None):
+        import torch
+        envs = self.st.envs
+        r = torch.empty(envs, dtype=torch.float32, device=com.device)
+        used = torch.empty(envs, dtype=torch.int32, device=com.device)
+        _check(load().pinmpc_landmark_reward(ctypes.byref(self.st), _ptr(com), int(tick),
+                                             _ptr(alpha), _ptr(qc), float(sigma), _ptr(r),
+                                             _ptr(used), self._stream(stream)))
+        return r, used

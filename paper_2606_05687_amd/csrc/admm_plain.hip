@@ -32,11 +32,14 @@ struct Lds {
   float* xi0;   // fixed lifted initial state (x0, ut_prev)
 };
 
+// `sweeps` sweeps in one launch: the iterates and the acceleration state stay
+// in registers between sweeps (loaded once, stored once); the operators are
+// read from memory every sweep.  sweeps = 1 is the plain form.
 template <int PAIRS, bool BF16>
 __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace ws, float rho,
                                                           int accel, float eta,
                                                           const int32_t* order,
-                                                          const int32_t* count) {
+                                                          const int32_t* count, int sweeps) {
   if (count && (int)blockIdx.x >= *count) return;
   OpLoad<BF16> op;
   if constexpr (BF16) {
@@ -88,6 +91,17 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
         zc[q] = C[0]; vc[q] = C[NL]; tc[q] = C[2 * NL]; bc[q] = C[3 * NL]; lc[q] = C[4 * NL];
       }
       eb[q] = (r < NX && e) ? e[(s0 + k) * NX + r] : 0.f;
+    }
+  }
+  float al = ws.alpha[b], cp = ws.cprev[b];
+  int nrest = 0;
+
+  for (int it = 0; it < sweeps; ++it) {
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    const int id = threadIdx.x + q * blockDim.x;
+    if (id < nact) {
+      const int k = id / NL, r = id % NL;
       L.b0[k * BUF + r] = vh[q] - bh[q];
       L.b1[k * BUF + r] = zh[q] - vh[q] - eb[q] + lh[q];
     }
@@ -263,23 +277,38 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
   bool restart = false;
   if (accel) {
     const float cm = stage_ordered_sum(L.b0, L.b2, N);
-    const float cp = ws.cprev[b];
-    const float al = ws.alpha[b];
     if (cm < eta * cp) {
       const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * al * al));
       f = (al - 1.f) / an;
-      __syncthreads();
-      if (threadIdx.x == 0) { ws.alpha[b] = an; ws.cprev[b] = cm; }
+      al = an;
+      cp = cm;
     } else {
       restart = true;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        ws.alpha[b] = 1.f;
-        ws.cprev[b] = cp / eta;
-        ws.restarts[b] += 1;
-      }
+      al = 1.f;
+      cp = cp / eta;
+      ++nrest;
     }
   }
+#pragma unroll
+  for (int q = 0; q < PAIRS; ++q) {
+    if (accel) {
+      if (restart) {
+        zh[q] = zc[q]; vh[q] = vc[q]; th[q] = tc[q]; bh[q] = bc[q]; lh[q] = lc[q];
+      } else {
+        zh[q] = zv[q] + f * (zv[q] - zc[q]);
+        vh[q] = vv[q] + f * (vv[q] - vc[q]);
+        th[q] = tv[q] + f * (tv[q] - tc[q]);
+        bh[q] = bvv[q] + f * (bvv[q] - bc[q]);
+        lh[q] = lv[q] + f * (lv[q] - lc[q]);
+      }
+      zc[q] = zv[q]; vc[q] = vv[q]; tc[q] = tv[q]; bc[q] = bvv[q]; lc[q] = lv[q];
+    } else {
+      zh[q] = zv[q]; vh[q] = vv[q]; th[q] = tv[q]; bh[q] = bvv[q]; lh[q] = lv[q];
+    }
+  }
+  __syncthreads();   // this sweep's LDS reads are done before the next one writes
+  }  // sweeps
+
 #pragma unroll
   for (int q = 0; q < PAIRS; ++q) {
     const int id = threadIdx.x + q * blockDim.x;
@@ -287,22 +316,17 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
       const int k = id / NL, r = id % NL;
       const size_t base = ((s0 + k) * NSTATE) * NL + r;
       float* H = ws.hat + base;
+      H[0] = zh[q]; H[NL] = vh[q]; H[2 * NL] = th[q]; H[3 * NL] = bh[q]; H[4 * NL] = lh[q];
       if (accel) {
         float* C = ws.cur + base;
-        if (restart) {
-          H[0] = zc[q]; H[NL] = vc[q]; H[2 * NL] = tc[q]; H[3 * NL] = bc[q]; H[4 * NL] = lc[q];
-        } else {
-          H[0] = zv[q] + f * (zv[q] - zc[q]);
-          H[NL] = vv[q] + f * (vv[q] - vc[q]);
-          H[2 * NL] = tv[q] + f * (tv[q] - tc[q]);
-          H[3 * NL] = bvv[q] + f * (bvv[q] - bc[q]);
-          H[4 * NL] = lv[q] + f * (lv[q] - lc[q]);
-        }
-        C[0] = zv[q]; C[NL] = vv[q]; C[2 * NL] = tv[q]; C[3 * NL] = bvv[q]; C[4 * NL] = lv[q];
-      } else {
-        H[0] = zv[q]; H[NL] = vv[q]; H[2 * NL] = tv[q]; H[3 * NL] = bvv[q]; H[4 * NL] = lv[q];
+        C[0] = zc[q]; C[NL] = vc[q]; C[2 * NL] = tc[q]; C[3 * NL] = bc[q]; C[4 * NL] = lc[q];
       }
     }
+  }
+  if (threadIdx.x == 0 && accel) {
+    ws.alpha[b] = al;
+    ws.cprev[b] = cp;
+    ws.restarts[b] += nrest;
   }
 }
 
@@ -424,7 +448,7 @@ hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st
 }
 
 static hipError_t sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
-                        const int32_t* ord, const int32_t* cnt, hipStream_t st) {
+                        const int32_t* ord, const int32_t* cnt, int sweeps, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
   const int work = NL * p.n_max;
   int threads = ((work + 63) / 64) * 64;
@@ -433,7 +457,7 @@ static hipError_t sweep(const Problem& p, const Workspace& w, const pinmpc_setti
   const size_t lds = (size_t)(5 * p.n_max * BUF + 32) * sizeof(float);
 #define PINMPC_SWEEP(P, BF)                                                                \
   hipLaunchKernelGGL((admm_sweep_kernel<P, BF>), dim3(p.batch), dim3(threads), lds, st, p, w, \
-                     s.rho, s.accel, s.restart_eta, ord, cnt)
+                     s.rho, s.accel, s.restart_eta, ord, cnt, sweeps)
   if (pairs == 1 && !s.precision) PINMPC_SWEEP(1, false);
   else if (pairs == 1) PINMPC_SWEEP(1, true);
   else if (pairs == 2 && !s.precision) PINMPC_SWEEP(2, false);
@@ -444,13 +468,14 @@ static hipError_t sweep(const Problem& p, const Workspace& w, const pinmpc_setti
 }
 
 hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
-                             hipStream_t st) {
-  return sweep(p, w, s, nullptr, nullptr, st);
+                             int sweeps, hipStream_t st) {
+  return sweep(p, w, s, nullptr, nullptr, sweeps, st);
 }
 
 hipError_t launch_admm_sweep_class(const Problem& p, const Workspace& w,
-                                   const pinmpc_settings& s, int cls, hipStream_t st) {
-  return sweep(p, w, s, w.order + (size_t)cls * p.batch, w.counts + cls, st);
+                                   const pinmpc_settings& s, int cls, int sweeps,
+                                   hipStream_t st) {
+  return sweep(p, w, s, w.order + (size_t)cls * p.batch, w.counts + cls, sweeps, st);
 }
 
 namespace {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -49,6 +50,10 @@ struct pinmpc_ctx_s {
   bool have_timing = false;
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey{};
+  // the last solve's shape, sweep count and refinement work counter
+  size_t last_stages = 0;
+  int last_iters = 0;
+  const unsigned long long* last_work = nullptr;
 };
 
 namespace {
@@ -96,6 +101,7 @@ size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.rlist = (int32_t*)take(Bn * 4);
   t.rcount = (int32_t*)take(4);
   t.rpass = (int32_t*)take(Bn * 4);
+  t.work = (unsigned long long*)take(8);
   t.bytes = off;
   t.warm_idx = nullptr;
   t.warm_store = nullptr;
@@ -155,31 +161,31 @@ Problem to_problem(const pinmpc_batch* in) {
 }
 
 // The fused kernel holds one problem per workgroup with one thread per
-// (stage, lifted row): horizons up to 1024 / 25 = 40 stages.
-static bool use_fused(const pinmpc_settings& s, int n_max) {
-  const bool fits = NL * n_max <= 1024;
-  if (s.form == 1) return fits;
-  if (s.form == -1) return fits;
-  return false;
-}
+// (stage, lifted row) and that row's operators in registers: horizons up to
+// 1024 / 25 = 40 stages.  Longer horizons in the fused and packed forms run all
+// sweeps in one launch of the streaming kernel (iterates resident, operators
+// streamed).
+static bool fits_fused(int n_max) { return NL * n_max <= 1024; }
 
 // The ADMM sweeps in the form the settings ask for.
 int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
                       hipStream_t st) {
-  if (s.form == -1 && p.n_max > CLASS_N[0] && iters > 0) {
+  if (iters <= 0) return PINMPC_OK;
+  if (s.form == -1 && p.n_max > CLASS_N[0]) {
     // pack problems by horizon class: fused kernels sized for each class,
-    // one-launch-per-sweep for the longest horizons
+    // the persistent streaming kernel for the longest horizons
     if (launch_classify(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
     for (int cls = 0; cls < 2; ++cls)
       if (launch_admm_fused_class(p, w, s, iters, cls, st) != hipSuccess) return PINMPC_EDEVICE;
-    if (p.n_max > CLASS_N[1])
-      for (int it = 0; it < iters; ++it)
-        if (launch_admm_sweep_class(p, w, s, 2, st) != hipSuccess) return PINMPC_EDEVICE;
-  } else if (use_fused(s, p.n_max)) {
+    if (p.n_max > CLASS_N[1] && launch_admm_sweep_class(p, w, s, 2, iters, st) != hipSuccess)
+      return PINMPC_EDEVICE;
+  } else if (s.form != 0 && fits_fused(p.n_max)) {
     if (launch_admm_fused(p, w, s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
+  } else if (s.form != 0) {
+    if (launch_admm_sweep(p, w, s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
   } else {
     for (int it = 0; it < iters; ++it)
-      if (launch_admm_sweep(p, w, s, st) != hipSuccess) return PINMPC_EDEVICE;
+      if (launch_admm_sweep(p, w, s, 1, st) != hipSuccess) return PINMPC_EDEVICE;
   }
   return PINMPC_OK;
 }
@@ -213,6 +219,11 @@ int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Wor
 }
 
 int run_admm(pinmpc_ctx c, const Problem& p, const Workspace& w, int iters, hipStream_t st) {
+  // the refinement adds its work to this counter (a fill kernel: graph-safe)
+  if (launch_fill_i32((int32_t*)w.work, 2, 0, 0, st) != hipSuccess) return PINMPC_EDEVICE;
+  c->last_stages = (size_t)p.batch * p.n_max;
+  c->last_iters = iters;
+  c->last_work = w.work;
   if (launch_setup(p, w, c->s, st) != hipSuccess) return PINMPC_EDEVICE;
   if (launch_admm_init(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[1], st);
@@ -461,6 +472,100 @@ int pinmpc_stats_back(pinmpc_ctx c, int32_t back, double* total_ms, double* setu
 int pinmpc_stats(pinmpc_ctx c, double* total_ms, double* setup_ms, double* admm_ms,
                  double* refine_ms) {
   return pinmpc_stats_back(c, 0, total_ms, setup_ms, admm_ms, refine_ms);
+}
+
+int pinmpc_stats_traffic(pinmpc_ctx c, double* bytes, double* gbytes_per_s) {
+  if (!c || !c->have_timing || c->nsolves == 0 || !c->last_work) return PINMPC_EINVAL;
+  hipEvent_t* ev = c->ring[(c->nsolves - 1) % PINMPC_STATS_RING];
+  if (hipEventSynchronize(ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  unsigned long long pass_stages = 0;
+  if (hipSetDevice(c->device) != hipSuccess ||
+      hipMemcpy(&pass_stages, c->last_work, sizeof(pass_stages), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return PINMPC_EDEVICE;
+  const double b = (double)c->last_stages *
+                       (PINMPC_SETUP_BYTES + (double)c->last_iters * PINMPC_SWEEP_BYTES) +
+                   (double)pass_stages * PINMPC_REFINE_BYTES;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ev[0], ev[3]) != hipSuccess) return PINMPC_EDEVICE;
+  if (bytes) *bytes = b;
+  if (gbytes_per_s) *gbytes_per_s = ms > 0.f ? b / ((double)ms * 1e6) : 0.0;
+  return PINMPC_OK;
+}
+
+int pinmpc_build_dynamics(const pinmpc_physics* in, float* A, float* Bu, float* e,
+                          void* hip_stream) {
+  if (!in || in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX) return PINMPC_EINVAL;
+  if (in->model < 0 || in->model > 1) return PINMPC_EINVAL;
+  if (in->batch == 0) return PINMPC_OK;
+  if (!A || !Bu || !in->c_ref || !in->feet || !in->mass || !in->dt) return PINMPC_EINVAL;
+  if (in->model == 0 && (!in->yaw || !in->inertia)) return PINMPC_EINVAL;
+  if (in->model == 1 && !e) return PINMPC_EINVAL;
+  Physics ph;
+  ph.batch = in->batch;
+  ph.n_max = in->n_max;
+  ph.model = in->model;
+  ph.N = in->N;
+  ph.yaw = in->yaw;
+  ph.c_ref = in->c_ref;
+  ph.feet = in->feet;
+  ph.mass = in->mass;
+  ph.inertia = in->inertia;
+  ph.dt = in->dt;
+  return launch_dynamics(ph, A, Bu, e, (hipStream_t)hip_stream) == hipSuccess ? PINMPC_OK
+                                                                             : PINMPC_EDEVICE;
+}
+
+static int to_store(const pinmpc_landmarks* in, LandmarkStore* st) {
+  if (!in || in->envs < 0 || in->n_landmarks < 1 || in->n_landmarks > 31 || in->ring < 2 ||
+      in->ticks_per_step < 1)
+    return PINMPC_EINVAL;
+  if (in->envs > 0 && (!in->com || !in->tag)) return PINMPC_EINVAL;
+  st->envs = in->envs;
+  st->n_landmarks = in->n_landmarks;
+  st->ring = in->ring;
+  st->ticks_per_step = in->ticks_per_step;
+  st->com = in->com;
+  st->tag = in->tag;
+  return PINMPC_OK;
+}
+
+int pinmpc_landmarks_clear(const pinmpc_landmarks* in, const uint8_t* env_mask,
+                           void* hip_stream) {
+  LandmarkStore st;
+  const int rc = to_store(in, &st);
+  if (rc) return rc;
+  return launch_landmarks_clear(st, env_mask, (hipStream_t)hip_stream) == hipSuccess
+             ? PINMPC_OK
+             : PINMPC_EDEVICE;
+}
+
+int pinmpc_landmarks_push(const pinmpc_landmarks* in, int32_t n_max, const int32_t* N,
+                          const float* x, int32_t tick, void* hip_stream) {
+  LandmarkStore st;
+  const int rc = to_store(in, &st);
+  if (rc) return rc;
+  if (n_max < 1 || n_max > PINMPC_NMAX || tick < 0) return PINMPC_EINVAL;
+  if ((int64_t)st.ring <= (int64_t)n_max * st.ticks_per_step) return PINMPC_EINVAL;
+  if ((int64_t)tick + (int64_t)n_max * st.ticks_per_step > INT32_MAX) return PINMPC_EINVAL;
+  if (st.envs > 0 && !x) return PINMPC_EINVAL;
+  return launch_landmarks_push(st, n_max, N, x, tick, (hipStream_t)hip_stream) == hipSuccess
+             ? PINMPC_OK
+             : PINMPC_EDEVICE;
+}
+
+int pinmpc_landmark_reward(const pinmpc_landmarks* in, const float* com, int32_t tick,
+                           const float* alpha, const float* qc, float sigma, float* reward,
+                           int32_t* used, void* hip_stream) {
+  LandmarkStore st;
+  const int rc = to_store(in, &st);
+  if (rc) return rc;
+  if (tick < 0 || !(sigma > 0.f) || !std::isfinite(sigma)) return PINMPC_EINVAL;
+  if (st.envs > 0 && (!com || !alpha || !qc || !reward)) return PINMPC_EINVAL;
+  return launch_landmark_reward(st, com, tick, alpha, qc, sigma, reward, used,
+                                (hipStream_t)hip_stream) == hipSuccess
+             ? PINMPC_OK
+             : PINMPC_EDEVICE;
 }
 
 int pinmpc_destroy(pinmpc_ctx c) {

@@ -14,6 +14,7 @@ constexpr int NL = NX + NU;     // 25: lifted state (x_k, u_{k-1}) of the veloci
 constexpr int NH = NL * (NL + 1) / 2;   // 325: packed symmetric H_k
 constexpr int NM = NU * (NU + 1) / 2;   // 78: packed symmetric M_k
 constexpr int NROW = 11;        // wrench rows per stance contact
+constexpr int NCONTACT = PINMPC_NCONTACT;   // 2 contacts
 constexpr int NSTATE = 5;       // ADMM iterate blocks z, v, theta, beta, lambda
 
 // BF16 (bfloat16) storage: round to nearest even from FP32, and back.
@@ -115,6 +116,9 @@ struct Workspace {
   int32_t* rlist;   // [b]
   int32_t* rcount;  // [1]
   int32_t* rpass;   // [b]
+  // refinement work of the solve: stages of every equality-constrained pass
+  // and interior-point iteration, summed over problems (64-bit counter)
+  unsigned long long* work;
   size_t bytes;
   // warm start (serving): per problem slot index into a device store of
   // iterates [slot][PINMPC_NMAX][5][25]; null / negative index = cold start
@@ -341,7 +345,28 @@ Problem to_problem(const pinmpc_batch* in);
 int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
                       hipStream_t st);
 
+// Compact physics of the stage matrices (device pointers, see pinmpc_physics).
+struct Physics {
+  int32_t batch, n_max, model;
+  const int32_t* N;
+  const float *yaw, *c_ref, *feet, *mass, *inertia, *dt;
+};
+
+// Landmark store (see pinmpc_landmarks).
+struct LandmarkStore {
+  int32_t envs, n_landmarks, ring, ticks_per_step;
+  float* com;
+  int32_t* tag;
+};
+
 // Kernel launchers (defined in the .hip units).
+hipError_t launch_landmarks_clear(const LandmarkStore& st, const uint8_t* mask, hipStream_t s);
+hipError_t launch_landmarks_push(const LandmarkStore& st, int n_max, const int32_t* N,
+                                 const float* x, int32_t tick, hipStream_t s);
+hipError_t launch_landmark_reward(const LandmarkStore& st, const float* com, int32_t tick,
+                                  const float* alpha, const float* qc, float sigma,
+                                  float* reward, int32_t* used, hipStream_t s);
+hipError_t launch_dynamics(const Physics& ph, float* A, float* B, float* e, hipStream_t st);
 hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                         hipStream_t st);
 hipError_t launch_admm_init(const Problem& p, const Workspace& w, hipStream_t st);
@@ -349,8 +374,11 @@ hipError_t launch_warm_save(const Problem& p, const Workspace& w, int accel, hip
 hipError_t launch_fill_i32(int32_t* dst, size_t n, int32_t base, int32_t step, hipStream_t st);
 hipError_t launch_fill_f32(float* dst, size_t n, float value, hipStream_t st);
 hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st);
+// `sweeps` ADMM sweeps in one launch of the streaming sweep kernel (1: the
+// plain form, one launch per sweep; more: iterates resident in registers
+// across the sweeps, operators streamed every sweep).
 hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
-                             hipStream_t st);
+                             int sweeps, hipStream_t st);
 hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                              int iters, hipStream_t st);
 // Horizon-class packing: class 0 N <= 20, class 1 20 < N <= 40, class 2 N > 40.
@@ -359,7 +387,8 @@ hipError_t launch_classify(const Problem& p, const Workspace& w, hipStream_t st)
 hipError_t launch_admm_fused_class(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                                    int iters, int cls, hipStream_t st);
 hipError_t launch_admm_sweep_class(const Problem& p, const Workspace& w,
-                                   const pinmpc_settings& s, int cls, hipStream_t st);
+                                   const pinmpc_settings& s, int cls, int sweeps,
+                                   hipStream_t st);
 hipError_t launch_admm_extract(const Problem& p, const Workspace& w, int accel,
                                float* z_out, hipStream_t st);
 hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,

@@ -1645,6 +1645,8 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
   for (int e = lane; e < (C.n + 1) * NX; e += W64)
     out_x[xx + e] = (e < (N + 1) * NX) ? (float)C.rx[e] : 0.f;
   if (lane == 0) {
+    // the solve's refinement work (stages of every pass and iteration)
+    atomicAdd(ws.work, (unsigned long long)(cnt.eq + cnt.ipm) * (unsigned long long)N);
     if (out_status)
       out_status[C.b] = refine ? (ok ? PINMPC_ST_OK : PINMPC_ST_UNPOLISHED) : PINMPC_ST_MAXITER;
     if (out_iters) out_iters[C.b] = admm_iters + cnt.eq + cnt.ipm;

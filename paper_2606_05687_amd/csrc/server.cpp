@@ -450,6 +450,65 @@ int pinmpc_server_stats(pinmpc_server s, int64_t* launches, int64_t* problems) {
   return s->error;
 }
 
+namespace {
+
+constexpr char kWarmMagic[4] = {'P', 'M', 'W', 'S'};
+constexpr int32_t kWarmVersion = 1;
+
+// Range checks shared by export and import; with the server mutex held,
+// PINMPC_EBUSY when a request that is not done uses one of the slots.
+int check_warm_range(pinmpc_server s, int32_t base, int32_t count, size_t bytes) {
+  if (base < 0 || count < 1 || (int64_t)base + count > s->warm_slots) return PINMPC_EINVAL;
+  if (bytes < PINMPC_WARM_IMAGE_BYTES(count)) return PINMPC_EINVAL;
+  const int64_t lo = base, hi = (int64_t)base + count;
+  for (const auto& kv : s->reqs) {
+    const Request& o = *kv.second;
+    if (o.done || o.warm_base < 0) continue;
+    if (lo < (int64_t)o.warm_base + o.in.batch && (int64_t)o.warm_base < hi) return PINMPC_EBUSY;
+  }
+  return PINMPC_OK;
+}
+
+}  // namespace
+
+int pinmpc_server_export_state(pinmpc_server s, int32_t slot_base, int32_t count,
+                               void* host_buf, size_t bytes) {
+  if (!s || !host_buf) return PINMPC_EINVAL;
+  std::lock_guard<std::mutex> lk(s->m);
+  const int rc = check_warm_range(s, slot_base, count, bytes);
+  if (rc) return rc;
+  char* h = (char*)host_buf;
+  const int32_t hdr[3] = {kWarmVersion, count, PINMPC_NMAX};
+  std::memcpy(h, kWarmMagic, 4);
+  std::memcpy(h + 4, hdr, sizeof(hdr));
+  const size_t slot_floats = PINMPC_WARM_SLOT_BYTES / 4;
+  if (hipSetDevice(s->device) != hipSuccess ||
+      hipMemcpy(h + 16, s->warm_store + (size_t)slot_base * slot_floats,
+                (size_t)count * PINMPC_WARM_SLOT_BYTES, hipMemcpyDeviceToHost) != hipSuccess)
+    return PINMPC_EDEVICE;
+  return PINMPC_OK;
+}
+
+int pinmpc_server_import_state(pinmpc_server s, int32_t slot_base, int32_t count,
+                               const void* host_buf, size_t bytes) {
+  if (!s || !host_buf) return PINMPC_EINVAL;
+  std::lock_guard<std::mutex> lk(s->m);
+  const int rc = check_warm_range(s, slot_base, count, bytes);
+  if (rc) return rc;
+  const char* h = (const char*)host_buf;
+  int32_t hdr[3];
+  std::memcpy(hdr, h + 4, sizeof(hdr));
+  if (std::memcmp(h, kWarmMagic, 4) != 0 || hdr[0] != kWarmVersion || hdr[1] != count ||
+      hdr[2] != PINMPC_NMAX)
+    return PINMPC_EINVAL;
+  const size_t slot_floats = PINMPC_WARM_SLOT_BYTES / 4;
+  if (hipSetDevice(s->device) != hipSuccess ||
+      hipMemcpy(s->warm_store + (size_t)slot_base * slot_floats, h + 16,
+                (size_t)count * PINMPC_WARM_SLOT_BYTES, hipMemcpyHostToDevice) != hipSuccess)
+    return PINMPC_EDEVICE;
+  return PINMPC_OK;
+}
+
 int pinmpc_server_destroy(pinmpc_server s) {
   if (!s) return PINMPC_EINVAL;
   {

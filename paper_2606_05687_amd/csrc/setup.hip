@@ -7,7 +7,9 @@
 //   H_k  = (Qbar_k + rho I + [k < N-1] rho Abar_{k+1}^T Abar_{k+1})^{-1}
 //          Qbar_k = diag(Q, R S_k^2),  Abar^T Abar = [[A^T A, A^T Bt], [Bt^T A, Bt^T Bt + I]]
 //   qbar_k = (Q x_ref[k], R S_k u_ref[k])
-// Products and inversions run in FP64 and are stored in FP32.
+// FP32 arithmetic throughout (the ADMM that uses these runs in FP32; both
+// matrices inverted are symmetric positive definite with eigenvalues >= 1 and
+// >= rho, so Gauss-Jordan without pivoting is stable).
 #include "pinmpc_internal.h"
 
 namespace pinmpc {
@@ -16,12 +18,43 @@ namespace {
 
 __device__ inline int stance_count(const uint8_t* c) { return (c[0] != 0) + (c[1] != 0); }
 
-__device__ inline double scale_of(const Problem& p, int b, int k, int j, bool scaling) {
-  if (!scaling) return 1.0;
+__device__ inline float scale_of(const Problem& p, int b, int k, int j, bool scaling) {
+  if (!scaling) return 1.f;
   const size_t s = (size_t)b * p.n_max + k;
   const int ns = stance_count(p.contact + 2 * s);
-  const double sf = (double)weight_of(p, b) / (ns > 0 ? ns : 1);
-  return (j % 6) < 3 ? sf : (double)p.tau_max[b];
+  const float sf = weight_of(p, b) / (float)(ns > 0 ? ns : 1);
+  return (j % 6) < 3 ? sf : p.tau_max[b];
+}
+
+// 1/a from the hardware estimate and one Newton step (SPD pivots: finite and
+// positive), within about an ulp of the FP32 quotient.
+__device__ inline float recip_f(float a) {
+  float r = __builtin_amdgcn_rcpf(a);
+  const float e = fmaf(-a, r, 1.f);
+  return fmaf(r, e, r);
+}
+
+__device__ inline float readlane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Gauss-Jordan without pivoting on a system whose column c is held by lane c
+// of the wave (col[r] is row r); the pivot column is broadcast from its lane.
+// Afterwards a lane holding column c of [M | X] holds column c of
+// [I | M^{-1} X].
+template <int n>
+__device__ inline void gj_columns_f(float (&col)[n]) {
+#pragma unroll
+  for (int p = 0; p < n; ++p) {
+    float pc[n];
+#pragma unroll
+    for (int r = 0; r < n; ++r) pc[r] = readlane_f(col[r], p);
+    const float t = col[p] * recip_f(pc[p]);
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+      if (r != p) col[r] = fmaf(-pc[r], t, col[r]);
+    col[p] = t;
+  }
 }
 
 __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, float rho,
@@ -30,8 +63,8 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
   const int b = s / p.n_max, k = s % p.n_max;
   const int lane = threadIdx.x;
   const int N = horizon(p, b);
-  __shared__ double sTop[NX * NL];             // [A_{k+1} | Bt_{k+1}], 13 x 25
-  __shared__ double sBt[NX * NU];              // Bt_k
+  __shared__ float sTop[NX * NL];              // [A_{k+1} | Bt_{k+1}], 13 x 25
+  __shared__ float sBt[NX * NU];               // Bt_k
   const bool sc = scaling != 0;
 
   if (k >= N) {   // padding stage: benign values, never read by the sweep
@@ -45,10 +78,10 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
   const float* Bk = p.B + (size_t)s * NX * NU;
   for (int i = lane; i < NX * NU; i += 64) {
     const int j = i % NU;
-    const double v = (double)Bk[i] * scale_of(p, b, k, j, sc);
+    const float v = Bk[i] * scale_of(p, b, k, j, sc);
     sBt[i] = v;
-    ws.Bt[(size_t)s * NX * NU + i] = (float)v;
-    if (bf16) ws.Btbf[(size_t)s * NX * NU + i] = to_bf16((float)v);
+    ws.Bt[(size_t)s * NX * NU + i] = v;
+    if (bf16) ws.Btbf[(size_t)s * NX * NU + i] = to_bf16(v);
   }
   const bool has_next = (k + 1 < N);
   if (has_next) {
@@ -56,12 +89,11 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
     const float* B1 = p.B + (size_t)(s + 1) * NX * NU;
     for (int e = lane; e < NX * NL; e += 64) {
       const int i = e / NL, c = e % NL;
-      sTop[e] = (c < NX) ? (double)A1[i * NX + c]
-                         : (double)B1[i * NU + c - NX] * scale_of(p, b, k + 1, c - NX, sc);
+      sTop[e] = (c < NX) ? A1[i * NX + c] : B1[i * NU + c - NX] * scale_of(p, b, k + 1, c - NX, sc);
     }
   }
   if (lane == 0) {
-    ws.sf[s] = (float)scale_of(p, b, k, 0, sc);
+    ws.sf[s] = scale_of(p, b, k, 0, sc);
     if (k == 0) ws.tsc[b] = sc ? p.tau_max[b] : 1.f;
   }
   if (bf16) {
@@ -71,76 +103,74 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
   __syncthreads();
 
   // H_k^{-1} = diag(Q, R S^2) + rho I + [has_next] rho Abar_{k+1}^T Abar_{k+1},
-  // with Abar_{k+1} = [[A, Bt], [0, I]]: lane c < 25 forms its column c
+  // with Abar_{k+1} = [[A, Bt], [0, I]]: lane c < 25 forms its column c,
+  // lanes 25..49 hold the identity's columns
   {
-    double col[NL];
+    float col[NL];
     if (lane < NL) {
-      double top[NX];
+      float top[NX];
 #pragma unroll
-      for (int i = 0; i < NX; ++i) top[i] = has_next ? sTop[i * NL + lane] : 0.0;
-      double dg;
+      for (int i = 0; i < NX; ++i) top[i] = has_next ? sTop[i * NL + lane] : 0.f;
+      float dg;
       if (lane < NX) {
-        dg = (double)p.Q[(size_t)b * NX + lane];
+        dg = p.Q[(size_t)b * NX + lane];
       } else {
-        const double sj = scale_of(p, b, k, lane - NX, sc);
-        dg = (double)p.R[(size_t)b * NU + lane - NX] * sj * sj;
+        const float sj = scale_of(p, b, k, lane - NX, sc);
+        dg = p.R[(size_t)b * NU + lane - NX] * sj * sj;
       }
 #pragma unroll
       for (int r = 0; r < NL; ++r) {
-        double g = 0.0;
+        float g = 0.f;
         if (has_next) {
 #pragma unroll
-          for (int i = 0; i < NX; ++i) g += sTop[i * NL + r] * top[i];
-          if (r >= NX && r == lane) g += 1.0;
+          for (int i = 0; i < NX; ++i) g = fmaf(sTop[i * NL + r], top[i], g);
+          if (r >= NX && r == lane) g += 1.f;
         }
-        col[r] = rho * g + ((r == lane) ? dg + rho : 0.0);
+        col[r] = rho * g + ((r == lane) ? dg + rho : 0.f);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < NL; ++r) col[r] = (r == lane - NL) ? 1.0 : 0.0;
+      for (int r = 0; r < NL; ++r) col[r] = (r == lane - NL) ? 1.f : 0.f;
     }
-    gj_columns<NL>(col);
+    gj_columns_f<NL>(col);
     if (lane >= NL && lane < 2 * NL) {
       const int c = lane - NL;
 #pragma unroll
       for (int r = 0; r < NL; ++r) {
         if (r <= c) {
-          const float v = (float)col[r];
+          const float v = col[r];
           ws.Hp[(size_t)s * NH + pk(r, c, NL)] = v;
           if (bf16) ws.Hbf[(size_t)s * NH + pk(r, c, NL)] = to_bf16(v);
         }
       }
     }
   }
-  // M_k = (Bt^T Bt + I)^{-1}: Gauss-Jordan on [Bt^T Bt + I | I] with lane
-  // 16 R + c holding column c of the matrix (c < 12, the same in every row R)
-  // or identity column 4 R + c - 12; pivot columns by DPP row broadcast
+  // M_k = (Bt^T Bt + I)^{-1}: lane c < 12 forms column c of Bt^T Bt + I,
+  // lanes 12..23 hold the identity's columns
   {
-    static_assert(NU == 12, "row elimination is written for 12 inputs");
-    const int hc = lane & 15, rhs = 4 * (lane >> 4) + hc - NU;
-    double col[NU];
-    if (hc < NU) {
-      double bc[NX];
+    float col[NU];
+    if (lane < NU) {
+      float bc[NX];
 #pragma unroll
-      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * NU + hc];
+      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * NU + lane];
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
-        double g = (r == hc) ? 1.0 : 0.0;
+        float g = 0.f;
 #pragma unroll
-        for (int i = 0; i < NX; ++i) g += sBt[i * NU + r] * bc[i];
-        col[r] = g;
+        for (int i = 0; i < NX; ++i) g = fmaf(sBt[i * NU + r], bc[i], g);
+        col[r] = g + ((r == lane) ? 1.f : 0.f);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < NU; ++r) col[r] = (r == rhs) ? 1.0 : 0.0;
+      for (int r = 0; r < NU; ++r) col[r] = (r == lane - NU) ? 1.f : 0.f;
     }
-    gj_rows(col);
-    if (hc >= NU && rhs < NU) {
-      const int c = rhs;
+    gj_columns_f<NU>(col);
+    if (lane >= NU && lane < 2 * NU) {
+      const int c = lane - NU;
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
         if (r <= c) {
-          const float v = (float)col[r];
+          const float v = col[r];
           ws.Mp[(size_t)s * NM + pk(r, c, NU)] = v;
           if (bf16) ws.Mbf[(size_t)s * NM + pk(r, c, NU)] = to_bf16(v);
         }
@@ -148,15 +178,15 @@ __global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, floa
     }
   }
   if (lane < NL) {
-    double q;
+    float q;
     if (lane < NX) {
-      q = (double)p.Q[(size_t)b * NX + lane] * (double)p.x_ref[(size_t)s * NX + lane];
+      q = p.Q[(size_t)b * NX + lane] * p.x_ref[(size_t)s * NX + lane];
     } else {
       const int j = lane - NX;
-      const double ur = p.u_ref ? (double)p.u_ref[(size_t)s * NU + j] : 0.0;
-      q = (double)p.R[(size_t)b * NU + j] * scale_of(p, b, k, j, sc) * ur;
+      const float ur = p.u_ref ? p.u_ref[(size_t)s * NU + j] : 0.f;
+      q = p.R[(size_t)b * NU + j] * scale_of(p, b, k, j, sc) * ur;
     }
-    ws.qb[(size_t)s * NL + lane] = (float)q;
+    ws.qb[(size_t)s * NL + lane] = q;
   }
 }
 

@@ -1,29 +1,37 @@
-"""Host logic of the schedule autotuner: the candidate set it measures."""
-import itertools
-
+"""Host logic of the schedule autotuner: the candidate sets it measures."""
 from paper_2606_05687_amd import autotune
 
 
-def test_candidate_grid_short_horizons():
-    cands = list(autotune.candidates(20))
-    assert len(cands) == 5 * 2 * 3 * 3
+def test_first_stage_grid_short_horizons():
+    cands = list(autotune.stage_a(20))
+    assert len(cands) == 4 * 9
     assert {c["form"] for c in cands} == {1}              # fused form up to 40 stages
-    assert {c["iters"] for c in cands} == {3, 5, 10, 20, 50}
-    assert {c["rho"] for c in cands} == {10.0, 30.0}
-    assert {c["refine_passes"] for c in cands} == {8, 12, 16}
-    assert {c["first_passes"] for c in cands} == {0, 2, 4}
+    assert {c["iters"] for c in cands} == {1, 2, 3, 5, 10, 20, 50, 100, 200}
+    assert {c["rho"] for c in cands} == {1.0, 3.0, 10.0, 30.0}
+    assert {c["refine_passes"] for c in cands} == {12}
+    assert {c["first_passes"] for c in cands} == {0}
     assert {c["precision"] for c in cands} == {0}
-    # every combination exactly once
     keys = {tuple(sorted(c.items())) for c in cands}
     assert len(keys) == len(cands)
-    # at least three ADMM sweeps before the refinement
-    assert min(c["iters"] for c in cands) >= 3
+    # a single ADMM sweep is a candidate: the refinement may not need more
+    assert min(c["iters"] for c in cands) == 1
 
 
-def test_candidate_grid_long_horizons_and_bf16():
-    cands = list(autotune.candidates(60, allow_bf16=True))
+def test_second_stage_varies_only_the_refinement_budget():
+    best = dict(form=1, iters=3, rho=10.0, refine_passes=12, first_passes=0, precision=0)
+    cands = list(autotune.stage_b(best))
+    assert len(cands) == 3 * 3 - 1                      # the base point is not re-measured
+    for c in cands:
+        assert {k: c[k] for k in ("form", "iters", "rho", "precision")} == \
+            {k: best[k] for k in ("form", "iters", "rho", "precision")}
+    assert {(c["refine_passes"], c["first_passes"]) for c in cands} | {(12, 0)} == \
+        {(a, b) for a in (8, 12, 16) for b in (0, 2, 4)}
+
+
+def test_long_horizons_and_bf16():
+    cands = list(autotune.stage_a(60, allow_bf16=True))
     assert {c["form"] for c in cands} == {-1}             # packed by horizon class beyond 40
     assert {c["precision"] for c in cands} == {0, 1}
-    assert len(cands) == 2 * 5 * 2 * 3 * 3
-    for a, b in itertools.combinations(cands[:6], 2):
-        assert a != b
+    assert len(cands) == 2 * 4 * 9
+    full = list(autotune.candidates(60, allow_bf16=True))
+    assert len({tuple(sorted(c.items())) for c in full}) == len(full)

@@ -124,3 +124,64 @@ def test_overlapping_warm_slots_rejected_while_in_flight():
     assert (obig["status"].cpu().numpy() == 0).all()
     for o in osm:
         assert (o["status"].cpu().numpy() == 0).all()
+
+
+def test_warm_state_export_import_resumes_bitwise():
+    """Checkpoint and resume of warm slots through the C ABI: a server that
+    imports another server's exported warm state continues exactly as the
+    exporter does (the next tick's results are bitwise equal); malformed
+    ranges and images are refused; an export while a request on those slots
+    is in flight is refused with PINMPC_EBUSY."""
+    import ctypes
+    from paper_2606_05687_amd import binding
+    reqs = _requests(2, 32, seed_offset=60)
+    devs = [binding.to_device(r) for r in reqs]
+
+    def tick(srv):
+        o = [binding.Solver.alloc_out(None, d) for d in devs]
+        t = [srv.submit(d, oo, warm_base=32 * i) for i, (d, oo) in enumerate(zip(devs, o))]
+        for tt in t:
+            srv.wait(tt)
+        return [{k: v.cpu().numpy() for k, v in oo.items()} for oo in o]
+
+    a = binding.Server(0, lanes=2, capacity=128, warm_slots=64)
+    tick(a)
+    image = a.export_state(0, 64)
+    assert len(image) == binding.warm_image_bytes(64) and image[:4] == b"PMWS"
+    next_a = tick(a)
+    b = binding.Server(0, lanes=1, capacity=128, warm_slots=64)
+    cold_b = tick(b)                      # b's slots now hold b's own state
+    b.import_state(0, 64, image)
+    next_b = tick(b)
+    for i in range(2):
+        for k in next_a[i]:
+            assert np.array_equal(next_a[i][k], next_b[i][k]), (i, k)
+        assert (next_b[i]["status"] == 0).all()
+    # the import really replaced b's state: without it the iterates differ
+    assert any(not np.array_equal(cold_b[i]["iters"], next_a[i]["iters"]) or
+               not np.array_equal(cold_b[i]["u"], next_a[i]["u"]) for i in range(2))
+    lib = binding.load()
+    buf = ctypes.create_string_buffer(binding.warm_image_bytes(64))
+    assert lib.pinmpc_server_export_state(a._h, 60, 8, buf, len(buf)) == -1    # past the slots
+    assert lib.pinmpc_server_export_state(a._h, 0, 64, buf, 100) == -1        # short buffer
+    bad = bytearray(image)
+    bad[0:4] = b"XXXX"
+    with pytest.raises(binding.PinmpcError):
+        b.import_state(0, 64, bytes(bad))
+    bad = bytearray(image)
+    bad[8:12] = (63).to_bytes(4, "little")                                    # wrong count
+    with pytest.raises(binding.PinmpcError):
+        b.import_state(0, 64, bytes(bad))
+    # a request in flight on slots 0..2047 blocks their export
+    big = binding.to_device(mpcgen.make_batch("uneven_b16384", indices=range(2048), n_max=60))
+    c = binding.Server(0, lanes=1, capacity=2048, warm_slots=2048)
+    ob = binding.Solver.alloc_out(None, big)
+    t = c.submit(big, ob, warm_base=0)
+    buf2 = ctypes.create_string_buffer(binding.warm_image_bytes(16))
+    rc = lib.pinmpc_server_export_state(c._h, 100, 16, buf2, len(buf2))
+    done = c.poll(t) is not None
+    assert rc == binding.E_BUSY or (rc == 0 and done), rc
+    c.wait(t) if not done else None
+    assert lib.pinmpc_server_export_state(c._h, 100, 16, buf2, len(buf2)) == 0
+    for s in (a, b, c):
+        s.close()

@@ -75,3 +75,25 @@ def test_noalloc_constants_match_header_and_null_calls_rejected():
     lib = binding.load()
     assert lib.pinmpc_solve_noalloc(None, None, None, None) == -1
     assert b"static scratch" in lib.pinmpc_strerror(binding.E_TOOBIG)
+
+
+def test_boundary_calls_reject_null_arguments():
+    lib = binding.load()
+    assert lib.pinmpc_build_dynamics(None, None, None, None, None) == -1
+    assert lib.pinmpc_server_export_state(None, 0, 1, None, 0) == -1
+    assert lib.pinmpc_server_import_state(None, 0, 1, None, 0) == -1
+    assert lib.pinmpc_stats_traffic(None, None, None) == -1
+    text = open(os.path.join(ROOT, "include", "pinmpc.h")).read()
+    assert int(re.search(r"#define PINMPC_NMAX (\d+)", text).group(1)) == binding.NMAX
+    assert binding.WARM_SLOT_BYTES == binding.NMAX * 5 * 25 * 4
+    assert ctypes.sizeof(binding.Physics) == 16 + 7 * 8
+
+
+def test_landmark_struct_and_null_store_rejected():
+    lib = binding.load()
+    assert ctypes.sizeof(binding.Landmarks) == 16 + 2 * 8
+    assert lib.pinmpc_landmarks_clear(None, None, None) == -1
+    assert lib.pinmpc_landmarks_push(None, 10, None, None, 0, None) == -1
+    assert lib.pinmpc_landmark_reward(None, None, 0, None, None, 1.0, None, None, None) == -1
+    empty = binding.Landmarks(0, 5, 11, 1, None, None)
+    assert lib.pinmpc_landmarks_clear(ctypes.byref(empty), None, None) == 0

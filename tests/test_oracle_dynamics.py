@@ -94,3 +94,60 @@ def test_agrees_with_generator_construction(config):
                                          batch["mass"][b], batch["inertia"][b], batch["dt"][b], N)
         assert np.allclose(A, batch["A"][b], rtol=0, atol=1e-13)
         assert np.allclose(B, batch["B"][b], rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------- the paper's momentum model
+
+@pytest.mark.parametrize("seed", range(6))
+def test_momentum_model_equations(seed):
+    """A x + B u + e reproduces the three discrete updates of Sec. II-A written
+    out directly, and the inert slots 9..12 keep their values."""
+    rng = np.random.default_rng([13, seed])
+    _, c_ref, feet, m, _, dt = _random_stage(rng)
+    A, B, e = dynamics.momentum_stage_matrices(c_ref, feet, m, dt)
+    x = rng.normal(0, 1, 13)
+    u = rng.normal(0, 50, 12)
+    x1 = A @ x + B @ u + e
+    c, l, kg = x[0:3], x[3:6], x[6:9]
+    f = [u[0:3], u[6:9]]
+    tau = [u[3:6], u[9:12]]
+    assert np.allclose(x1[0:3], c + dt * l / m, atol=1e-12)
+    assert np.allclose(x1[3:6], l + dt * (m * np.array([0, 0, -G]) + f[0] + f[1]), atol=1e-9)
+    kk = kg + dt * sum(np.cross(feet[i] - c_ref, f[i]) + tau[i] for i in range(2))
+    assert np.allclose(x1[6:9], kk, atol=1e-9)
+    assert np.array_equal(x1[9:13], x[9:13])
+    # gravity only through the affine term: e = (0, dt m g, 0, inert zeros)
+    assert np.allclose(e, np.r_[0, 0, 0, 0, 0, -dt * m * G, np.zeros(7)], atol=1e-12)
+
+
+def test_momentum_model_agrees_with_generator_construction():
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=range(4), as_float32=False,
+                              model="momentum")
+    for b in range(4):
+        N = int(batch["N"][b])
+        A, B, e = dynamics.momentum_horizon_matrices(batch["c_ref"][b], batch["feet"][b],
+                                                     batch["mass"][b], batch["dt"][b], N)
+        assert np.allclose(A, batch["A"][b], rtol=0, atol=1e-13)
+        assert np.allclose(B, batch["B"][b], rtol=0, atol=1e-13)
+        assert np.allclose(e, batch["e"][b], rtol=0, atol=1e-12)
+
+
+def test_momentum_embedding_leaves_the_optimum_unchanged():
+    """The inert slots start at zero, are never driven and have zero reference:
+    the optimum does not depend on their weights (so it is the optimum of the
+    9-state problem), they stay zero, and the result is certified."""
+    from oracle import kkt, qp
+    batch = mpcgen.make_batch("plain_b4096_n20", indices=[0, 1], model="momentum")
+    for b in range(2):
+        p = mpcgen.problem_fp64(batch, b)
+        ref = qp.solve(p)
+        assert np.all(ref["x"][:, 9:13] == 0)
+        p2 = dict(p)
+        p2["Q"] = p["Q"].copy()
+        p2["Q"][9:13] = 123.0
+        alt = qp.solve(p2)
+        assert np.allclose(alt["u"], ref["u"], rtol=0, atol=1e-9 * np.abs(ref["u"]).max())
+        assert kkt.residuals(p, ref["u"], ref["x"])["kkt"] <= 1e-9
+        # gravity is carried: the optimum supports the weight on average
+        fz = ref["u"][:, [2, 8]].sum(axis=1)
+        assert abs(fz.mean() - p["weight"]) < 0.5 * p["weight"]

@@ -14,7 +14,10 @@ that zero e_k, u_ref and u_prev could not reveal:
 
 and, in the stage matrices built from compact physics (Sec. II-A), the
 world-frame inertia rotated the wrong way, the lever-arm cross product
-reversed, and the angle rates taken through R_z instead of R_z^T.
+reversed, and the angle rates taken through R_z instead of R_z^T; in the
+landmark reward (Sec. II-C), the landmark offsets without their leading 1, the
+confidence weights dropped, and the target tick counted in MPC steps instead
+of ticks.
 """
 import os
 import shutil
@@ -54,6 +57,18 @@ MUTANTS = [
      "d[0:3] = Rz.T @ omega",
      "d[0:3] = Rz @ omega",
      "tests/test_oracle_dynamics.py"),
+    ("lm-offset-base", "oracle/landmarks.py",
+     "return [1 + math.floor(Fraction(l, n_landmarks - 1) * (N - 1)) for l in range(n_landmarks)]",
+     "return [math.floor(Fraction(l, n_landmarks - 1) * (N - 1)) for l in range(n_landmarks)]",
+     "tests/test_oracle_landmarks.py"),
+    ("lm-alpha-dropped", "oracle/landmarks.py",
+     "total += alpha[l] * float(e @ (np.asarray(qc, dtype=np.float64) * e)) / sigma ** 2",
+     "total += float(e @ (np.asarray(qc, dtype=np.float64) * e)) / sigma ** 2",
+     "tests/test_oracle_landmarks.py"),
+    ("lm-target-in-steps", "oracle/landmarks.py",
+     "self.table[(env, step + n * self.d, l)]",
+     "self.table[(env, step + n, l)]",
+     "tests/test_oracle_landmarks.py"),
 ]
 
 
