@@ -54,6 +54,10 @@ REFINE_DENSE_BACKWARD = 3744 + 312 + 4394 + 338 + 4056 + 3744 + 4368 + 3744 + 59
 REFINE_DENSE_FORWARD = 1250 + 650 + 500
 # setup, once per stage: operators read, H, M, qbar and the scaled B written
 SETUP_BYTES_PER_STAGE = 3_200
+# interior-point cap, polish passes and certificate threshold for horizons
+# beyond 64 stages (the multiplier-sign residual is normalised by terms that
+# grow with the costates over a long horizon)
+LONG_BASE = dict(ipm_iters=150, polish_passes=20, kkt_tol=1e-10)
 # FP64 peak of the chip: vector FMA units and matrix cores have the same rate
 FP64_PEAK_TFLOPS = 78.6
 
@@ -472,6 +476,15 @@ def main():
                     refine_passes=args.refine_passes, first_passes=args.first_passes,
                     precision=args.precision)
     if args.serving:
+        if args.autotune:
+            # the schedule tuned on a held-out slice of the serving workload
+            from paper_2606_05687_amd import autotune
+            held = mpcgen.make_batch("serving_tick", indices=range(32768, 32768 + 4096))
+            hdev = binding.to_device(held, "cuda:0")
+            settings.update(autotune.tune(hdev, cache_path=os.path.join(ROOT, "gpurun_out",
+                                                                        "tune.json"),
+                                          force=True, in_flight=1))
+            del hdev
         print(json.dumps(serving(args, settings)), flush=True)
         return
     tuned = None
@@ -481,14 +494,18 @@ def main():
         nb = mpcgen.CONFIGS[args.workload]["batch"]
         held = mpcgen.make_batch(args.workload, indices=range(nb, 2 * nb))
         hdev = binding.to_device(held, "cuda:0")
+        # hundreds of stages need a larger interior-point cap than the default
+        base = LONG_BASE if int(held["A"].shape[1]) > 64 else None
         tuned = autotune.tune(hdev, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
-                              force=True, in_flight=max(1, args.streams))
+                              force=True, in_flight=max(1, args.streams), base=base)
+        if tuned is None:   # no candidate certified enough: the base schedule
+            tuned = dict(base or {})
         settings.update(tuned)
         tune_curve = [{k: r[k] for k in ("iters", "rho", "ms", "certified", "eq_passes",
                                           "ipm_iters")}
                       for r in autotune.LAST_LOG
-                      if r["rho"] == tuned["rho"] and r["refine_passes"] == 12
-                      and r["first_passes"] == 0 and r["precision"] == tuned["precision"]]
+                      if r["rho"] == tuned.get("rho") and r["refine_passes"] == 12
+                      and r["first_passes"] == 0 and r["precision"] == tuned.get("precision")]
         del hdev
     batch = mpcgen.make_batch(args.workload)
     Bn, n = batch["A"].shape[0], batch["A"].shape[1]

@@ -50,7 +50,12 @@ extern "C" {
 #define PINMPC_NU 12
 #define PINMPC_NCONTACT 2
 #define PINMPC_NRES 5      /* r_dyn, r_ineq, r_stat, r_comp, r_sign */
-#define PINMPC_NMAX 64     /* largest supported horizon */
+#define PINMPC_NMAX 64     /* largest horizon of the serving loop and of the
+                              one-workgroup-per-problem kernels */
+#define PINMPC_NMAX_LONG 512  /* largest horizon pinmpc_solve accepts: beyond
+                              PINMPC_NMAX the ADMM splits each horizon across
+                              workgroups and the refinement keeps its stage
+                              buffers in the workspace */
 
 enum {
   PINMPC_OK = 0,
@@ -91,9 +96,13 @@ typedef struct {
   double kkt_tol;          /* certification threshold; default 1e-9 */
   int32_t precision;       /* 0: FP32 operators; 1: BF16 operators */
   int32_t form;            /* 0: plain (one launch per sweep);
-                              1: fused sweep kernel (all sweeps in one launch,
-                                 horizons up to 40);
-                              -1: choose (fused when it fits) */
+                              1: fused (all sweeps in one launch: operators in
+                                 registers up to 40 stages, streamed beyond);
+                              -1: pack problems by horizon class;
+                              2: horizon split across workgroups (a chain of
+                                 stage-parallel launches per sweep).
+                              Horizons beyond PINMPC_NMAX always split.  Every
+                              form computes bitwise the same iterates. */
   int32_t graph;           /* 1: capture the whole solve as a hipGraph on first
                               use and replay it while the batch shape, buffers
                               and settings are unchanged; default 1 */
@@ -103,6 +112,10 @@ typedef struct {
                               interior point) in a second launch with the
                               other uncertified problems.  0: all passes in
                               the first launch; default 4 */
+  int32_t group;           /* problems per workgroup of the fused sweep kernel
+                              (1, 2 or 4; fewer when the horizon leaves no
+                              room: each problem takes round_up(25 N, 64)
+                              threads of at most 1024); default 1 */
 } pinmpc_settings;
 
 typedef struct pinmpc_ctx_s* pinmpc_ctx;
@@ -110,7 +123,8 @@ typedef struct pinmpc_ctx_s* pinmpc_ctx;
 /* One batch of problems (device pointers). */
 typedef struct {
   int32_t batch;           /* number of problems B (0 allowed) */
-  int32_t n_max;           /* padded horizon, 1..PINMPC_NMAX */
+  int32_t n_max;           /* padded horizon, 1..PINMPC_NMAX_LONG (the
+                              serving loop: 1..PINMPC_NMAX) */
   const int32_t* N;        /* [B] horizon per problem in 1..n_max; NULL: all n_max */
   const float* A;          /* [B][n_max][13][13] */
   const float* Bu;         /* [B][n_max][13][12] */
@@ -170,7 +184,7 @@ int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
 int pinmpc_set_settings(pinmpc_ctx c, const pinmpc_settings* s);
 
 /* Bytes of workspace a solve of this shape needs (host call, no GPU work;
- * PINMPC_EINVAL for a shape outside 0 <= batch, 1 <= n_max <= PINMPC_NMAX). */
+ * PINMPC_EINVAL for a shape outside 0 <= batch, 1 <= n_max <= PINMPC_NMAX_LONG). */
 int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_max,
                            size_t* bytes);
 
@@ -276,7 +290,7 @@ const char* pinmpc_strerror(int code);
  * (k >= N[b]) get A = I, B = 0, e = 0.  FP32 arithmetic. */
 typedef struct {
   int32_t batch;           /* B (0 allowed) */
-  int32_t n_max;           /* padded horizon, 1..PINMPC_NMAX */
+  int32_t n_max;           /* padded horizon, 1..PINMPC_NMAX_LONG */
   int32_t model;           /* 0: 13-state single rigid body; 1: 9-state momentum */
   const int32_t* N;        /* [B] horizon per problem; NULL: all n_max */
   const float* yaw;        /* [B][n_max] yaw psi_k of the linearisation */

@@ -50,6 +50,9 @@ CONFIGS = {
     "precision_b16384_n30": dict(batch=16384, horizons=(30,), dt=0.03,
                                  duty=0.6, mu=(0.3, 0.9), push=0.5,
                                  payload=0.0, seed=4),
+    # long single horizons at small batch (horizon split across workgroups)
+    "long_b64_n400": dict(batch=64, horizons=(100, 200, 400), dt=0.03, duty=0.6,
+                          mu=(0.3, 0.9), push=0.5, payload=0.0, seed=6),
     "serving_tick": dict(batch=32768, horizons=tuple(range(10, 61)), dt=0.03,
                          duty=None, mu=(0.3, 0.9), push=0.5, payload=10.0,
                          seed=5),

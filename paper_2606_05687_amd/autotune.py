@@ -3,9 +3,10 @@
 Chooses, by measurement on a sample of the workload, the number of ADMM
 sweeps K (from one to 200: more sweeps cost sweep time but may give the FP64
 refinement a better active set and fewer passes), the penalty rho (1 to 30),
-the operator precision, then, at the best of those, the active-set pass budget
-and how many of those passes run for every problem before the uncertified
-ones are handed to the second refinement launch.  The sweep form follows the
+the operator precision, then, at the best of those, the active-set pass budget,
+how many of those passes run for every problem before the uncertified ones are
+handed to the second refinement launch, and how many problems share one
+workgroup of the fused sweep (1, 2 or 4 where they fit).  The sweep form follows the
 horizon (fused up to 40 stages, packed by horizon class beyond).  Every
 candidate's mean refinement work is logged beside its time, which gives the
 refinement-passes-versus-K curve of the workload.  The score
@@ -45,7 +46,17 @@ RHOS = (1.0, 3.0, 10.0, 30.0)
 ITERS = (1, 2, 3, 5, 10, 20, 50, 100, 200)
 PASSES = (8, 12, 16)
 FIRSTS = (0, 2, 4)
+GROUPS = (1, 2, 4)
 BASE_PASSES, BASE_FIRST = 12, 0
+
+
+def groups_for(n_max):
+    """Problems per workgroup of the fused sweep that fit one workgroup of at
+    most 1024 threads (round_up(25 N, 64) threads per problem); the packed
+    form (beyond 40 stages) packs its shortest class (20 stages) so."""
+    n = n_max if n_max <= 40 else 20
+    tpp = ((25 * n + 63) // 64) * 64
+    return tuple(g for g in GROUPS if g * tpp <= 1024)
 
 
 def form_for(n_max):
@@ -59,16 +70,17 @@ def stage_a(n_max, allow_bf16=False):
     precs = [0, 1] if allow_bf16 else [0]
     for r, k, p in itertools.product(RHOS, ITERS, precs):
         yield dict(form=form_for(n_max), iters=k, rho=r, refine_passes=BASE_PASSES,
-                   first_passes=BASE_FIRST, precision=p)
+                   first_passes=BASE_FIRST, precision=p, group=1)
 
 
-def stage_b(best):
-    """Second stage: the refinement's pass budget and launch split at the best
-    ADMM schedule of the first stage."""
-    for pa, p1 in itertools.product(PASSES, FIRSTS):
-        if (pa, p1) == (best["refine_passes"], best["first_passes"]):
+def stage_b(best, n_max=20):
+    """Second stage: the refinement's pass budget and launch split, and the
+    problems per workgroup of the fused sweep, at the best ADMM schedule of the
+    first stage."""
+    for pa, p1, g in itertools.product(PASSES, FIRSTS, groups_for(n_max)):
+        if (pa, p1, g) == (best["refine_passes"], best["first_passes"], best["group"]):
             continue
-        yield dict(best, refine_passes=pa, first_passes=p1)
+        yield dict(best, refine_passes=pa, first_passes=p1, group=g)
 
 
 def candidates(n_max, allow_bf16=False):
@@ -76,7 +88,7 @@ def candidates(n_max, allow_bf16=False):
     winners); the search itself measures stage_a, then stage_b of its best."""
     seen = set()
     for a in stage_a(n_max, allow_bf16):
-        for c in [a, *stage_b(a)]:
+        for c in [a, *stage_b(a, n_max)]:
             key = tuple(sorted(c.items()))
             if key not in seen:
                 seen.add(key)
@@ -107,11 +119,15 @@ def measure(solvers, streams, dev, outs, bs, settings, reps=4, kkt_bar=1e-5):
 
 
 def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, verbose=False,
-         force=False, in_flight=1):
+         force=False, in_flight=1, base=None):
     """Best settings (dict) for batches shaped like ``dev``, measured with
-    `in_flight` solves on as many streams; cached."""
+    `in_flight` solves on as many streams, every candidate on top of the
+    settings in ``base`` (for example a larger interior-point cap for long
+    horizons); cached."""
     import torch
     key = _key(dev, allow_bf16) + f"|inflight{int(in_flight)}"
+    if base:
+        key += "|" + ",".join(f"{k}={v}" for k, v in sorted(base.items()))
     cache = {}
     if os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -121,7 +137,7 @@ def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, v
         LAST_LOG = cache[key].get("log", [])
         return cache[key]["settings"]
     n = max(1, int(in_flight))
-    solvers = [binding.Solver(0) for _ in range(n)]
+    solvers = [binding.Solver(0, **(base or {})) for _ in range(n)]
     outs = [sv.alloc_out(dev) for sv in solvers]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n - 1)]
     bs = binding.make_batch_struct(dev)
@@ -143,10 +159,12 @@ def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, v
 
     run(stage_a(int(dev["A"].shape[1]), allow_bf16))
     if best is not None:
-        run(list(stage_b(best)))
+        run(list(stage_b(best, int(dev["A"].shape[1]))))
     for sv in solvers:
         sv.close()
     LAST_LOG = log
+    if best is not None and base:
+        best = dict(base, **best)
     cache[key] = {"settings": best, "score": best_score, "log": log}
     os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
     with open(cache_path, "w") as f:

@@ -37,6 +37,7 @@ class Settings(ctypes.Structure):
         ("form", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("first_passes", ctypes.c_int32),
+        ("group", ctypes.c_int32),
     ]
 
 
@@ -152,6 +153,7 @@ _lib = None
 
 STATS_RING = 64   # PINMPC_STATS_RING
 NMAX = 64         # PINMPC_NMAX
+NMAX_LONG = 512   # PINMPC_NMAX_LONG
 WARM_SLOT_BYTES = NMAX * 5 * 25 * 4   # PINMPC_WARM_SLOT_BYTES
 E_BUSY = -5       # PINMPC_EBUSY
 

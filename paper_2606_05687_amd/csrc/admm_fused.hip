@@ -2,7 +2,9 @@
 // problem in one launch, with every thread's share of the stage operators
 // loaded once into registers and kept there across the sweeps.
 //
-// A workgroup owns one problem; thread (k, r) owns lifted row r of stage k:
+// A workgroup owns PPW problems (one, or two or four short ones packed into one
+// workgroup), each with its own group of threads and LDS buffers; thread
+// (k, r) of a problem's group owns lifted row r of stage k:
 //   r < 13 : row r of H_k, row r and column r of A_k, row r of Bt_k
 //   r >= 13: row r of H_k, column j = r-13 of Bt_k, row j of M_k
 // which is exactly what its share of the stage products needs:
@@ -24,7 +26,12 @@ namespace {
 
 constexpr int V25 = 25;
 
-template <int MAXT, bool BF16>
+// LDS floats of one problem for a capacity of n stages.
+__host__ __device__ inline size_t fused_lds_floats(int n) {
+  return (size_t)(5 * n * V25 + 4 * n * NU + 32);
+}
+
+template <int MAXT, bool BF16, int PPW>
 __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace ws, float rho,
                                                           int accel, float eta, int iters,
                                                           const int32_t* order,
@@ -36,14 +43,26 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
     op.A = p.A; op.Bt = ws.Bt; op.H = ws.Hp; op.M = ws.Mp;
   }
   extern __shared__ float lds[];
-  if (count && (int)blockIdx.x >= *count) return;
-  const int b = order ? order[blockIdx.x] : (int)blockIdx.x;
+  const int slots = count ? *count : p.batch;   // problems this launch walks
+  if ((int)blockIdx.x * PPW >= slots) return;   // the whole workgroup: uniform
+  // this thread's problem slot in the workgroup, and its index in that group
+  const int tpp = PPW == 1 ? (int)blockDim.x : (int)blockDim.x / PPW;
+  const int sub = PPW == 1 ? 0 : (int)threadIdx.x / tpp;
+  const int slot = (int)blockIdx.x * PPW + sub;
   const int n = p.n_max;          // stage stride of the global arrays
-  const int N = horizon(p, b);
   const int ln = lds_n;           // stage capacity of the LDS buffers
-  if (N > ln) return;             // never for a valid packing: keeps LDS in bounds
-  // LDS: per stage vectors
-  float* W = lds;                 // w = vhat - betahat; restart terms [N][25]
+  // a slot past the end, or a horizon beyond the LDS capacity (never for a
+  // valid packing), leaves its group idle: it still takes part in the barriers
+  bool live = slot < slots;
+  const int b = live ? (order ? order[slot] : slot) : 0;
+  int N = live ? horizon(p, b) : 0;
+  if constexpr (PPW == 1) {
+    if (N > ln || N == 0) return;   // the whole (one-problem) workgroup
+  }
+  if (N > ln) N = 0;
+  live = live && N > 0;
+  // LDS: per stage vectors of this group's problem
+  float* W = lds + (size_t)sub * (fused_lds_floats(ln));   // w = vhat - betahat; restart terms [N][25]
   float* Y = W + ln * V25;        // y = zhat - vhat - e + lamhat [N][25]
   float* ATY = Y + ln * V25;      // Abar^T y                     [N][25]
   float* HT = ATY + ln * V25;     // htilde                       [N][25]
@@ -54,17 +73,17 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
   float* PO = PIN + ln * NU;      // projection output            [N][12]
   float* XI0 = PO + ln * NU;      // [32]
 
-  const int tid = threadIdx.x;
+  const int tid = PPW == 1 ? (int)threadIdx.x : (int)threadIdx.x - sub * tpp;
   const bool act = tid < N * NL;
   const int k = act ? tid / NL : 0;
   const int r = act ? tid % NL : 0;
   const size_t s0 = (size_t)b * n;
   const size_t st = s0 + k;
-  const float mu = p.mu[b];
-  const float tmax = p.tau_max[b];
-  const float tsc = ws.tsc[b];
+  const float mu = live ? p.mu[b] : 0.f;
+  const float tmax = live ? p.tau_max[b] : 0.f;
+  const float tsc = live ? ws.tsc[b] : 1.f;
 
-  if (tid < NL) {
+  if (live && tid < NL) {
     float v;
     if (tid < NX) v = p.x0[(size_t)b * NX + tid];
     else v = p.u_prev ? p.u_prev[(size_t)b * NU + tid - NX] /
@@ -102,9 +121,9 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
     zc = ws.cur[base]; vc = ws.cur[base + NL]; tc = ws.cur[base + 2 * NL];
     bc = ws.cur[base + 3 * NL]; lc = ws.cur[base + 4 * NL];
   }
-  float alpha = ws.alpha[b], cprev = ws.cprev[b];
+  float alpha = live ? ws.alpha[b] : 1.f, cprev = live ? ws.cprev[b] : 0.f;
   int restarts = 0;
-  const float Fz = p.fz_max[b];
+  const float Fz = live ? p.fz_max[b] : 0.f;
   __syncthreads();
 
   for (int it = 0; it < iters; ++it) {
@@ -202,7 +221,7 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
       }
     }
     if (accel) {
-      const float cm = stage_ordered_sum(W, T1, N);
+      const float cm = stage_ordered_sum(W, T1, N, tid);
       if (cm < eta * cprev) {
         const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * alpha * alpha));
         const float f = (alpha - 1.f) / an;
@@ -231,7 +250,7 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
       ws.cur[base + 3 * NL] = bc; ws.cur[base + 4 * NL] = lc;
     }
   }
-  if (tid == 0) {
+  if (live && tid == 0) {
     ws.alpha[b] = alpha;
     ws.cprev[b] = cprev;
     ws.restarts[b] += restarts;
@@ -240,49 +259,78 @@ __global__ void __launch_bounds__(MAXT) admm_fused_kernel(Problem p, Workspace w
 
 }  // namespace
 
-// LDS of one workgroup for a capacity of n stages: five 25-vectors and four
+// LDS of one problem for a capacity of n stages: five 25-vectors and four
 // 12-vectors per stage, then the fixed initial lifted state (32 floats).
-size_t fused_lds_bytes(int n) {
-  return (size_t)(5 * n * V25 + 4 * n * NU + 32) * sizeof(float);
+size_t fused_lds_bytes(int n) { return fused_lds_floats(n) * sizeof(float); }
+
+// Problems per workgroup that fit: ppw groups of round_up(25 n, 64) threads.
+static int fit_ppw(int ppw, int n) {
+  const int tpp = ((NL * n + 63) / 64) * 64;
+  while (ppw > 1 && ppw * tpp > 1024) ppw /= 2;
+  return ppw < 1 ? 1 : ppw;
 }
+
+// The instantiation for (threads, precision, problems per workgroup).
+#define PINMPC_FUSED_DISPATCH                                           \
+  if (threads <= 512) {                                                 \
+    if (!s.precision) {                                                 \
+      if (ppw == 1) PINMPC_FUSED(512, false, 1);                        \
+      else if (ppw == 2) PINMPC_FUSED(512, false, 2);                   \
+      else PINMPC_FUSED(512, false, 4);                                 \
+    } else {                                                            \
+      if (ppw == 1) PINMPC_FUSED(512, true, 1);                         \
+      else if (ppw == 2) PINMPC_FUSED(512, true, 2);                    \
+      else PINMPC_FUSED(512, true, 4);                                  \
+    }                                                                   \
+  } else {                                                              \
+    if (!s.precision) {                                                 \
+      if (ppw == 1) PINMPC_FUSED(1024, false, 1);                       \
+      else if (ppw == 2) PINMPC_FUSED(1024, false, 2);                  \
+      else PINMPC_FUSED(1024, false, 4);                                \
+    } else {                                                            \
+      if (ppw == 1) PINMPC_FUSED(1024, true, 1);                        \
+      else if (ppw == 2) PINMPC_FUSED(1024, true, 2);                   \
+      else PINMPC_FUSED(1024, true, 4);                                 \
+    }                                                                   \
+  }
 
 hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                              int iters, hipStream_t st) {
   if (p.batch == 0 || iters == 0) return hipSuccess;
   const int work = NL * p.n_max;
   if (work > 1024) return hipErrorInvalidValue;
-  const int threads = ((work + 63) / 64) * 64;
+  const int ppw = fit_ppw(s.group, p.n_max);
+  const int tpp = ((work + 63) / 64) * 64;
+  const int threads = ppw * tpp;
+  const unsigned grid = (unsigned)((p.batch + ppw - 1) / ppw);
+  const size_t lds = (size_t)ppw * fused_lds_bytes(p.n_max);
   // up to 512 threads the kernel may use 256 VGPRs (two waves per SIMD)
-#define PINMPC_FUSED(T, BF)                                                                 \
-  hipLaunchKernelGGL((admm_fused_kernel<T, BF>), dim3(p.batch), dim3(threads),                \
-                     fused_lds_bytes(p.n_max), st, p, w, s.rho, s.accel, s.restart_eta, iters, \
-                     (const int32_t*)nullptr, (const int32_t*)nullptr, p.n_max)
-  if (threads <= 512 && !s.precision) PINMPC_FUSED(512, false);
-  else if (threads <= 512) PINMPC_FUSED(512, true);
-  else if (!s.precision) PINMPC_FUSED(1024, false);
-  else PINMPC_FUSED(1024, true);
+#define PINMPC_FUSED(T, BF, G)                                                              \
+  hipLaunchKernelGGL((admm_fused_kernel<T, BF, G>), dim3(grid), dim3(threads), lds, st, p, w, \
+                     s.rho, s.accel, s.restart_eta, iters, (const int32_t*)nullptr,          \
+                     (const int32_t*)nullptr, p.n_max)
+  PINMPC_FUSED_DISPATCH
 #undef PINMPC_FUSED
   return hipGetLastError();
 }
 
 // Problems of horizon class cls, walked through the order array; the grid
-// covers the whole batch and blocks past the class count exit at once.
+// covers the whole batch and workgroups past the class count exit at once.
 hipError_t launch_admm_fused_class(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                                    int iters, int cls, hipStream_t st) {
   if (p.batch == 0 || iters == 0) return hipSuccess;
   const int cap = CLASS_N[cls] < p.n_max ? CLASS_N[cls] : p.n_max;
-  const int threads = ((NL * cap + 63) / 64) * 64;
+  const int ppw = fit_ppw(s.group, cap);
+  const int threads = ppw * (((NL * cap + 63) / 64) * 64);
+  const unsigned grid = (unsigned)((p.batch + ppw - 1) / ppw);
+  const size_t lds = (size_t)ppw * fused_lds_bytes(cap);
   const int32_t* ord = w.order + (size_t)cls * p.batch;
   const int32_t* cnt = w.counts + cls;
-#define PINMPC_FUSED_C(T, BF)                                                              \
-  hipLaunchKernelGGL((admm_fused_kernel<T, BF>), dim3(p.batch), dim3(threads),             \
-                     fused_lds_bytes(cap), st, p, w, s.rho, s.accel, s.restart_eta, iters, \
-                     ord, cnt, cap)
-  if (threads <= 512 && !s.precision) PINMPC_FUSED_C(512, false);
-  else if (threads <= 512) PINMPC_FUSED_C(512, true);
-  else if (!s.precision) PINMPC_FUSED_C(1024, false);
-  else PINMPC_FUSED_C(1024, true);
-#undef PINMPC_FUSED_C
+#define PINMPC_FUSED(T, BF, G)                                                                \
+  hipLaunchKernelGGL((admm_fused_kernel<T, BF, G>), dim3(grid), dim3(threads), lds, st, p, w, \
+                     s.rho, s.accel, s.restart_eta, iters, ord, cnt, cap)
+  PINMPC_FUSED_DISPATCH
+#undef PINMPC_FUSED
   return hipGetLastError();
 }
 

@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
   float f = 0.f;
   bool restart = false;
   if (accel) {
-    const float cm = stage_ordered_sum(L.b0, L.b2, N);
+    const float cm = stage_ordered_sum(L.b0, L.b2, N, threadIdx.x);
     if (cm < eta * cp) {
       const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * al * al));
       f = (al - 1.f) / an;

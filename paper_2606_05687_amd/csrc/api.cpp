@@ -26,7 +26,7 @@ static bool same_settings(const pinmpc_settings& a, const pinmpc_settings& b) {
          a.refine_passes == b.refine_passes && a.ipm_iters == b.ipm_iters &&
          a.polish_passes == b.polish_passes && a.kkt_tol == b.kkt_tol &&
          a.precision == b.precision && a.form == b.form && a.graph == b.graph &&
-         a.first_passes == b.first_passes;
+         a.first_passes == b.first_passes && a.group == b.group;
 }
 
 static bool same_key(const GraphKey& a, const GraphKey& b) {
@@ -102,6 +102,12 @@ size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.rcount = (int32_t*)take(4);
   t.rpass = (int32_t*)take(Bn * 4);
   t.work = (unsigned long long*)take(8);
+  t.sp_aty = (float*)take(S * NL * 4);
+  t.sp_du = (float*)take(S * NU * 4);
+  t.sp_xi = (float*)take(S * NL * 4);
+  t.sp_new = (float*)take(S * NSTATE * NL * 4);
+  t.sp_ct = (float*)take(S * 4);
+  t.sp_dec = (float*)take(Bn * 2 * 4);
   t.bytes = off;
   t.warm_idx = nullptr;
   t.warm_store = nullptr;
@@ -119,9 +125,10 @@ int check_settings(const pinmpc_settings* s) {
     return PINMPC_EINVAL;
   if (!(s->kkt_tol > 0.0)) return PINMPC_EINVAL;
   if (s->precision < 0 || s->precision > 1) return PINMPC_EINVAL;
-  if (s->form < -1 || s->form > 1) return PINMPC_EINVAL;
+  if (s->form < -1 || s->form > 2) return PINMPC_EINVAL;
   if (s->graph < 0 || s->graph > 1) return PINMPC_EINVAL;
   if (s->first_passes < 0) return PINMPC_EINVAL;
+  if (s->group != 1 && s->group != 2 && s->group != 4) return PINMPC_EINVAL;
   // a refinement needs at least one pass or interior-point iteration: the
   // outputs are the last pass's solution
   if (s->refine && s->refine_passes == 0 && s->ipm_iters == 0) return PINMPC_EINVAL;
@@ -130,7 +137,7 @@ int check_settings(const pinmpc_settings* s) {
 
 int check_batch(const pinmpc_batch* in) {
   if (!in) return PINMPC_EINVAL;
-  if (in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX) return PINMPC_EINVAL;
+  if (in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX_LONG) return PINMPC_EINVAL;
   if (in->batch == 0) return PINMPC_OK;
   if (!in->A || !in->Bu || !in->x0 || !in->x_ref || !in->Q || !in->R || !in->contact ||
       !in->mu || !in->fz_max || !in->tau_max)
@@ -171,7 +178,10 @@ static bool fits_fused(int n_max) { return NL * n_max <= 1024; }
 int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
                       hipStream_t st) {
   if (iters <= 0) return PINMPC_OK;
-  if (s.form == -1 && p.n_max > CLASS_N[0]) {
+  if (s.form == 2 || p.n_max > PINMPC_NMAX) {
+    // the horizon split across workgroups: every horizon up to PINMPC_NMAX_LONG
+    if (launch_admm_split(p, w, s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
+  } else if (s.form == -1 && p.n_max > CLASS_N[0]) {
     // pack problems by horizon class: fused kernels sized for each class,
     // the persistent streaming kernel for the longest horizons
     if (launch_classify(p, w, st) != hipSuccess) return PINMPC_EDEVICE;
@@ -251,6 +261,7 @@ void pinmpc_default_settings(pinmpc_settings* s) {
   s->form = 0;
   s->graph = 1;
   s->first_passes = 4;
+  s->group = 1;
 }
 
 int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
@@ -289,7 +300,7 @@ int pinmpc_set_settings(pinmpc_ctx c, const pinmpc_settings* s) {
 
 int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_max,
                            size_t* bytes) {
-  if (!bytes || batch < 0 || n_max < 1 || n_max > PINMPC_NMAX) return PINMPC_EINVAL;
+  if (!bytes || batch < 0 || n_max < 1 || n_max > PINMPC_NMAX_LONG) return PINMPC_EINVAL;
   (void)s;
   *bytes = carve_workspace(nullptr, batch, n_max, nullptr);
   return PINMPC_OK;
@@ -495,7 +506,7 @@ int pinmpc_stats_traffic(pinmpc_ctx c, double* bytes, double* gbytes_per_s) {
 
 int pinmpc_build_dynamics(const pinmpc_physics* in, float* A, float* Bu, float* e,
                           void* hip_stream) {
-  if (!in || in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX) return PINMPC_EINVAL;
+  if (!in || in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX_LONG) return PINMPC_EINVAL;
   if (in->model < 0 || in->model > 1) return PINMPC_EINVAL;
   if (in->batch == 0) return PINMPC_OK;
   if (!A || !Bu || !in->c_ref || !in->feet || !in->mass || !in->dt) return PINMPC_EINVAL;
@@ -545,7 +556,7 @@ int pinmpc_landmarks_push(const pinmpc_landmarks* in, int32_t n_max, const int32
   LandmarkStore st;
   const int rc = to_store(in, &st);
   if (rc) return rc;
-  if (n_max < 1 || n_max > PINMPC_NMAX || tick < 0) return PINMPC_EINVAL;
+  if (n_max < 1 || n_max > PINMPC_NMAX_LONG || tick < 0) return PINMPC_EINVAL;
   if ((int64_t)st.ring <= (int64_t)n_max * st.ticks_per_step) return PINMPC_EINVAL;
   if ((int64_t)tick + (int64_t)n_max * st.ticks_per_step > INT32_MAX) return PINMPC_EINVAL;
   if (st.envs > 0 && !x) return PINMPC_EINVAL;

@@ -119,6 +119,14 @@ struct Workspace {
   // refinement work of the solve: stages of every equality-constrained pass
   // and interior-point iteration, summed over problems (64-bit counter)
   unsigned long long* work;
+  // horizon split across workgroups (admm_split.hip): per-stage exchange of
+  // one sweep, the sweep's new iterates, the restart-test terms and decisions
+  float* sp_aty;    // [s][25] Abar_k^T y_k
+  float* sp_du;     // [s][12] du_k
+  float* sp_xi;     // [s][25] xi_{k+1}
+  float* sp_new;    // [s][5][25] new iterates of the sweep
+  float* sp_ct;     // [s] restart-test term of the stage
+  float* sp_dec;    // [b][2] extrapolation factor, restart flag
   size_t bytes;
   // warm start (serving): per problem slot index into a device store of
   // iterates [slot][PINMPC_NMAX][5][25]; null / negative index = cold start
@@ -133,10 +141,13 @@ struct Workspace {
 // per stage: feedforward (12), inputs (12), costates (13), gradient (12), row
 // multipliers, slacks, interior-point multipliers and their steps (5 x 22)
 // and step du (12); and states x and dx ((n+1) x 13 each).
+// Horizons beyond PINMPC_NMAX (the long-horizon path) keep two more 16-wide
+// per-stage vectors there (the costate chain's and the rollout's stage
+// buffers, which live in LDS for shorter horizons).
 constexpr int TILE = 256;
 __host__ __device__ constexpr size_t refine_block_doubles(int n) {
   return (((size_t)n * (5 * TILE + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
-           2 * (size_t)(n + 1) * NX) + 3) & ~(size_t)3;
+           2 * (size_t)(n + 1) * NX + (n > PINMPC_NMAX ? (size_t)n * 32 : 0)) + 3) & ~(size_t)3;
 }
 
 // 1/a from the hardware estimate refined by two Newton steps (the pivots of
@@ -293,11 +304,11 @@ __device__ inline void project_pyramid(T mu, T F, T yx, T yy, T yz, T* px, T* py
 // cp[k * 25 + r], in an order fixed by N alone (rows in order within a
 // stage, then stages in order), so the result does not depend on the launch
 // shape and a problem computes bitwise the same alone or inside any batch.
-// ss: N + 1 floats of LDS scratch.  Requires blockDim.x >= N; every thread
-// must call it.
-__device__ inline float stage_ordered_sum(const float* cp, float* ss, int N) {
+// ss: N + 1 floats of LDS scratch; t: the calling thread's index among the
+// problem's threads (at least N of them).  Every thread of the workgroup must
+// call it.
+__device__ inline float stage_ordered_sum(const float* cp, float* ss, int N, int t) {
   __syncthreads();
-  const int t = threadIdx.x;
   if (t < N) {
     float a = 0.f;
     for (int r = 0; r < NL; ++r) a += cp[t * NL + r];
@@ -381,8 +392,13 @@ hipError_t launch_admm_sweep(const Problem& p, const Workspace& w, const pinmpc_
                              int sweeps, hipStream_t st);
 hipError_t launch_admm_fused(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                              int iters, hipStream_t st);
+// All sweeps with the horizon split across workgroups (a chain of
+// stage-parallel launches per sweep); any horizon up to PINMPC_NMAX_LONG.
+hipError_t launch_admm_split(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             int iters, hipStream_t st);
 // Horizon-class packing: class 0 N <= 20, class 1 20 < N <= 40, class 2 N > 40.
 constexpr int CLASS_N[3] = {20, 40, PINMPC_NMAX};
+static_assert(PINMPC_NMAX_LONG >= PINMPC_NMAX, "long horizons extend the short ones");
 hipError_t launch_classify(const Problem& p, const Workspace& w, hipStream_t st);
 hipError_t launch_admm_fused_class(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                                    int iters, int cls, hipStream_t st);

@@ -46,6 +46,7 @@ struct Ctx {
   const GMEM uint8_t* contact;
   gd rT, rK, rL, rHwx, rS;   // per-stage 16 x 16 tiles (32-byte aligned)
   gd rkap, ru, rx, rlam, rg, rmu, rs, rz, rds, rdz, rdu, rdx;
+  gd rPV, rGV;   // long horizons: the stage buffers of the rollout and costates
   GMEM int32_t* faces;
 };
 
@@ -242,6 +243,30 @@ struct Sh {
   double xv[NX], xn[NX];
   double Qd[NX], Rd[NU]; // diagonal weights of the problem
 };
+
+// The per-stage 16-wide vectors of the rollout and the costate chain: in LDS
+// up to PINMPC_NMAX stages; for longer horizons (LONG) in the problem's scratch
+// block, where a hand-off between lanes needs the barrier with its memory fence
+// instead of the wave's LDS ordering.
+template <bool LONG>
+struct StageBufs;
+template <>
+struct StageBufs<false> {
+  double* PV;
+  double* GV;
+  __device__ StageBufs(Sh& sh, const Ctx&) : PV(sh.c.PV), GV(sh.c.GV) {}
+};
+template <>
+struct StageBufs<true> {
+  gd PV;
+  gd GV;
+  __device__ StageBufs(Sh&, const Ctx& C) : PV(C.rPV), GV(C.rGV) {}
+};
+template <bool LONG>
+__device__ inline void bufsync() {
+  if constexpr (LONG) gsync();
+  else wsync();
+}
 
 // ------------------------------------------------------------ 16 x 16 tiles
 //
@@ -512,7 +537,7 @@ __device__ inline double dot_row_bcast12(double v, const double (&a)[12], double
   return (s + s1) + (s2 + s3);
 }
 
-template <Mode mode, bool factor>
+template <Mode mode, bool factor, bool LONG>
 __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec, int ktop) {
   const int N = __builtin_amdgcn_readfirstlane(C.N);
   ktop = (mode == Mode::EQ) ? __builtin_amdgcn_readfirstlane(ktop < N ? ktop : N) : N;
@@ -724,6 +749,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   // costate buffers, free here) and are copied out after the loop.
   gd xout = newton ? prdx : prx;
   gd uout = newton ? prdu : pru;
+  const StageBufs<LONG> sb(sh, C);
   const int fi = lane & 15;
   const int ix = clampi(fi, NX - 1), iu = clampi(fi, NU - 1);
   const gcf pev = pe ? pe : pA;   // a valid address when there is no e
@@ -790,21 +816,22 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     const double u = newton ? (stance ? w : 0.0) : dot_row_bcast12(w, pc, cc);
     double xn = dot_row_bcast13(xv, a, ee);
     xn = dot_row_bcast12(u, b, xn);
-    if (lane < NU) sh.c.GV[k * 16 + fi] = u;
-    if (lane < NX) sh.c.PV[k * 16 + fi] = xn;
+    if (lane < NU) sb.GV[k * 16 + fi] = u;
+    if (lane < NX) sb.PV[k * 16 + fi] = xn;
     xv = xn;
   }
-  wsync();
+  bufsync<LONG>();
   if (lane < NX) xout[lane] = newton ? 0.0 : (double)uni(C.x0)[lane];
-  for (int e = lane; e < N * NU; e += W64) uout[e] = sh.c.GV[(e / NU) * 16 + e % NU];
-  for (int e = lane; e < N * NX; e += W64) xout[NX + e] = sh.c.PV[(e / NX) * 16 + e % NX];
+  for (int e = lane; e < N * NU; e += W64) uout[e] = sb.GV[(e / NU) * 16 + e % NU];
+  for (int e = lane; e < N * NX; e += W64) xout[NX + e] = sb.PV[(e / NX) * 16 + e % NX];
   gsync();
 }
 
+template <bool LONG>
 __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec, int ktop) {
-  if (mode == Mode::EQ) riccati_t<Mode::EQ, true>(C, sh, rcvec, ktop);
-  else if (factor) riccati_t<Mode::NEWTON, true>(C, sh, rcvec, ktop);
-  else riccati_t<Mode::NEWTON, false>(C, sh, rcvec, ktop);
+  if (mode == Mode::EQ) riccati_t<Mode::EQ, true, LONG>(C, sh, rcvec, ktop);
+  else if (factor) riccati_t<Mode::NEWTON, true, LONG>(C, sh, rcvec, ktop);
+  else riccati_t<Mode::NEWTON, false, LONG>(C, sh, rcvec, ktop);
 }
 
 // Costates p_{k+1} = Q (x_{k+1} - r_k) + A_{k+1}^T p_{k+2} and the reduced
@@ -820,22 +847,24 @@ __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec,
 // loads only); p and g stay in LDS until the chain is done.  Returns the
 // state-side magnitude max |Q (x_{k+1} - r_k)|, |p|, |p - Q (x_{k+1} - r_k)|
 // (= |A^T p_{k+2}|) over all stages, which the KKT scaling needs.
+template <bool LONG>
 __device__ __attribute__((noinline)) double costates_grad(const Ctx& C, Sh& sh) {
   gsync();
+  const StageBufs<LONG> sb(sh, C);
   const int lane = threadIdx.x;
   const int N = __builtin_amdgcn_readfirstlane(C.N);
   const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pur = uni(C.u_ref);
   const gd prx = uni(C.rx), pru = uni(C.ru), prlam = uni(C.rlam), prg = uni(C.rg);
   for (int e = lane; e < N * NX; e += W64) {
     const int k = e / NX, i = e % NX;
-    sh.c.PV[k * 16 + i] = C.Q[i] * (prx[(size_t)(k + 1) * NX + i] - (double)pxr[(size_t)k * NX + i]);
+    sb.PV[k * 16 + i] = C.Q[i] * (prx[(size_t)(k + 1) * NX + i] - (double)pxr[(size_t)k * NX + i]);
   }
   for (int e = lane; e < N * NU; e += W64) {
     const int k = e / NU, i = e % NU;
     const double ur = pur ? (double)pur[(size_t)k * NU + i] : 0.0;
-    sh.c.GV[k * 16 + i] = C.R[i] * (pru[(size_t)k * NU + i] - ur);
+    sb.GV[k * 16 + i] = C.R[i] * (pru[(size_t)k * NU + i] - ur);
   }
-  wsync();
+  bufsync<LONG>();
   const int i = lane & 15;
   const int ia = clampi(i, NX - 1), ib = clampi(i, NU - 1);
   struct ColRaw {
@@ -878,19 +907,19 @@ __device__ __attribute__((noinline)) double costates_grad(const Ctx& C, Sh& sh) 
       }
       pin_memory();
       cfetch(k - CD >= 0 ? k - CD : 0, ring[d]);
-      const double qx = (i < NX) ? sh.c.PV[k * 16 + i] : 0.0;
-      const double rg = (i < NU) ? sh.c.GV[k * 16 + i] : 0.0;
+      const double qx = (i < NX) ? sb.PV[k * 16 + i] : 0.0;
+      const double rg = (i < NU) ? sb.GV[k * 16 + i] : 0.0;
       p = dot_row_bcast13(p, a, qx);          // p_{k+1}
       const double gk = dot_row_bcast13(p, b, rg);
       if (i < NX) tstate = fmax(tstate, fmax(fabs(qx), fmax(fabs(p), fabs(p - qx))));
-      if (lane < NX) sh.c.PV[k * 16 + i] = p;
-      if (lane < NU) sh.c.GV[k * 16 + i] = gk;
+      if (lane < NX) sb.PV[k * 16 + i] = p;
+      if (lane < NU) sb.GV[k * 16 + i] = gk;
     }
   }
 chain_done:
-  wsync();
-  for (int e = lane; e < N * NX; e += W64) prlam[e] = sh.c.PV[(e / NX) * 16 + e % NX];
-  for (int e = lane; e < N * NU; e += W64) prg[e] = sh.c.GV[(e / NU) * 16 + e % NU];
+  bufsync<LONG>();
+  for (int e = lane; e < N * NX; e += W64) prlam[e] = sb.PV[(e / NX) * 16 + e % NX];
+  for (int e = lane; e < N * NU; e += W64) prg[e] = sb.GV[(e / NU) * 16 + e % NU];
   gsync();
   return wave_max(tstate);
 }
@@ -1148,10 +1177,11 @@ __device__ __attribute__((noinline)) void faces_from_u(const Ctx& C, gcd u_src, 
 // and factors are still in the scratch block.
 // The pass's x is the FP64 rollout of its u, so its dynamics residual is
 // rounding only: it is checked once, on the final trajectory, by the caller.
+template <bool LONG>
 __device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double res[PINMPC_NRES],
                                                    int ktop) {
-  riccati(C, sh, Mode::EQ, true, nullptr, ktop);
-  const double ts = costates_grad(C, sh);
+  riccati<LONG>(C, sh, Mode::EQ, true, nullptr, ktop);
+  const double ts = costates_grad<LONG>(C, sh);
   return multipliers_kkt(C, res, ts);
 }
 
@@ -1197,6 +1227,7 @@ struct Counts {
 // Returns the number of iterations; *certified tells whether a crossover pass
 // certified (then ru, rx, res and *kkt are that pass's), else the faces from
 // z > s are left for the polish passes.
+template <bool LONG>
 __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, double tol, Counts* cnt,
                    double res[PINMPC_NRES], double* kkt_out, bool* certified) {
   *certified = false;
@@ -1242,7 +1273,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
     rpn = wave_max(rpn);
     if (muv <= 1e-10 && rpn <= 1e-9) break;
     // predictor (affine target rc = s z)
-    riccati(C, sh, Mode::NEWTON, true, rc, C.N);
+    riccati<LONG>(C, sh, Mode::NEWTON, true, rc, C.N);
     double amax_s = 1.0, amax_z = 1.0;
     for (int e = lane; e < N * 2; e += W64) {
       const int k = e >> 1, i = e & 1;
@@ -1298,7 +1329,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
       store_r(rc, rb, cv);
     }
     // corrector: same matrix, new right-hand side
-    riccati(C, sh, Mode::NEWTON, false, rc, C.N);
+    riccati<LONG>(C, sh, Mode::NEWTON, false, rc, C.N);
     amax_s = 1.0;
     amax_z = 1.0;
     for (int e = lane; e < N * 2; e += W64) {
@@ -1382,7 +1413,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
       gsync();
       for (int e = lane; e < N * NU; e += W64) C.rdu[e] = C.ru[e];
       for (int e = lane; e < (N + 1) * NX; e += W64) C.rdx[e] = C.rx[e];
-      const double kkt = eq_pass(C, sh, res, N);
+      const double kkt = eq_pass<LONG>(C, sh, res, N);
       ++cnt->eq;
       cnt->stf += N;
       if (kkt <= tol) {
@@ -1402,6 +1433,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
 }
 
 // Active-set loop; returns true if certified.  cnt accumulates.
+template <bool LONG>
 __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, Counts* cnt,
                                 double res[PINMPC_NRES], double* kkt_out,
                                 bool* cycled = nullptr) {
@@ -1411,7 +1443,7 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, Coun
   int nh = 0;
   int ktop = C.N;   // the first pass solves the whole horizon
   for (int it = 0; it < maxp; ++it) {
-    const double kkt = eq_pass(C, sh, res, ktop);
+    const double kkt = eq_pass<LONG>(C, sh, res, ktop);
     ++cnt->eq;
     cnt->stf += ktop < C.N ? ktop : C.N;
     *kkt_out = kkt;
@@ -1471,7 +1503,7 @@ __device__ __attribute__((noinline)) void admm_point(const Ctx& C, gcf zsrc, gcf
 // to PHASE 2, which runs the interior point and the polish passes for the
 // listed problems only (surplus blocks exit).  The slow problems thus start
 // together instead of behind a second round of easy ones.
-template <int PHASE>
+template <int PHASE, bool LONG>
 __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, float* out_u,
                                                     float* out_x, float* out_res,
                                                     int32_t* out_iters, int32_t* out_status,
@@ -1526,7 +1558,9 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     C.rdz = blk;                      blk += (size_t)n * 2 * NROW;
     C.rdu = blk;                      blk += (size_t)n * NU;
     C.rx = blk;                       blk += (size_t)(n + 1) * NX;
-    C.rdx = blk;
+    C.rdx = blk;                      blk += (size_t)(n + 1) * NX;
+    C.rPV = blk;                      blk += (size_t)n * 16;
+    C.rGV = blk;   // inside the block only for n > PINMPC_NMAX (LONG)
     C.faces = (GMEM int32_t*)(ws.faces + s0 * 2);
   }
   }
@@ -1597,7 +1631,7 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     if (PHASE == 1) {
       faces_from_u(C, C.ru, 1e-5);
       bool cycled = false;
-      ok = active_set_loop(C, sh, p1, tol, &cnt, res, &kkt, &cycled);
+      ok = active_set_loop<LONG>(C, sh, p1, tol, &cnt, res, &kkt, &cycled);
       const bool more = !cycled && p1 < pass_a;
       if (!ok && (more || ipm_max > 0)) {
         if (lane == 0) {
@@ -1615,14 +1649,14 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
       cnt.stf = (rp >> 10) & ((1 << 20) - 1);
       if ((rp >> 30) & 1) {
         // resume the active-set passes from the faces the first launch left
-        ok = active_set_loop(C, sh, pass_a - cnt.eq, tol, &cnt, res, &kkt);
+        ok = active_set_loop<LONG>(C, sh, pass_a - cnt.eq, tol, &cnt, res, &kkt);
       }
       if (!ok && ipm_max > 0) {
         // interior point from the ADMM point
         admm_point(C, zsrc, sf, tsc);
         rollout_ru(C, sh);
-        cnt.ipm = ipm(C, sh, ipm_max, tol, &cnt, res, &kkt, &ok);
-        if (!ok) ok = active_set_loop(C, sh, pass_c, tol, &cnt, res, &kkt);
+        cnt.ipm = ipm<LONG>(C, sh, ipm_max, tol, &cnt, res, &kkt, &ok);
+        if (!ok) ok = active_set_loop<LONG>(C, sh, pass_c, tol, &cnt, res, &kkt);
       }
     }
     // the dynamics residual of the returned trajectory, checked independently
@@ -1633,7 +1667,7 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     // the ADMM point as it is: rollout, faces from slack, residuals
     faces_from_u(C, C.ru, 1e-5);
     rollout_ru(C, sh);
-    const double ts = costates_grad(C, sh);
+    const double ts = costates_grad<LONG>(C, sh);
     kkt = multipliers_kkt(C, res, ts);
     res[0] = dyn_residual(C);
   }
@@ -1673,13 +1707,20 @@ hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_sett
     const hipError_t e = launch_fill_i32(w.rcount, 1, 0, 0, st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(refine_kernel<1>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
-                     out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
-                     s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes);
-  if (second)
-    hipLaunchKernelGGL(refine_kernel<2>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
-                       out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
-                       s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes);
+#define PINMPC_REFINE(PH, L)                                                                 \
+  hipLaunchKernelGGL((refine_kernel<PH, L>), dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x, \
+                     out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,    \
+                     s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes)
+  // horizons beyond PINMPC_NMAX keep the rollout's and the costates' stage
+  // buffers in the scratch block (refine_block_doubles sizes it so)
+  const bool lng = p.n_max > PINMPC_NMAX;
+  if (lng) PINMPC_REFINE(1, true);
+  else PINMPC_REFINE(1, false);
+  if (second) {
+    if (lng) PINMPC_REFINE(2, true);
+    else PINMPC_REFINE(2, false);
+  }
+#undef PINMPC_REFINE
   return hipGetLastError();
 }
 

@@ -292,6 +292,23 @@ def test_persistent_sweeps_beyond_40_stages_match_plain(solver):
     _compare(batch, persistent, [int(np.argmax(batch["N"] == 60)), 1, 2])
 
 
+def test_problems_per_workgroup_match_plain(solver):
+    """Two or four short problems packed into one workgroup of the fused sweep
+    (each with its own thread group and LDS buffers), batches not divisible
+    by the packing, and the horizon-packed form with its shortest class packed
+    two per workgroup: bitwise the one-problem-per-workgroup results."""
+    for cfg, n_max, count, groups, form in (("small_b64_n10", 10, 61, (2, 4), 1),
+                                             ("plain_b4096_n20", 20, 301, (2,), 1),
+                                             ("uneven_b16384", 60, 203, (2,), -1)):
+        batch = mpcgen.make_batch(cfg, indices=range(count), n_max=n_max)
+        plain = _solve(solver, batch, form=0)
+        for g in groups:
+            got = _solve(solver, batch, form=form, group=g)
+            for k in plain:
+                assert np.array_equal(plain[k], got[k]), (cfg, g, k)
+        assert (plain["status"] == 0).all()
+
+
 def test_horizon_class_packing_matches_plain(solver):
     """Auto form on uneven horizons (10..60): problems are bucketed by horizon
     into 512- and 1024-thread fused launches and one persistent streaming
@@ -385,7 +402,7 @@ def test_autotuner_picks_a_certifying_schedule(tmp_path):
     rec = json.loads(cache.read_text())
     (key, entry), = rec.items()
     assert entry["settings"] == best and entry["score"] > 0
-    assert len(entry["log"]) == len(list(autotune.stage_a(10))) + 8
+    assert len(entry["log"]) == len(list(autotune.stage_a(10))) + 3 * 3 * 3 - 1
     assert all("eq_passes" in r and "ipm_iters" in r for r in entry["log"])
     again = autotune.tune(dev, cache_path=str(cache), in_flight=1)
     assert again == best

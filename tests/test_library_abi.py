@@ -27,7 +27,7 @@ def test_header_symbols_exported():
 
 def test_struct_layouts_match_header():
     # field order and C types as declared in include/pinmpc.h
-    assert ctypes.sizeof(binding.Settings) == 64
+    assert ctypes.sizeof(binding.Settings) == 72
     assert ctypes.sizeof(binding.Batch) == 8 + 15 * 8
     assert ctypes.sizeof(binding.Out) == 6 * 8
 
@@ -41,7 +41,9 @@ def test_default_settings_and_errors():
     assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 4096, 20, ctypes.byref(nb)) == 0
     assert 1e8 < nb.value < 2e9
     assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, 0, ctypes.byref(nb)) == -1
-    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, 65, ctypes.byref(nb)) == -1
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, binding.NMAX_LONG + 1,
+                                      ctypes.byref(nb)) == -1
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, binding.NMAX_LONG, ctypes.byref(nb)) == 0
     # null context / null arguments are rejected before any device call
     assert lib.pinmpc_solve(None, None, None, None) == -1
     assert lib.pinmpc_destroy(None) == -1
@@ -50,7 +52,8 @@ def test_default_settings_and_errors():
     assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1
     # settings are validated before any device call
     for over in (dict(refine_passes=0, ipm_iters=0), dict(refine_passes=1001),
-                 dict(ipm_iters=-1), dict(form=2), dict(precision=3), dict(kkt_tol=0.0)):
+                 dict(ipm_iters=-1), dict(form=3), dict(form=-2), dict(precision=3),
+                 dict(kkt_tol=0.0), dict(group=0), dict(group=3), dict(group=8)):
         bad = binding.default_settings(**over)
         assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1, over
         assert lib.pinmpc_workspace_bytes(ctypes.byref(bad), 16, 10, ctypes.byref(nb)) in (0, -1)
@@ -85,6 +88,7 @@ def test_boundary_calls_reject_null_arguments():
     assert lib.pinmpc_stats_traffic(None, None, None) == -1
     text = open(os.path.join(ROOT, "include", "pinmpc.h")).read()
     assert int(re.search(r"#define PINMPC_NMAX (\d+)", text).group(1)) == binding.NMAX
+    assert int(re.search(r"#define PINMPC_NMAX_LONG (\d+)", text).group(1)) == binding.NMAX_LONG
     assert binding.WARM_SLOT_BYTES == binding.NMAX * 5 * 25 * 4
     assert ctypes.sizeof(binding.Physics) == 16 + 7 * 8
 

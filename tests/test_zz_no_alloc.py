@@ -45,6 +45,25 @@ def test_noalloc_matches_solve_twice_then_smaller():
         solver.close()
 
 
+def test_noalloc_long_horizons():
+    """Long horizons (the split sweeps and the refinement's long variant)
+    through the entry point that allocates nothing, equal to pinmpc_solve."""
+    from paper_2606_05687_amd import binding
+    cfg = dict(mpcgen.CONFIGS["long_b64_n400"], horizons=(100, 400), batch=6)
+    batch = mpcgen.make_batch(cfg, indices=range(6), n_max=400)
+    solver = binding.Solver(0, iters=3, refine_passes=16, first_passes=0, ipm_iters=150,
+                            polish_passes=20, kkt_tol=1e-10, graph=0)
+    try:
+        dev = binding.to_device(batch)
+        ref = _run(solver, dev, noalloc=False)
+        got = _run(solver, dev, noalloc=True)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), k
+        assert (got["status"] == binding.ST_OK).all()
+    finally:
+        solver.close()
+
+
 def test_noalloc_rejects_batch_beyond_scratch():
     import ctypes
     from paper_2606_05687_amd import binding
