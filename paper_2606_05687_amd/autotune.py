@@ -44,7 +44,7 @@ def _key(dev, allow_bf16):
 
 RHOS = (1.0, 3.0, 10.0, 30.0)
 ITERS = (1, 2, 3, 5, 10, 20, 50, 100, 200)
-PASSES = (8, 12, 16)
+PASSES = (2, 4, 8, 12, 16)
 FIRSTS = (0, 2, 4)
 GROUPS = (1, 2, 4)
 BASE_PASSES, BASE_FIRST = 12, 0

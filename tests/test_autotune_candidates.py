@@ -21,12 +21,12 @@ def test_second_stage_varies_only_the_refinement_budget():
     best = dict(form=1, iters=3, rho=10.0, refine_passes=12, first_passes=0, precision=0,
                 group=1)
     cands = list(autotune.stage_b(best, 20))
-    assert len(cands) == 3 * 3 * 2 - 1                  # the base point is not re-measured
+    assert len(cands) == 5 * 3 * 2 - 1                  # the base point is not re-measured
     for c in cands:
         assert {k: c[k] for k in ("form", "iters", "rho", "precision")} == \
             {k: best[k] for k in ("form", "iters", "rho", "precision")}
     assert {(c["refine_passes"], c["first_passes"], c["group"]) for c in cands} | {(12, 0, 1)} \
-        == {(a, b, g) for a in (8, 12, 16) for b in (0, 2, 4) for g in (1, 2)}
+        == {(a, b, g) for a in (2, 4, 8, 12, 16) for b in (0, 2, 4) for g in (1, 2)}
     # problems per workgroup that fit 1024 threads: 512 per problem at 20 stages,
     # 256 at 10, 1024 at 40
     assert autotune.groups_for(20) == (1, 2) and autotune.groups_for(10) == (1, 2, 4)

@@ -402,7 +402,7 @@ def test_autotuner_picks_a_certifying_schedule(tmp_path):
     rec = json.loads(cache.read_text())
     (key, entry), = rec.items()
     assert entry["settings"] == best and entry["score"] > 0
-    assert len(entry["log"]) == len(list(autotune.stage_a(10))) + 3 * 3 * 3 - 1
+    assert len(entry["log"]) == len(list(autotune.stage_a(10))) + 5 * 3 * 3 - 1
     assert all("eq_passes" in r and "ipm_iters" in r for r in entry["log"])
     again = autotune.tune(dev, cache_path=str(cache), in_flight=1)
     assert again == best
