@@ -224,7 +224,7 @@ def _counter_rows(run_dir):
     return rows
 
 
-TUNED = "--autotune 0 --form 1 --iters 3 --rho 30 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
+TUNED = "--autotune 0 --form 1 --iters 2 --rho 1 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
 PMC_COMMANDS = [
     f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
     f"python3 bench.py {TUNED} --steps 2 --warmup 1",
@@ -236,6 +236,16 @@ PMC_COMMANDS = [
     "python3 bench.py --copy-calibration 1073741824",
     "python3 bench.py --pmc-summary gpurun_out",
 ]
+
+
+def _kernel_match(kernel, name):
+    """Whether a demangled kernel name is `kernel` ("refine_kernel<1>" also
+    matches the instantiation refine_kernel<1, false>, and a plain name any
+    instantiation of it)."""
+    if "<" in kernel:
+        head = "::" + kernel[:-1]
+        return head + ">" in name or head + "," in name
+    return "::" + kernel + "(" in name or "::" + kernel + "<" in name
 
 
 def pmc_summary(prof_dir, command):
@@ -260,9 +270,7 @@ def pmc_summary(prof_dir, command):
         per = {}
         for counter, sub in (("FETCH_SIZE", "pmc_fetch"), ("WRITE_SIZE", "pmc_write")):
             vals = [float(r["Counter_Value"]) for r in _counter_rows(os.path.join(prof_dir, sub))
-                    if r["Counter_Name"] == counter and
-                    ("::" + kernel + "(" in r["Kernel_Name"] or "::" + kernel + "<" in r["Kernel_Name"] or
-                     ("<" in kernel and "::" + kernel in r["Kernel_Name"]))]
+                    if r["Counter_Name"] == counter and _kernel_match(kernel, r["Kernel_Name"])]
             if vals:
                 per[counter] = (len(vals), sum(vals) / len(vals))
         if len(per) < 2:

@@ -38,6 +38,32 @@ def test_parity_plain_b4096_n20_full_launch(solver):
     _check_invariants(batch, out, range(0, 4096, 97))
 
 
+@pytest.mark.parametrize("config,kw", [
+    ("uneven_b16384", dict(n_max=60, form=-1, iters=2, rho=3.0, refine_passes=16, first_passes=0)),
+    ("precision_b16384_n30", dict(form=1, iters=3, precision=1, refine_passes=12,
+                                  first_passes=0)),
+])
+def test_parity_full_size_batches(solver, config, kw):
+    """The uneven-horizon and precision workloads at their full 16 384 problems
+    in the benchmark's schedule (horizon-packed sweeps; BF16 operators): every
+    problem certified under the bar, sampled problems of every horizon and
+    across the batch compared with the oracle, invariants on a spread."""
+    kw = dict(kw)
+    n_max = kw.pop("n_max", None)
+    batch = mpcgen.make_batch(config, n_max=n_max) if n_max else mpcgen.make_batch(config)
+    out = _solve(solver, batch, **kw)
+    ok = out["status"] == 0
+    print(config, "certified", ok.mean(), "max res", out["res"].max())
+    assert ok.all(), np.where(~ok)[0][:20]
+    assert np.all(out["res"] <= TOL_KKT)
+    pick = []
+    for n in sorted(set(batch["N"].tolist())):
+        pick += [int(i) for i in np.where(batch["N"] == n)[0][[0, -1]]]
+    pick += list(range(1000, 16384, 1531))
+    _compare(batch, out, sorted(set(pick)))
+    _check_invariants(batch, out, range(0, 16384, 211))
+
+
 def test_parity_interior_point_path(solver):
     """Every problem that reached the interior-point fallback (and its
     crossover) is compared with the oracle: with the default schedule, and
