@@ -12,7 +12,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpinmpc.so")
 
 SOURCES = ["api.cpp", "server.cpp", "setup.hip", "admm_plain.hip", "admm_fused.hip",
-           "refine.hip", "noalloc.hip", "dynamics.hip", "landmarks.hip", "admm_split.hip"]
+           "refine.hip", "noalloc.hip", "dynamics.hip", "landmarks.hip", "admm_split.hip",
+           "copy.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

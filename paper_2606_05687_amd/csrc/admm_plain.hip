@@ -382,18 +382,6 @@ __global__ void fill_i32_kernel(int32_t* dst, size_t n, int32_t base, int32_t st
     dst[i] = base + step * (int32_t)i;
 }
 
-__global__ void fill_f32_kernel(float* dst, size_t n, float v) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = v;
-}
-
-__global__ void half_of_kernel(float* dst, const float* src, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = 0.5f * src[i];
-}
-
 // z iterates (current) in unscaled coordinates, [b][n_max][25].
 __global__ void admm_extract_kernel(Problem p, Workspace ws, int accel, float* z_out) {
   const size_t total = (size_t)p.batch * p.n_max * NL;
@@ -432,18 +420,6 @@ static unsigned grid_for(size_t n) {
 hipError_t launch_fill_i32(int32_t* dst, size_t n, int32_t base, int32_t step, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, n, base, step);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_f32(float* dst, size_t n, float value, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, n, value);
-  return hipGetLastError();
-}
-
-hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(half_of_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

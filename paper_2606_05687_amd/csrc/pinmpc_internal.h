@@ -370,7 +370,21 @@ struct LandmarkStore {
   int32_t* tag;
 };
 
+// One array of one request to gather into (or scatter from) a serving lane's
+// staging: `rows` rows of `row_bytes`, source rows `src_pitch` apart,
+// destination rows `dst_pitch` apart; work items (rows) of all descriptors of
+// a table are numbered consecutively from `row0`.
+enum { COPY_WORDS = 0, COPY_BYTES = 1, COPY_FILL = 2, COPY_HALF = 3 };
+struct CopyDesc {
+  const void* src;          // null for COPY_FILL
+  void* dst;
+  uint32_t row_bytes, src_pitch, dst_pitch, rows;
+  int32_t op, a, b, pad;    // COPY_FILL writes the int32 pattern a + b i
+  uint64_t row0;
+};
+
 // Kernel launchers (defined in the .hip units).
+hipError_t launch_copy_batch(const CopyDesc* table, int nd, uint64_t rows_total, hipStream_t st);
 hipError_t launch_landmarks_clear(const LandmarkStore& st, const uint8_t* mask, hipStream_t s);
 hipError_t launch_landmarks_push(const LandmarkStore& st, int n_max, const int32_t* N,
                                  const float* x, int32_t tick, hipStream_t s);
@@ -383,8 +397,6 @@ hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_setti
 hipError_t launch_admm_init(const Problem& p, const Workspace& w, hipStream_t st);
 hipError_t launch_warm_save(const Problem& p, const Workspace& w, int accel, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* dst, size_t n, int32_t base, int32_t step, hipStream_t st);
-hipError_t launch_fill_f32(float* dst, size_t n, float value, hipStream_t st);
-hipError_t launch_half_of(float* dst, const float* src, size_t n, hipStream_t st);
 // `sweeps` ADMM sweeps in one launch of the streaming sweep kernel (1: the
 // plain form, one launch per sweep; more: iterates resident in registers
 // across the sweeps, operators streamed every sweep).

@@ -5,8 +5,9 @@
 // the host.  A scheduler thread packs whatever is queued into the next free
 // lane as soon as one frees up (continuous batching: a launch takes every
 // waiting request that fits its capacity), gathers the packed inputs into the
-// lane's staging buffers with device-to-device copies on the lane's own HIP
-// stream, runs the solve there and scatters the outputs back.  Lanes run
+// lane's staging buffers on the lane's own HIP stream (one kernel over a table
+// of copy descriptors for every array of every request), runs the solve there
+// and scatters the outputs back the same way.  Lanes run
 // concurrently, so requests that arrive while others are on the GPU are
 // admitted into the next lane and their work overlaps on the device.  A
 // completion thread polls each lane's event and stamps request latency
@@ -61,12 +62,20 @@ struct Lane {
   int32_t *N, *warm_idx;
   float *u, *x, *res;
   int32_t *iters, *status, *detail;
+  // copy descriptors of a launch's gather and scatter (pinned host table and
+  // its device copy, room for kMaxDescPerProblem per problem of capacity)
+  CopyDesc* desc_host = nullptr;
+  CopyDesc* desc_dev = nullptr;
   std::vector<Request*> inflight;
   bool busy = false;      // owns requests (set by the scheduler before enqueueing)
   bool launched = false;  // its event was recorded after the last enqueued work
 };
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Gather: up to 16 arrays per request, scatter: up to 6; a request holds at
+// least one problem.
+constexpr int kMaxDescPerProblem = 22;
 
 size_t staging_bytes(int cap) {
   const size_t S = (size_t)cap * PINMPC_NMAX;
@@ -78,6 +87,7 @@ size_t staging_bytes(int cap) {
   add((size_t)cap * 4); add(S * 2); add((size_t)cap * 4); add((size_t)cap * 4);
   add(S * NU * 4); add((size_t)cap * (PINMPC_NMAX + 1) * NX * 4); add((size_t)cap * PINMPC_NRES * 4);
   add((size_t)cap * 4); add((size_t)cap * 4); add((size_t)cap * 4 * 4);
+  add((size_t)cap * kMaxDescPerProblem * sizeof(CopyDesc));
   return b;
 }
 
@@ -107,16 +117,38 @@ void carve_lane(Lane& L, int cap) {
   L.iters = (int32_t*)take((size_t)cap * 4);
   L.status = (int32_t*)take((size_t)cap * 4);
   L.detail = (int32_t*)take((size_t)cap * 4 * 4);
+  L.desc_dev = (CopyDesc*)take((size_t)cap * kMaxDescPerProblem * sizeof(CopyDesc));
 }
 
-// Pitched device-to-device copy of [rows][spitch] -> [rows][dpitch] (bytes).
-hipError_t copy2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
-                  size_t rows, hipStream_t st) {
-  if (rows == 0 || width == 0) return hipSuccess;
-  if (dpitch == spitch && spitch == width)
-    return hipMemcpyAsync(dst, src, width * rows, hipMemcpyDeviceToDevice, st);
-  return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice, st);
-}
+// Builds a table of copy descriptors (rows numbered consecutively).
+struct Table {
+  CopyDesc* d;
+  int n = 0;
+  uint64_t rows = 0;
+  void add(const void* src, void* dst, size_t row_bytes, size_t src_pitch, size_t dst_pitch,
+           size_t nrows, int op = -1, int32_t a = 0, int32_t b = 0) {
+    if (nrows == 0 || row_bytes == 0) return;
+    CopyDesc& c = d[n++];
+    if (op < 0) {
+      const bool words = (row_bytes % 4 == 0) && (src_pitch % 4 == 0) && (dst_pitch % 4 == 0) &&
+                         ((uintptr_t)src % 4 == 0) && ((uintptr_t)dst % 4 == 0);
+      op = words ? COPY_WORDS : COPY_BYTES;
+    }
+    c.src = src;
+    c.dst = dst;
+    c.row_bytes = (uint32_t)row_bytes;
+    c.src_pitch = (uint32_t)src_pitch;
+    c.dst_pitch = (uint32_t)dst_pitch;
+    c.rows = (uint32_t)nrows;
+    c.op = op;
+    c.a = a;
+    c.b = b;
+    c.pad = 0;
+    c.row0 = rows;
+    rows += nrows;
+  }
+};
+
 
 }  // namespace
 
@@ -155,42 +187,75 @@ int pinmpc_server_s::launch(Lane& L, std::vector<Request*>& rq) {
     has_w |= r->in.weight != nullptr;
     warm |= r->warm_base >= 0;
   }
+  // gather table: every array of every request into the lane's staging,
+  // stage arrays re-pitched from the request's n_max to the launch's n
+  Table g{L.desc_host};
   int off = 0;
   for (Request* r : rq) {
     const pinmpc_batch& q = r->in;
-    const size_t nb = (size_t)q.batch, nr = (size_t)q.n_max;
-    const size_t o = (size_t)off;
+    const size_t nb = (size_t)q.batch, nr = (size_t)q.n_max, o = (size_t)off;
     auto stg = [&](void* dst, const void* src, size_t elem) {
-      return copy2d((char*)dst + o * n * elem, n * elem, src, nr * elem, nr * elem, nb, st);
+      g.add(src, (char*)dst + o * n * elem, nr * elem, nr * elem, n * elem, nb);
     };
-    hipError_t e = hipSuccess;
-    e = e ? e : stg(L.A, q.A, NX * NX * 4);
-    e = e ? e : stg(L.B, q.Bu, NX * NU * 4);
-    e = e ? e : stg(L.x_ref, q.x_ref, NX * 4);
-    e = e ? e : stg(L.contact, q.contact, 2);
-    if (has_e) e = e ? e : (q.e ? stg(L.e, q.e, NX * 4)
-                                : launch_fill_f32(L.e + o * n * NX, nb * n * NX, 0.f, st));
-    if (has_ur) e = e ? e : (q.u_ref ? stg(L.u_ref, q.u_ref, NU * 4)
-                                     : launch_fill_f32(L.u_ref + o * n * NU, nb * n * NU, 0.f, st));
     auto per = [&](void* dst, const void* src, size_t elem) {
-      return hipMemcpyAsync((char*)dst + o * elem, src, nb * elem, hipMemcpyDeviceToDevice, st);
+      g.add(src, (char*)dst + o * elem, nb * elem, nb * elem, nb * elem, 1);
     };
-    e = e ? e : per(L.x0, q.x0, NX * 4);
-    e = e ? e : per(L.Q, q.Q, NX * 4);
-    e = e ? e : per(L.R, q.R, NU * 4);
-    e = e ? e : per(L.mu, q.mu, 4);
-    e = e ? e : per(L.fz, q.fz_max, 4);
-    e = e ? e : per(L.tau, q.tau_max, 4);
-    if (has_up) e = e ? e : (q.u_prev ? per(L.u_prev, q.u_prev, NU * 4)
-                                      : launch_fill_f32(L.u_prev + o * NU, nb * NU, 0.f, st));
-    if (has_w) e = e ? e : (q.weight ? per(L.weight, q.weight, 4)
-                                     : launch_half_of(L.weight + o, q.fz_max, nb, st));
-    e = e ? e : (q.N ? per(L.N, q.N, 4) : launch_fill_i32(L.N + o, nb, q.n_max, 0, st));
-    if (warm) e = e ? e : launch_fill_i32(L.warm_idx + o, nb, r->warm_base < 0 ? -1 : r->warm_base,
-                                          r->warm_base < 0 ? 0 : 1, st);
-    if (e != hipSuccess) return PINMPC_EDEVICE;
+    auto fill = [&](void* dst, size_t count, int32_t a, int32_t b) {
+      g.add(nullptr, dst, count * 4, 0, 0, 1, COPY_FILL, a, b);
+    };
+    stg(L.A, q.A, NX * NX * 4);
+    stg(L.B, q.Bu, NX * NU * 4);
+    stg(L.x_ref, q.x_ref, NX * 4);
+    stg(L.contact, q.contact, 2);
+    if (has_e) {
+      if (q.e) stg(L.e, q.e, NX * 4);
+      else fill(L.e + o * n * NX, nb * n * NX, 0, 0);
+    }
+    if (has_ur) {
+      if (q.u_ref) stg(L.u_ref, q.u_ref, NU * 4);
+      else fill(L.u_ref + o * n * NU, nb * n * NU, 0, 0);
+    }
+    per(L.x0, q.x0, NX * 4);
+    per(L.Q, q.Q, NX * 4);
+    per(L.R, q.R, NU * 4);
+    per(L.mu, q.mu, 4);
+    per(L.fz, q.fz_max, 4);
+    per(L.tau, q.tau_max, 4);
+    if (has_up) {
+      if (q.u_prev) per(L.u_prev, q.u_prev, NU * 4);
+      else fill(L.u_prev + o * NU, nb * NU, 0, 0);
+    }
+    if (has_w) {
+      if (q.weight) per(L.weight, q.weight, 4);
+      else g.add(q.fz_max, L.weight + o, nb * 4, nb * 4, nb * 4, 1, COPY_HALF);
+    }
+    if (q.N) per(L.N, q.N, 4);
+    else fill(L.N + o, nb, q.n_max, 0);
+    if (warm) fill(L.warm_idx + o, nb, r->warm_base < 0 ? -1 : r->warm_base,
+                   r->warm_base < 0 ? 0 : 1);
     off += q.batch;
   }
+  // scatter table: the launch's outputs back into each request's buffers
+  Table sc{L.desc_host + g.n};
+  off = 0;
+  for (Request* r : rq) {
+    const pinmpc_out& d = r->out;
+    const size_t nb = (size_t)r->in.batch, nr = (size_t)r->in.n_max, o = (size_t)off;
+    sc.add(L.u + o * n * NU, d.u, nr * NU * 4, (size_t)n * NU * 4, nr * NU * 4, nb);
+    sc.add(L.x + o * (n + 1) * NX, d.x, (nr + 1) * NX * 4, (size_t)(n + 1) * NX * 4,
+           (nr + 1) * NX * 4, nb);
+    if (d.res) sc.add(L.res + o * PINMPC_NRES, d.res, nb * PINMPC_NRES * 4, 0, 0, 1);
+    if (d.iters) sc.add(L.iters + o, d.iters, nb * 4, 0, 0, 1);
+    if (d.status) sc.add(L.status + o, d.status, nb * 4, 0, 0, 1);
+    if (d.detail) sc.add(L.detail + o * 4, d.detail, nb * 16, 0, 0, 1);
+    off += r->in.batch;
+  }
+  // the scatter rows are numbered from zero in their own table
+  const size_t nd = (size_t)g.n + sc.n;
+  if (hipMemcpyAsync(L.desc_dev, L.desc_host, nd * sizeof(CopyDesc), hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      launch_copy_batch(L.desc_dev, g.n, g.rows, st) != hipSuccess)
+    return PINMPC_EDEVICE;
   pinmpc_batch sb{};
   sb.batch = total;
   sb.n_max = n;
@@ -212,26 +277,8 @@ int pinmpc_server_s::launch(Lane& L, std::vector<Request*>& rq) {
   pinmpc_out so{L.u, L.x, L.res, L.iters, L.status, L.detail};
   int rc = solve_internal(L.ctx, &sb, &so, st, warm ? L.warm_idx : nullptr, warm_store);
   if (rc) return rc;
-  off = 0;
-  for (Request* r : rq) {
-    const pinmpc_out& d = r->out;
-    const size_t nb = (size_t)r->in.batch, nr = (size_t)r->in.n_max, o = (size_t)off;
-    hipError_t e = hipSuccess;
-    e = e ? e : copy2d(d.u, nr * NU * 4, L.u + o * n * NU, (size_t)n * NU * 4, nr * NU * 4, nb, st);
-    e = e ? e : copy2d(d.x, (nr + 1) * NX * 4, L.x + o * (n + 1) * NX, (size_t)(n + 1) * NX * 4,
-                       (nr + 1) * NX * 4, nb, st);
-    if (d.res)
-      e = e ? e : hipMemcpyAsync(d.res, L.res + o * PINMPC_NRES, nb * PINMPC_NRES * 4,
-                                 hipMemcpyDeviceToDevice, st);
-    if (d.iters)
-      e = e ? e : hipMemcpyAsync(d.iters, L.iters + o, nb * 4, hipMemcpyDeviceToDevice, st);
-    if (d.status)
-      e = e ? e : hipMemcpyAsync(d.status, L.status + o, nb * 4, hipMemcpyDeviceToDevice, st);
-    if (d.detail)
-      e = e ? e : hipMemcpyAsync(d.detail, L.detail + o * 4, nb * 16, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return PINMPC_EDEVICE;
-    off += r->in.batch;
-  }
+  if (launch_copy_batch(L.desc_dev + g.n, sc.n, sc.rows, st) != hipSuccess)
+    return PINMPC_EDEVICE;
   if (hipEventRecord(L.ev, st) != hipSuccess) return PINMPC_EDEVICE;
   return PINMPC_OK;
 }
@@ -349,7 +396,10 @@ int pinmpc_server_create(pinmpc_server* out, int device, const pinmpc_settings* 
     if ((rc = reserve_internal(L.ctx, lane_capacity, PINMPC_NMAX))) break;
     if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&L.mem, staging_bytes(lane_capacity)) != hipSuccess) {
+        hipMalloc(&L.mem, staging_bytes(lane_capacity)) != hipSuccess ||
+        hipHostMalloc((void**)&L.desc_host,
+                      (size_t)lane_capacity * kMaxDescPerProblem * sizeof(CopyDesc),
+                      hipHostMallocDefault) != hipSuccess) {
       rc = PINMPC_ENOMEM;
       break;
     }
@@ -367,6 +417,7 @@ int pinmpc_server_create(pinmpc_server* out, int device, const pinmpc_settings* 
       if (L.stream) (void)hipStreamDestroy(L.stream);
       if (L.ev) (void)hipEventDestroy(L.ev);
       if (L.mem) (void)hipFree(L.mem);
+      if (L.desc_host) (void)hipHostFree(L.desc_host);
     }
     if (srv->warm_store) (void)hipFree(srv->warm_store);
     delete srv;
@@ -533,6 +584,7 @@ int pinmpc_server_destroy(pinmpc_server s) {
     (void)hipStreamDestroy(L.stream);
     (void)hipEventDestroy(L.ev);
     (void)hipFree(L.mem);
+    (void)hipHostFree(L.desc_host);
   }
   if (s->warm_store) (void)hipFree(s->warm_store);
   delete s;

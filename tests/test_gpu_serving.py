@@ -185,3 +185,45 @@ def test_warm_state_export_import_resumes_bitwise():
     assert lib.pinmpc_server_export_state(c._h, 100, 16, buf2, len(buf2)) == 0
     for s in (a, b, c):
         s.close()
+
+
+def test_mix_of_optional_arrays_and_horizons():
+    """Requests with and without the optional arrays (e, u_ref, u_prev, weight,
+    per-problem horizons) and with different padded horizons packed into one
+    launch: the gather fills what a request leaves out exactly as
+    pinmpc_solve defaults it, so every result equals its request solved alone
+    (bitwise)."""
+    import torch
+    from paper_2606_05687_amd import binding
+    reqs = [mpcgen.make_batch("serving_tick", indices=range(i * 16, i * 16 + 16), offsets=True)
+            for i in range(2)]
+    reqs += [mpcgen.make_batch("plain_b4096_n20", indices=range(i * 7, i * 7 + 7)) for i in range(2)]
+    devs = []
+    for i, r in enumerate(reqs):
+        d = binding.to_device(r)
+        if i >= 2:          # leave the optional arrays out
+            for k in ("e", "u_ref", "u_prev", "weight", "N"):
+                d.pop(k, None)
+        devs.append(d)
+    solver = binding.Solver(0, graph=0, iters=3, refine_passes=12, first_passes=0)
+    alone = []
+    for d in devs:
+        o = solver.solve(d)
+        torch.cuda.synchronize()
+        alone.append({k: v.cpu().numpy() for k, v in o.items()})
+    solver.close()
+    srv = binding.Server(0, lanes=1, capacity=128, iters=3, refine_passes=12, first_passes=0)
+    outs = [binding.Solver.alloc_out(None, d) for d in devs]
+    for o in outs:
+        for v in o.values():
+            v.fill_(-7)
+    tickets = [srv.submit(d, o) for d, o in zip(devs, outs)]
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    assert st["launches"] < len(devs)
+    for i, o in enumerate(outs):
+        for k, v in o.items():
+            assert np.array_equal(v.cpu().numpy(), alone[i][k]), (i, k)
+        assert (alone[i]["status"] == 0).all()
