@@ -19,6 +19,22 @@ __device__ inline int find_desc(const CopyDesc* D, int nd, uint64_t g) {
   return lo;
 }
 
+// Copy n units of T from s to d with four loads in flight per thread (a
+// block-strided loop with one load per thread waits on every load in turn).
+template <class T>
+__device__ inline void copy_units(T* __restrict__ d, const T* __restrict__ s, uint32_t n) {
+  constexpr uint32_t B = 256;
+  uint32_t i = threadIdx.x;
+  for (; i + 3 * B < n; i += 4 * B) {
+    const T v0 = s[i], v1 = s[i + B], v2 = s[i + 2 * B], v3 = s[i + 3 * B];
+    d[i] = v0;
+    d[i + B] = v1;
+    d[i + 2 * B] = v2;
+    d[i + 3 * B] = v3;
+  }
+  for (; i < n; i += B) d[i] = s[i];
+}
+
 __global__ void __launch_bounds__(256) copy_batch_kernel(const CopyDesc* D, int nd,
                                                          uint64_t rows_total) {
   for (uint64_t g = blockIdx.x; g < rows_total; g += gridDim.x) {
@@ -28,11 +44,14 @@ __global__ void __launch_bounds__(256) copy_batch_kernel(const CopyDesc* D, int 
     const char* src = d.src ? (const char*)d.src + row * d.src_pitch : nullptr;
     switch (d.op) {
       case COPY_WORDS:
-        for (uint32_t i = threadIdx.x; i < d.row_bytes / 4; i += blockDim.x)
-          ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
+        // 16-byte units when both ends and the length allow it
+        if ((((uintptr_t)dst | (uintptr_t)src | d.row_bytes) & 15) == 0)
+          copy_units((uint4*)dst, (const uint4*)src, d.row_bytes / 16);
+        else
+          copy_units((uint32_t*)dst, (const uint32_t*)src, d.row_bytes / 4);
         break;
       case COPY_BYTES:
-        for (uint32_t i = threadIdx.x; i < d.row_bytes; i += blockDim.x) dst[i] = src[i];
+        copy_units((uint8_t*)dst, (const uint8_t*)src, d.row_bytes);
         break;
       case COPY_FILL:   // int32 pattern a + b i
         for (uint32_t i = threadIdx.x; i < d.row_bytes / 4; i += blockDim.x)
