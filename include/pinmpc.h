@@ -212,8 +212,8 @@ int pinmpc_solve(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out,
  * allocating library routine); its first call on a device resolves that
  * device's copy of the array once.  Each GPU that runs it holds the array
  * until the process ends.  A batch whose workspace (pinmpc_workspace_bytes)
- * exceeds the array returns PINMPC_ETOOBIG before any GPU work: at 17.4 KB
- * per stage that is about 15 400 stages, e.g. 770 problems at N = 20 or 257
+ * exceeds the array returns PINMPC_ETOOBIG before any GPU work: at 12.3 KB
+ * per stage that is about 21 800 stages, e.g. 1091 problems at N = 20 or 364
  * at N = 60.  Every call on one GPU shares that GPU's array and leaves its
  * contents behind (the kernels initialise everything they read): calls that
  * overlap on one GPU (two streams, two host threads, two contexts) race and

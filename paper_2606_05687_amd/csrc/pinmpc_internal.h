@@ -134,19 +134,29 @@ struct Workspace {
   float* warm_store;
 };
 
-// FP64 scratch of the refinement per problem with n stages.  Four 16 x 16
-// tiles per stage come first, so every tile is 32-byte aligned: the stage's
-// input tile (face projector and offset, or the interior-point input Hessian
-// and linear term), the gain tile, the inverse input Hessian and Hwx.  Then
-// per stage: feedforward (12), inputs (12), costates (13), gradient (12), row
-// multipliers, slacks, interior-point multipliers and their steps (5 x 22)
-// and step du (12); and states x and dx ((n+1) x 13 each).
+// FP64 scratch of the refinement per problem with n stages.  The stage
+// blocks come first, each stored compactly (only the entries that can be
+// nonzero; the register tiles are rebuilt from them entry by entry):
+//   T    stage input: per contact its 6 x 6 diagonal block (row-major), then
+//        its 6 offsets (face projector and point, or the interior-point input
+//        Hessian and linear term)
+//   K    gains, 12 x 13 row-major
+//   L    inverse input Hessian, 12 x 12 row-major (interior-point steps)
+//   Hwx  12 x 13 row-major (interior-point steps)
+//   S    value function: lower triangle of S (13 x 13, row by row), then s
+// Then per stage: feedforward (12), inputs (12), costates (13), gradient (12),
+// row multipliers, slacks, interior-point multipliers and their steps
+// (5 x 22) and step du (12); and states x and dx ((n+1) x 13 each).
 // Horizons beyond PINMPC_NMAX (the long-horizon path) keep two more 16-wide
 // per-stage vectors there (the costate chain's and the rollout's stage
 // buffers, which live in LDS for shorter horizons).
-constexpr int TILE = 256;
+constexpr int TS_T = 2 * (36 + 6);
+constexpr int TS_K = NU * NX;
+constexpr int TS_L = NU * NU;
+constexpr int TS_H = NU * NX;
+constexpr int TS_S = NX * (NX + 1) / 2 + NX;
 __host__ __device__ constexpr size_t refine_block_doubles(int n) {
-  return (((size_t)n * (5 * TILE + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
+  return (((size_t)n * (TS_T + TS_K + TS_L + TS_H + TS_S + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
            2 * (size_t)(n + 1) * NX + (n > PINMPC_NMAX ? (size_t)n * 32 : 0)) + 3) & ~(size_t)3;
 }
 

@@ -44,7 +44,7 @@ struct Ctx {
   const LMEM double* R;
   gcf A, B, e, x_ref, u_ref, x0;
   const GMEM uint8_t* contact;
-  gd rT, rK, rL, rHwx, rS;   // per-stage 16 x 16 tiles (32-byte aligned)
+  gd rT, rK, rL, rHwx, rS;   // per-stage compact blocks (TS_T, TS_K, ... doubles)
   gd rkap, ru, rx, rlam, rg, rmu, rs, rz, rds, rdz, rdu, rdx;
   gd rPV, rGV;   // long horizons: the stage buffers of the rollout and costates
   GMEM int32_t* faces;
@@ -297,10 +297,6 @@ __device__ inline d4 mmT(d4 u, d4 v, d4 acc) {
   return acc;
 }
 
-__device__ inline d4 ld_tile(gcd base) {
-  return reinterpret_cast<const GMEM d4*>(base)[threadIdx.x];
-}
-__device__ inline void st_tile(gd base, d4 t) { reinterpret_cast<GMEM d4*>(base)[threadIdx.x] = t; }
 // Column-VC vector of a tile to / from memory (len entries).
 __device__ inline void vec_store(gd v, int len, d4 t) {
   if (tj() == VC) {
@@ -311,14 +307,104 @@ __device__ inline void vec_store(gd v, int len, d4 t) {
 }
 __device__ inline d4 sel(bool c, d4 a) { return c ? a : zero4(); }
 
-// Address of entry (r, c) of a stage tile in memory: lane 16 (r % 4) + c
-// holds it as item r / 4.
-__device__ inline size_t tile_at(int r, int c) { return (size_t)4 * (16 * (r % 4) + c) + r / 4; }
+// Stage blocks in memory hold only the entries a tile can have nonzero (the
+// layouts are listed with refine_block_doubles).  A map packs, for each of a
+// lane's four tile items, the item's offset in the block (in doubles, 8 bits
+// per item) or 255 for an item the block does not hold.  Blocks are read and
+// written with buffer instructions whose range is the block: an item mapped
+// to 255 lies past the end (255 doubles exceed every block), so its load
+// returns zero and its store is dropped by the hardware's range check.  A
+// fetch issued a stage ahead thus needs no masking and stores need no
+// branches.
+constexpr uint32_t NOT_HELD = 255;
+static_assert(TS_T < 255 && TS_K < 255 && TS_L < 255 && TS_H < 255 && TS_S < 255,
+              "a stage block must end before the out-of-range offset");
+__device__ inline uint32_t pack_map(const int o[4]) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) m |= (uint32_t)o[q] << (8 * q);
+  return m;
+}
+// rows x cols, row-major
+__device__ inline uint32_t map_rect(int rows, int cols) {
+  int o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + tg(), c = tj();
+    o[q] = (r < rows && c < cols) ? r * cols + c : (int)NOT_HELD;
+  }
+  return pack_map(o);
+}
+// stage input block: the two contacts' 6 x 6 diagonal blocks and offsets
+__device__ inline uint32_t map_T() {
+  int o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + tg(), c = tj();
+    const bool blk = r < NU && c < NU && (r / 6) == (c / 6);
+    const bool off = r < NU && c == VC;
+    o[q] = blk ? (r / 6) * 42 + (r % 6) * 6 + (c % 6)
+               : (off ? (r / 6) * 42 + 36 + (r % 6) : (int)NOT_HELD);
+  }
+  return pack_map(o);
+}
+// value function: S symmetric (13 x 13, lower triangle), s in column VC;
+// `store` selects the lower triangle only, a load reads both triangles
+__device__ inline uint32_t map_S(bool store) {
+  int o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + tg(), c = tj();
+    const int hi = r > c ? r : c, lo = r > c ? c : r;
+    const bool sym = r < NX && c < NX && (!store || c <= r);
+    const bool vec = r < NX && c == VC;
+    o[q] = sym ? hi * (hi + 1) / 2 + lo : (vec ? NX * (NX + 1) / 2 + r : (int)NOT_HELD);
+  }
+  return pack_map(o);
+}
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+// buffer resource over one stage block of `doubles` entries (raw buffer:
+// stride 0, 32-bit data format, range checked against the block's bytes)
+__device__ inline __amdgpu_buffer_rsrc_t block_rsrc(gcd base, int doubles) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, doubles * 8, 0x00020000);
+}
+// Item q's byte offset, kept in a vector register: an offset the compiler
+// could prove constant would otherwise move into the instruction's immediate
+// field, and the range check is meant to see every offset the same way.
+__device__ inline int map_offset(uint32_t map, int q) {
+  int off = (int)(((map >> (8 * q)) & 255) * 8);
+  asm volatile("" : "+v"(off));
+  return off;
+}
+// (Element values move through memcpy: a bit cast applied directly to a
+// vector element has been seen to read element 0 for every element.)
+__device__ inline d4 ld_map(gcd base, int doubles, uint32_t map) {
+  const __amdgpu_buffer_rsrc_t r = block_rsrc(base, doubles);
+  d4 t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const u2 w = __builtin_amdgcn_raw_buffer_load_b64(r, map_offset(map, q), 0, 0);
+    double v;
+    __builtin_memcpy(&v, &w, 8);
+    t[q] = v;
+  }
+  return t;
+}
+__device__ inline void st_map(gd base, int doubles, uint32_t map, d4 t) {
+  const __amdgpu_buffer_rsrc_t r = block_rsrc(base, doubles);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double v = t[q];
+    u2 w;
+    __builtin_memcpy(&w, &v, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, map_offset(map, q), 0, 0);
+  }
+}
 
-// Stage input tiles, written in parallel over (stage, contact): each lane
-// computes one contact's 6 x 6 diagonal block (columns 0..11) and its six
-// column-VC entries in registers and stores them into the stage's tile.  The
-// rest of every tile is zero (cleared once per launch).
+// Stage input blocks, written in parallel over (stage, contact): each lane
+// computes one contact's 6 x 6 diagonal block and its six offsets (column VC
+// of the tile) in registers and stores them, whole, into the stage's block
+// (zero for a swing contact).
 //   equality passes: the face projector P (block diagonal) and the face
 //                    offset c of the contact;
 //   Newton steps:    the input Hessian R + G^T diag(z/s) G and the linear term
@@ -331,7 +417,7 @@ __device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec, int kn) {
   const int lane = threadIdx.x;
   for (int e = lane; e < kn * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
-    gd base = C.rT + (size_t)k * TILE;
+    gd base = C.rT + (size_t)k * TS_T + i * 42;
     double P6[6][6], c6[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
@@ -376,10 +462,9 @@ __device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec, int kn) {
     }
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      const int r = 6 * i + a;
 #pragma unroll
-      for (int b = 0; b < 6; ++b) base[tile_at(r, 6 * i + b)] = P6[a][b];
-      base[tile_at(r, VC)] = c6[a];
+      for (int b = 0; b < 6; ++b) base[a * 6 + b] = P6[a][b];
+      base[36 + a] = c6[a];
     }
   }
 }
@@ -560,6 +645,10 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     Qr[q] = C.Q[clampi(4 * q + g, NX - 1)];
     Rr[q] = C.R[clampi(4 * q + g, NU - 1)];
   }
+  // maps of the stage blocks this variant moves
+  const uint32_t mT = map_T();
+  const uint32_t mS = map_S(true);
+  const uint32_t mL = map_rect(NU, NU), mH = map_rect(NU, NX);
   auto fetch = [&](int k, BackRaw& s) {
     gather(pA + (size_t)k * NX * NX, false, NX, NX, s.a);
     gather(pB + (size_t)k * NX * NU, true, NX, NU, s.bt);
@@ -576,10 +665,10 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
 #pragma unroll
       for (int q = 0; q < 4; ++q) s.xn[q] = prx[(size_t)(k + 1) * NX + clampi(4 * q + g, NX - 1)];
     }
-    s.T = ld_tile(prT + (size_t)k * TILE);
+    s.T = ld_map(prT + (size_t)k * TS_T, TS_T, mT);
     if (newton && !factor) {
-      s.HI = ld_tile(prL + (size_t)k * TILE);
-      s.HX = ld_tile(prH + (size_t)k * TILE);
+      s.HI = ld_map(prL + (size_t)k * TS_L, TS_L, mL);
+      s.HX = ld_map(prH + (size_t)k * TS_H, TS_H, mH);
     } else {
       s.HI = s.HX = zero4();
     }
@@ -591,7 +680,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   };
 
   // value function of x_{k+1}: S in columns 0..12, s in VC
-  d4 Ss = (ktop < N) ? ld_tile(prS + (size_t)ktop * TILE) : zero4();
+  d4 Ss = (ktop < N) ? ld_map(prS + (size_t)ktop * TS_S, TS_S, map_S(false)) : zero4();
   BackRaw raw;
   fetch(ktop > 0 ? ktop - 1 : 0, raw);
   for (int k = ktop - 1; k >= 0; --k) {
@@ -695,10 +784,12 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         const int r = 4 * q + g;
         KK[q] = (r < NU && (j < NX || j == VC)) ? sh.r.KK[r * 16 + j] : 0.0;   // [K | kap]
       }
-      // [K | kap] row-major (row r at 16 r) for the rollout; rows 4q + g, q < 3,
-      // are the 12 input rows
+      // K row-major (row r at NX r) for the rollout; rows 4q + g, q < 3, are
+      // the 12 input rows (kap goes to its own vector)
+      if (j < NX) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) prK[(size_t)k * TILE + (4 * q + g) * 16 + j] = KK[q];
+        for (int q = 0; q < 3; ++q) prK[(size_t)k * TS_K + (4 * q + g) * NX + j] = KK[q];
+      }
       vec_store(prkap + (size_t)k * NU, NU, KK);
       if (newton) {
         d4 HI;
@@ -707,8 +798,8 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
           const int r = 4 * q + g;
           HI[q] = (r < NU && j < NU) ? sh.r.HI[r * 16 + j] : 0.0;
         }
-        st_tile(prL + (size_t)k * TILE, HI);
-        st_tile(prH + (size_t)k * TILE, sel(j < NX, D5));
+        st_map(prL + (size_t)k * TS_L, TS_L, mL, HI);
+        st_map(prH + (size_t)k * TS_H, TS_H, mH, D5);
       }
       // S = A^T W A + Hwx^T K, s = A^T (W d + q + s) + Hwx^T kap
       Sn = mmT<3>(sel(j < NX, D5), KK, SA);
@@ -722,7 +813,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
         const int r = 4 * q + g;
         if (r < NX && j < NX) Sn[q] = 0.5 * (Sn[q] + sh.r.ST[j * 17 + r]);
       }
-      if (mode == Mode::EQ) st_tile(prS + (size_t)k * TILE, Sn);
+      if (mode == Mode::EQ) st_map(prS + (size_t)k * TS_S, TS_S, mS, Sn);
       wsync();
     } else {
       // second right-hand side of the stored Newton matrix (d = 0, so
@@ -755,21 +846,22 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   const gcf pev = pe ? pe : pA;   // a valid address when there is no e
   struct FwdRaw {
     double kr[NX];   // K[i][0..12]
-    double pc[NU];   // P[0..11][i] (equality passes)
+    double p6[6];    // P[6 (i / 6) + a][i], a = 0..5 (equality passes)
     double c, kap;
     float a[NX], b[NU], e;
     int ct;
   };
   auto ffetch = [&](int k, FwdRaw& s) {
-    const gcd kr = prK + (size_t)k * TILE + iu * 16;
+    const gcd kr = prK + (size_t)k * TS_K + iu * NX;
 #pragma unroll
     for (int r = 0; r < NX; ++r) s.kr[r] = kr[r];
     s.kap = prkap[(size_t)k * NU + iu];
     if (!newton) {
-      const gcd tt = prT + (size_t)k * TILE;
+      // column iu of P is nonzero only inside its contact's block
+      const gcd tt = prT + (size_t)k * TS_T + (iu / 6) * 42;
 #pragma unroll
-      for (int r = 0; r < NU; ++r) s.pc[r] = tt[tile_at(r, iu)];
-      s.c = tt[tile_at(iu, VC)];
+      for (int a = 0; a < 6; ++a) s.p6[a] = tt[a * 6 + iu % 6];
+      s.c = tt[36 + iu % 6];
     }
     const gcf ar = pA + (size_t)k * NX * NX + ix * NX;
 #pragma unroll
@@ -794,7 +886,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     }
 #pragma unroll
     for (int r = 0; r < NU; ++r) {
-      pc[r] = newton ? 0.0 : fr.pc[r];
+      pc[r] = (newton || r / 6 != iu / 6) ? 0.0 : fr.p6[r % 6];
       b[r] = (double)fr.b[r];
     }
     const double kap = fr.kap, cc = newton ? 0.0 : fr.c;
@@ -1542,11 +1634,11 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
   {
     const int n = C.n;
     gd blk = (gd)(ws.rblk + (size_t)C.b * refine_block_doubles(n));
-    C.rT = blk;                       blk += (size_t)n * TILE;
-    C.rK = blk;                       blk += (size_t)n * TILE;
-    C.rL = blk;                       blk += (size_t)n * TILE;
-    C.rHwx = blk;                     blk += (size_t)n * TILE;
-    C.rS = blk;                       blk += (size_t)n * TILE;
+    C.rT = blk;                       blk += (size_t)n * TS_T;
+    C.rK = blk;                       blk += (size_t)n * TS_K;
+    C.rL = blk;                       blk += (size_t)n * TS_L;
+    C.rHwx = blk;                     blk += (size_t)n * TS_H;
+    C.rS = blk;                       blk += (size_t)n * TS_S;
     C.rkap = blk;                     blk += (size_t)n * NU;
     C.ru = blk;                       blk += (size_t)n * NU;
     C.rlam = blk;                     blk += (size_t)n * NX;
@@ -1612,9 +1704,6 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
     return;
   }
 
-  // stage input tiles: everything outside the contacts' diagonal blocks and
-  // offset column stays zero
-  for (int k = 0; k < N; ++k) st_tile(C.rT + (size_t)k * TILE, zero4());
   gcf zsrc = (gcf)((accel ? ws.cur : ws.hat) + s0 * NSTATE * NL);
   gcf sf = (gcf)(ws.sf + s0);
   const float tsc = ws.tsc[C.b];
