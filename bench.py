@@ -105,6 +105,9 @@ def parse():
                     help="solves in flight: S library contexts on S streams (default "
                          "priority) take the timed solves round robin, so one solve's "
                          "refinement tail overlaps the next solve's setup and sweeps")
+    ap.add_argument("--scan", type=int, default=0,
+                    help="refinement backward recursion: 0 sequential, 2/4/8 associative "
+                         "scan over that many chunks of the horizon")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: time captured-graph replays (phase times then come from a "
                          "second, uncaptured loop)")
@@ -496,7 +499,7 @@ def main():
     torch.cuda.set_device(0)
     settings = dict(iters=args.iters, form=args.form, rho=args.rho,
                     refine_passes=args.refine_passes, first_passes=args.first_passes,
-                    precision=args.precision)
+                    precision=args.precision, scan=args.scan)
     if args.serving:
         if args.autotune:
             # the schedule tuned on a held-out slice of the serving workload
@@ -532,6 +535,9 @@ def main():
     batch = mpcgen.make_batch(args.workload)
     Bn, n = batch["A"].shape[0], batch["A"].shape[1]
     stages = int(batch["N"].sum())
+    if n > 64:   # the long-horizon refinement budget (also for a fixed schedule)
+        for k, v in LONG_BASE.items():
+            settings.setdefault(k, v)
     dev = binding.to_device(batch, "cuda:0")
     nst = max(1, args.streams)
     solvers = [binding.Solver(0, **settings) for _ in range(nst)]
@@ -636,7 +642,7 @@ def main():
             "dense_flops_per_solve": dense_flops}
     kernels = {
         "setup_kernel": {"ms": setup_ms},
-        "admm": {"ms": admm_ms, "form": {0: "plain", 1: "fused", -1: "packed"}[settings["form"]]},
+        "admm": {"ms": admm_ms, "form": {0: "plain", 1: "fused", -1: "packed", 2: "split"}[settings["form"]]},
         "refine_kernel": {"ms": refine_ms},
     }
     # algorithmic work of each phase per launch
@@ -713,7 +719,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "batch": int(Bn), "horizon": int(n),
                    "admm_iters": K, "rho": settings["rho"],
-                   "form": {0: "plain", 1: "fused", -1: "packed"}[settings["form"]],
+                   "form": {0: "plain", 1: "fused", -1: "packed", 2: "split"}[settings["form"]],
                    "precision": "bf16" if settings.get("precision") else "fp32",
                    "refine_passes": int(settings.get("refine_passes", 8)),
                    "first_passes": int(settings.get("first_passes", 4)),

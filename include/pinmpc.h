@@ -116,6 +116,16 @@ typedef struct {
                               (1, 2 or 4; fewer when the horizon leaves no
                               room: each problem takes round_up(25 N, 64)
                               threads of at most 1024); default 1 */
+  int32_t scan;            /* the refinement's backward recursion (the LQ
+                              solve of every active-set pass and the factored
+                              Newton step of every interior-point iteration):
+                              0: sequential over the horizon, one wave per
+                              problem; 2, 4 or 8: an associative scan over
+                              that many chunks of the horizon (one wave per
+                              chunk; depth about 3 N / W + W stage steps
+                              instead of N; results equal the sequential
+                              recursion's to rounding).  Horizons shorter than
+                              8 stages stay sequential.  Default 0 */
 } pinmpc_settings;
 
 typedef struct pinmpc_ctx_s* pinmpc_ctx;

@@ -6,7 +6,10 @@ refinement a better active set and fewer passes), the penalty rho (1 to 30),
 the operator precision, then, at the best of those, the active-set pass budget,
 how many of those passes run for every problem before the uncertified ones are
 handed to the second refinement launch, and how many problems share one
-workgroup of the fused sweep (1, 2 or 4 where they fit).  The sweep form follows the
+workgroup of the fused sweep (1, 2 or 4 where they fit); last, at the best of
+everything so far, whether the refinement's backward recursion runs
+sequentially over the horizon or as an associative scan over 2, 4 or 8 chunks
+of it (one wave per chunk).  The sweep form follows the
 horizon (fused up to 40 stages, packed by horizon class beyond).  Every
 candidate's mean refinement work is logged beside its time, which gives the
 refinement-passes-versus-K curve of the workload.  The score
@@ -47,6 +50,7 @@ ITERS = (1, 2, 3, 5, 10, 20, 50, 100, 200)
 PASSES = (2, 4, 8, 12, 16)
 FIRSTS = (0, 2, 4)
 GROUPS = (1, 2, 4)
+SCANS = (0, 2, 4, 8)
 BASE_PASSES, BASE_FIRST = 12, 0
 
 
@@ -70,7 +74,7 @@ def stage_a(n_max, allow_bf16=False):
     precs = [0, 1] if allow_bf16 else [0]
     for r, k, p in itertools.product(RHOS, ITERS, precs):
         yield dict(form=form_for(n_max), iters=k, rho=r, refine_passes=BASE_PASSES,
-                   first_passes=BASE_FIRST, precision=p, group=1)
+                   first_passes=BASE_FIRST, precision=p, group=1, scan=0)
 
 
 def stage_b(best, n_max=20):
@@ -83,12 +87,24 @@ def stage_b(best, n_max=20):
         yield dict(best, refine_passes=pa, first_passes=p1, group=g)
 
 
+def stage_c(best, n_max=20):
+    """Third stage: the refinement's backward recursion, sequential or an
+    associative scan over 2, 4 or 8 chunks of the horizon, at the best
+    schedule of the first two stages (horizons under 8 stages always run
+    sequentially, so only longer ones try the scan)."""
+    if n_max < 8:
+        return
+    for w in SCANS:
+        if w != best.get("scan", 0):
+            yield dict(best, scan=w)
+
+
 def candidates(n_max, allow_bf16=False):
     """Every candidate the search can measure (both stages over all first-stage
     winners); the search itself measures stage_a, then stage_b of its best."""
     seen = set()
     for a in stage_a(n_max, allow_bf16):
-        for c in [a, *stage_b(a, n_max)]:
+        for c in [a, *stage_b(a, n_max), *stage_c(a, n_max)]:
             key = tuple(sorted(c.items()))
             if key not in seen:
                 seen.add(key)
@@ -160,6 +176,8 @@ def tune(dev, allow_bf16=False, cache_path=DEFAULT_CACHE, min_certified=0.999, v
     run(stage_a(int(dev["A"].shape[1]), allow_bf16))
     if best is not None:
         run(list(stage_b(best, int(dev["A"].shape[1]))))
+    if best is not None:
+        run(list(stage_c(best, int(dev["A"].shape[1]))))
     for sv in solvers:
         sv.close()
     LAST_LOG = log

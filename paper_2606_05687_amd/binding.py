@@ -38,6 +38,7 @@ class Settings(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("first_passes", ctypes.c_int32),
         ("group", ctypes.c_int32),
+        ("scan", ctypes.c_int32),
     ]
 
 

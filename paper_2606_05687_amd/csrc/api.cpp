@@ -26,7 +26,7 @@ static bool same_settings(const pinmpc_settings& a, const pinmpc_settings& b) {
          a.refine_passes == b.refine_passes && a.ipm_iters == b.ipm_iters &&
          a.polish_passes == b.polish_passes && a.kkt_tol == b.kkt_tol &&
          a.precision == b.precision && a.form == b.form && a.graph == b.graph &&
-         a.first_passes == b.first_passes && a.group == b.group;
+         a.first_passes == b.first_passes && a.group == b.group && a.scan == b.scan;
 }
 
 static bool same_key(const GraphKey& a, const GraphKey& b) {
@@ -129,6 +129,7 @@ int check_settings(const pinmpc_settings* s) {
   if (s->graph < 0 || s->graph > 1) return PINMPC_EINVAL;
   if (s->first_passes < 0) return PINMPC_EINVAL;
   if (s->group != 1 && s->group != 2 && s->group != 4) return PINMPC_EINVAL;
+  if (s->scan != 0 && s->scan != 2 && s->scan != 4 && s->scan != 8) return PINMPC_EINVAL;
   // a refinement needs at least one pass or interior-point iteration: the
   // outputs are the last pass's solution
   if (s->refine && s->refine_passes == 0 && s->ipm_iters == 0) return PINMPC_EINVAL;
@@ -262,6 +263,7 @@ void pinmpc_default_settings(pinmpc_settings* s) {
   s->graph = 1;
   s->first_passes = 4;
   s->group = 1;
+  s->scan = 0;
 }
 
 int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
@@ -276,7 +278,8 @@ int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return PINMPC_EDEVICE;
-  if (hipSetDevice(device) != hipSuccess) return PINMPC_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess || refine_prepare() != hipSuccess)
+    return PINMPC_EDEVICE;
   pinmpc_ctx c = new (std::nothrow) pinmpc_ctx_s;
   if (!c) return PINMPC_ENOMEM;
   c->device = device;

@@ -429,6 +429,9 @@ hipError_t launch_admm_sweep_class(const Problem& p, const Workspace& w,
                                    hipStream_t st);
 hipError_t launch_admm_extract(const Problem& p, const Workspace& w, int accel,
                                float* z_out, hipStream_t st);
+// Once per device before the first solve: lets the refinement's scanning
+// kernels take the dynamic LDS they need (see the scan setting).
+hipError_t refine_prepare();
 hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                          const pinmpc_out& out, hipStream_t st);
 

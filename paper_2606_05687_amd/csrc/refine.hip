@@ -62,7 +62,21 @@ __device__ inline void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
-__device__ inline void gsync() { __syncthreads(); }
+// With the associative scan of the backward recursion a problem's workgroup
+// holds several waves; the first runs the refinement and the others join it
+// only at the scan's own barriers.  There, the hand-off between lanes of the
+// first wave needs the fence alone (the waves of a workgroup share the CU's
+// caches), never the workgroup barrier.
+__device__ inline void gsync() {
+  if (blockDim.x == W64) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+// lane within the wave (the workgroup may hold several waves)
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63); }
 
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -225,16 +239,17 @@ __device__ void face_affine(int code, double mu, double fz, double tm, double P[
 // Hand-off buffers of the stage recursion; everything else of a stage lives
 // in registers as 16 x 16 tiles.
 constexpr int GS = NU + NX + 2;   // row stride of the Gauss-Jordan hand-off
+struct ShR {
+  double G[NU * GS];     // [H | Hwx | hw] of the stage, row-major
+  double KK[NU * 16];    // [K | 0 | kap]: gains, feedforward in column 13
+  double HI[NU * 16];    // H^{-1} (Newton steps, chunk summaries)
+  double ST[16 * 17];    // S of the stage, for its transpose
+};
 struct Sh {
   // the Riccati recursion's hand-off buffers and the costate recursion's
   // stage vectors share storage: the two never run at the same time
   union {
-    struct {
-      double G[NU * GS];     // [H | Hwx | hw] of the stage, row-major
-      double KK[NU * 16];    // [K | 0 | kap]: gains, feedforward in column 13
-      double HI[NU * 16];    // H^{-1} (Newton steps)
-      double ST[16 * 17];    // S of the stage, for its transpose
-    } r;
+    ShR r;
     struct {
       double PV[PINMPC_NMAX * 16];   // Q (x_{k+1} - r_k), then p_{k+1}
       double GV[PINMPC_NMAX * 16];   // R (u_k - u_ref_k), then g_k
@@ -286,8 +301,8 @@ __device__ inline d4 zero4() {
   d4 z = {0.0, 0.0, 0.0, 0.0};
   return z;
 }
-__device__ inline int tg() { return threadIdx.x >> 4; }
-__device__ inline int tj() { return threadIdx.x & 15; }
+__device__ inline int tg() { return lane_id() >> 4; }
+__device__ inline int tj() { return lane_id() & 15; }
 
 // U^T V + acc, contracting over the first 4 NQ rows (NQ = 3: the input rows).
 template <int NQ>
@@ -414,7 +429,7 @@ __device__ inline void st_map(gd base, int doubles, uint32_t map, d4 t) {
 // row weight z / (s sc^2), linear coefficient (z + (-rc + z rp) / s) / sc with
 // rp = (g u - h) / sc + s.
 __device__ void build_tiles(const Ctx& C, bool newton, gcd rcvec, int kn) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   for (int e = lane; e < kn * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     gd base = C.rT + (size_t)k * TS_T + i * 42;
@@ -622,6 +637,363 @@ __device__ inline double dot_row_bcast12(double v, const double (&a)[12], double
   return (s + s1) + (s2 + s3);
 }
 
+// Backward recursion over stages k_hi - 1 down to k_lo from the value
+// function Ss of x_{k_hi} (S in columns 0..12, s in VC); returns the value
+// function of x_{k_lo}.  It stores each stage's gains and feedforward (and,
+// for equality passes, its value function; for Newton steps H^-1 and Hwx).
+// ELEM: the chunk summary of the associative scan instead (see below): the
+// recursion starts from a zero value at x_{k_hi}, stores nothing and also
+// composes the closed-loop affine map TE (transposed, offset in row 13,
+// (13, 13) = 1) and the reachability term CE of the chunk.
+template <Mode mode, bool factor, bool LONG, bool ELEM>
+__device__ __attribute__((always_inline)) inline d4 backward(const Ctx& C, ShR& sr, int k_lo,
+                                                             int k_hi, d4 Ss, d4* TEo, d4* CEo) {
+  static_assert(!ELEM || factor, "a chunk summary factors every stage");
+  const int lane = lane_id(), g = tg(), j = tj();
+  constexpr bool newton = (mode == Mode::NEWTON);
+  const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pe = uni(C.e), pur = uni(C.u_ref);
+  const GMEM uint8_t* pct = uni(C.contact);
+  const GMEM int32_t* pfc = uni(C.faces);
+  const gd prT = uni(C.rT), prK = uni(C.rK), prL = uni(C.rL), prH = uni(C.rHwx), prS = uni(C.rS);
+  const gd prkap = uni(C.rkap), prx = uni(C.rx), pru = uni(C.ru), prdx = uni(C.rdx),
+           prdu = uni(C.rdu);
+  // the diagonal weights where this lane uses them
+  const double Qj = C.Q[clampi(j, NX - 1)];
+  d4 Qr, Rr;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Qr[q] = C.Q[clampi(4 * q + g, NX - 1)];
+    Rr[q] = C.R[clampi(4 * q + g, NU - 1)];
+  }
+  // maps of the stage blocks this variant moves
+  const uint32_t mT = map_T();
+  const uint32_t mS = map_S(true);
+  const uint32_t mL = map_rect(NU, NU), mH = map_rect(NU, NX);
+  auto fetch = [&](int k, BackRaw& s) {
+    gather(pA + (size_t)k * NX * NX, false, NX, NX, s.a);
+    gather(pB + (size_t)k * NX * NU, true, NX, NU, s.bt);
+    gatherv(pxr + (size_t)k * NX, NX, s.xr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s.ev[q] = 0.f;
+      s.ur[q] = 0.f;
+      s.xn[q] = 0.0;
+    }
+    if (!newton && pe) gatherv(pe + (size_t)k * NX, NX, s.ev);
+    if (!newton && pur) gatherv(pur + (size_t)k * NU, NU, s.ur);
+    if (newton) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s.xn[q] = prx[(size_t)(k + 1) * NX + clampi(4 * q + g, NX - 1)];
+    }
+    s.T = ld_map(prT + (size_t)k * TS_T, TS_T, mT);
+    if (newton && !factor) {
+      s.HI = ld_map(prL + (size_t)k * TS_L, TS_L, mL);
+      s.HX = ld_map(prH + (size_t)k * TS_H, TS_H, mH);
+    } else {
+      s.HI = s.HX = zero4();
+    }
+    s.ct = newton ? (int)pct[k * 2 + (j < NU ? j / 6 : 0)] : 0;
+    s.c0 = __builtin_amdgcn_readfirstlane((int)pct[k * 2]);
+    s.c1 = __builtin_amdgcn_readfirstlane((int)pct[k * 2 + 1]);
+    s.f0 = newton ? 0 : __builtin_amdgcn_readfirstlane(pfc[k * 2]);
+    s.f1 = newton ? 0 : __builtin_amdgcn_readfirstlane(pfc[k * 2 + 1]);
+  };
+
+  BackRaw raw;
+  fetch(k_hi > k_lo ? k_hi - 1 : k_lo, raw);
+  d4 TE = zero4(), CE = zero4();
+  if constexpr (ELEM) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) TE[q] = (4 * q + g == j && j <= VC) ? 1.0 : 0.0;
+  }
+  for (int k = k_hi - 1; k >= k_lo; --k) {
+    // this stage's data
+    const d4 At = cook(raw.a, false, NX, NX);
+    const d4 BT = cook(raw.bt, true, NX, NU);
+    const d4 T = raw.T, HIs = raw.HI, HXs = raw.HX;
+    d4 om, ev, ur;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * q + g;
+      const bool vr = (j == VC && r < NX);
+      const double xr = (double)raw.xr[q];
+      om[q] = vr ? (newton ? Qr[q] * (raw.xn[q] - xr) : -Qr[q] * xr) : 0.0;
+      ev[q] = vr ? (double)raw.ev[q] : 0.0;
+      ur[q] = (j == VC && r < NU) ? (double)raw.ur[q] : 0.0;
+    }
+    if (ELEM && k == k_hi - 1) {
+      // a zero value at x_{k_hi}: S = -Q and s = -q make W = S + Q and
+      // q + s vanish at the chunk's last stage
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        Ss[q] = (j < NX && 4 * q + g == j) ? -Qj : ((j == VC) ? -om[q] : 0.0);
+    }
+    const d4 Pt = newton ? mask_tile(raw.ct) : sel(j < NU, T);
+    const uint32_t unit = null_inputs(raw.c0, raw.c1, raw.f0, raw.f1, newton);
+    pin(At); pin(BT); pin(T); pin(om); pin(ev); pin(ur); pin(Pt);
+    if (newton && !factor) { pin(HIs); pin(HXs); }
+    pin_memory();
+    if (k > k_lo) fetch(k - 1, raw);
+
+    // [Bp | 0 | d] = B [P | 0 | c] + [0 | 0 | e]
+    const d4 yc = (!newton && j == VC) ? T : Pt;
+    d4 D1 = mmT<3>(BT, yc, ev);
+    d4 PRP = zero4();
+    if (!newton && factor) {
+      d4 RP;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) RP[q] = (j < NU && 4 * q + g < NU) ? Rr[q] * T[q] : 0.0;
+      const d4 Py = (j < NU) ? T : sel(j == VC, T - ur);
+      PRP = mmT<3>(RP, Py, zero4());
+    }
+    const d4 Bp = sel(j < NU, D1);
+    d4 Sn;
+    if (factor) {
+      d4 Wt;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        Wt[q] = (j < NX) ? Ss[q] + ((4 * q + g == j) ? Qj : 0.0) : 0.0;
+      const d4 yA = (j < NX) ? At : sel(j == VC, D1);
+      d4 D2 = mmT<4>(Wt, yA, zero4());      // [W A | W d]
+      if (j == VC) D2 += om + Ss;            // [W A | W d + q + s]
+      const d4 D3 = mmT<4>(Wt, Bp, zero4()); // W Bp
+      d4 D4 = mmT<4>(Bp, D3, zero4());       // Bp^T W Bp
+      const d4 D5 = mmT<4>(Bp, D2, zero4()); // [Hwx | Bp^T (W d + q + s)]
+      if (newton) {
+        // P R' P and P rho straight from the stage tile (P a mask there)
+        D4 += sel(j < NU || j == VC, T);
+      } else {
+        // P R P and P R (c - u_ref) = P (R c + rho), independent of the chain
+        // above (its instructions overlap it)
+        D4 += PRP;
+      }
+      // A^T [W A | W d + q + s]: the part of S that needs no gains, issued
+      // before the elimination
+      const d4 SA = mmT<4>(At, D2, zero4());
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int r = 4 * q + g;
+        if (j < NU) sr.G[r * GS + j] = D4[q] + ((r == j) ? 1.0 : 0.0) - Pt[q];
+        if (j < NX) sr.G[r * GS + NU + j] = D5[q];
+        if (j == VC) sr.G[r * GS + NU + NX] = D5[q] + D4[q];
+      }
+      wsync();
+      // Gauss-Jordan elimination (H is SPD: no pivoting) of [H | Hwx | hw]
+      // (and, for Newton steps, which keep H^-1, of [H | I] beside it): lane
+      // 16 R + c holds column c of H (c < NU, the same in every row R) or
+      // right-hand side 4 R + c - NU (Hwx columns 0..12, hw as 13 = VC;
+      // identity columns 0..11); afterwards the right-hand sides are
+      // H^-1 Hwx, H^-1 hw (and H^-1).
+      static_assert(NU == 12, "row elimination is written for 12 inputs");
+      const int hc = lane & 15, rhs = 4 * (lane >> 4) + hc - NU;
+      const bool is_h = hc < NU;
+      double col[NU];
+#pragma unroll
+      for (int r = 0; r < NU; ++r)
+        col[r] = (is_h || rhs <= NX) ? sr.G[r * GS + (is_h ? hc : NU + rhs)] : 0.0;
+      if constexpr (!newton && !ELEM) {
+        gj_rows(col, unit);
+      } else {
+        double icol[NU];
+#pragma unroll
+        for (int r = 0; r < NU; ++r) icol[r] = is_h ? col[r] : ((r == rhs) ? 1.0 : 0.0);
+        gj_rows2(col, icol, unit);
+        if (!is_h && rhs < NU) {
+#pragma unroll
+          for (int r = 0; r < NU; ++r) sr.HI[r * 16 + rhs] = icol[r];
+        }
+      }
+      if (!is_h && rhs <= NX) {
+#pragma unroll
+        for (int r = 0; r < NU; ++r) sr.KK[r * 16 + rhs] = -col[r];
+      }
+      wsync();
+      d4 KK;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g;
+        KK[q] = (r < NU && (j < NX || j == VC)) ? sr.KK[r * 16 + j] : 0.0;   // [K | kap]
+      }
+      if constexpr (!ELEM) {
+        // K row-major (row r at NX r) for the rollout; rows 4q + g, q < 3, are
+        // the 12 input rows (kap goes to its own vector)
+        if (j < NX) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) prK[(size_t)k * TS_K + (4 * q + g) * NX + j] = KK[q];
+        }
+        vec_store(prkap + (size_t)k * NU, NU, KK);
+        if (newton) {
+          d4 HI;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = 4 * q + g;
+            HI[q] = (r < NU && j < NU) ? sr.HI[r * 16 + j] : 0.0;
+          }
+          st_map(prL + (size_t)k * TS_L, TS_L, mL, HI);
+          st_map(prH + (size_t)k * TS_H, TS_H, mH, D5);
+        }
+      } else {
+        d4 HI;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 4 * q + g;
+          HI[q] = (r < NU && j < NU) ? sr.HI[r * 16 + j] : 0.0;
+        }
+        // the stage's closed-loop map [A + Bp K | d + Bp kap] with a 1 at
+        // (13, 13), composed after the chunk's map; the reachability term
+        // grows by A_E Bp H^-1 Bp^T A_E^T (A_E before the composition)
+        const d4 BpT = mmT<3>(Pt, BT, zero4());    // (B P)^T = P B^T
+        const d4 LK = mmT<3>(BpT, KK, zero4());    // [Bp K | Bp kap]
+        d4 Ah;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 4 * q + g;
+          Ah[q] = (j < NX) ? At[q] + LK[q]
+                           : ((j == VC) ? ((r < NX) ? LK[q] + D1[q] : (r == VC ? 1.0 : 0.0)) : 0.0);
+        }
+        const d4 ZT = mmT<4>(Bp, TE, zero4());     // (A_E Bp)^T
+        const d4 Y = mmT<3>(HI, ZT, zero4());      // H^-1 (A_E Bp)^T
+        CE = mmT<3>(ZT, Y, CE);
+        TE = mmT<4>(Ah, TE, zero4());
+      }
+      // S = A^T W A + Hwx^T K, s = A^T (W d + q + s) + Hwx^T kap
+      Sn = mmT<3>(sel(j < NX, D5), KK, SA);
+      // keep S exactly symmetric: its rounding is not, and an asymmetric part
+      // is carried back through the open-loop A and grows along the horizon
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sr.ST[(4 * q + g) * 17 + j] = Sn[q];
+      wsync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g;
+        if (r < NX && j < NX) Sn[q] = 0.5 * (Sn[q] + sr.ST[j * 17 + r]);
+      }
+      if (mode == Mode::EQ && !ELEM) st_map(prS + (size_t)k * TS_S, TS_S, mS, Sn);
+      wsync();
+    } else {
+      // second right-hand side of the stored Newton matrix (d = 0, so
+      // W d + q + s = q + s)
+      const d4 wv = sel(j == VC, om + Ss);
+      d4 hw = mmT<4>(Bp, wv, zero4());
+      hw += sel(j == VC, T);
+      const d4 kap = -mmT<3>(HIs, hw, zero4());
+      vec_store(prkap + (size_t)k * NU, NU, kap);
+      Sn = mmT<4>(At, wv, zero4());
+      Sn = mmT<3>(HXs, kap, Sn);
+    }
+    Ss = Sn;
+  }
+  if constexpr (ELEM) {
+    *TEo = TE;
+    *CEo = CE;
+  }
+  return Ss;
+}
+
+// Forward rollout after the backward recursion (all N stages).
+template <Mode mode, bool LONG>
+__device__ __attribute__((always_inline)) inline void forward(const Ctx& C, Sh& sh) {
+  const int N = __builtin_amdgcn_readfirstlane(C.N);
+  const int lane = lane_id();
+  constexpr bool newton = (mode == Mode::NEWTON);
+  const gcf pA = uni(C.A), pB = uni(C.B), pe = uni(C.e);
+  const GMEM uint8_t* pct = uni(C.contact);
+  const gd prT = uni(C.rT), prK = uni(C.rK), prkap = uni(C.rkap), prx = uni(C.rx),
+           pru = uni(C.ru), prdx = uni(C.rdx), prdu = uni(C.rdu);
+  // forward rollout: w = K x + kap, u = P^T w + c (P from the stage tile;
+  // the stance mask for Newton steps), x' = A x + B u + e.  It is a chain of
+  // 13-vector products, so it runs on the vector units: lane i of every
+  // 16-lane row holds x_i, w_i, u_i (the rows identical) with row i of K, A,
+  // B and column i of P, and each product is a block of fused multiply-adds
+  // whose vector factor arrives by DPP row broadcast.  The stage data is
+  // fetched a stage ahead (unconditionally, so every path back to the loop
+  // head has issued the same loads); u_k and x_{k+1} collect in LDS (the
+  // costate buffers, free here) and are copied out after the loop.
+  gd xout = newton ? prdx : prx;
+  gd uout = newton ? prdu : pru;
+  const StageBufs<LONG> sb(sh, C);
+  const int fi = lane & 15;
+  const int ix = clampi(fi, NX - 1), iu = clampi(fi, NU - 1);
+  const gcf pev = pe ? pe : pA;   // a valid address when there is no e
+  struct FwdRaw {
+    double kr[NX];   // K[i][0..12]
+    double p6[6];    // P[6 (i / 6) + a][i], a = 0..5 (equality passes)
+    double c, kap;
+    float a[NX], b[NU], e;
+    int ct;
+  };
+  auto ffetch = [&](int k, FwdRaw& s) {
+    const gcd kr = prK + (size_t)k * TS_K + iu * NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s.kr[r] = kr[r];
+    s.kap = prkap[(size_t)k * NU + iu];
+    if (!newton) {
+      // column iu of P is nonzero only inside its contact's block
+      const gcd tt = prT + (size_t)k * TS_T + (iu / 6) * 42;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) s.p6[a] = tt[a * 6 + iu % 6];
+      s.c = tt[36 + iu % 6];
+    }
+    const gcf ar = pA + (size_t)k * NX * NX + ix * NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s.a[r] = ar[r];
+    const gcf br = pB + (size_t)k * NX * NU + ix * NU;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) s.b[r] = br[r];
+    s.e = pev[pe ? (size_t)k * NX + ix : 0];
+    s.ct = newton ? (int)pct[k * 2 + iu / 6] : 0;
+  };
+  double xv = 0.0;   // x_k, entry fi
+  if (!newton) xv = (double)uni(C.x0)[ix];
+  FwdRaw fr;
+  ffetch(0, fr);
+  pin_memory();
+  for (int k = 0; k < N; ++k) {
+    double kr[NX], pc[NU], a[NX], b[NU];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      kr[r] = fr.kr[r];
+      a[r] = (double)fr.a[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      pc[r] = (newton || r / 6 != iu / 6) ? 0.0 : fr.p6[r % 6];
+      b[r] = (double)fr.b[r];
+    }
+    const double kap = fr.kap, cc = newton ? 0.0 : fr.c;
+    const double ee = (!newton && pe) ? (double)fr.e : 0.0;
+    const bool stance = fr.ct != 0;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      pin(kr[r]);
+      pin(a[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      pin(pc[r]);
+      pin(b[r]);
+    }
+    pin_memory();
+    ffetch(k + 1 < N ? k + 1 : k, fr);
+    const double w = dot_row_bcast13(xv, kr, kap);
+    const double u = newton ? (stance ? w : 0.0) : dot_row_bcast12(w, pc, cc);
+    double xn = dot_row_bcast13(xv, a, ee);
+    xn = dot_row_bcast12(u, b, xn);
+    if (lane < NU) sb.GV[k * 16 + fi] = u;
+    if (lane < NX) sb.PV[k * 16 + fi] = xn;
+    xv = xn;
+  }
+  bufsync<LONG>();
+  if (lane < NX) xout[lane] = newton ? 0.0 : (double)uni(C.x0)[lane];
+  for (int e = lane; e < N * NU; e += W64) uout[e] = sb.GV[(e / NU) * 16 + e % NU];
+  for (int e = lane; e < N * NX; e += W64) xout[NX + e] = sb.PV[(e / NX) * 16 + e % NX];
+  gsync();
+}
+
+// The sequential recursion over the whole horizon (one wave), then the
+// rollout.  Its stage loop is the one `backward` runs, written out here once
+// more: compiled through the shared function, this hot loop took about 230
+// more register moves per stage and its launch about 4 % longer.
 template <Mode mode, bool factor, bool LONG>
 __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rcvec, int ktop) {
   const int N = __builtin_amdgcn_readfirstlane(C.N);
@@ -629,7 +1001,7 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
   gsync();
   build_tiles(C, mode == Mode::NEWTON, rcvec, ktop);
   gsync();
-  const int lane = threadIdx.x, g = tg(), j = tj();
+  const int lane = lane_id(), g = tg(), j = tj();
   constexpr bool newton = (mode == Mode::NEWTON);
   const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pe = uni(C.e), pur = uni(C.u_ref);
   const GMEM uint8_t* pct = uni(C.contact);
@@ -829,98 +1201,286 @@ __device__ __attribute__((noinline)) void riccati_t(const Ctx& C, Sh& sh, gcd rc
     Ss = Sn;
   }
 
-  // forward rollout: w = K x + kap, u = P^T w + c (P from the stage tile;
-  // the stance mask for Newton steps), x' = A x + B u + e.  It is a chain of
-  // 13-vector products, so it runs on the vector units: lane i of every
-  // 16-lane row holds x_i, w_i, u_i (the rows identical) with row i of K, A,
-  // B and column i of P, and each product is a block of fused multiply-adds
-  // whose vector factor arrives by DPP row broadcast.  The stage data is
-  // fetched a stage ahead (unconditionally, so every path back to the loop
-  // head has issued the same loads); u_k and x_{k+1} collect in LDS (the
-  // costate buffers, free here) and are copied out after the loop.
-  gd xout = newton ? prdx : prx;
-  gd uout = newton ? prdu : pru;
-  const StageBufs<LONG> sb(sh, C);
-  const int fi = lane & 15;
-  const int ix = clampi(fi, NX - 1), iu = clampi(fi, NU - 1);
-  const gcf pev = pe ? pe : pA;   // a valid address when there is no e
-  struct FwdRaw {
-    double kr[NX];   // K[i][0..12]
-    double p6[6];    // P[6 (i / 6) + a][i], a = 0..5 (equality passes)
-    double c, kap;
-    float a[NX], b[NU], e;
-    int ct;
-  };
-  auto ffetch = [&](int k, FwdRaw& s) {
-    const gcd kr = prK + (size_t)k * TS_K + iu * NX;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s.kr[r] = kr[r];
-    s.kap = prkap[(size_t)k * NU + iu];
-    if (!newton) {
-      // column iu of P is nonzero only inside its contact's block
-      const gcd tt = prT + (size_t)k * TS_T + (iu / 6) * 42;
-#pragma unroll
-      for (int a = 0; a < 6; ++a) s.p6[a] = tt[a * 6 + iu % 6];
-      s.c = tt[36 + iu % 6];
-    }
-    const gcf ar = pA + (size_t)k * NX * NX + ix * NX;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s.a[r] = ar[r];
-    const gcf br = pB + (size_t)k * NX * NU + ix * NU;
-#pragma unroll
-    for (int r = 0; r < NU; ++r) s.b[r] = br[r];
-    s.e = pev[pe ? (size_t)k * NX + ix : 0];
-    s.ct = newton ? (int)pct[k * 2 + iu / 6] : 0;
-  };
-  double xv = 0.0;   // x_k, entry fi
-  if (!newton) xv = (double)uni(C.x0)[ix];
-  FwdRaw fr;
-  ffetch(0, fr);
-  pin_memory();
-  for (int k = 0; k < N; ++k) {
-    double kr[NX], pc[NU], a[NX], b[NU];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      kr[r] = fr.kr[r];
-      a[r] = (double)fr.a[r];
-    }
-#pragma unroll
-    for (int r = 0; r < NU; ++r) {
-      pc[r] = (newton || r / 6 != iu / 6) ? 0.0 : fr.p6[r % 6];
-      b[r] = (double)fr.b[r];
-    }
-    const double kap = fr.kap, cc = newton ? 0.0 : fr.c;
-    const double ee = (!newton && pe) ? (double)fr.e : 0.0;
-    const bool stance = fr.ct != 0;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      pin(kr[r]);
-      pin(a[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < NU; ++r) {
-      pin(pc[r]);
-      pin(b[r]);
-    }
-    pin_memory();
-    ffetch(k + 1 < N ? k + 1 : k, fr);
-    const double w = dot_row_bcast13(xv, kr, kap);
-    const double u = newton ? (stance ? w : 0.0) : dot_row_bcast12(w, pc, cc);
-    double xn = dot_row_bcast13(xv, a, ee);
-    xn = dot_row_bcast12(u, b, xn);
-    if (lane < NU) sb.GV[k * 16 + fi] = u;
-    if (lane < NX) sb.PV[k * 16 + fi] = xn;
-    xv = xn;
-  }
-  bufsync<LONG>();
-  if (lane < NX) xout[lane] = newton ? 0.0 : (double)uni(C.x0)[lane];
-  for (int e = lane; e < N * NU; e += W64) uout[e] = sb.GV[(e / NU) * 16 + e % NU];
-  for (int e = lane; e < N * NX; e += W64) xout[NX + e] = sb.PV[(e / NX) * 16 + e % NX];
-  gsync();
+  forward<mode, LONG>(C, sh);
 }
 
+// ---------------------------------------- associative scan over the horizon
+//
+// The backward recursion composes one map of the value function per stage,
+// and that composition is associative.  With the horizon [0, ktop) cut into
+// chunks, each chunk's composition (its summary) is formed on its own, the
+// value functions at the chunk boundaries follow from the summaries alone,
+// from the last chunk back to the first, and every chunk then runs the
+// ordinary recursion from its boundary value, all chunks at once.  The
+// summary of stages [k0, k1), from a zero value at x_{k1}, is
+//   A_E, b_E  the closed-loop affine map from x_{k0} to x_{k1} (TE),
+//   C_E       its reachability term, the sum of A' Bp H^-1 Bp^T A'^T (CE),
+//   S_E, s_E  the value function of x_{k0} (SE),
+// and the value function at x_{k0} for a value (S, s) at x_{k1} is, with
+// J = S + Q and eta = -(s + q_{k1-1}) (the cost of x_{k1} included),
+//   G = (J^-1 + C_E)^-1,   S_0 = A_E^T G A_E + S_E,
+//   s_0 = s_E - A_E^T (I - G C_E)(eta - J b_E).
+// The recursion is the paper's horizon-parallel treatment (Sec. III) applied
+// to the LQ solve of the refinement: depth about 3 N / W + W stage steps for
+// W chunks instead of N.  One wave per chunk: the problem's first wave runs
+// the refinement; the others (helpers) take the scan's commands at the
+// workgroup barrier and run the summaries and recursions of their chunks.
+
+constexpr int SCAN_WMAX = 8;       // chunks (waves) per problem
+constexpr int SCAN_MIN_CHUNK = 4;  // fewer stages per chunk: sequential
+enum { SCAN_EXIT = 0, SCAN_EQ = 1, SCAN_NEWTON = 2 };
+struct ScanCtl {
+  int op, nch;
+  int bounds[SCAN_WMAX + 1];
+};
+constexpr int TILE_D = 256;   // doubles of a register tile kept in LDS (lane-major)
+
+__shared__ ScanCtl scan_ctl;
+extern __shared__ __attribute__((aligned(16))) double scan_dyn[];
+
+// Dynamic LDS of a scanning workgroup with W waves: the helpers' hand-off
+// buffers, three summary tiles per chunk and a boundary value per chunk.
+struct ScanLds {
+  ShR* shr;
+  double* exch;
+  double* bnd;
+};
+__device__ inline ScanLds scan_lds(int W) {
+  ScanLds L;
+  L.shr = reinterpret_cast<ShR*>(scan_dyn);
+  L.exch = scan_dyn + (size_t)(W - 1) * (sizeof(ShR) / 8);
+  L.bnd = L.exch + (size_t)W * 3 * TILE_D;
+  return L;
+}
+
+__device__ inline void st_tile_lds(double* base, const d4& t) {
+  const int l = lane_id();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) base[l * 4 + q] = t[q];
+}
+__device__ inline d4 ld_tile_lds(const double* base) {
+  const int l = lane_id();
+  d4 t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = base[l * 4 + q];
+  return t;
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Inverse of the SPD 13 x 13 block of a tile by Gauss-Jordan elimination
+// without pivoting: lane c < 13 holds column c of the matrix, lane 16 + c
+// column c of the identity; each pivot's column reaches every lane by lane
+// reads.  buf: 256 doubles of LDS.
+__device__ d4 inv13(const d4& M, double* buf) {
+  const int lane = lane_id(), g = tg(), j = tj();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) buf[(4 * q + g) * 16 + j] = M[q];
+  wsync();
+  const int c = lane & 15;
+  const bool mat = lane < NX, idn = lane >= 16 && lane < 16 + NX;
+  double col[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) col[r] = mat ? buf[r * 16 + c] : ((idn && r == c) ? 1.0 : 0.0);
+  wsync();
+#pragma unroll
+  for (int pv = 0; pv < NX; ++pv) {
+    double m[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) m[r] = readlane_d(col[r], pv);
+    const double rp = col[pv] * recip(m[pv]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+      if (r != pv) col[r] = fma(-m[r], rp, col[r]);
+    col[pv] = rp;
+  }
+  if (idn) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) buf[r * 16 + c] = col[r];
+  }
+  wsync();
+  d4 R;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    R[q] = (r < NX && j < NX) ? buf[r * 16 + j] : 0.0;
+  }
+  wsync();
+  return R;
+}
+
+// S exactly symmetric on its 13 x 13 block (the average with its transpose).
+__device__ inline d4 symmetrize(d4 S, double* buf) {
+  const int g = tg(), j = tj();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) buf[(4 * q + g) * 17 + j] = S[q];
+  wsync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    if (r < NX && j < NX) S[q] = 0.5 * (S[q] + buf[j * 17 + r]);
+  }
+  wsync();
+  return S;
+}
+
+// Value function [S_0 | s_0] at x_{k0} of a chunk with summary (TE, CE, SE)
+// for the value V = [S | s] at x_{k1}; om holds q_{k1-1} in column VC.
+__device__ d4 combine_value(const d4& TE, const d4& CE, const d4& SE, const d4& V, const d4& om,
+                            double Qj, double* buf) {
+  const int g = tg(), j = tj();
+  d4 J, eta, E13;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    J[q] = (j < NX) ? V[q] + ((r == j) ? Qj : 0.0) : 0.0;
+    eta[q] = (j == VC && r < NX) ? -(V[q] + om[q]) : 0.0;
+    E13[q] = (r == VC && j == VC) ? 1.0 : 0.0;
+  }
+  const d4 Ji = inv13(J, buf);
+  d4 X;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) X[q] = (j < NX) ? Ji[q] + CE[q] : 0.0;
+  const d4 G = inv13(X, buf);
+  // b_E (row 13 of TE) as column VC, then t = eta - J b_E, u = (I - G C_E) t
+  d4 bE = mmT<4>(TE, E13, zero4());
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bE[q] = (4 * q + g < NX) ? bE[q] : 0.0;
+  const d4 t = eta - mmT<4>(J, bE, zero4());
+  const d4 u = t - mmT<4>(G, mmT<4>(CE, t, zero4()), zero4());
+  // A_E: the transpose of TE's 13 x 13 block
+#pragma unroll
+  for (int q = 0; q < 4; ++q) buf[(4 * q + g) * 16 + j] = TE[q];
+  wsync();
+  d4 AE;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + g;
+    AE[q] = (r < NX && j < NX) ? buf[j * 16 + r] : 0.0;
+  }
+  wsync();
+  const d4 GA = mmT<4>(G, AE, zero4());
+  d4 S0 = mmT<4>(AE, GA, SE);                     // [A^T G A + S_E | s_E]
+  S0 -= sel(j == VC, mmT<4>(AE, u, zero4()));     // s_E - A^T u
+  return symmetrize(S0, buf);
+}
+
+// The backward recursion as a scan over the horizon (the problem's first
+// wave; the helpers run scan_helper).  Falls back to the sequential recursion
+// when the horizon is too short to cut.
+template <Mode mode, bool LONG>
+__device__ __attribute__((noinline)) void riccati_scan(const Ctx& C, Sh& sh, gcd rcvec, int ktop) {
+  const int N = __builtin_amdgcn_readfirstlane(C.N);
+  ktop = (mode == Mode::EQ) ? __builtin_amdgcn_readfirstlane(ktop < N ? ktop : N) : N;
+  gsync();
+  build_tiles(C, mode == Mode::NEWTON, rcvec, ktop);
+  gsync();
+  constexpr bool newton = (mode == Mode::NEWTON);
+  const int lane = lane_id(), g = tg(), j = tj();
+  const int W = (int)(blockDim.x >> 6);
+  const int nch = __builtin_amdgcn_readfirstlane(
+      ktop / SCAN_MIN_CHUNK < W ? ktop / SCAN_MIN_CHUNK : W);
+  const d4 Vk = (ktop < N) ? ld_map(uni(C.rS) + (size_t)ktop * TS_S, TS_S, map_S(false)) : zero4();
+  if (nch < 2) {
+    backward<mode, true, LONG, false>(C, sh.r, 0, ktop, Vk, nullptr, nullptr);
+    forward<mode, LONG>(C, sh);
+    return;
+  }
+  const ScanLds L = scan_lds(W);
+  if (lane == 0) {
+    scan_ctl.op = newton ? SCAN_NEWTON : SCAN_EQ;
+    scan_ctl.nch = nch;
+    for (int w = 0; w <= nch; ++w) scan_ctl.bounds[w] = (int)(((long)w * ktop) / nch);
+  }
+  __syncthreads();   // the command reaches the helpers
+  __syncthreads();   // the helpers' chunk summaries are in LDS
+  // boundary values, from the last chunk back to the first (the first chunk's
+  // summary is not needed: its recursion starts from the boundary value)
+  const gcf pxr = uni(C.x_ref);
+  const gd prx = uni(C.rx);
+  const double Qj = C.Q[clampi(j, NX - 1)];
+  double* buf = L.exch;   // the first chunk's summary slot, free
+  d4 V = Vk;
+  st_tile_lds(L.bnd + (size_t)(nch - 1) * TILE_D, V);
+  for (int w = nch - 1; w >= 1; --w) {
+    const int k1 = __builtin_amdgcn_readfirstlane((int)(((long)(w + 1) * ktop) / nch));
+    d4 om;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * q + g;
+      const int rc = clampi(r, NX - 1);
+      const double xr = (double)pxr[(size_t)(k1 - 1) * NX + rc];
+      const double Qr = C.Q[rc];
+      om[q] = (j == VC && r < NX) ? (newton ? Qr * (prx[(size_t)k1 * NX + rc] - xr) : -Qr * xr)
+                                  : 0.0;
+    }
+    const double* ex = L.exch + (size_t)w * 3 * TILE_D;
+    V = combine_value(ld_tile_lds(ex), ld_tile_lds(ex + TILE_D), ld_tile_lds(ex + 2 * TILE_D), V,
+                      om, Qj, buf);
+    st_tile_lds(L.bnd + (size_t)(w - 1) * TILE_D, V);
+  }
+  __syncthreads();   // the boundary values reach the helpers
+  backward<mode, true, LONG, false>(C, sh.r, 0, (int)(ktop / nch), V, nullptr, nullptr);
+  __syncthreads();   // every chunk's gains and values are stored
+  forward<mode, LONG>(C, sh);
+}
+
+// A helper wave of a scanning workgroup: summary and recursion of its chunk
+// for every scan command, until the first wave releases it.
+template <bool LONG>
+__device__ __attribute__((noinline)) void scan_helper(const Ctx& C) {
+  const int wave = (int)(threadIdx.x >> 6), W = (int)(blockDim.x >> 6);
+  const ScanLds L = scan_lds(W);
+  ShR& sr = L.shr[wave - 1];
+  for (;;) {
+    __syncthreads();   // a command
+    const int op = __builtin_amdgcn_readfirstlane(scan_ctl.op);
+    if (op == SCAN_EXIT) return;
+    const int nch = __builtin_amdgcn_readfirstlane(scan_ctl.nch);
+    const bool mine = wave < nch;
+    const int k0 = mine ? __builtin_amdgcn_readfirstlane(scan_ctl.bounds[wave]) : 0;
+    const int k1 = mine ? __builtin_amdgcn_readfirstlane(scan_ctl.bounds[wave + 1]) : 0;
+    if (mine) {
+      d4 TE, CE, SE;
+      if (op == SCAN_EQ)
+        SE = backward<Mode::EQ, true, LONG, true>(C, sr, k0, k1, zero4(), &TE, &CE);
+      else
+        SE = backward<Mode::NEWTON, true, LONG, true>(C, sr, k0, k1, zero4(), &TE, &CE);
+      double* ex = L.exch + (size_t)wave * 3 * TILE_D;
+      st_tile_lds(ex, TE);
+      st_tile_lds(ex + TILE_D, CE);
+      st_tile_lds(ex + 2 * TILE_D, SE);
+    }
+    __syncthreads();   // summaries written
+    __syncthreads();   // boundary values written
+    if (mine) {
+      const d4 V = ld_tile_lds(L.bnd + (size_t)wave * TILE_D);
+      if (op == SCAN_EQ)
+        backward<Mode::EQ, true, LONG, false>(C, sr, k0, k1, V, nullptr, nullptr);
+      else
+        backward<Mode::NEWTON, true, LONG, false>(C, sr, k0, k1, V, nullptr, nullptr);
+    }
+    __syncthreads();   // chunk recursions done
+  }
+}
+
+// Releases the helpers of a scanning workgroup (the first wave, once).
+__device__ inline void scan_release() {
+  if (lane_id() == 0) scan_ctl.op = SCAN_EXIT;
+  __syncthreads();
+}
 template <bool LONG>
 __device__ void riccati(const Ctx& C, Sh& sh, Mode mode, bool factor, gcd rcvec, int ktop) {
+  if (blockDim.x > W64 && factor) {   // a scanning workgroup
+    if (mode == Mode::EQ) riccati_scan<Mode::EQ, LONG>(C, sh, rcvec, ktop);
+    else riccati_scan<Mode::NEWTON, LONG>(C, sh, rcvec, ktop);
+    return;
+  }
   if (mode == Mode::EQ) riccati_t<Mode::EQ, true, LONG>(C, sh, rcvec, ktop);
   else if (factor) riccati_t<Mode::NEWTON, true, LONG>(C, sh, rcvec, ktop);
   else riccati_t<Mode::NEWTON, false, LONG>(C, sh, rcvec, ktop);
@@ -943,7 +1503,7 @@ template <bool LONG>
 __device__ __attribute__((noinline)) double costates_grad(const Ctx& C, Sh& sh) {
   gsync();
   const StageBufs<LONG> sb(sh, C);
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   const int N = __builtin_amdgcn_readfirstlane(C.N);
   const gcf pA = uni(C.A), pB = uni(C.B), pxr = uni(C.x_ref), pur = uni(C.u_ref);
   const gd prx = uni(C.rx), pru = uni(C.ru), prlam = uni(C.rlam), prg = uni(C.rg);
@@ -1051,7 +1611,7 @@ __device__ inline void rows_of(const Ctx& C, const double u[6], double gu[NROW],
 __device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double res[PINMPC_NRES],
                                                            double term_state) {
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   double r_ineq = 0.0, stat = 0.0, term = term_state, comp = 0.0, mumax = 0.0, neg = 0.0;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
@@ -1180,7 +1740,7 @@ __device__ __attribute__((noinline)) double multipliers_kkt(const Ctx& C, double
 // Dynamics residual of the FP64 trajectory (rx, ru).
 __device__ __attribute__((noinline)) double dyn_residual(const Ctx& C) {
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   double r = 0.0;
   for (int e = lane; e < C.N * NX; e += W64) {
     const int k = e / NX, i = e % NX;
@@ -1204,7 +1764,7 @@ __device__ __attribute__((noinline)) double dyn_residual(const Ctx& C) {
 // changed (0: none did).
 __device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C, int* ktop) {
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   uint64_t hsh = 0;
   int kch = 0;
   for (int e = lane; e < C.N * 2; e += W64) {
@@ -1241,7 +1801,7 @@ __device__ __attribute__((noinline)) uint64_t pdas_update(const Ctx& C, int* kto
 // Faces from slack: rows whose slack is below tol * row scale.
 __device__ __attribute__((noinline)) void faces_from_u(const Ctx& C, gcd u_src, double tol) {
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
     const int st = k;
@@ -1281,7 +1841,7 @@ __device__ __attribute__((noinline)) double eq_pass(const Ctx& C, Sh& sh, double
 // order-independent hash of the face set.
 __device__ __attribute__((noinline)) uint64_t faces_from_zs(const Ctx& C) {
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   uint64_t hsh = 0;
   for (int e = lane; e < C.N * 2; e += W64) {
     const int k = e >> 1, i = e & 1;
@@ -1324,7 +1884,7 @@ __device__ __attribute__((noinline)) int ipm(const Ctx& C, Sh& sh, int maxit, do
                    double res[PINMPC_NRES], double* kkt_out, bool* certified) {
   *certified = false;
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   const int N = C.N;
   // number of stance rows
   int mloc = 0;
@@ -1556,7 +2116,7 @@ __device__ bool active_set_loop(const Ctx& C, Sh& sh, int maxp, double tol, Coun
 __device__ __attribute__((noinline)) void rollout_ru(const Ctx& C, Sh& sh) {
   gsync();
   // x = rollout of ru from x0, in FP64, into rx
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   if (lane < NX) sh.xv[lane] = (double)C.x0[lane];
   wsync();
   if (lane < NX) C.rx[lane] = sh.xv[lane];
@@ -1579,7 +2139,7 @@ __device__ __attribute__((noinline)) void rollout_ru(const Ctx& C, Sh& sh) {
 // The ADMM's input iterate, unscaled, into ru (swing inputs exactly 0).
 __device__ __attribute__((noinline)) void admm_point(const Ctx& C, gcf zsrc, gcf sf, float tsc) {
   gsync();
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   for (int e = lane; e < C.N * NU; e += W64) {
     const int k = e / NU, j = e % NU;
     const double sc = (j % 6 < 3) ? (double)sf[k] : (double)tsc;
@@ -1595,8 +2155,16 @@ __device__ __attribute__((noinline)) void admm_point(const Ctx& C, gcf zsrc, gcf
 // to PHASE 2, which runs the interior point and the polish passes for the
 // listed problems only (surplus blocks exit).  The slow problems thus start
 // together instead of behind a second round of easy ones.
-template <int PHASE, bool LONG>
-__global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, float* out_u,
+// The first wave releases a scanning workgroup's helpers on every way out.
+template <bool SCAN>
+struct ScanRelease {
+  __device__ ~ScanRelease() {
+    if constexpr (SCAN) scan_release();
+  }
+};
+
+template <int PHASE, bool LONG, bool SCAN>
+__global__ void __launch_bounds__(SCAN ? 64 * SCAN_WMAX : 64, 2) refine_kernel(Problem p, Workspace ws, float* out_u,
                                                     float* out_x, float* out_res,
                                                     int32_t* out_iters, int32_t* out_status,
                                                     int32_t* out_detail,
@@ -1607,12 +2175,21 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
   // the problem context lives in LDS: its pointers are loaded where they are
   // used instead of being held in registers across the whole kernel
   __shared__ Ctx C;
-  const int lane = threadIdx.x;
   int pb = blockIdx.x;
   if (PHASE == 2) {
     if ((int)blockIdx.x >= ws.rcount[0]) return;
     pb = ws.rlist[blockIdx.x];
   }
+  if constexpr (SCAN) {
+    // with the horizon scan the workgroup holds one wave per chunk: all but
+    // the first take the scan's commands until the first releases them
+    if (threadIdx.x >= W64) {
+      scan_helper<LONG>(C);
+      return;
+    }
+  }
+  const ScanRelease<SCAN> release;
+  const int lane = lane_id();
   if (lane == 0) {
   C.b = pb;
   C.n = p.n_max;
@@ -1786,6 +2363,24 @@ __global__ void __launch_bounds__(64, 2) refine_kernel(Problem p, Workspace ws, 
 
 }  // namespace
 
+size_t scan_lds_bytes(int W) {
+  return W > 1 ? (size_t)(W - 1) * sizeof(ShR) + (size_t)W * 4 * TILE_D * sizeof(double) : 0;
+}
+
+hipError_t refine_prepare() {
+  // the scanning kernels may take more dynamic LDS than the default limit
+  const int lds = (int)scan_lds_bytes(SCAN_WMAX);
+  const void* k[] = {reinterpret_cast<const void*>(&refine_kernel<1, false, true>),
+                     reinterpret_cast<const void*>(&refine_kernel<1, true, true>),
+                     reinterpret_cast<const void*>(&refine_kernel<2, false, true>),
+                     reinterpret_cast<const void*>(&refine_kernel<2, true, true>)};
+  for (const void* f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                          const pinmpc_out& out, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
@@ -1796,18 +2391,36 @@ hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_sett
     const hipError_t e = launch_fill_i32(w.rcount, 1, 0, 0, st);
     if (e != hipSuccess) return e;
   }
-#define PINMPC_REFINE(PH, L)                                                                 \
-  hipLaunchKernelGGL((refine_kernel<PH, L>), dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x, \
-                     out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,    \
-                     s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol, s.first_passes)
+  // the horizon scan: one wave per chunk, dynamic LDS for the helpers'
+  // buffers, the summaries and the boundary values
+  const int W = s.scan > 1 ? s.scan : 1;
+  const size_t lds = scan_lds_bytes(W);
+#define PINMPC_REFINE(PH, L, SC)                                                               \
+  hipLaunchKernelGGL((refine_kernel<PH, L, SC>), dim3(p.batch), dim3(64 * W), lds, st, p, w,     \
+                     out.u, out.x, out.res, out.iters, out.status, out.detail, s.iters, s.accel, \
+                     s.refine, s.refine_passes, s.ipm_iters, s.polish_passes, s.kkt_tol,        \
+                     s.first_passes)
   // horizons beyond PINMPC_NMAX keep the rollout's and the costates' stage
   // buffers in the scratch block (refine_block_doubles sizes it so)
   const bool lng = p.n_max > PINMPC_NMAX;
-  if (lng) PINMPC_REFINE(1, true);
-  else PINMPC_REFINE(1, false);
-  if (second) {
-    if (lng) PINMPC_REFINE(2, true);
-    else PINMPC_REFINE(2, false);
+  for (int ph = 1; ph <= (second ? 2 : 1); ++ph) {
+    if (ph == 1) {
+      if (W > 1) {
+        if (lng) PINMPC_REFINE(1, true, true);
+        else PINMPC_REFINE(1, false, true);
+      } else {
+        if (lng) PINMPC_REFINE(1, true, false);
+        else PINMPC_REFINE(1, false, false);
+      }
+    } else {
+      if (W > 1) {
+        if (lng) PINMPC_REFINE(2, true, true);
+        else PINMPC_REFINE(2, false, true);
+      } else {
+        if (lng) PINMPC_REFINE(2, true, false);
+        else PINMPC_REFINE(2, false, false);
+      }
+    }
   }
 #undef PINMPC_REFINE
   return hipGetLastError();

@@ -41,3 +41,15 @@ def test_long_horizons_and_bf16():
     assert len(cands) == 2 * 4 * 9
     full = list(autotune.candidates(60, allow_bf16=True))
     assert len({tuple(sorted(c.items())) for c in full}) == len(full)
+
+
+def test_third_stage_chooses_the_backward_recursion():
+    best = dict(form=1, iters=2, rho=1.0, refine_passes=12, first_passes=0, precision=0,
+                group=1, scan=0)
+    cands = list(autotune.stage_c(best, 20))
+    assert [c["scan"] for c in cands] == [2, 4, 8]
+    for c in cands:
+        assert {k: v for k, v in c.items() if k != "scan"} == \
+            {k: v for k, v in best.items() if k != "scan"}
+    assert list(autotune.stage_c(best, 7)) == []          # too short to cut: sequential only
+    assert {c["scan"] for c in autotune.stage_a(20)} == {0}

@@ -53,7 +53,8 @@ def test_default_settings_and_errors():
     # settings are validated before any device call
     for over in (dict(refine_passes=0, ipm_iters=0), dict(refine_passes=1001),
                  dict(ipm_iters=-1), dict(form=3), dict(form=-2), dict(precision=3),
-                 dict(kkt_tol=0.0), dict(group=0), dict(group=3), dict(group=8)):
+                 dict(kkt_tol=0.0), dict(group=0), dict(group=3), dict(group=8),
+                 dict(scan=1), dict(scan=3), dict(scan=16), dict(scan=-2)):
         bad = binding.default_settings(**over)
         assert lib.pinmpc_create(ctypes.byref(h), 0, 0, ctypes.byref(bad)) == -1, over
         assert lib.pinmpc_workspace_bytes(ctypes.byref(bad), 16, 10, ctypes.byref(nb)) in (0, -1)
