@@ -428,7 +428,8 @@ def test_autotuner_picks_a_certifying_schedule(tmp_path):
     rec = json.loads(cache.read_text())
     (key, entry), = rec.items()
     assert entry["settings"] == best and entry["score"] > 0
-    assert len(entry["log"]) == len(list(autotune.stage_a(10))) + 5 * 3 * 3 - 1
+    # first stage, second stage (all but its base point), third stage (scan 2, 4, 8)
+    assert len(entry["log"]) == len(list(autotune.stage_a(10))) + 5 * 3 * 3 - 1 + 3
     assert all("eq_passes" in r and "ipm_iters" in r for r in entry["log"])
     again = autotune.tune(dev, cache_path=str(cache), in_flight=1)
     assert again == best
