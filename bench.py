@@ -100,7 +100,7 @@ def parse():
                          "32768 problems per 20 ms tick (the tick is stretched by 1 / load)")
     ap.add_argument("--serving-ticks", type=int, default=3)
     ap.add_argument("--lanes", type=int, default=3)
-    ap.add_argument("--lane-capacity", type=int, default=4096)
+    ap.add_argument("--lane-capacity", type=int, default=8192)
     ap.add_argument("--streams", type=int, default=2,
                     help="solves in flight: S library contexts on S streams (default "
                          "priority) take the timed solves round robin, so one solve's "
