@@ -12,6 +12,7 @@ gravity carried as a state):
 
     x = (roll, pitch, yaw, p (3), omega (3), v (3), g_s)      13 states
     u = per contact i in {0, 1}: (f_i (3), tau_i (3))          12 inputs
+        (model "hands": contacts 2, 3 are the hands, 24 inputs)
     A_k = I + dt * A_c(yaw),   B_k = dt * B_c(yaw, r_{i,k}, m, I_body)
     r_{i,k} = p_i - c_ref,k  (foot position minus reference CoM at stage k)
 
@@ -56,7 +57,21 @@ CONFIGS = {
     "serving_tick": dict(batch=32768, horizons=tuple(range(10, 61)), dt=0.03,
                          duty=None, mu=(0.3, 0.9), push=0.5, payload=10.0,
                          seed=5),
+    # loco-manipulation: both feet and both hands as contacts (24 inputs)
+    "hands_b4096_n20": dict(batch=4096, horizons=(20,), dt=0.03, duty=0.6,
+                            mu=(0.3, 0.9), push=0.5, payload=10.0, seed=7,
+                            model="hands"),
 }
+
+# Hands (model "hands"): nominal position relative to the CoM in the heading
+# frame, and the contact frame of a hand: its local z axis (the normal of the
+# wrench set's pyramid) points backwards along the heading, so a pushing hand
+# takes the reaction of the pushed object as a normal force, and its local x
+# axis points up.  Hand inputs are expressed in that frame.
+HAND_NOMINAL = ((0.35, 0.20, 0.25), (0.35, -0.20, 0.25))
+HAND_FRAME = np.array([[0.0, 0.0, -1.0],
+                       [0.0, 1.0, 0.0],
+                       [1.0, 0.0, 0.0]])
 
 
 def _cfg(config):
@@ -109,7 +124,18 @@ def _skew(r):
     return S
 
 
-def _draw_offsets(seed, idx, n, N, mass):
+def _draw_hands(seed, idx):
+    """Per-problem draws of the hand contacts (model "hands"), from a substream
+    of their own: position offsets N(0, 0.05) m per hand, the phase and the
+    fraction U(0.5, 1) of the push cycle (twice the gait period) the hands are
+    in contact, and each hand's reference normal force U(40, 120) N (the
+    pushing-force reference of loco-manipulation)."""
+    rng = np.random.default_rng([int(seed), int(idx), 11])
+    return dict(off=rng.normal(0.0, 0.05, (2, 3)), phase=rng.uniform(0.0, 1.0),
+                duty=rng.uniform(0.5, 1.0), push=rng.uniform(40.0, 120.0, 2))
+
+
+def _draw_offsets(seed, idx, n, N, mass, nc=NC):
     """Nonzero affine terms of one problem, from a substream of its own (so the
     draws of ``_draw`` and every workload without offsets are unchanged):
 
@@ -124,9 +150,9 @@ def _draw_offsets(seed, idx, n, N, mass):
     rng = np.random.default_rng([int(seed), int(idx), 7])
     sd = np.array([2e-3] * 6 + [0.02] * 6 + [1e-3])
     e = rng.normal(0.0, 1.0, (n, NX)) * sd
-    ur = np.zeros((n, NU))
-    up = np.zeros(NU)
-    for i in range(NC):
+    ur = np.zeros((n, 6 * nc))
+    up = np.zeros(6 * nc)
+    for i in range(nc):
         ur[:, 6 * i:6 * i + 3] = rng.normal(0.0, 1.0, (n, 3)) * np.array([20.0, 20.0, 30.0])
         ur[:, 6 * i + 2] += 0.5 * mass * GRAVITY
         ur[:, 6 * i + 3:6 * i + 6] = rng.normal(0.0, 5.0, (n, 3))
@@ -138,7 +164,7 @@ def _draw_offsets(seed, idx, n, N, mass):
 
 
 def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
-               dt=None, as_float32=True, offsets=False, model="srb"):
+               dt=None, as_float32=True, offsets=False, model=None):
     """Build a batch of problems.
 
     config   name in CONFIGS or a dict with the same keys
@@ -152,18 +178,29 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
              13-slot layout, slots 9..12 inert (A = I, B = 0, e = 0, x0 = 0,
              reference 0, weight 1), gravity in e_k = (0, dt m g, 0); the same
              draws, the weights carried over (Q_v / m^2 on l, Q_omega / I^2 on
-             k), the lever arm at the reference CoM
+             k), the lever arm at the reference CoM; "hands": the 13-state
+             form with four contacts, the feet (0, 1) and the hands (2, 3):
+             a hand sits at the reference CoM plus its nominal offset (turned
+             by the yaw) plus its drawn offset, its force and moment are in
+             its contact frame (HAND_FRAME turned by the yaw), both hands are
+             in contact on the same push cycle, its input reference is its
+             drawn normal force while in contact, and its force weight in R is
+             1e-3 (the moments keep 1e-5); default: the config's model, else
+             "srb"
 
     Returns a dict of arrays (float32 unless ``as_float32`` is False):
-      N [B] int32, A [B,n,13,13], B [B,n,13,12], e [B,n,13], x0 [B,13],
-      u_prev [B,12], x_ref [B,n,13] (reference for x_{k+1}), u_ref [B,n,12],
-      Q [B,13], R [B,12] (diagonals), contact [B,n,2] uint8 (1 = stance),
+      N [B] int32, A [B,n,13,13], B [B,n,13,m], e [B,n,13], x0 [B,13],
+      u_prev [B,m], x_ref [B,n,13] (reference for x_{k+1}), u_ref [B,n,m],
+      Q [B,13], R [B,m] (diagonals), contact [B,n,c] uint8 (1 = stance) with
+      c contacts and m = 6 c inputs (c = 4 for "hands", else 2),
       mu [B], fz_max [B], tau_max [B], weight [B] (m g, the force scale),
       and the compact physics of A and B: yaw_k [B,n], c_ref [B,n,3], feet
       [B,n,2,3], mass [B], inertia [B,3], dt [B].
     Stages k >= N[b] are padding: A = I, B = 0, e = 0, references 0, swing.
     """
     cfg = _cfg(config)
+    if model is None:
+        model = cfg.get("model", "srb")
     if seed is None:
         seed = cfg["seed"]
     if dt is None:
@@ -181,7 +218,7 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
     n = n_max
 
     if Bn == 0:
-        return _empty(n)
+        return _empty(n, 4 if model == "hands" else NC)
 
     def col(key):
         return np.array([d[key] for d in draws], dtype=np.float64)
@@ -302,13 +339,42 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
         qq[:, 3:6] = q[:, 9:12] / mass[:, None] ** 2
         qq[:, 6:9] = q[:, 6:9] / inertia.mean(axis=1)[:, None] ** 2
         out.update(A=Am, B=Bq, e=eq, x0=xq0, x_ref=xqr, Q=qq)
+    elif model == "hands":
+        hd = [_draw_hands(seed, i) for i in indices]
+        Bh = np.zeros((Bn, n, NX, 6 * 4))
+        Bh[..., :NU] = Bm
+        ch = np.zeros((Bn, n, 4), dtype=bool)
+        ch[..., :NC] = contact
+        urh = np.zeros((Bn, n, 6 * 4))
+        Rh = np.full((Bn, 6 * 4), 1e-5)
+        hoff = np.array([d["off"] for d in hd])                     # [B,2,3]
+        hph = np.array([d["phase"] for d in hd])
+        hdu = np.array([d["duty"] for d in hd])
+        hpush = np.array([d["push"] for d in hd])                   # [B,2]
+        frame = Rz @ HAND_FRAME                                      # [B,3,3]
+        hfr = hph[:, None] + stage[None, :] * dt / (2.0 * GAIT_PERIOD)
+        hcon = ((hfr - np.floor(hfr)) < hdu[:, None]) & valid         # [B,n]
+        for h in range(2):
+            i = NC + h
+            r = (Rz @ np.array(HAND_NOMINAL[h])) + hoff[:, h, :]      # [B,3]
+            Bh[:, :, 6:9, 6 * i:6 * i + 3] = (Iw_inv @ _skew(r) @ frame)[:, None]
+            Bh[:, :, 6:9, 6 * i + 3:6 * i + 6] = (Iw_inv @ frame)[:, None]
+            Bh[:, :, 9:12, 6 * i:6 * i + 3] = (frame / mass[:, None, None])[:, None]
+            ch[..., i] = hcon
+            urh[:, :, 6 * i + 2] = np.where(hcon, hpush[:, h, None], 0.0)
+            Rh[:, 6 * i:6 * i + 3] = 1e-3
+        Bh[:, :, :, NU:] *= dt
+        Bh[~valid] = 0.0
+        out.update(B=Bh, contact=ch.astype(np.uint8), u_ref=urh, R=Rh,
+                   u_prev=np.zeros((Bn, 6 * 4)))
     elif model != "srb":
         raise ValueError(f"unknown model {model!r}")
     if offsets:
+        nc = out["contact"].shape[2]
         for j, idx in enumerate(indices):
-            e, ur, up = _draw_offsets(seed, idx, n, int(Nh[j]), mass[j])
+            e, ur, up = _draw_offsets(seed, idx, n, int(Nh[j]), mass[j], nc)
             out["e"][j] = e
-            out["u_ref"][j] = ur
+            out["u_ref"][j] = ur if model != "hands" else ur + out["u_ref"][j]
             out["u_prev"][j] = up
     if as_float32:
         for k, v in out.items():
@@ -319,15 +385,16 @@ def make_batch(config, indices=None, batch=None, seed=None, n_max=None,
     return out
 
 
-def _empty(n):
+def _empty(n, nc=NC):
     f = np.float32
+    nu = 6 * nc
     return {
         "N": np.zeros(0, np.int32), "A": np.zeros((0, n, NX, NX), f),
-        "B": np.zeros((0, n, NX, NU), f), "e": np.zeros((0, n, NX), f),
-        "x0": np.zeros((0, NX), f), "u_prev": np.zeros((0, NU), f),
-        "x_ref": np.zeros((0, n, NX), f), "u_ref": np.zeros((0, n, NU), f),
-        "Q": np.zeros((0, NX), f), "R": np.zeros((0, NU), f),
-        "contact": np.zeros((0, n, NC), np.uint8), "mu": np.zeros(0, f),
+        "B": np.zeros((0, n, NX, nu), f), "e": np.zeros((0, n, NX), f),
+        "x0": np.zeros((0, NX), f), "u_prev": np.zeros((0, nu), f),
+        "x_ref": np.zeros((0, n, NX), f), "u_ref": np.zeros((0, n, nu), f),
+        "Q": np.zeros((0, NX), f), "R": np.zeros((0, nu), f),
+        "contact": np.zeros((0, n, nc), np.uint8), "mu": np.zeros(0, f),
         "fz_max": np.zeros(0, f), "tau_max": np.zeros(0, f),
         "weight": np.zeros(0, f), "yaw_k": np.zeros((0, n), f),
         "c_ref": np.zeros((0, n, 3), f), "feet": np.zeros((0, n, NC, 3), f),

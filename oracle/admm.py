@@ -31,20 +31,21 @@ from __future__ import annotations
 import numpy as np
 
 from .projection import project_input
-from .qp import rollout
+from .qp import n_contacts, rollout
 
-NX, NU, NL = 13, 12, 25
+NX = 13
 
 
 def input_scale(p, scaling=True):
-    """Diagonal S_k [N,12] of the block-constant input scaling."""
+    """Diagonal S_k [N, 6 contacts] of the block-constant input scaling."""
     N = p["N"]
-    S = np.ones((N, NU))
+    nc = n_contacts(p)
+    S = np.ones((N, 6 * nc))
     if not scaling:
         return S
     for k in range(N):
         ns = max(1, int(np.sum(p["contact"][k])))
-        for i in range(2):
+        for i in range(nc):
             S[k, 6 * i:6 * i + 3] = p["weight"] / ns
             S[k, 6 * i + 3:6 * i + 6] = p["tau_max"]
     return S
@@ -52,6 +53,8 @@ def input_scale(p, scaling=True):
 
 def setup(p, rho, scaling=True):
     N = p["N"]
+    NU = 6 * n_contacts(p)
+    NL = NX + NU
     S = input_scale(p, scaling)
     Bt = p["B"] * S[:, None, :]
     Ab = np.zeros((N, NL, NL))
@@ -97,6 +100,7 @@ def iterate(p, c, st):
     st = dict(z, v, th, be, la) (the 'hat' values).  Returns the new iterates
     and the block-1 outputs (xi, du)."""
     N, rho = p["N"], c["rho"]
+    NL = c["H"].shape[1]
     Ab, Bb, eb, H, J, qb = c["Ab"], c["Bb"], c["eb"], c["H"], c["J"], c["qb"]
     z, v, th, be, la = st["z"], st["v"], st["th"], st["be"], st["la"]
     # block 1
@@ -129,7 +133,7 @@ def solve(p, iters=100, rho=1.0, scaling=True, accel=True, eta=0.999,
           history=False):
     """Run the ADMM for a fixed number of sweeps from zero iterates.
 
-    Returns dict with u [N,12] (unscaled input of z), x (rollout of u), the
+    Returns dict with u [N, 6 contacts] (unscaled input of z), x (rollout of u), the
     final iterates, the multiplier estimates lam_x = -rho lambda_x (costate
     of x_{k+1}) and mu_u = rho S^{-1} (theta - lambda)_u (= G^T mu), the
     number of restarts and, when ``history`` is set, the iterates after every
@@ -137,7 +141,7 @@ def solve(p, iters=100, rho=1.0, scaling=True, accel=True, eta=0.999,
     """
     N = p["N"]
     c = setup(p, rho, scaling)
-    zero = np.zeros((N, NL))
+    zero = np.zeros((N, c["H"].shape[1]))
     cur = dict(z=zero.copy(), v=zero.copy(), th=zero.copy(), be=zero.copy(), la=zero.copy())
     prev = {k: v.copy() for k, v in cur.items()}
     hat = {k: v.copy() for k, v in cur.items()}

@@ -29,7 +29,7 @@ import numpy as np
 import scipy.optimize
 
 from .projection import wrench_rows
-from .qp import costates
+from .qp import costates, n_contacts
 
 NX, NU = 13, 12
 
@@ -58,14 +58,15 @@ def residuals(p, u, x, lam=None, mu=None, act_tol=1e-7):
 
     if lam is None:
         lam = costates(p, x)
+    nc = n_contacts(p)
     r_ineq = 0.0
-    grad_u = np.zeros((N, NU))
+    grad_u = np.zeros((N, 6 * nc))
     terms = [0.0]
     for k in range(N):
         ru = p["R"] * (u[k] - p["u_ref"][k])
         bl = B[k].T @ lam[k]
         grad_u[k] = ru + bl
-        for i in range(2):
+        for i in range(nc):
             sl = slice(6 * i, 6 * i + 6)
             if p["contact"][k][i]:
                 terms += [abs(ru[sl]).max(), abs(bl[sl]).max()]
@@ -74,9 +75,9 @@ def residuals(p, u, x, lam=None, mu=None, act_tol=1e-7):
                 r_ineq = max(r_ineq, abs(u[k, sl]).max() / mg)
 
     if mu is None:
-        mu = np.zeros((N, 2, 11))
+        mu = np.zeros((N, nc, 11))
         for k in range(N):
-            for i in range(2):
+            for i in range(nc):
                 if not p["contact"][k][i]:
                     continue
                 sl = slice(6 * i, 6 * i + 6)
@@ -90,7 +91,7 @@ def residuals(p, u, x, lam=None, mu=None, act_tol=1e-7):
     mu_max = float(np.max(mu)) if mu.size else 0.0
     stat = 0.0
     for k in range(N):
-        for i in range(2):
+        for i in range(nc):
             if not p["contact"][k][i]:
                 continue
             sl = slice(6 * i, 6 * i + 6)
@@ -110,7 +111,7 @@ def residuals(p, u, x, lam=None, mu=None, act_tol=1e-7):
     r_stat = stat / (1.0 + max(terms))
     neg = 0.0
     for k in range(N):
-        for i in range(2):
+        for i in range(nc):
             if p["contact"][k][i]:
                 neg = max(neg, float(np.max(-mu[k, i])))
     r_sign = max(0.0, neg) / (1.0 + max(terms))

@@ -95,9 +95,10 @@ def project_contact(y, stance, mu, fz_max, tau_max):
 
 
 def project_input(u, contact_k, mu, fz_max, tau_max):
-    """Projection of a stage input (12-vector) onto U_k."""
-    out = np.empty(12)
-    for i in range(2):
+    """Projection of a stage input (6 entries per contact of contact_k) onto
+    U_k."""
+    out = np.empty(6 * len(contact_k))
+    for i in range(len(contact_k)):
         out[6 * i:6 * i + 6] = project_contact(u[6 * i:6 * i + 6], bool(contact_k[i]),
                                                mu, fz_max, tau_max)
     return out

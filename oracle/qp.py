@@ -37,6 +37,12 @@ from .projection import wrench_rows
 NX, NU = 13, 12
 
 
+def n_contacts(p):
+    """Contacts per stage of a problem (2: the feet; 4: feet and hands), from
+    its contact schedule [N, contacts]; every contact contributes six inputs."""
+    return int(np.shape(p["contact"])[-1])
+
+
 class NotCertified(RuntimeError):
     pass
 
@@ -44,21 +50,22 @@ class NotCertified(RuntimeError):
 def condense(p):
     """X = Gam @ U + c for X = (x_1..x_N), U = (u_0..u_{N-1}) stacked."""
     N = p["N"]
-    Gam = np.zeros((N * NX, N * NU))
+    nu = 6 * n_contacts(p)
+    Gam = np.zeros((N * NX, N * nu))
     c = np.zeros(N * NX)
-    row = np.zeros((NX, N * NU))
+    row = np.zeros((NX, N * nu))
     xc = p["x0"].copy()
     for k in range(N):
         xc = p["A"][k] @ xc + p["e"][k]
         row = p["A"][k] @ row
-        row[:, k * NU:(k + 1) * NU] += p["B"][k]
+        row[:, k * nu:(k + 1) * nu] += p["B"][k]
         Gam[k * NX:(k + 1) * NX] = row
         c[k * NX:(k + 1) * NX] = xc
     return Gam, c
 
 
 def rollout(p, u):
-    """States x_0..x_N of the dynamics driven by u [N,12]."""
+    """States x_0..x_N of the dynamics driven by u [N, 6 contacts]."""
     N = p["N"]
     x = np.zeros((N + 1, NX))
     x[0] = p["x0"]
@@ -104,20 +111,22 @@ def dense_qp(p):
     ru = p["u_ref"].reshape(-1)
     H = Gam.T @ (qv[:, None] * Gam) + np.diag(rv)
     g = Gam.T @ (qv * (c - r)) - rv * ru
+    nc = n_contacts(p)
+    nu = 6 * nc
     free = []
     for k in range(N):
-        for i in range(2):
+        for i in range(nc):
             if p["contact"][k][i]:
-                free.extend(range(k * NU + 6 * i, k * NU + 6 * i + 6))
+                free.extend(range(k * nu + 6 * i, k * nu + 6 * i + 6))
     free = np.array(free, dtype=np.int64)
     col = {int(f): j for j, f in enumerate(free)}
     Gc, hc = wrench_rows(p["mu"], p["fz_max"], p["tau_max"])
     Grows, hrows, rows = [], [], []
     for k in range(N):
-        for i in range(2):
+        for i in range(nc):
             if not p["contact"][k][i]:
                 continue
-            base = k * NU + 6 * i
+            base = k * nu + 6 * i
             for j in range(11):
                 gr = np.zeros(len(free))
                 for t in range(6):
@@ -241,21 +250,23 @@ def solve_dense(H, g, G, h, feas_scale, max_passes=60):
 def solve(p):
     """Certified optimum of one problem (dict from mpcgen.problem_fp64).
 
-    Returns dict with u [N,12], x [N+1,13], lam [N,13] (costate of x_{k+1}),
-    mu [N,2,11] (row multipliers, 0 for swing), cost and the certificate.
+    Returns dict with u [N, 6 nc], x [N+1,13], lam [N,13] (costate of
+    x_{k+1}), mu [N, nc, 11] (row multipliers, 0 for swing; nc contacts per
+    stage), cost and the certificate.
     """
     N = p["N"]
     H, g, G, h, free, rows = dense_qp(p)
     fs = max(1.0, float(p["weight"]))
-    U = np.zeros(N * NU)
+    nc = n_contacts(p)
+    U = np.zeros(N * 6 * nc)
     meas = dict(stat=0.0, feas=0.0, comp=0.0)
     z = np.zeros(len(h))
     if len(free):
         Uf, z, meas = solve_dense(H, g, G, h, fs)
         U[free] = Uf
-    u = U.reshape(N, NU)
+    u = U.reshape(N, 6 * nc)
     x = rollout(p, u)
-    mu = np.zeros((N, 2, 11))
+    mu = np.zeros((N, nc, 11))
     for (k, i, j), zz in zip(rows, z):
         mu[k, i, j] = zz
     return dict(u=u, x=x, lam=costates(p, x), mu=mu, cost=cost(p, u, x), cert=meas)

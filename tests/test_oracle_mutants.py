@@ -11,6 +11,8 @@ that zero e_k, u_ref and u_prev could not reveal:
   * the sign of the R r^u term of the condensed linear cost flipped;
   * the e_k term dropped from the condensed state trajectory;
   * complementarity measured without the row multiplier;
+  * feasibility measured, or the wrench rows built, for the two feet only
+    when the hands are contacts too;
 
 and, in the stage matrices built from compact physics (Sec. II-A), the
 world-frame inertia rotated the wrong way, the lever-arm cross product
@@ -45,6 +47,14 @@ MUTANTS = [
      "r_comp = max(r_comp, (mu[k, i] * slack).max() / (1.0 + mu_max * mg))",
      "r_comp = max(r_comp, (0.0 * mu[k, i] * slack).max() / (1.0 + mu_max * mg))",
      "complementarity"),
+    ("kkt-ineq-feet-only", "oracle/kkt.py",
+     "grad_u[k] = ru + bl\n        for i in range(nc):",
+     "grad_u[k] = ru + bl\n        for i in range(2):",
+     "hands"),
+    ("qp-hand-rows-dropped", "oracle/qp.py",
+     "    for k in range(N):\n        for i in range(nc):\n            if not p[\"contact\"][k][i]:",
+     "    for k in range(N):\n        for i in range(2):\n            if not p[\"contact\"][k][i]:",
+     "hands or hand"),
     ("dyn-inertia-rotation", "oracle/dynamics.py",
      "Iw = Rz @ np.diag(inertia) @ Rz.T",
      "Iw = Rz.T @ np.diag(inertia) @ Rz",

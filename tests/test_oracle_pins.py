@@ -16,6 +16,15 @@ import mpcgen
 from oracle import admm, kkt, projection, qp
 
 NX, NU = 13, 12
+HANDS = "hands_b4096_n20"     # four contacts per stage: feet and hands
+
+
+def _nu(p):
+    return p["B"].shape[-1]
+
+
+def _nc(p):
+    return p["B"].shape[-1] // 6
 
 
 def _prob(config="small_b64_n10", b=0, offsets=False, **over):
@@ -96,7 +105,7 @@ def _riccati_lq(p):
         S = A.T @ W @ A + Hux.T @ K[k]
         s = A.T @ (W @ e + w) + Hux.T @ kf[k]
     x = p["x0"].copy()
-    u = np.zeros((N, NU))
+    u = np.zeros((N, _nu(p)))
     for k in range(N):
         u[k] = K[k] @ x + kf[k]
         x = p["A"][k] @ x + p["B"][k] @ u[k] + p["e"][k]
@@ -112,12 +121,19 @@ def _loose(p):
 
 @pytest.mark.parametrize("offsets", OFFSETS)
 @pytest.mark.parametrize("config,b", [("small_b64_n10", 0), ("small_b64_n10", 3),
-                                      ("plain_b4096_n20", 1)])
+                                      ("plain_b4096_n20", 1), (HANDS, 2)])
 def test_unconstrained_equals_riccati(config, b, offsets):
     p = _loose(_prob(config, b, offsets))
+    if _nc(p) == 4:
+        # keep every normal force positive (inside the loose pyramids): a
+        # heavier input weight around a large normal-force reference
+        p["R"] = np.full(24, 1e-2)
+        p["u_ref"] = p["u_ref"].copy()
+        p["u_ref"][:, 2::6] += 400.0
     u_ric = _riccati_lq(p)
     Gc, hc = projection.wrench_rows(p["mu"], p["fz_max"], p["tau_max"])
-    slack = min(np.min(hc - Gc @ u_ric[k, 6 * i:6 * i + 6]) for k in range(p["N"]) for i in range(2))
+    slack = min(np.min(hc - Gc @ u_ric[k, 6 * i:6 * i + 6]) for k in range(p["N"])
+                for i in range(_nc(p)))
     assert slack > 0, "case must be strictly inside the loose set"
     sol = qp.solve(p)
     assert np.max(np.abs(sol["u"] - u_ric)) <= 1e-8 * max(1.0, np.max(np.abs(u_ric)))
@@ -128,8 +144,9 @@ def test_unconstrained_equals_riccati(config, b, offsets):
 
 
 @pytest.mark.parametrize("offsets", OFFSETS)
-def test_single_stage_closed_form(offsets):
-    p = _loose(_prob("small_b64_n10", 5, offsets))
+@pytest.mark.parametrize("config", ["small_b64_n10", HANDS])
+def test_single_stage_closed_form(config, offsets):
+    p = _loose(_prob(config, 5, offsets))
     p["N"] = 1
     for key in ("A", "B", "e", "x_ref", "u_ref", "contact"):
         p[key] = p[key][:1]
@@ -155,11 +172,11 @@ def _brute_force(p, with_moments):
     the feasible polytope and minimises the cost over that face's affine hull,
     so the feasible face minimiser of least cost is the optimum."""
     N = p["N"]
-    stance = [(k, i) for k in range(N) for i in range(2) if p["contact"][k][i]]
+    stance = [(k, i) for k in range(N) for i in range(_nc(p)) if p["contact"][k][i]]
     nv = 6 * len(stance)
 
     def cost(U):
-        u = np.zeros((N, NU))
+        u = np.zeros((N, _nu(p)))
         for j, (k, i) in enumerate(stance):
             u[k, 6 * i:6 * i + 6] = U[6 * j:6 * j + 6]
         x, c = p["x0"], 0.0
@@ -232,8 +249,8 @@ def _brute_force(p, with_moments):
     return best, stance, best_nact
 
 
-def _to_u(U, stance, N):
-    u = np.zeros((N, NU))
+def _to_u(U, stance, N, nu=NU):
+    u = np.zeros((N, nu))
     for j, (k, i) in enumerate(stance):
         u[k, 6 * i:6 * i + 6] = U[6 * j:6 * j + 6]
     return u
@@ -282,13 +299,38 @@ def test_bruteforce_double_support_forces(offsets):
     assert np.max(np.abs(sol["u"] - _to_u(U, stance, 1))) <= 1e-6 * p["weight"]
 
 
+def test_bruteforce_hand_and_foot_forces():
+    """One stage with a foot and a hand in contact (the hand's force in its
+    own contact frame, whose pyramid is the foot's), every face pair."""
+    p = _prob(HANDS, 3, False)
+    p = _trim(p, 1, [[True, False, True, False]], tau_max=1e6,
+              fz_max=0.5 * p["weight"], mu=0.3)
+    U, stance, nact = _brute_force(p, with_moments=False)
+    assert nact >= 1
+    sol = qp.solve(p)
+    assert np.max(np.abs(sol["u"] - _to_u(U, stance, 1, 24))) <= 1e-6 * p["weight"]
+
+
+@pytest.mark.parametrize("offsets", OFFSETS)
+def test_bruteforce_hand_full_wrench(offsets):
+    """One stage with only a hand in contact: force faces and moment bounds."""
+    p = _prob(HANDS, 6, offsets)
+    p = _trim(p, 1, [[False, False, False, True]], tau_max=3.0,
+              fz_max=0.3 * p["weight"])
+    U, stance, nact = _brute_force(p, with_moments=True)
+    assert nact >= 1
+    sol = qp.solve(p)
+    assert np.max(np.abs(sol["u"] - _to_u(U, stance, 1, 24))) <= 1e-6 * p["weight"]
+
+
 # -------------------------------------------------------------- certificate
 
 @pytest.mark.parametrize("config,count,offsets", [("small_b64_n10", 6, False),
                                                   ("plain_b4096_n20", 3, False),
                                                   ("uneven_b16384", 2, False),
                                                   ("small_b64_n10", 4, True),
-                                                  ("plain_b4096_n20", 3, True)])
+                                                  ("plain_b4096_n20", 3, True),
+                                                  (HANDS, 3, False), (HANDS, 2, True)])
 def test_oracle_kkt_certificate(config, count, offsets):
     batch = mpcgen.make_batch(config, indices=range(count), offsets=offsets)
     for b in range(count):
@@ -318,6 +360,27 @@ def test_kkt_measure_detects_planted_errors():
     assert kkt.residuals(p, u2, qp.rollout(p, u2))["r_ineq"] > 1e-3
     eu, ex = kkt.rel_err(u, sol["u"], sol["x"], sol["x"], p["weight"])
     assert eu > 1e-3 and ex == 0
+
+
+def test_kkt_measure_detects_planted_errors_on_hands():
+    """Every measure covers the hand contacts too: a hand force pushed out of
+    its pyramid, a hand in swing carrying a force, a hand input off the
+    optimum."""
+    p = _prob(HANDS, 1)
+    sol = qp.solve(p)
+    assert kkt.residuals(p, sol["u"], sol["x"])["kkt"] <= 1e-10
+    k = int(np.argwhere(p["contact"][:, 2])[0][0])
+    u = sol["u"].copy()
+    u[k, 12] = p["mu"] * u[k, 14] + 20.0     # |f_x| > mu f_n on hand 2
+    assert kkt.residuals(p, u, qp.rollout(p, u))["r_ineq"] > 1e-3
+    sw = np.argwhere(~p["contact"][:, 3])
+    if len(sw):
+        u2 = sol["u"].copy()
+        u2[int(sw[0][0]), 18 + 4] = 1.0      # swing hand carries a moment
+        assert kkt.residuals(p, u2, qp.rollout(p, u2))["r_ineq"] > 1e-3
+    u3 = sol["u"].copy()
+    u3[k, 14] += 5.0                          # 5 N off on a hand's normal force
+    assert kkt.residuals(p, u3, qp.rollout(p, u3))["r_stat"] > 1e-6
 
 
 @pytest.mark.parametrize("offsets", OFFSETS)
@@ -384,10 +447,10 @@ def test_kkt_measure_rejects_wrong_face_with_negative_multiplier():
 
 def _lifted(p):
     """Abar, Bbar, ebar, Qbar, qbar written from Sec. III directly."""
-    N = p["N"]
-    Ab = [np.block([[p["A"][k], p["B"][k]], [np.zeros((NU, NX)), np.eye(NU)]]) for k in range(N)]
-    Bb = [np.vstack([p["B"][k], np.eye(NU)]) for k in range(N)]
-    eb = [np.concatenate([p["e"][k], np.zeros(NU)]) for k in range(N)]
+    N, nu = p["N"], _nu(p)
+    Ab = [np.block([[p["A"][k], p["B"][k]], [np.zeros((nu, NX)), np.eye(nu)]]) for k in range(N)]
+    Bb = [np.vstack([p["B"][k], np.eye(nu)]) for k in range(N)]
+    eb = [np.concatenate([p["e"][k], np.zeros(nu)]) for k in range(N)]
     Qb = np.diag(np.concatenate([p["Q"], p["R"]]))
     qb = [Qb @ np.concatenate([p["x_ref"][k], p["u_ref"][k]]) for k in range(N)]
     return Ab, Bb, eb, Qb, qb
@@ -430,14 +493,15 @@ def _aug_lagrangian(p, rho, xi0, du, xi, z, v, th, be, la, Ab, Bb, eb, Qb, qb):
 
 def _random_state(p, seed):
     rng = np.random.default_rng(seed)
-    N = p["N"]
-    return {k: rng.normal(0, 1, (N, 25)) * np.concatenate([np.ones(NX), 100 * np.ones(NU)])
+    N, nu = p["N"], _nu(p)
+    return {k: rng.normal(0, 1, (N, NX + nu)) * np.concatenate([np.ones(NX), 100 * np.ones(nu)])
             for k in ("z", "v", "th", "be", "la")}
 
 
 @pytest.mark.parametrize("offsets", OFFSETS)
-def test_admm_block1_is_exact_minimiser(offsets):
-    p = _prob("small_b64_n10", 6, offsets)
+@pytest.mark.parametrize("config", ["small_b64_n10", HANDS])
+def test_admm_block1_is_exact_minimiser(config, offsets):
+    p = _prob(config, 6, offsets)
     p["N"] = 4
     for key in ("A", "B", "e", "x_ref", "u_ref", "contact"):
         p[key] = p[key][:4]
@@ -476,8 +540,8 @@ def _sample_feasible(rng, p, k):
     """A random point of Xbar_k = R^13 x U_k (convex combination of
     pyramid vertices, box moments, zero on swing)."""
     w = rng.normal(0, 1, NX)
-    u = np.zeros(NU)
-    for i in range(2):
+    u = np.zeros(_nu(p))
+    for i in range(_nc(p)):
         if p["contact"][k][i]:
             lam = rng.dirichlet(np.ones(5))
             verts = _vertices(p["mu"], p["fz_max"])
@@ -487,8 +551,9 @@ def _sample_feasible(rng, p, k):
 
 
 @pytest.mark.parametrize("offsets", OFFSETS)
-def test_admm_block2_is_minimiser_over_set(offsets):
-    p = _prob("small_b64_n10", 7, offsets)
+@pytest.mark.parametrize("config", ["small_b64_n10", HANDS])
+def test_admm_block2_is_minimiser_over_set(config, offsets):
+    p = _prob(config, 7, offsets)
     rho = 1.3
     st = _random_state(p, 5)
     c = admm.setup(p, rho, scaling=False)
@@ -531,6 +596,20 @@ def test_admm_fixed_point_is_the_qp_optimum(offsets):
         assert eu <= 1e-6 and ex <= 1e-6, (eu, ex)
         # multiplier recovery at the fixed point: p_{k+1} = -rho lambda_{k,x}
         assert np.allclose(out["lam_x"], ref["lam"], atol=1e-3 * (1 + np.abs(ref["lam"]).max()))
+
+
+
+def test_admm_fixed_point_with_hands():
+    """The same fixed-point property with four contacts (feet and hands)."""
+    p = _prob(HANDS, 8, True)
+    p = _trim(p, 4, [[True, False, True, True], [True, False, True, True],
+                     [True, True, True, False], [False, True, False, False]],
+              R=np.full(24, 2e-3))
+    ref = qp.solve(p)
+    out = admm.solve(p, iters=2500, rho=10.0, scaling=True, accel=True)
+    eu, ex = kkt.rel_err(out["u"], ref["u"], out["x"], ref["x"], p["weight"])
+    assert eu <= 1e-6 and ex <= 1e-6, (eu, ex)
+    assert np.allclose(out["lam_x"], ref["lam"], atol=1e-3 * (1 + np.abs(ref["lam"]).max()))
 
 
 # ---------------------------------------------------------------- generator
@@ -584,3 +663,27 @@ def test_fp32_rounded_optimum_meets_the_kkt_bar():
         assert kkt.residuals(p, u, x, act_tol=ACT_TOL_FP32)["kkt"] <= 1e-5, j
         if j == 0:
             assert kkt.residuals(p, u, x, act_tol=1e-7)["r_stat"] > 1e-5
+
+
+def test_generator_hands():
+    """Hand contacts: the feet part is the two-contact model's, and a hand's
+    normal force (its contact frame's z, in its own input coordinates) pushes
+    the body backwards along the heading, level, through the hand's lever
+    arm."""
+    h = mpcgen.make_batch(HANDS, indices=range(3))
+    f = mpcgen.make_batch(HANDS, indices=range(3), model="srb")
+    assert h["B"].shape[-1] == 24 and h["contact"].shape[-1] == 4
+    assert np.array_equal(h["B"][..., :12], f["B"]) and np.array_equal(h["A"], f["A"])
+    assert np.array_equal(h["contact"][..., :2], f["contact"])
+    for b in range(3):
+        m, dt = float(h["mass"][b]), float(h["dt"][b])
+        yaw = float(h["yaw_k"][b, 0])
+        back = -np.array([np.cos(yaw), np.sin(yaw), 0.0])
+        for i in (2, 3):
+            dv = h["B"][b, 0, 9:12, 6 * i + 2].astype(np.float64)
+            assert np.allclose(dv, dt / m * back, atol=1e-6 * dt / m)
+            # moments of a hand act on the angular rates only
+            assert np.all(h["B"][b, 0, 9:12, 6 * i + 3:6 * i + 6] == 0)
+            on = h["contact"][b, :, i].astype(bool)
+            assert np.all(h["u_ref"][b, on, 6 * i + 2] >= 40.0)
+            assert np.all(h["u_ref"][b, ~on, 6 * i + 2] == 0.0)
