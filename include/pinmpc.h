@@ -12,7 +12,12 @@
  *        swing contact:                f = 0, tau = 0
  *
  * with n = 13 states, m = 12 inputs = 2 contacts x (force 3, moment 3), in
- * the order (f0x, f0y, f0z, t0x, t0y, t0z, f1x, ..., t1z).
+ * the order (f0x, f0y, f0z, t0x, t0y, t0z, f1x, ..., t1z).  For
+ * loco-manipulation (Sec. II-A: the contact set may hold hand contacts beside
+ * the feet) a batch may instead carry 4 contacts per stage, m = 24 inputs
+ * (pinmpc_batch.contacts): every contact's force and moment are expressed in
+ * that contact's own frame (its B_k columns carry the frame), so the same
+ * wrench rows, with the pyramid about the contact normal, hold for each.
  *
  * The solve runs the paper's ADMM (velocity-form lifting, the z/v variable
  * splitting, three stage-parallel closed-form block updates with cached
@@ -49,6 +54,8 @@ extern "C" {
 #define PINMPC_NX 13
 #define PINMPC_NU 12
 #define PINMPC_NCONTACT 2
+#define PINMPC_NCONTACT_MAX 4   /* feet and hands (pinmpc_batch.contacts) */
+#define PINMPC_NU_MAX 24
 #define PINMPC_NRES 5      /* r_dyn, r_ineq, r_stat, r_comp, r_sign */
 #define PINMPC_NMAX 64     /* largest horizon of the serving loop and of the
                               one-workgroup-per-problem kernels */
@@ -137,7 +144,7 @@ typedef struct {
                               serving loop: 1..PINMPC_NMAX) */
   const int32_t* N;        /* [B] horizon per problem in 1..n_max; NULL: all n_max */
   const float* A;          /* [B][n_max][13][13] */
-  const float* Bu;         /* [B][n_max][13][12] */
+  const float* Bu;         /* [B][n_max][13][12] (m = 6 contacts inputs) */
   const float* e;          /* [B][n_max][13]; NULL: 0 */
   const float* x0;         /* [B][13] */
   const float* u_prev;     /* [B][12] input before stage 0 (velocity form); NULL: 0 */
@@ -151,11 +158,26 @@ typedef struct {
   const float* tau_max;    /* [B] moment bound per axis */
   const float* weight;     /* [B] force scale m g (input scaling and residual
                               normalisation); NULL: fz_max / 2 */
+  int32_t contacts;        /* contacts per stage C: 2 (the feet; 0 means 2)
+                              or 4 (feet and hands, loco-manipulation).  The
+                              input arrays above and the output u hold m =
+                              6 C inputs per stage: Bu [B][n_max][13][m],
+                              u_prev [B][m], u_ref [B][n_max][m], R [B][m],
+                              contact [B][n_max][C], u [B][n_max][m].  With 4
+                              contacts: n_max <= PINMPC_NMAX, the ADMM sweeps
+                              run in the streamed form (settings.form 0: one
+                              launch per sweep, else all sweeps in one launch)
+                              and the FP64 refinement is the interior point
+                              alone (settings.ipm_iters iterations, at least
+                              1; refine_passes, first_passes, polish_passes
+                              and scan do not apply); the serving loop takes
+                              2 contacts only */
 } pinmpc_batch;
 
 /* Outputs (device pointers, caller-allocated). */
 typedef struct {
-  float* u;                /* [B][n_max][12] optimal inputs (0 on padding) */
+  float* u;                /* [B][n_max][12] optimal inputs (0 on padding;
+                              [B][n_max][24] with 4 contacts) */
   float* x;                /* [B][n_max+1][13] rollout of u (x_0 = x0) */
   float* res;              /* [B][PINMPC_NRES] FP64-evaluated KKT residuals of
                               the returned (u, x), each normalised by the
@@ -193,10 +215,16 @@ int pinmpc_create(pinmpc_ctx* out, int device, size_t hbm_budget_bytes,
  * ones in place). */
 int pinmpc_set_settings(pinmpc_ctx c, const pinmpc_settings* s);
 
-/* Bytes of workspace a solve of this shape needs (host call, no GPU work;
- * PINMPC_EINVAL for a shape outside 0 <= batch, 1 <= n_max <= PINMPC_NMAX_LONG). */
+/* Bytes of workspace a solve of this shape needs with 2 contacts per stage
+ * (host call, no GPU work; PINMPC_EINVAL for a shape outside 0 <= batch,
+ * 1 <= n_max <= PINMPC_NMAX_LONG).  A batch with 4 contacts needs the bytes
+ * of pinmpc_workspace_bytes_contacts. */
 int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_max,
                            size_t* bytes);
+/* The same for `contacts` (2 or 4) contacts per stage; PINMPC_EINVAL also
+ * for another contact count, or 4 contacts with n_max > PINMPC_NMAX. */
+int pinmpc_workspace_bytes_contacts(const pinmpc_settings* s, int32_t batch, int32_t n_max,
+                                    int32_t contacts, size_t* bytes);
 
 /* Solve every problem of `in`, the standard-form LTV MPC of Sec. III with the
  * wrench sets of Sec. II-B, by the ADMM of Sec. III (velocity-form lifting,
@@ -234,7 +262,8 @@ int pinmpc_solve_noalloc(pinmpc_ctx c, const pinmpc_batch* in, pinmpc_out* out,
 
 /* The ADMM of Sec. III only (setup and `iters` sweeps, no refinement), for
  * iterate-level checks.  z_out: caller-owned device buffer [B][n_max][25] of
- * the final z iterates (lifted (x_{k+1}, u_k), inputs unscaled).
+ * the final z iterates (lifted (x_{k+1}, u_k), inputs unscaled; [B][n_max][37]
+ * with 4 contacts).
  * Stream-ordered; errors as pinmpc_solve. */
 int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters,
                 float* z_out, void* hip_stream);

@@ -61,6 +61,7 @@ class Batch(ctypes.Structure):
         ("fz_max", ctypes.c_void_p),
         ("tau_max", ctypes.c_void_p),
         ("weight", ctypes.c_void_p),
+        ("contacts", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,9 @@ EXPORTS = {
     "pinmpc_set_settings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Settings)]),
     "pinmpc_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Settings), ctypes.c_int32,
                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "pinmpc_workspace_bytes_contacts": (ctypes.c_int, [ctypes.POINTER(Settings), ctypes.c_int32,
+                                                       ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.POINTER(ctypes.c_size_t)]),
     "pinmpc_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Out),
                                     ctypes.c_void_p]),
     "pinmpc_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Batch),
@@ -222,12 +226,18 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def n_inputs(dev: dict) -> int:
+    """Inputs per stage of a batch (12: two contacts; 24: feet and hands)."""
+    return int(dev["B"].shape[-1])
+
+
 def make_batch_struct(dev: dict) -> Batch:
     import torch
     A = dev["A"]
     assert A.dtype == torch.float32 and A.is_contiguous()
     b = Batch()
     b.batch, b.n_max = int(A.shape[0]), int(A.shape[1])
+    b.contacts = n_inputs(dev) // 6
     for k in FIELDS:
         t = dev.get(k)
         if t is not None:
@@ -269,7 +279,7 @@ class Solver:
         Bn, n = int(dev["A"].shape[0]), int(dev["A"].shape[1])
         d = dev["A"].device
         return {
-            "u": torch.empty((Bn, n, NU), dtype=torch.float32, device=d),
+            "u": torch.empty((Bn, n, n_inputs(dev)), dtype=torch.float32, device=d),
             "x": torch.empty((Bn, n + 1, NX), dtype=torch.float32, device=d),
             "res": torch.empty((Bn, NRES), dtype=torch.float32, device=d),
             "iters": torch.empty((Bn,), dtype=torch.int32, device=d),
@@ -302,10 +312,10 @@ class Solver:
         return out
 
     def admm(self, dev: dict, iters: int, stream=None):
-        """ADMM only: final z iterates [B][n][25] (unscaled)."""
+        """ADMM only: final z iterates [B][n][13 + inputs] (unscaled)."""
         import torch
         Bn, n = int(dev["A"].shape[0]), int(dev["A"].shape[1])
-        z = torch.empty((Bn, n, NX + NU), dtype=torch.float32, device=dev["A"].device)
+        z = torch.empty((Bn, n, NX + n_inputs(dev)), dtype=torch.float32, device=dev["A"].device)
         b = make_batch_struct(dev)
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(load().pinmpc_admm(self._h, ctypes.byref(b), int(iters),

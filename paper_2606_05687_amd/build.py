@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libpinmpc.so")
 
 SOURCES = ["api.cpp", "server.cpp", "setup.hip", "admm_plain.hip", "admm_fused.hip",
            "refine.hip", "noalloc.hip", "dynamics.hip", "landmarks.hip", "admm_split.hip",
-           "copy.hip"]
+           "copy.hip", "refine_wide.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -2,9 +2,9 @@
 // launch per sweep, operators and iterates streamed from HBM every sweep.
 //
 // A workgroup owns one problem; thread t handles (stage k, lifted row r),
-// r in 0..24, so every stage-local update of the three blocks runs in
-// parallel across the horizon.  The only cross-stage exchanges are the
-// ones the splitting leaves: block 1 at stage k needs Abar_{k+1}^T y_{k+1}
+// r in 0..24 (0..36 with four contacts), so every stage-local update of the
+// three blocks runs in parallel across the horizon.  The only cross-stage
+// exchanges are the ones the splitting leaves: block 1 at stage k needs Abar_{k+1}^T y_{k+1}
 // from stage k+1, block 2 at stage k needs xi_k from stage k-1 of the same
 // sweep; both go through LDS.
 //
@@ -21,25 +21,26 @@ namespace pinmpc {
 
 namespace {
 
-constexpr int BUF = 25;   // floats per stage per LDS buffer
-
-struct Lds {
+struct Lds {     // each buffer: L floats per stage (L = 13 + inputs)
   float* b0;    // w = vhat - betahat           -> later htilde -> restart terms
   float* b1;    // y = zhat - vhat - ebar + lamhat -> later xi (block-1 output)
-  float* b2;    // Bt^T w_x + w_u (12)          -> later projection input (12)
-  float* b3;    // du (12)                      -> later projection output (12)
+  float* b2;    // Bt^T w_x + w_u (inputs)      -> later projection input
+  float* b3;    // du (inputs)                  -> later projection output
   float* aty;   // Abar^T y of the stage
   float* xi0;   // fixed lifted initial state (x0, ut_prev)
 };
 
 // `sweeps` sweeps in one launch: the iterates and the acceleration state stay
 // in registers between sweeps (loaded once, stored once); the operators are
-// read from memory every sweep.  sweeps = 1 is the plain form.
-template <int PAIRS, bool BF16>
+// read from memory every sweep.  sweeps = 1 is the plain form.  NC contacts
+// per stage (2: feet, 4: feet and hands).
+template <int PAIRS, bool BF16, int NC>
 __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace ws, float rho,
                                                           int accel, float eta,
                                                           const int32_t* order,
                                                           const int32_t* count, int sweeps) {
+  constexpr int NU = Dims<NC>::U, NL = Dims<NC>::L, NH = Dims<NC>::H, NM = Dims<NC>::M;
+  constexpr int BUF = NL;
   if (count && (int)blockIdx.x >= *count) return;
   OpLoad<BF16> op;
   if constexpr (BF16) {
@@ -233,11 +234,11 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
   }
   __syncthreads();
   // projection: one thread per (stage, contact)
-  for (int id = threadIdx.x; id < N * 2; id += blockDim.x) {
-    const int k = id >> 1, i = id & 1;
+  for (int id = threadIdx.x; id < N * NC; id += blockDim.x) {
+    const int k = id / NC, i = id % NC;
     const float* y = L.b2 + k * BUF + 6 * i;
     float* o = L.b3 + k * BUF + 6 * i;
-    if (p.contact[(s0 + k) * 2 + i]) {
+    if (p.contact[(s0 + k) * NC + i]) {
       const float sf = ws.sf[s0 + k];
       const float F = p.fz_max[b] / sf;
       const float tm = tmax / ws.tsc[b];
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
   float f = 0.f;
   bool restart = false;
   if (accel) {
-    const float cm = stage_ordered_sum(L.b0, L.b2, N, threadIdx.x);
+    const float cm = stage_ordered_sum<NL>(L.b0, L.b2, N, threadIdx.x);
     if (cm < eta * cp) {
       const float an = 0.5f * (1.f + sqrtf(1.f + 4.f * al * al));
       f = (al - 1.f) / an;
@@ -334,6 +335,7 @@ __global__ void __launch_bounds__(1024) admm_sweep_kernel(Problem p, Workspace w
 // problem's slot shifted by one stage (slot k takes stored slot k+1, the last
 // stage repeats).  Acceleration state restarts.
 __global__ void admm_init_kernel(Problem p, Workspace ws) {
+  const int NL = NX + 6 * p.nc;
   const size_t total = (size_t)p.batch * p.n_max * NSTATE * NL;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -363,6 +365,7 @@ __global__ void admm_init_kernel(Problem p, Workspace ws) {
 
 // Store the final iterates of warm-started problems into their slots.
 __global__ void warm_save_kernel(Problem p, Workspace ws, int accel) {
+  const int NL = NX + 6 * p.nc;
   const size_t per = (size_t)NSTATE * NL;
   const size_t total = (size_t)p.batch * p.n_max * per;
   const float* src = accel ? ws.cur : ws.hat;
@@ -382,8 +385,9 @@ __global__ void fill_i32_kernel(int32_t* dst, size_t n, int32_t base, int32_t st
     dst[i] = base + step * (int32_t)i;
 }
 
-// z iterates (current) in unscaled coordinates, [b][n_max][25].
+// z iterates (current) in unscaled coordinates, [b][n_max][13 + inputs].
 __global__ void admm_extract_kernel(Problem p, Workspace ws, int accel, float* z_out) {
+  const int NL = NX + 6 * p.nc;
   const size_t total = (size_t)p.batch * p.n_max * NL;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -426,19 +430,34 @@ hipError_t launch_fill_i32(int32_t* dst, size_t n, int32_t base, int32_t step, h
 static hipError_t sweep(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                         const int32_t* ord, const int32_t* cnt, int sweeps, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
-  const int work = NL * p.n_max;
+  const int nl = NX + 6 * p.nc;
+  const int work = nl * p.n_max;
   int threads = ((work + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
   const int pairs = (work + threads - 1) / threads;
-  const size_t lds = (size_t)(5 * p.n_max * BUF + 32) * sizeof(float);
-#define PINMPC_SWEEP(P, BF)                                                                \
-  hipLaunchKernelGGL((admm_sweep_kernel<P, BF>), dim3(p.batch), dim3(threads), lds, st, p, w, \
-                     s.rho, s.accel, s.restart_eta, ord, cnt, sweeps)
-  if (pairs == 1 && !s.precision) PINMPC_SWEEP(1, false);
-  else if (pairs == 1) PINMPC_SWEEP(1, true);
-  else if (pairs == 2 && !s.precision) PINMPC_SWEEP(2, false);
-  else if (pairs == 2) PINMPC_SWEEP(2, true);
-  else return hipErrorInvalidValue;
+  // five stage buffers and the initial lifted state
+  const size_t lds = (size_t)(5 * p.n_max * nl + 64) * sizeof(float);
+#define PINMPC_SWEEP(P, BF, C)                                                              \
+  hipLaunchKernelGGL((admm_sweep_kernel<P, BF, C>), dim3(p.batch), dim3(threads), lds, st, p, \
+                     w, s.rho, s.accel, s.restart_eta, ord, cnt, sweeps)
+  const bool bf = s.precision != 0;
+  if (p.nc == 2) {
+    if (pairs == 1 && !bf) PINMPC_SWEEP(1, false, 2);
+    else if (pairs == 1) PINMPC_SWEEP(1, true, 2);
+    else if (pairs == 2 && !bf) PINMPC_SWEEP(2, false, 2);
+    else if (pairs == 2) PINMPC_SWEEP(2, true, 2);
+    else return hipErrorInvalidValue;
+  } else if (p.nc == 4) {
+    if (pairs == 1 && !bf) PINMPC_SWEEP(1, false, 4);
+    else if (pairs == 1) PINMPC_SWEEP(1, true, 4);
+    else if (pairs == 2 && !bf) PINMPC_SWEEP(2, false, 4);
+    else if (pairs == 2) PINMPC_SWEEP(2, true, 4);
+    else if (pairs == 3 && !bf) PINMPC_SWEEP(3, false, 4);
+    else if (pairs == 3) PINMPC_SWEEP(3, true, 4);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
 #undef PINMPC_SWEEP
   return hipGetLastError();
 }

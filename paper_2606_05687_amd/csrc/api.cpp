@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -66,8 +67,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 namespace pinmpc {
 
-// Carve (or size, when base == nullptr) the workspace for batch x n.
-size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w) {
+// Carve (or size, when base == nullptr) the workspace for batch x n with nc
+// contacts per stage.
+size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w, int nc) {
+  const size_t NU = 6 * (size_t)nc, NL = NX + NU;
+  const size_t NH = NL * (NL + 1) / 2, NM = NU * (NU + 1) / 2;
+  const size_t rdoubles = nc == 4 ? std::max(refine_block_doubles(n), refine_wide_block_doubles(n))
+                                  : refine_block_doubles(n);
   const size_t S = (size_t)batch * n;        // stages
   const size_t Bn = (size_t)batch;
   const size_t X = (size_t)batch * (n + 1);  // state slots
@@ -94,7 +100,7 @@ size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w) {
   t.cprev = (float*)take(Bn * 4);
   t.restarts = (int32_t*)take(Bn * 4);
   t.flags = (uint32_t*)take(Bn * 4);
-  t.rblk = (double*)take(Bn * refine_block_doubles(n) * 8);
+  t.rblk = (double*)take(Bn * rdoubles * 8);
   t.faces = (int32_t*)take(S * 2 * 4);
   t.order = (int32_t*)take(Bn * 3 * 4);
   t.counts = (int32_t*)take(4 * 4);
@@ -136,9 +142,13 @@ int check_settings(const pinmpc_settings* s) {
   return PINMPC_OK;
 }
 
+int contacts_of(const pinmpc_batch* in) { return in->contacts == 4 ? 4 : 2; }
+
 int check_batch(const pinmpc_batch* in) {
   if (!in) return PINMPC_EINVAL;
   if (in->batch < 0 || in->n_max < 1 || in->n_max > PINMPC_NMAX_LONG) return PINMPC_EINVAL;
+  if (in->contacts != 0 && in->contacts != 2 && in->contacts != 4) return PINMPC_EINVAL;
+  if (in->contacts == 4 && in->n_max > PINMPC_NMAX) return PINMPC_EINVAL;
   if (in->batch == 0) return PINMPC_OK;
   if (!in->A || !in->Bu || !in->x0 || !in->x_ref || !in->Q || !in->R || !in->contact ||
       !in->mu || !in->fz_max || !in->tau_max)
@@ -150,6 +160,7 @@ Problem to_problem(const pinmpc_batch* in) {
   Problem p;
   p.batch = in->batch;
   p.n_max = in->n_max;
+  p.nc = contacts_of(in);
   p.N = in->N;
   p.A = in->A;
   p.B = in->Bu;
@@ -179,6 +190,17 @@ static bool fits_fused(int n_max) { return NL * n_max <= 1024; }
 int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
                       hipStream_t st) {
   if (iters <= 0) return PINMPC_OK;
+  if (p.nc != NCONTACT) {
+    // four contacts: the streaming sweep kernel, one launch per sweep (form
+    // 0) or all sweeps in one launch
+    if (s.form == 0) {
+      for (int it = 0; it < iters; ++it)
+        if (launch_admm_sweep(p, w, s, 1, st) != hipSuccess) return PINMPC_EDEVICE;
+    } else if (launch_admm_sweep(p, w, s, iters, st) != hipSuccess) {
+      return PINMPC_EDEVICE;
+    }
+    return PINMPC_OK;
+  }
   if (s.form == 2 || p.n_max > PINMPC_NMAX) {
     // the horizon split across workgroups: every horizon up to PINMPC_NMAX_LONG
     if (launch_admm_split(p, w, s, iters, st) != hipSuccess) return PINMPC_EDEVICE;
@@ -201,12 +223,19 @@ int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspac
   return PINMPC_OK;
 }
 
+// The FP64 refinement for the batch's contact count.
+hipError_t launch_refine_any(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                             const pinmpc_out& out, hipStream_t st) {
+  return p.nc == NCONTACT ? launch_refine(p, w, s, out, st) : launch_refine_wide(p, w, s, out, st);
+}
+
 }  // namespace pinmpc
 
 namespace {
 
-int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Workspace* w) {
-  const size_t need = carve_workspace(nullptr, batch, n, nullptr);
+int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, int nc, hipStream_t st,
+                     Workspace* w) {
+  const size_t need = carve_workspace(nullptr, batch, n, nullptr, nc);
   if (need > c->budget) return PINMPC_EBUDGET;
   if (need > c->mem_bytes) {
     if (c->mem) {
@@ -225,7 +254,7 @@ int ensure_workspace(pinmpc_ctx c, int32_t batch, int32_t n, hipStream_t st, Wor
     }
     c->mem_bytes = need;
   }
-  carve_workspace((char*)c->mem, batch, n, w);
+  carve_workspace((char*)c->mem, batch, n, w, nc);
   return PINMPC_OK;
 }
 
@@ -309,6 +338,16 @@ int pinmpc_workspace_bytes(const pinmpc_settings* s, int32_t batch, int32_t n_ma
   return PINMPC_OK;
 }
 
+int pinmpc_workspace_bytes_contacts(const pinmpc_settings* s, int32_t batch, int32_t n_max,
+                                    int32_t contacts, size_t* bytes) {
+  if (contacts == 0 || contacts == 2) return pinmpc_workspace_bytes(s, batch, n_max, bytes);
+  if (contacts != 4 || !bytes || batch < 0 || n_max < 1 || n_max > PINMPC_NMAX)
+    return PINMPC_EINVAL;
+  (void)s;
+  *bytes = carve_workspace(nullptr, batch, n_max, nullptr, 4);
+  return PINMPC_OK;
+}
+
 }  // extern "C"
 
 namespace pinmpc {
@@ -321,10 +360,11 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_i
   int rc = check_batch(in);
   if (rc) return rc;
   if (in->batch > 0 && (!out->u || !out->x)) return PINMPC_EINVAL;
+  if (contacts_of(in) != NCONTACT && c->s.refine && c->s.ipm_iters == 0) return PINMPC_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
   if (in->batch == 0) return PINMPC_OK;
   Workspace w;
-  rc = ensure_workspace(c, in->batch, in->n_max, st, &w);
+  rc = ensure_workspace(c, in->batch, in->n_max, contacts_of(in), st, &w);
   if (rc) return rc;
   w.warm_idx = warm_idx;
   w.warm_store = warm_store;
@@ -355,7 +395,7 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_i
         crc = PINMPC_EDEVICE;
       } else {
         crc = run_admm(c, p, w, c->s.iters, cap);
-        if (!crc && launch_refine(p, w, c->s, *out, cap) != hipSuccess) crc = PINMPC_EDEVICE;
+        if (!crc && launch_refine_any(p, w, c->s, *out, cap) != hipSuccess) crc = PINMPC_EDEVICE;
         if (hipStreamEndCapture(cap, &g) != hipSuccess) crc = PINMPC_EDEVICE;
       }
       c->have_timing = timing;
@@ -385,7 +425,7 @@ int solve_internal(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_i
   if (rc) return rc;
   if (warm_idx && launch_warm_save(p, w, c->s.accel, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[2], st);
-  if (launch_refine(p, w, c->s, *out, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (launch_refine_any(p, w, c->s, *out, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
   ++c->nsolves;
   return PINMPC_OK;
@@ -398,11 +438,14 @@ int solve_in_buffer(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_
   int rc = check_batch(in);
   if (rc) return rc;
   if (in->batch > 0 && (!out.u || !out.x)) return PINMPC_EINVAL;
-  if (carve_workspace(nullptr, in->batch, in->n_max, nullptr) > capacity) return PINMPC_ETOOBIG;
+  if (contacts_of(in) != NCONTACT && c->s.refine && c->s.ipm_iters == 0) return PINMPC_EINVAL;
+  const int nc = contacts_of(in);
+  if (carve_workspace(nullptr, in->batch, in->n_max, nullptr, nc) > capacity)
+    return PINMPC_ETOOBIG;
   if (in->batch == 0) return PINMPC_OK;
   if (!base) return PINMPC_EINVAL;
   Workspace w;
-  carve_workspace((char*)base, in->batch, in->n_max, &w);
+  carve_workspace((char*)base, in->batch, in->n_max, &w, nc);
   const Problem p = to_problem(in);
   // eager launches only: instantiating a graph would allocate
   const int slot = (int)(c->nsolves % PINMPC_STATS_RING);
@@ -412,7 +455,7 @@ int solve_in_buffer(pinmpc_ctx c, const pinmpc_batch* in, const pinmpc_out* out_
   rc = run_admm(c, p, w, c->s.iters, st);
   if (rc) return rc;
   if (c->have_timing) (void)hipEventRecord(c->ev[2], st);
-  if (launch_refine(p, w, c->s, out, st) != hipSuccess) return PINMPC_EDEVICE;
+  if (launch_refine_any(p, w, c->s, out, st) != hipSuccess) return PINMPC_EDEVICE;
   if (c->have_timing) (void)hipEventRecord(c->ev[3], st);
   ++c->nsolves;
   return PINMPC_OK;
@@ -424,7 +467,7 @@ int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n) {
   if (!c) return PINMPC_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return PINMPC_EDEVICE;
   Workspace w;
-  return ensure_workspace(c, batch, n, nullptr, &w);
+  return ensure_workspace(c, batch, n, NCONTACT, nullptr, &w);
 }
 
 }  // namespace pinmpc
@@ -444,7 +487,7 @@ int pinmpc_admm(pinmpc_ctx c, const pinmpc_batch* in, int32_t iters, float* z_ou
   hipStream_t st = (hipStream_t)hip_stream;
   if (in->batch == 0) return PINMPC_OK;
   Workspace w;
-  rc = ensure_workspace(c, in->batch, in->n_max, st, &w);
+  rc = ensure_workspace(c, in->batch, in->n_max, contacts_of(in), st, &w);
   if (rc) return rc;
   const Problem p = to_problem(in);
   const bool timing = c->have_timing;

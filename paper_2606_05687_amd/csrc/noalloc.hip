@@ -41,7 +41,7 @@ extern "C" int pinmpc_solve_noalloc(pinmpc_ctx c, const pinmpc_batch* in, pinmpc
   const int rc = pinmpc::check_batch(in);
   if (rc) return rc;
   size_t need = 0;
-  pinmpc_workspace_bytes(nullptr, in->batch, in->n_max, &need);
+  pinmpc_workspace_bytes_contacts(nullptr, in->batch, in->n_max, pinmpc::contacts_of(in), &need);
   if (need > PINMPC_NOALLOC_SCRATCH_BYTES) return PINMPC_ETOOBIG;
   if (hipSetDevice(device) != hipSuccess) return PINMPC_EDEVICE;
   void* base = scratch_on(device);

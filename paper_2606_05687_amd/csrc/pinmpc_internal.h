@@ -17,6 +17,17 @@ constexpr int NROW = 11;        // wrench rows per stance contact
 constexpr int NCONTACT = PINMPC_NCONTACT;   // 2 contacts
 constexpr int NSTATE = 5;       // ADMM iterate blocks z, v, theta, beta, lambda
 
+// Dimensions with NC contacts per stage (2: the feet; 4: feet and hands).
+template <int NC>
+struct Dims {
+  static constexpr int U = 6 * NC;                 // inputs
+  static constexpr int L = NX + U;                 // lifted state
+  static constexpr int H = L * (L + 1) / 2;        // packed symmetric H_k
+  static constexpr int M = U * (U + 1) / 2;        // packed symmetric M_k
+};
+static_assert(Dims<NCONTACT>::L == NL && Dims<NCONTACT>::H == NH && Dims<NCONTACT>::M == NM,
+              "two contacts are the default dimensions");
+
 // BF16 (bfloat16) storage: round to nearest even from FP32, and back.
 __host__ __device__ inline uint16_t to_bf16(float f) {
   uint32_t u;
@@ -62,6 +73,7 @@ __host__ __device__ inline int pk(int r, int c, int n) {
 // null and then mean zero / the documented default).
 struct Problem {
   int32_t batch, n_max;
+  int32_t nc;   // contacts per stage: 2 or 4 (inputs 6 nc)
   const int32_t* N;
   const float *A, *B, *e, *x0, *u_prev, *x_ref, *u_ref, *Q, *R;
   const uint8_t* contact;
@@ -158,6 +170,16 @@ constexpr int TS_S = NX * (NX + 1) / 2 + NX;
 __host__ __device__ constexpr size_t refine_block_doubles(int n) {
   return (((size_t)n * (TS_T + TS_K + TS_L + TS_H + TS_S + NU + NU + NX + NU + 5 * 2 * NROW + NU) +
            2 * (size_t)(n + 1) * NX + (n > PINMPC_NMAX ? (size_t)n * 32 : 0)) + 3) & ~(size_t)3;
+}
+
+// FP64 scratch of the four-contact refinement (refine_wide.hip) per problem
+// with n stages: gains (24 x 13), feedforward, inputs, their step and the
+// costates (24 each), the stage input terms (per contact a 6 x 6 block and
+// six entries), slacks, multipliers, their steps and the complementarity
+// target (11 per contact each), then x and dx ((n+1) x 13 each).
+__host__ __device__ constexpr size_t refine_wide_block_doubles(int n) {
+  return ((size_t)n * (24 * NX + 4 * 24 + 4 * 42 + 5 * 4 * NROW) + 2 * (size_t)(n + 1) * NX + 3) &
+         ~(size_t)3;
 }
 
 // 1/a from the hardware estimate refined by two Newton steps (the pivots of
@@ -310,18 +332,19 @@ __device__ inline void project_pyramid(T mu, T F, T yx, T yy, T yz, T* px, T* py
   *pz = bz;
 }
 
-// Sum of one value per (stage k < N, lifted row r < 25) held in LDS at
-// cp[k * 25 + r], in an order fixed by N alone (rows in order within a
+// Sum of one value per (stage k < N, lifted row r < W) held in LDS at
+// cp[k * W + r] (W = 25 with two contacts), in an order fixed by N alone (rows in order within a
 // stage, then stages in order), so the result does not depend on the launch
 // shape and a problem computes bitwise the same alone or inside any batch.
 // ss: N + 1 floats of LDS scratch; t: the calling thread's index among the
 // problem's threads (at least N of them).  Every thread of the workgroup must
 // call it.
+template <int W = NL>
 __device__ inline float stage_ordered_sum(const float* cp, float* ss, int N, int t) {
   __syncthreads();
   if (t < N) {
     float a = 0.f;
-    for (int r = 0; r < NL; ++r) a += cp[t * NL + r];
+    for (int r = 0; r < W; ++r) a += cp[t * W + r];
     ss[t] = a;
   }
   __syncthreads();
@@ -359,9 +382,10 @@ int reserve_internal(pinmpc_ctx c, int32_t batch, int32_t n);
 // returns the bytes), validate settings and a batch, view a batch as the
 // kernels' Problem, and enqueue the ADMM sweeps in the form the settings ask
 // for.
-size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w);
+size_t carve_workspace(char* base, int32_t batch, int32_t n, Workspace* w, int nc = NCONTACT);
 int check_settings(const pinmpc_settings* s);
 int check_batch(const pinmpc_batch* in);
+int contacts_of(const pinmpc_batch* in);   // 2 or 4
 Problem to_problem(const pinmpc_batch* in);
 int launch_admm_phase(const pinmpc_settings& s, const Problem& p, const Workspace& w, int iters,
                       hipStream_t st);
@@ -434,5 +458,9 @@ hipError_t launch_admm_extract(const Problem& p, const Workspace& w, int accel,
 hipError_t refine_prepare();
 hipError_t launch_refine(const Problem& p, const Workspace& w, const pinmpc_settings& s,
                          const pinmpc_out& out, hipStream_t st);
+// The FP64 refinement of problems with four contacts per stage (refine_wide.hip).
+hipError_t launch_refine_wide(const Problem& p, const Workspace& w, const pinmpc_settings& s,
+                              const pinmpc_out& out, hipStream_t st);
+
 
 }  // namespace pinmpc

@@ -434,6 +434,7 @@ int pinmpc_submit(pinmpc_server s, const pinmpc_batch* req, const pinmpc_out* ou
   if (!s || !req || !out || !ticket) return PINMPC_EINVAL;
   if (req->batch < 1 || req->batch > s->cap || req->n_max < 1 || req->n_max > PINMPC_NMAX)
     return PINMPC_EINVAL;
+  if (req->contacts != 0 && req->contacts != 2) return PINMPC_EINVAL;   // feet only
   if (!req->A || !req->Bu || !req->x0 || !req->x_ref || !req->Q || !req->R || !req->contact ||
       !req->mu || !req->fz_max || !req->tau_max || !out->u || !out->x)
     return PINMPC_EINVAL;

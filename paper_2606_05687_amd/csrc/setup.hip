@@ -1,4 +1,4 @@
-// Per-stage ADMM setup (Sec. III cached quantities), one 64-lane wave per stage.
+// Per-stage ADMM setup (Sec. III cached quantities), one workgroup per stage.
 //
 // For stage k of problem b, with block-constant input scaling S_k
 // (force triples m g / stance count, moment triples tau_max):
@@ -16,12 +16,19 @@ namespace pinmpc {
 
 namespace {
 
-__device__ inline int stance_count(const uint8_t* c) { return (c[0] != 0) + (c[1] != 0); }
+template <int NC>
+__device__ inline int stance_count(const uint8_t* c) {
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) n += (c[i] != 0);
+  return n;
+}
 
+template <int NC>
 __device__ inline float scale_of(const Problem& p, int b, int k, int j, bool scaling) {
   if (!scaling) return 1.f;
   const size_t s = (size_t)b * p.n_max + k;
-  const int ns = stance_count(p.contact + 2 * s);
+  const int ns = stance_count<NC>(p.contact + NC * s);
   const float sf = weight_of(p, b) / (float)(ns > 0 ? ns : 1);
   return (j % 6) < 3 ? sf : p.tau_max[b];
 }
@@ -57,138 +64,154 @@ __device__ inline void gj_columns_f(float (&col)[n]) {
   }
 }
 
-__global__ void __launch_bounds__(64) setup_kernel(Problem p, Workspace ws, float rho,
-                                                   int scaling, int bf16) {
+// One workgroup per stage.  With NC = 4 the lifted system has 37 columns and
+// [H | I] 74, more than a wave has lanes: the workgroup then holds two waves,
+// each eliminating all of H (the same arithmetic in the same order) beside
+// its own share of the identity's columns.
+template <int NC>
+__global__ void __launch_bounds__(64 * (NC / 2)) setup_kernel(Problem p, Workspace ws, float rho,
+                                                              int scaling, int bf16) {
+  using D = Dims<NC>;
+  constexpr int U = D::U, L = D::L;
   const int s = blockIdx.x;                    // stage index b * n_max + k
   const int b = s / p.n_max, k = s % p.n_max;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int N = horizon(p, b);
-  __shared__ float sTop[NX * NL];              // [A_{k+1} | Bt_{k+1}], 13 x 25
-  __shared__ float sBt[NX * NU];               // Bt_k
+  __shared__ float sTop[NX * L];               // [A_{k+1} | Bt_{k+1}], 13 x L
+  __shared__ float sBt[NX * U];                // Bt_k
   const bool sc = scaling != 0;
 
   if (k >= N) {   // padding stage: benign values, never read by the sweep
-    for (int i = lane; i < NX * NU; i += 64) ws.Bt[(size_t)s * NX * NU + i] = 0.f;
-    for (int i = lane; i < NH; i += 64) ws.Hp[(size_t)s * NH + i] = 0.f;
-    for (int i = lane; i < NM; i += 64) ws.Mp[(size_t)s * NM + i] = 0.f;
-    for (int i = lane; i < NL; i += 64) ws.qb[(size_t)s * NL + i] = 0.f;
-    if (lane == 0) ws.sf[s] = 1.f;
+    for (int i = tid; i < NX * U; i += blockDim.x) ws.Bt[(size_t)s * NX * U + i] = 0.f;
+    for (int i = tid; i < D::H; i += blockDim.x) ws.Hp[(size_t)s * D::H + i] = 0.f;
+    for (int i = tid; i < D::M; i += blockDim.x) ws.Mp[(size_t)s * D::M + i] = 0.f;
+    for (int i = tid; i < L; i += blockDim.x) ws.qb[(size_t)s * L + i] = 0.f;
+    if (tid == 0) ws.sf[s] = 1.f;
     return;
   }
-  const float* Bk = p.B + (size_t)s * NX * NU;
-  for (int i = lane; i < NX * NU; i += 64) {
-    const int j = i % NU;
-    const float v = Bk[i] * scale_of(p, b, k, j, sc);
+  const float* Bk = p.B + (size_t)s * NX * U;
+  for (int i = tid; i < NX * U; i += blockDim.x) {
+    const int j = i % U;
+    const float v = Bk[i] * scale_of<NC>(p, b, k, j, sc);
     sBt[i] = v;
-    ws.Bt[(size_t)s * NX * NU + i] = v;
-    if (bf16) ws.Btbf[(size_t)s * NX * NU + i] = to_bf16(v);
+    ws.Bt[(size_t)s * NX * U + i] = v;
+    if (bf16) ws.Btbf[(size_t)s * NX * U + i] = to_bf16(v);
   }
   const bool has_next = (k + 1 < N);
   if (has_next) {
     const float* A1 = p.A + (size_t)(s + 1) * NX * NX;
-    const float* B1 = p.B + (size_t)(s + 1) * NX * NU;
-    for (int e = lane; e < NX * NL; e += 64) {
-      const int i = e / NL, c = e % NL;
-      sTop[e] = (c < NX) ? A1[i * NX + c] : B1[i * NU + c - NX] * scale_of(p, b, k + 1, c - NX, sc);
+    const float* B1 = p.B + (size_t)(s + 1) * NX * U;
+    for (int e = tid; e < NX * L; e += blockDim.x) {
+      const int i = e / L, c = e % L;
+      sTop[e] = (c < NX) ? A1[i * NX + c]
+                         : B1[i * U + c - NX] * scale_of<NC>(p, b, k + 1, c - NX, sc);
     }
   }
-  if (lane == 0) {
-    ws.sf[s] = scale_of(p, b, k, 0, sc);
+  if (tid == 0) {
+    ws.sf[s] = scale_of<NC>(p, b, k, 0, sc);
     if (k == 0) ws.tsc[b] = sc ? p.tau_max[b] : 1.f;
   }
   if (bf16) {
     const float* A = p.A + (size_t)s * NX * NX;
-    for (int i = lane; i < NX * NX; i += 64) ws.Abf[(size_t)s * NX * NX + i] = to_bf16(A[i]);
+    for (int i = tid; i < NX * NX; i += blockDim.x) ws.Abf[(size_t)s * NX * NX + i] = to_bf16(A[i]);
   }
   __syncthreads();
 
   // H_k^{-1} = diag(Q, R S^2) + rho I + [has_next] rho Abar_{k+1}^T Abar_{k+1},
-  // with Abar_{k+1} = [[A, Bt], [0, I]]: lane c < 25 forms its column c,
-  // lanes 25..49 hold the identity's columns
+  // with Abar_{k+1} = [[A, Bt], [0, I]]: lane c < L forms its column c, the
+  // other lanes of wave w hold the identity's columns w (64 - L) + lane - L
   {
-    float col[NL];
-    if (lane < NL) {
+    constexpr int PER = 64 - L;                // identity columns per wave
+    const int ic = wave * PER + lane - L;      // this lane's identity column
+    float col[L];
+    if (lane < L) {
       float top[NX];
 #pragma unroll
-      for (int i = 0; i < NX; ++i) top[i] = has_next ? sTop[i * NL + lane] : 0.f;
+      for (int i = 0; i < NX; ++i) top[i] = has_next ? sTop[i * L + lane] : 0.f;
       float dg;
       if (lane < NX) {
         dg = p.Q[(size_t)b * NX + lane];
       } else {
-        const float sj = scale_of(p, b, k, lane - NX, sc);
-        dg = p.R[(size_t)b * NU + lane - NX] * sj * sj;
+        const float sj = scale_of<NC>(p, b, k, lane - NX, sc);
+        dg = p.R[(size_t)b * U + lane - NX] * sj * sj;
       }
 #pragma unroll
-      for (int r = 0; r < NL; ++r) {
+      for (int r = 0; r < L; ++r) {
         float g = 0.f;
         if (has_next) {
 #pragma unroll
-          for (int i = 0; i < NX; ++i) g = fmaf(sTop[i * NL + r], top[i], g);
+          for (int i = 0; i < NX; ++i) g = fmaf(sTop[i * L + r], top[i], g);
           if (r >= NX && r == lane) g += 1.f;
         }
         col[r] = rho * g + ((r == lane) ? dg + rho : 0.f);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < NL; ++r) col[r] = (r == lane - NL) ? 1.f : 0.f;
+      for (int r = 0; r < L; ++r) col[r] = (r == ic) ? 1.f : 0.f;
     }
-    gj_columns_f<NL>(col);
-    if (lane >= NL && lane < 2 * NL) {
-      const int c = lane - NL;
+    gj_columns_f<L>(col);
+    if (lane >= L && ic < L) {
+      const int c = ic;
 #pragma unroll
-      for (int r = 0; r < NL; ++r) {
+      for (int r = 0; r < L; ++r) {
         if (r <= c) {
           const float v = col[r];
-          ws.Hp[(size_t)s * NH + pk(r, c, NL)] = v;
-          if (bf16) ws.Hbf[(size_t)s * NH + pk(r, c, NL)] = to_bf16(v);
+          ws.Hp[(size_t)s * D::H + pk(r, c, L)] = v;
+          if (bf16) ws.Hbf[(size_t)s * D::H + pk(r, c, L)] = to_bf16(v);
         }
       }
     }
   }
-  // M_k = (Bt^T Bt + I)^{-1}: lane c < 12 forms column c of Bt^T Bt + I,
-  // lanes 12..23 hold the identity's columns
+  if (wave != 0) return;
+  // M_k = (Bt^T Bt + I)^{-1}: lane c < U forms column c of Bt^T Bt + I,
+  // lanes U..2U-1 hold the identity's columns
   {
-    float col[NU];
-    if (lane < NU) {
+    float col[U];
+    if (lane < U) {
       float bc[NX];
 #pragma unroll
-      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * NU + lane];
+      for (int i = 0; i < NX; ++i) bc[i] = sBt[i * U + lane];
 #pragma unroll
-      for (int r = 0; r < NU; ++r) {
+      for (int r = 0; r < U; ++r) {
         float g = 0.f;
 #pragma unroll
-        for (int i = 0; i < NX; ++i) g = fmaf(sBt[i * NU + r], bc[i], g);
+        for (int i = 0; i < NX; ++i) g = fmaf(sBt[i * U + r], bc[i], g);
         col[r] = g + ((r == lane) ? 1.f : 0.f);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < NU; ++r) col[r] = (r == lane - NU) ? 1.f : 0.f;
+      for (int r = 0; r < U; ++r) col[r] = (r == lane - U) ? 1.f : 0.f;
     }
-    gj_columns_f<NU>(col);
-    if (lane >= NU && lane < 2 * NU) {
-      const int c = lane - NU;
+    gj_columns_f<U>(col);
+    if (lane >= U && lane < 2 * U) {
+      const int c = lane - U;
 #pragma unroll
-      for (int r = 0; r < NU; ++r) {
+      for (int r = 0; r < U; ++r) {
         if (r <= c) {
           const float v = col[r];
-          ws.Mp[(size_t)s * NM + pk(r, c, NU)] = v;
-          if (bf16) ws.Mbf[(size_t)s * NM + pk(r, c, NU)] = to_bf16(v);
+          ws.Mp[(size_t)s * D::M + pk(r, c, U)] = v;
+          if (bf16) ws.Mbf[(size_t)s * D::M + pk(r, c, U)] = to_bf16(v);
         }
       }
     }
   }
-  if (lane < NL) {
+  if (lane < L) {
     float q;
     if (lane < NX) {
       q = p.Q[(size_t)b * NX + lane] * p.x_ref[(size_t)s * NX + lane];
     } else {
       const int j = lane - NX;
-      const float ur = p.u_ref ? p.u_ref[(size_t)s * NU + j] : 0.f;
-      q = p.R[(size_t)b * NU + j] * scale_of(p, b, k, j, sc) * ur;
+      const float ur = p.u_ref ? p.u_ref[(size_t)s * U + j] : 0.f;
+      q = p.R[(size_t)b * U + j] * scale_of<NC>(p, b, k, j, sc) * ur;
     }
-    ws.qb[(size_t)s * NL + lane] = q;
+    ws.qb[(size_t)s * L + lane] = q;
   }
 }
+
+static_assert(2 * Dims<2>::U <= 64 && 2 * Dims<4>::U <= 64, "[M | I] fits one wave");
+static_assert(2 * (64 - Dims<4>::L) >= Dims<4>::L && 64 - Dims<2>::L >= Dims<2>::L,
+              "the identity columns of [H | I] fit the workgroup's waves");
 
 }  // namespace
 
@@ -196,8 +219,12 @@ hipError_t launch_setup(const Problem& p, const Workspace& w, const pinmpc_setti
                         hipStream_t st) {
   const size_t stages = (size_t)p.batch * p.n_max;
   if (stages == 0) return hipSuccess;
-  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)stages), dim3(64), 0, st, p, w, s.rho,
-                     s.scaling, s.precision);
+  if (p.nc == 4)
+    hipLaunchKernelGGL(setup_kernel<4>, dim3((unsigned)stages), dim3(128), 0, st, p, w, s.rho,
+                       s.scaling, s.precision);
+  else
+    hipLaunchKernelGGL(setup_kernel<2>, dim3((unsigned)stages), dim3(64), 0, st, p, w, s.rho,
+                       s.scaling, s.precision);
   return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ def _check_invariants(batch, out, idx):
         u = out["u"][b, :N].astype(np.float64)
         x = out["x"][b, :N + 1].astype(np.float64)
         sw = ~p["contact"]
-        for i in range(2):
+        for i in range(p["contact"].shape[1]):
             assert np.all(out["u"][b, :N, 6 * i:6 * i + 6][sw[:, i]] == 0.0)
         assert np.all(out["u"][b, N:] == 0)
         r = kkt.residuals(p, u, x)

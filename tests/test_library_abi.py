@@ -28,7 +28,9 @@ def test_header_symbols_exported():
 def test_struct_layouts_match_header():
     # field order and C types as declared in include/pinmpc.h
     assert ctypes.sizeof(binding.Settings) == 72
-    assert ctypes.sizeof(binding.Batch) == 8 + 15 * 8
+    # batch, n_max, 15 pointers, contacts (int32, padded to 8)
+    assert ctypes.sizeof(binding.Batch) == 8 + 15 * 8 + 8
+    assert binding.Batch.contacts.offset == 8 + 15 * 8
     assert ctypes.sizeof(binding.Out) == 6 * 8
 
 
@@ -44,6 +46,18 @@ def test_default_settings_and_errors():
     assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, binding.NMAX_LONG + 1,
                                       ctypes.byref(nb)) == -1
     assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 16, binding.NMAX_LONG, ctypes.byref(nb)) == 0
+    # four contacts per stage (feet and hands): horizons up to NMAX, more bytes
+    n2, n4 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.pinmpc_workspace_bytes_contacts(ctypes.byref(s), 4096, 20, 2, ctypes.byref(n2)) == 0
+    assert lib.pinmpc_workspace_bytes(ctypes.byref(s), 4096, 20, ctypes.byref(nb)) == 0
+    assert n2.value == nb.value
+    assert lib.pinmpc_workspace_bytes_contacts(ctypes.byref(s), 4096, 20, 4, ctypes.byref(n4)) == 0
+    assert n4.value > n2.value
+    assert lib.pinmpc_workspace_bytes_contacts(ctypes.byref(s), 16, binding.NMAX, 4,
+                                               ctypes.byref(n4)) == 0
+    for bad_c, n in ((4, binding.NMAX + 1), (3, 10), (1, 10), (-4, 10)):
+        assert lib.pinmpc_workspace_bytes_contacts(ctypes.byref(s), 16, n, bad_c,
+                                                   ctypes.byref(n4)) == -1, (bad_c, n)
     # null context / null arguments are rejected before any device call
     assert lib.pinmpc_solve(None, None, None, None) == -1
     assert lib.pinmpc_destroy(None) == -1
