@@ -52,6 +52,21 @@ REFINE_BYTES_PER_PASS_STAGE = 4_500
 # every pass)
 REFINE_DENSE_BACKWARD = 3744 + 312 + 4394 + 338 + 4056 + 3744 + 4368 + 3744 + 5904 + 9100
 REFINE_DENSE_FORWARD = 1250 + 650 + 500
+# The four-contact refinement (feet and hands, 24 inputs) per stage of one
+# interior-point iteration: two factorisations of the stage system (W B 8112,
+# W A 4394, B^T W B 14976, B^T W A 8112, B^T w 624, Gauss-Jordan on the 24 x 38
+# system 41952, S and s 13468: 91 638 each) and two rollouts of the gains
+# (1586 each); bytes: each factorisation reads A, B (FP32) and the stage terms
+# and writes the gains (5956 B), each rollout reads the gains and A, B (4612 B),
+# the row and input updates about 2900 B
+WIDE_FLOPS_PER_IPM_STAGE = 2 * (8112 + 4394 + 14976 + 8112 + 624 + 41952 + 13468) + 2 * 1586
+WIDE_BYTES_PER_IPM_STAGE = 2 * 5956 + 2 * 4612 + 2900
+# its sweep per stage: operators A 676 + Bt 1248 + H packed 2812 + M packed
+# 1200 + qbar 148 + e 52 + contact 4 + force scale 4 = 6144 B read, iterates
+# (5 x 37 each) 1480 B read + 1480 B written; setup per stage: A_k, A_{k+1},
+# B_k, B_{k+1} read (3848 B), Bt, H, M, qbar written (5408 B)
+WIDE_SWEEP_BYTES_PER_STAGE = 6144 + 2960
+WIDE_SETUP_BYTES_PER_STAGE = 3848 + 5408
 # setup, once per stage: operators read, H, M, qbar and the scaled B written
 SETUP_BYTES_PER_STAGE = 3_200
 # interior-point cap, polish passes and certificate threshold for horizons
@@ -534,6 +549,7 @@ def main():
         del hdev
     batch = mpcgen.make_batch(args.workload)
     Bn, n = batch["A"].shape[0], batch["A"].shape[1]
+    wide = batch["contact"].shape[-1] == 4   # feet and hands: the interior-point refinement
     stages = int(batch["N"].sum())
     if n > 64:   # the long-horizon refinement budget (also for a fixed schedule)
         for k, v in LONG_BASE.items():
@@ -633,6 +649,10 @@ def main():
     dense_flops = float(stf.sum() * REFINE_DENSE_BACKWARD +
                         (N_b * eq_p).sum() * REFINE_DENSE_FORWARD +
                         (N_b * ipm_p).sum() * (REFINE_DENSE_BACKWARD + 2 * REFINE_DENSE_FORWARD))
+    if wide:   # already a dense count
+        dense_flops = float(pass_stages) * WIDE_FLOPS_PER_IPM_STAGE
+    sweep_b = WIDE_SWEEP_BYTES_PER_STAGE if wide else SWEEP_BYTES_PER_STAGE
+    setup_b = WIDE_SETUP_BYTES_PER_STAGE if wide else SETUP_BYTES_PER_STAGE
     work = {"pass_stages": pass_stages,
             "equality_passes_mean": float(eq_p.mean()),
             "interior_point_iters_mean": float(ipm_p.mean()),
@@ -640,44 +660,52 @@ def main():
             "frac_finished_in_second_launch": float((det[:, 3] == 2).mean()),
             "stages_factored_per_equality_pass": float(stf.sum() / max(1, eq_p.sum())),
             "dense_flops_per_solve": dense_flops}
+    # four contacts take the streamed sweep whatever the form (all sweeps in one
+    # launch unless the form is 0)
+    form_name = ("streamed" if wide and settings["form"] != 0 else
+                 {0: "plain", 1: "fused", -1: "packed", 2: "split"}[settings["form"]])
     kernels = {
         "setup_kernel": {"ms": setup_ms},
-        "admm": {"ms": admm_ms, "form": {0: "plain", 1: "fused", -1: "packed", 2: "split"}[settings["form"]]},
+        "admm": {"ms": admm_ms, "form": form_name},
         "refine_kernel": {"ms": refine_ms},
     }
     # algorithmic work of each phase per launch
-    refine_flops = float(pass_stages) * REFINE_FLOPS_PER_PASS_STAGE
-    refine_bytes = float(pass_stages) * REFINE_BYTES_PER_PASS_STAGE
+    flops_ps = WIDE_FLOPS_PER_IPM_STAGE if wide else REFINE_FLOPS_PER_PASS_STAGE
+    bytes_ps = WIDE_BYTES_PER_IPM_STAGE if wide else REFINE_BYTES_PER_PASS_STAGE
+    refine_flops = float(pass_stages) * flops_ps
+    refine_bytes = float(pass_stages) * bytes_ps
     kernels["refine_kernel"]["tflops"] = refine_flops / (refine_ms * 1e-3) / 1e12
     kernels["refine_kernel"]["gbs"] = refine_bytes / (refine_ms * 1e-3) / 1e9
     kernels["refine_kernel"]["dense_tflops"] = dense_flops / (refine_ms * 1e-3) / 1e12
-    if settings["form"] == 0:
-        sweep_bytes = stages * SWEEP_BYTES_PER_STAGE
+    if settings["form"] == 0 or wide:
+        sweep_bytes = stages * sweep_b
         kernels["admm"]["gbs"] = sweep_bytes * K / (admm_ms * 1e-3) / 1e9
     else:
         kernels["admm"]["tflops"] = stages * SWEEP_FLOPS_PER_STAGE * K / (admm_ms * 1e-3) / 1e12
     dominant = max(kernels, key=lambda k: kernels[k]["ms"])
     if dominant == "refine_kernel":
-        src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "refine.hip")
+        kname = "refine_wide_kernel" if wide else "refine_kernel"
+        src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc",
+                           "refine_wide.hip" if wide else "refine.hip")
         achieved = kernels["refine_kernel"]["tflops"]
         # FP64 arithmetic on the vector units and matrix cores (the same FP64
         # peak on this chip); the HBM fraction of the same launch beside it
-        roof = {"kernel": "refine_kernel<1>+<2>", "bound": "alu", "achieved": achieved,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        roof = {"kernel": kname if wide else "refine_kernel<1>+<2>", "bound": "alu",
+                "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": measured_traffic(src, "refine_kernel"),
+                "traffic": measured_traffic(src, kname),
                 "launch_ms": refine_ms, "flops_per_launch": refine_flops,
-                "pass_stages": pass_stages, "flops_per_pass_stage": REFINE_FLOPS_PER_PASS_STAGE,
+                "pass_stages": pass_stages, "flops_per_pass_stage": flops_ps,
                 "hbm_gbs": kernels["refine_kernel"]["gbs"],
                 "hbm_frac": kernels["refine_kernel"]["gbs"] / HBM_PEAK_GBS,
-                "bytes_per_pass_stage": REFINE_BYTES_PER_PASS_STAGE, "dtype": "f64"}
-    elif dominant == "admm" and settings["form"] == 0:
+                "bytes_per_pass_stage": bytes_ps, "dtype": "f64"}
+    elif dominant == "admm" and (settings["form"] == 0 or wide):
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_plain.hip")
         achieved = kernels["admm"]["gbs"]
         roof = {"kernel": "admm_sweep_kernel", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(src, "admm_sweep_kernel"),
-                "launch_ms": admm_ms / max(1, K), "bytes_per_launch": stages * SWEEP_BYTES_PER_STAGE}
+                "launch_ms": admm_ms / max(1, K), "bytes_per_launch": stages * sweep_b}
     elif dominant == "admm":
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "admm_fused.hip")
         achieved = kernels["admm"]["tflops"]
@@ -693,7 +721,7 @@ def main():
     # the whole solve against HBM: setup once per stage, K sweeps of operators
     # and iterates, the refinement's pass-stages, over the throughput interval
     # (solves in flight) and over one uncontended solve
-    solve_bytes = float(stages * (SETUP_BYTES_PER_STAGE + K * SWEEP_BYTES_PER_STAGE) + refine_bytes)
+    solve_bytes = float(stages * (setup_b + K * sweep_b) + refine_bytes)
     whole = {"bytes_per_solve": solve_bytes,
              "interval_ms": ms_per_step,
              "gbs": solve_bytes / (ms_per_step * 1e-3) / 1e9,
@@ -719,7 +747,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "batch": int(Bn), "horizon": int(n),
                    "admm_iters": K, "rho": settings["rho"],
-                   "form": {0: "plain", 1: "fused", -1: "packed", 2: "split"}[settings["form"]],
+                   "form": form_name,
                    "precision": "bf16" if settings.get("precision") else "fp32",
                    "refine_passes": int(settings.get("refine_passes", 8)),
                    "first_passes": int(settings.get("first_passes", 4)),
