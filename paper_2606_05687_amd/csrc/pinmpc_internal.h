@@ -176,10 +176,11 @@ __host__ __device__ constexpr size_t refine_block_doubles(int n) {
 // with n stages: gains (24 x 13), feedforward, inputs, their step and the
 // costates (24 each), the stage input terms (per contact a 6 x 6 block and
 // six entries), slacks, multipliers, their steps and the complementarity
-// target (11 per contact each), then x and dx ((n+1) x 13 each).
+// target (11 per contact each), the inverse input Hessian (24 x 24) and Hwx
+// (24 x 13), then x and dx ((n+1) x 13 each).
 __host__ __device__ constexpr size_t refine_wide_block_doubles(int n) {
-  return ((size_t)n * (24 * NX + 4 * 24 + 4 * 42 + 5 * 4 * NROW) + 2 * (size_t)(n + 1) * NX + 3) &
-         ~(size_t)3;
+  return ((size_t)n * (24 * NX + 4 * 24 + 4 * 42 + 5 * 4 * NROW + 24 * 24 + 24 * NX) +
+          2 * (size_t)(n + 1) * NX + 3) & ~(size_t)3;
 }
 
 // 1/a from the hardware estimate refined by two Newton steps (the pivots of

@@ -58,11 +58,12 @@ struct WCtx {
   double mu, fz, tm, mg, scf, scm;   // bounds, force scale, row scales
   const float *A, *B, *e, *x_ref, *u_ref, *x0;
   const uint8_t* contact;            // [n][4]
-  double *K, *kap, *u, *du, *x, *dx, *lam, *T, *s, *z, *ds, *dz, *rc;
+  double *K, *kap, *u, *du, *x, *dx, *lam, *T, *s, *z, *ds, *dz, *rc, *Hi, *Hx;
 };
 
 static_assert(refine_wide_block_doubles(1) >=
-                  (size_t)U4 * NX + 4 * U4 + C4 * TB + 5 * C4 * NROW + 2 * 2 * NX,
+                  (size_t)U4 * NX + 4 * U4 + C4 * TB + 5 * C4 * NROW + U4 * U4 + U4 * NX +
+                      2 * 2 * NX,
               "the carve below fits the scratch block");
 
 __device__ void carve(WCtx& C, double* blk) {
@@ -78,6 +79,8 @@ __device__ void carve(WCtx& C, double* blk) {
   C.ds = blk;   blk += (size_t)n * C4 * NROW;
   C.dz = blk;   blk += (size_t)n * C4 * NROW;
   C.rc = blk;   blk += (size_t)n * C4 * NROW;
+  C.Hi = blk;   blk += (size_t)n * U4 * U4;
+  C.Hx = blk;   blk += (size_t)n * U4 * NX;
   C.x = blk;    blk += (size_t)(n + 1) * NX;
   C.dx = blk;
 }
@@ -85,7 +88,7 @@ __device__ void carve(WCtx& C, double* blk) {
 // LDS of the stage recursion.
 struct WSh {
   double A[NX * NX], B[NX * U4], W[NX * NX], WA[NX * NX], WB[NX * U4], Hwx[U4 * NX], K[U4 * NX];
-  double Aug[(L4 + 1) * U4];
+  double Aug[(L4 + 1) * U4];   // [H | Hwx | hw], column by column
   double S[NX * NX], sv[NX], w[NX], kap[U4], T[C4 * TB], Sn[NSN];
   double v13[NX], v24[U4], Q[NX], R[U4];
 };
@@ -192,10 +195,61 @@ __device__ __attribute__((noinline)) void build_terms(const WCtx& C, const WSh& 
 }
 
 // Backward recursion of the Newton step, stages N-1 .. 0: gains and
-// feedforward of every stage into the scratch.
-__device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh) {
+// feedforward of every stage into the scratch.  The elimination also turns the
+// identity carried in lanes 38..61 into H^{-1}, kept with Hwx for a second
+// right-hand side of the same Newton matrix (factor = false: the corrector of
+// an interior-point iteration), whose recursion is the vector part alone:
+// hw = rho + B^T w, kap = -H^{-1} hw, s = A^T w + Hwx^T kap.
+__device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool factor) {
   const int lane = threadIdx.x;
   __syncthreads();
+  if (!factor) {
+    if (lane < NX) sh.sv[lane] = 0.0;
+    for (int k = C.N - 1; k >= 0; --k) {
+      __syncthreads();
+      if (lane < NX) {
+        const double q = sh.Q[lane] * (C.x[(size_t)(k + 1) * NX + lane] -
+                                       (double)C.x_ref[(size_t)k * NX + lane]);
+        sh.w[lane] = sh.sv[lane] + q;
+      }
+      __syncthreads();
+      if (lane < U4) {
+        // swing inputs: zero rho and a unit row of H^{-1}, so kap = 0 there
+        const bool on = stance(C, k, lane / 6);
+        double a = C.T[(size_t)k * C4 * TB + (lane / 6) * TB + 36 + lane % 6];
+        const float* Bk = C.B + (size_t)k * NX * U4;
+        if (on) {
+#pragma unroll
+          for (int i = 0; i < NX; ++i) a = fma((double)Bk[i * U4 + lane], sh.w[i], a);
+        }
+        sh.v24[lane] = a;
+      }
+      __syncthreads();
+      if (lane < U4) {
+        // row `lane` of H^{-1} (its columns are stored one after the other)
+        const double* Hc = C.Hi + (size_t)k * U4 * U4 + lane;
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < U4; ++j) a = fma(Hc[j * U4], sh.v24[j], a);
+        sh.kap[lane] = -a;
+        C.kap[(size_t)k * U4 + lane] = -a;
+      }
+      if (k == 0) break;
+      __syncthreads();
+      if (lane < NX) {
+        const float* Ak = C.A + (size_t)k * NX * NX;
+        const double* Hx = C.Hx + (size_t)k * U4 * NX;
+        double a = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) a = fma((double)Ak[l * NX + lane], sh.w[l], a);
+#pragma unroll
+        for (int r = 0; r < U4; ++r) a = fma(Hx[r * NX + lane], sh.kap[r], a);
+        sh.sv[lane] = a;
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int e = lane; e < NX * NX; e += 64) sh.S[e] = 0.0;
   if (lane < NX) sh.sv[lane] = 0.0;
   for (int k = C.N - 1; k >= 0; --k) {
@@ -249,6 +303,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh) {
 #pragma unroll
         for (int i = 0; i < NX; ++i) a = fma(sh.B[i * U4 + r], sh.WA[i * NX + j], a);
         sh.Hwx[r * NX + j] = a;
+        C.Hx[(size_t)k * U4 * NX + r * NX + j] = a;
       } else {
         a = sh.T[(r / 6) * TB + 36 + r % 6];
 #pragma unroll
@@ -259,7 +314,8 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh) {
     __syncthreads();
     double col[U4];
 #pragma unroll
-    for (int r = 0; r < U4; ++r) col[r] = lane <= L4 ? sh.Aug[lane * U4 + r] : 0.0;
+    for (int r = 0; r < U4; ++r)
+      col[r] = lane <= L4 ? sh.Aug[lane * U4 + r] : (lane - L4 - 1 == r ? 1.0 : 0.0);
     gj_columns<U4>(col, unit);
     if (lane >= U4 && lane < L4) {
       const int j = lane - U4;
@@ -275,6 +331,11 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh) {
         sh.kap[r] = -col[r];
         C.kap[(size_t)k * U4 + r] = -col[r];
       }
+    } else if (lane > L4 && lane < L4 + 1 + U4) {
+      // column lane - 38 of H^{-1}
+      const int j = lane - L4 - 1;
+      #pragma unroll
+      for (int r = 0; r < U4; ++r) C.Hi[(size_t)k * U4 * U4 + j * U4 + r] = col[r];
     }
     if (k == 0) break;   // x_0 is fixed: its value function is not needed
     __syncthreads();
@@ -619,7 +680,7 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
     }
     // predictor: affine target rc = s z (in C.rc)
     build_terms(C, sh);
-    backward(C, sh);
+    backward(C, sh, true);
     forward(C, sh);
     double sigma = 0.0;
     if (m > 0.0) {
@@ -643,6 +704,7 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       const double mu_aff = wsum(sm) / m;
       sigma = muv > 0.0 ? pow(mu_aff / muv, 3.0) : 0.0;
       // corrector: rc = s z + ds_aff dz_aff - sigma mu, the same Newton matrix
+      // (solved with the inverse the predictor's elimination left)
       for (int e = lane; e < C.N * C4; e += 64) {
         const int k = e / C4, i = e % C4;
         if (!stance(C, k, i)) continue;
@@ -650,8 +712,11 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
         #pragma unroll
         for (int r = 0; r < NROW; ++r) cv[r] -= sigma * muv;
       }
+      // (near the optimum the corrector factors again: the product with the
+      // kept inverse carries the Hessian's conditioning into the step, which
+      // then limits how closely u meets stationarity)
       build_terms(C, sh);
-      backward(C, sh);
+      backward(C, sh, muv <= 1e-6);
       forward(C, sh);
     }
     const double a = m > 0.0 ? fmin(1.0, 0.99 * row_steps(C)) : 1.0;
