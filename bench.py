@@ -56,11 +56,15 @@ REFINE_DENSE_FORWARD = 1250 + 650 + 500
 # interior-point iteration: two factorisations of the stage system (W B 8112,
 # W A 4394, B^T W B 14976, B^T W A 8112, B^T w 624, Gauss-Jordan on the 24 x 38
 # system 41952, S and s 13468: 91 638 each) and two rollouts of the gains
-# (1586 each); bytes: each factorisation reads A, B (FP32) and the stage terms
-# and writes the gains (5956 B), each rollout reads the gains and A, B (4612 B),
-# the row and input updates about 2900 B
+# (1586 each).  Bytes: the iteration's data flow, each array crossing HBM once
+# per phase that uses it: the factorisation reads A, B (FP32), the stage terms
+# and x, and writes K, kappa, H^-1 and Hwx (13 216 B); the corrector's vector
+# pass reads B, A, rho, x, H^-1 and Hwx and writes kappa (9568 B); two rollouts
+# of the gains (4908 B each); two builds of the stage terms (2592 B each); two
+# slack and multiplier steps (2144 B each); the step and the next residuals
+# (3736 B); the corrector's target (1760 B)
 WIDE_FLOPS_PER_IPM_STAGE = 2 * (8112 + 4394 + 14976 + 8112 + 624 + 41952 + 13468) + 2 * 1586
-WIDE_BYTES_PER_IPM_STAGE = 2 * 5956 + 2 * 4612 + 2900
+WIDE_BYTES_PER_IPM_STAGE = 13216 + 9568 + 2 * 4908 + 2 * 2592 + 2 * 2144 + 3736 + 1760
 # its sweep per stage: operators A 676 + Bt 1248 + H packed 2812 + M packed
 # 1200 + qbar 148 + e 52 + contact 4 + force scale 4 = 6144 B read, iterates
 # (5 x 37 each) 1480 B read + 1480 B written; setup per stage: A_k, A_{k+1},
@@ -103,6 +107,9 @@ def parse():
                     help="only summarise rocprofv3 --pmc runs found under this folder "
                          "(pmc_fetch, pmc_write, pmc_copy_fetch, pmc_copy_write) into "
                          "profiles/traffic.json")
+    ap.add_argument("--pmc-args", default=TUNED,
+                    help="the benchmark arguments of those runs (recorded with each kernel's "
+                         "entry; entries of kernels the runs did not see are kept)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="generator configuration of the timed batch (the metric is quoted on "
                          "plain_b4096_n20; the others are reported beside it)")
@@ -216,10 +223,12 @@ def cpu_baseline(sample, workers, admm_k=None, rho=10.0):
 KERNEL_SOURCES = {
     "refine_kernel<1>": "refine.hip",
     "refine_kernel<2>": "refine.hip",
-    "setup_kernel": "setup.hip",
+    "setup_kernel<2>": "setup.hip",
+    "setup_kernel<4>": "setup.hip",
     "admm_fused_kernel": "admm_fused.hip",
     "admm_sweep_kernel": "admm_plain.hip",
     "dynamics_kernel": "dynamics.hip",
+    "refine_wide_kernel": "refine_wide.hip",
 }
 
 
@@ -243,17 +252,22 @@ def _counter_rows(run_dir):
 
 
 TUNED = "--autotune 0 --form 1 --iters 2 --rho 1 --refine-passes 12 --first-passes 0 --cpu-sample 0 --streams 1"
-PMC_COMMANDS = [
-    f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
-    f"python3 bench.py {TUNED} --steps 2 --warmup 1",
-    f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o w --output-format csv -- "
-    f"python3 bench.py {TUNED} --steps 2 --warmup 1",
-    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_copy_fetch -o cf --output-format csv -- "
-    "python3 bench.py --copy-calibration 1073741824",
-    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_copy_write -o cw --output-format csv -- "
-    "python3 bench.py --copy-calibration 1073741824",
-    "python3 bench.py --pmc-summary gpurun_out",
-]
+
+
+def pmc_commands(run_args):
+    """The rocprofv3 counter runs that a summary reads, for benchmark
+    arguments `run_args`."""
+    return [
+        f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
+        f"python3 bench.py {run_args} --steps 2 --warmup 1",
+        f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o w --output-format csv -- "
+        f"python3 bench.py {run_args} --steps 2 --warmup 1",
+        "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_copy_fetch -o cf --output-format csv -- "
+        "python3 bench.py --copy-calibration 1073741824",
+        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_copy_write -o cw --output-format csv -- "
+        "python3 bench.py --copy-calibration 1073741824",
+        f"python3 bench.py --pmc-summary gpurun_out --pmc-args '{run_args}'",
+    ]
 
 
 def _kernel_match(kernel, name):
@@ -266,12 +280,13 @@ def _kernel_match(kernel, name):
     return "::" + kernel + "(" in name or "::" + kernel + "<" in name
 
 
-def pmc_summary(prof_dir, command):
+def pmc_summary(prof_dir, run_args):
     """HBM bytes per launch of the library's kernels from two rocprofv3 --pmc
     runs of the benchmark (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
     scaled by what the same counter reads for the --copy-calibration kernel,
-    whose bytes are known.  Writes profiles/traffic.json; returns a text
-    summary."""
+    whose bytes are known.  Updates profiles/traffic.json (one entry per
+    kernel, with the calibration and commands it was taken with); returns a
+    text summary."""
     cal = {}
     for counter, sub in (("FETCH_SIZE", "pmc_copy_fetch"), ("WRITE_SIZE", "pmc_copy_write")):
         vals = [float(r["Counter_Value"]) for r in _counter_rows(os.path.join(prof_dir, sub))
@@ -279,9 +294,16 @@ def pmc_summary(prof_dir, command):
         known_kib = 1073741824 / 1024.0
         cal[counter] = {"dispatches": len(vals), "mean_kib": sum(vals) / len(vals),
                         "scale": known_kib / (sum(vals) / len(vals))}
-    out = {"calibration": {"kernel": "elementwise multiply by 1 over 1 GiB (read 1 GiB, write 1 GiB)",
-                           "FETCH_SIZE": cal["FETCH_SIZE"], "WRITE_SIZE": cal["WRITE_SIZE"]},
-           "commands": PMC_COMMANDS}
+    calib = {"kernel": "elementwise multiply by 1 over 1 GiB (read 1 GiB, write 1 GiB)",
+             "FETCH_SIZE": cal["FETCH_SIZE"], "WRITE_SIZE": cal["WRITE_SIZE"]}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
+    for k in ("calibration", "commands"):   # the single-run layout of earlier records
+        out.pop(k, None)
+    seen = {}
     lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes per launch |",
              "|---|---|---|---|---|"]
     for kernel, src in KERNEL_SOURCES.items():
@@ -295,22 +317,25 @@ def pmc_summary(prof_dir, command):
             continue
         nb = per["FETCH_SIZE"][1] * 1024 * cal["FETCH_SIZE"]["scale"] + \
             per["WRITE_SIZE"][1] * 1024 * cal["WRITE_SIZE"]["scale"]
-        out[kernel] = {"source_sha": _kernel_sha(os.path.join(ROOT, "paper_2606_05687_amd", "csrc", src)),
-                       "fetch_kib": per["FETCH_SIZE"][1], "write_kib": per["WRITE_SIZE"][1],
-                       "bytes_per_launch": nb}
+        seen[kernel] = {"source_sha": _kernel_sha(os.path.join(ROOT, "paper_2606_05687_amd", "csrc", src)),
+                        "fetch_kib": per["FETCH_SIZE"][1], "write_kib": per["WRITE_SIZE"][1],
+                        "bytes_per_launch": nb, "calibration": calib,
+                        "commands": pmc_commands(run_args)}
         lines.append(f"| {kernel} | {per['FETCH_SIZE'][0]} | {per['FETCH_SIZE'][1]:.0f} | "
                      f"{per['WRITE_SIZE'][1]:.0f} | {nb / 1e9:.3f} GB |")
     # the refinement runs as a pair of launches per solve (every problem's
     # active-set passes, then the problems they leave): its bytes per solve
-    if "refine_kernel<1>" in out and "refine_kernel<2>" in out:
-        out["refine_kernel"] = {
-            "source_sha": out["refine_kernel<1>"]["source_sha"],
-            "bytes_per_launch": out["refine_kernel<1>"]["bytes_per_launch"] +
-            out["refine_kernel<2>"]["bytes_per_launch"],
-            "note": "sum of the two refinement launches of one solve"}
+    if "refine_kernel<1>" in seen and "refine_kernel<2>" in seen:
+        seen["refine_kernel"] = {
+            "source_sha": seen["refine_kernel<1>"]["source_sha"],
+            "bytes_per_launch": seen["refine_kernel<1>"]["bytes_per_launch"] +
+            seen["refine_kernel<2>"]["bytes_per_launch"],
+            "note": "sum of the two refinement launches of one solve",
+            "commands": pmc_commands(run_args)}
         lines.append(f"| refine_kernel<1> + <2> (per solve) | | | | "
-                     f"{out['refine_kernel']['bytes_per_launch'] / 1e9:.3f} GB |")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+                     f"{seen['refine_kernel']['bytes_per_launch'] / 1e9:.3f} GB |")
+    out.update(seen)
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
     lines += ["", f"FETCH_SIZE scale {cal['FETCH_SIZE']['scale']:.4f} "
               f"(calibration kernel reads {cal['FETCH_SIZE']['mean_kib']:.0f} KiB for 1 GiB read), "
@@ -486,7 +511,7 @@ def before_after(batch, reps=20):
 def main():
     args = parse()
     if args.pmc_summary:
-        print(pmc_summary(args.pmc_summary, " ".join(sys.argv[1:])))
+        print(pmc_summary(args.pmc_summary, args.pmc_args))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -717,7 +742,8 @@ def main():
         src = os.path.join(ROOT, "paper_2606_05687_amd", "csrc", "setup.hip")
         roof = {"kernel": "setup_kernel", "bound": "alu", "achieved": None,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": measured_traffic(src, "setup_kernel"), "launch_ms": setup_ms}
+                "traffic": measured_traffic(src, "setup_kernel<4>" if wide else "setup_kernel<2>"),
+                "launch_ms": setup_ms}
     # the whole solve against HBM: setup once per stage, K sweeps of operators
     # and iterates, the refinement's pass-stages, over the throughput interval
     # (solves in flight) and over one uncontended solve
