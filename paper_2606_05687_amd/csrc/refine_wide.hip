@@ -451,22 +451,31 @@ __device__ inline void frow(int r, double mu, double g[3]) {
 // squares).  An optimal support has at most three independent rows, so the
 // candidates are every subset of at most three rows of `am` with a
 // nonsingular Gram matrix whose least-squares multipliers are nonnegative.
+// Every loop below unrolls completely (the subset S is a constant in each
+// copy), so no array is indexed at run time and all of them stay in registers.
 __device__ void force_refit(int am, double mu, const double gf[3], double m[5]) {
   double best = gf[0] * gf[0] + gf[1] * gf[1] + gf[2] * gf[2];
 #pragma unroll
   for (int t = 0; t < 5; ++t) m[t] = 0.0;
   const double scale = 1.0 + mu * mu;
+#pragma unroll
   for (int S = 1; S < 32; ++S) {
-    if ((S & am) != S || __builtin_popcount(S) > 3) continue;
+    if (__builtin_popcount(S) > 3) continue;
+    if ((S & am) != S) continue;
     int idx[3] = {0, 0, 0}, k = 0;
+#pragma unroll
     for (int r = 0; r < 5; ++r)
       if ((S >> r) & 1) idx[k++] = r;
     double g[3][3];
+#pragma unroll
     for (int j = 0; j < 3; ++j) frow(j < k ? idx[j] : 0, mu, g[j]);
-    // Gram matrix and right-hand side -G_S gf (k x k, k <= 3)
+    // Gram matrix and right-hand side -G_S gf (k x k, k <= 3), the identity
+    // on the unused rows
     double M[3][3], b[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       b[a] = a < k ? -(g[a][0] * gf[0] + g[a][1] * gf[1] + g[a][2] * gf[2]) : 0.0;
+#pragma unroll
       for (int c = 0; c < 3; ++c)
         M[a][c] = (a < k && c < k) ? g[a][0] * g[c][0] + g[a][1] * g[c][1] + g[a][2] * g[c][2]
                                    : (a == c ? 1.0 : 0.0);
@@ -476,25 +485,36 @@ __device__ void force_refit(int am, double mu, const double gf[3], double m[5]) 
                        M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
     if (!(fabs(det) > 1e-10 * scale * scale * scale)) continue;   // dependent rows
     double x[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       double D[3][3];
+#pragma unroll
       for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int c = 0; c < 3; ++c) D[i][c] = c == a ? b[i] : M[i][c];
       x[a] = (D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
               D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
               D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0])) / det;
     }
     bool ok = true;
-    for (int a = 0; a < k; ++a) ok = ok && x[a] >= 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = ok && (a >= k || x[a] >= 0.0);
     if (!ok) continue;
     double rv[3] = {gf[0], gf[1], gf[2]};
-    for (int a = 0; a < k; ++a)
-      for (int c = 0; c < 3; ++c) rv[c] += x[a] * g[a][c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rv[c] += a < k ? x[a] * g[a][c] : 0.0;
     const double res = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     if (res < best) {
       best = res;
-      for (int t = 0; t < 5; ++t) m[t] = 0.0;
-      for (int a = 0; a < k; ++a) m[idx[a]] = x[a];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v = (a < k && idx[a] == t) ? x[a] : v;
+        m[t] = v;
+      }
     }
   }
 }
