@@ -52,6 +52,18 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
+// The kernel runs one 64-lane wave per workgroup.  LDS operations of a wave
+// execute in issue order, so a hand-off between its lanes through LDS needs
+// only a point the compiler moves no memory access across (wsync); the stage
+// loops use it, so that loads of the next stage and stores of this one stay
+// in flight across the hand-offs.  Data passed between lanes through global
+// memory (one phase's results for the next) goes through the workgroup
+// barrier with its memory fence at the phase boundaries.
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // The problem's FP64 scratch (refine_wide_block_doubles(n) doubles).
 struct WCtx {
   int b, n, N;
@@ -200,78 +212,137 @@ __device__ __attribute__((noinline)) void build_terms(const WCtx& C, const WSh& 
 // right-hand side of the same Newton matrix (factor = false: the corrector of
 // an interior-point iteration), whose recursion is the vector part alone:
 // hw = rho + B^T w, kap = -H^{-1} hw, s = A^T w + Hwx^T kap.
-__device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool factor) {
+__device__ __attribute__((noinline)) void backward_rhs(const WCtx& C, WSh& sh) {
   const int lane = threadIdx.x;
   __syncthreads();
-  if (!factor) {
+  {
     if (lane < NX) sh.sv[lane] = 0.0;
-    for (int k = C.N - 1; k >= 0; --k) {
-      __syncthreads();
-      if (lane < NX) {
-        const double q = sh.Q[lane] * (C.x[(size_t)(k + 1) * NX + lane] -
-                                       (double)C.x_ref[(size_t)k * NX + lane]);
-        sh.w[lane] = sh.sv[lane] + q;
+    // per stage: lanes 0..23 the linear term and their column of B, lanes
+    // 0..12 x_{k+1}, x_ref[k] and their column of A, fetched a stage ahead
+    // from clamped addresses; the rows of H^{-1} and columns of Hwx at the
+    // top of their own stage
+    const int lu = min(lane, U4 - 1), lx = min(lane, NX - 1);
+    double frho, fx, fr;
+    float fbc[NX], fac[NX];
+    auto fetch = [&](int k) {
+      frho = C.T[(size_t)k * C4 * TB + (lu / 6) * TB + 36 + lu % 6];
+      const float* Bk = C.B + (size_t)k * NX * U4;
+      const float* Ak = C.A + (size_t)k * NX * NX;
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        fbc[i] = Bk[i * U4 + lu];
+        fac[i] = Ak[i * NX + lx];
       }
-      __syncthreads();
+      fx = C.x[(size_t)(k + 1) * NX + lx];
+      fr = (double)C.x_ref[(size_t)k * NX + lx];
+    };
+    fetch(C.N - 1);
+    for (int k = C.N - 1; k >= 0; --k) {
+      double h[U4], hw[U4], rho = frho, bc[NX], ac[NX];
+      const double* Hc = C.Hi + (size_t)k * U4 * U4 + lu;
+      const double* Hx = C.Hx + (size_t)k * U4 * NX + lx;
+#pragma unroll
+      for (int j = 0; j < U4; ++j) {
+        h[j] = Hc[j * U4];
+        hw[j] = Hx[j * NX];
+      }
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        bc[i] = (double)fbc[i];
+        ac[i] = (double)fac[i];
+      }
+      const double q = sh.Q[lx] * (fx - fr);
+      fetch(k > 0 ? k - 1 : 0);   // in flight during this stage
+      wsync();
+      if (lane < NX) sh.w[lane] = sh.sv[lane] + q;
+      wsync();
       if (lane < U4) {
         // swing inputs: zero rho and a unit row of H^{-1}, so kap = 0 there
-        const bool on = stance(C, k, lane / 6);
-        double a = C.T[(size_t)k * C4 * TB + (lane / 6) * TB + 36 + lane % 6];
-        const float* Bk = C.B + (size_t)k * NX * U4;
-        if (on) {
+        double a = rho;
+        if (stance(C, k, lane / 6)) {
 #pragma unroll
-          for (int i = 0; i < NX; ++i) a = fma((double)Bk[i * U4 + lane], sh.w[i], a);
+          for (int i = 0; i < NX; ++i) a = fma(bc[i], sh.w[i], a);
         }
         sh.v24[lane] = a;
       }
-      __syncthreads();
+      wsync();
       if (lane < U4) {
         // row `lane` of H^{-1} (its columns are stored one after the other)
-        const double* Hc = C.Hi + (size_t)k * U4 * U4 + lane;
         double a = 0.0;
 #pragma unroll
-        for (int j = 0; j < U4; ++j) a = fma(Hc[j * U4], sh.v24[j], a);
+        for (int j = 0; j < U4; ++j) a = fma(h[j], sh.v24[j], a);
         sh.kap[lane] = -a;
         C.kap[(size_t)k * U4 + lane] = -a;
       }
       if (k == 0) break;
-      __syncthreads();
+      wsync();
       if (lane < NX) {
-        const float* Ak = C.A + (size_t)k * NX * NX;
-        const double* Hx = C.Hx + (size_t)k * U4 * NX;
         double a = 0.0;
 #pragma unroll
-        for (int l = 0; l < NX; ++l) a = fma((double)Ak[l * NX + lane], sh.w[l], a);
+        for (int l = 0; l < NX; ++l) a = fma(ac[l], sh.w[l], a);
 #pragma unroll
-        for (int r = 0; r < U4; ++r) a = fma(Hx[r * NX + lane], sh.kap[r], a);
+        for (int r = 0; r < U4; ++r) a = fma(hw[r], sh.kap[r], a);
         sh.sv[lane] = a;
       }
     }
     __syncthreads();
+  }
+}
+
+__device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool factor) {
+  if (!factor) {
+    backward_rhs(C, sh);
     return;
   }
+  const int lane = threadIdx.x;
+  __syncthreads();
   for (int e = lane; e < NX * NX; e += 64) sh.S[e] = 0.0;
   if (lane < NX) sh.sv[lane] = 0.0;
+  // the stage data a lane moves into LDS (A: 3, B: 5, stage terms: 3 items per
+  // lane; x_{k+1} and x_ref[k] in lanes 0..12), fetched a stage ahead; the
+  // addresses are clamped into the stage's arrays, so every lane issues the
+  // same loads on every path
+  float fa[3], fb[5];
+  double ft[3], fx, fr;
+  auto fetch = [&](int k) {
+    const float* Ak = C.A + (size_t)k * NX * NX;
+    const float* Bk = C.B + (size_t)k * NX * U4;
+    const double* Tk = C.T + (size_t)k * C4 * TB;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fa[i] = Ak[min(lane + 64 * i, NX * NX - 1)];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) fb[i] = Bk[min(lane + 64 * i, NX * U4 - 1)];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ft[i] = Tk[min(lane + 64 * i, C4 * TB - 1)];
+    const int l = min(lane, NX - 1);
+    fx = C.x[(size_t)(k + 1) * NX + l];
+    fr = (double)C.x_ref[(size_t)k * NX + l];
+  };
+  fetch(C.N - 1);
   for (int k = C.N - 1; k >= 0; --k) {
-    __syncthreads();
+    wsync();
     uint32_t unit = 0;
     #pragma unroll
     for (int i = 0; i < C4; ++i)
       if (!stance(C, k, i)) unit |= 0x3Fu << (6 * i);
-    for (int e = lane; e < NX * NX; e += 64) {
-      sh.A[e] = (double)C.A[(size_t)k * NX * NX + e];
-      const int i = e / NX, j = e % NX;
-      sh.W[e] = sh.S[e] + (i == j ? sh.Q[i] : 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int e = lane + 64 * i;
+      if (e < NX * NX) {
+        sh.A[e] = (double)fa[i];
+        const int r = e / NX, c = e % NX;
+        sh.W[e] = sh.S[e] + (r == c ? sh.Q[r] : 0.0);
+      }
+      if (e < C4 * TB) sh.T[e] = ft[i];
     }
-    for (int e = lane; e < NX * U4; e += 64)
-      sh.B[e] = ((unit >> (e % U4)) & 1u) ? 0.0 : (double)C.B[(size_t)k * NX * U4 + e];
-    for (int e = lane; e < C4 * TB; e += 64) sh.T[e] = C.T[(size_t)k * C4 * TB + e];
-    if (lane < NX) {
-      const double q =
-          sh.Q[lane] * (C.x[(size_t)(k + 1) * NX + lane] - (double)C.x_ref[(size_t)k * NX + lane]);
-      sh.w[lane] = sh.sv[lane] + q;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const int e = lane + 64 * i;
+      if (e < NX * U4) sh.B[e] = ((unit >> (e % U4)) & 1u) ? 0.0 : (double)fb[i];
     }
-    __syncthreads();
+    if (lane < NX) sh.w[lane] = sh.sv[lane] + sh.Q[lane] * (fx - fr);
+    fetch(k > 0 ? k - 1 : 0);   // in flight during this stage
+    wsync();
     // W B and W A, element parallel
     for (int e = lane; e < NX * U4 + NX * NX; e += 64) {
       double a = 0.0;
@@ -287,7 +358,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
         sh.WA[f] = a;
       }
     }
-    __syncthreads();
+    wsync();
     // the columns of [H | Hwx | hw] (column c at Aug[c][0..23]):
     // H = R' + B^T (W B), Hwx = B^T (W A), hw = rho + B^T w
     for (int e = lane; e < (L4 + 1) * U4; e += 64) {
@@ -311,7 +382,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
       }
       sh.Aug[e] = a;
     }
-    __syncthreads();
+    wsync();
     double col[U4];
 #pragma unroll
     for (int r = 0; r < U4; ++r)
@@ -338,7 +409,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
       for (int r = 0; r < U4; ++r) C.Hi[(size_t)k * U4 * U4 + j * U4 + r] = col[r];
     }
     if (k == 0) break;   // x_0 is fixed: its value function is not needed
-    __syncthreads();
+    wsync();
     for (int e = lane; e < NSN; e += 64) {
       double a = 0.0;
       if (e < NX * NX) {
@@ -356,7 +427,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
       }
       sh.Sn[e] = a;
     }
-    __syncthreads();
+    wsync();
     for (int e = lane; e < NX * NX; e += 64) {
       const int i = e / NX, j = e % NX;
       sh.S[e] = 0.5 * (sh.Sn[i * NX + j] + sh.Sn[j * NX + i]);
@@ -375,28 +446,52 @@ __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
     sh.v13[lane] = 0.0;
     C.dx[lane] = 0.0;
   }
+  // a stage's gains row and feedforward (lanes 0..23) and rows of A and B
+  // (lanes 0..12), fetched a stage ahead from clamped addresses
+  const int lk = min(lane, U4 - 1), lx = min(lane, NX - 1);
+  double fk[NX], fp;
+  float fa[NX], fb[U4];
+  auto fetch = [&](int k) {
+    const double* Kr = C.K + (size_t)k * U4 * NX + lk * NX;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) fk[c] = Kr[c];
+    fp = C.kap[(size_t)k * U4 + lk];
+    const float* Ar = C.A + (size_t)k * NX * NX + lx * NX;
+    const float* Br = C.B + (size_t)k * NX * U4 + lx * U4;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) fa[c] = Ar[c];
+#pragma unroll
+    for (int r = 0; r < U4; ++r) fb[r] = Br[r];
+  };
+  fetch(0);
   for (int k = 0; k < C.N; ++k) {
-    __syncthreads();
+    double kr[NX], kp = fp, ar[NX], br[U4];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      kr[c] = fk[c];
+      ar[c] = (double)fa[c];
+    }
+#pragma unroll
+    for (int r = 0; r < U4; ++r) br[r] = (double)fb[r];
+    fetch(k + 1 < C.N ? k + 1 : k);   // in flight during this stage
+    wsync();
     if (lane < U4) {
-      double a = C.kap[(size_t)k * U4 + lane];
-      const double* Kr = C.K + (size_t)k * U4 * NX + lane * NX;
+      double a = kp;
       #pragma unroll
-      for (int c = 0; c < NX; ++c) a = fma(Kr[c], sh.v13[c], a);
+      for (int c = 0; c < NX; ++c) a = fma(kr[c], sh.v13[c], a);
       sh.v24[lane] = a;
       C.du[(size_t)k * U4 + lane] = a;
     }
-    __syncthreads();
+    wsync();
     double nx = 0.0;
     if (lane < NX) {
-      const float* Ar = C.A + (size_t)k * NX * NX + lane * NX;
-      const float* Br = C.B + (size_t)k * NX * U4 + lane * U4;
       #pragma unroll
-      for (int c = 0; c < NX; ++c) nx = fma((double)Ar[c], sh.v13[c], nx);
+      for (int c = 0; c < NX; ++c) nx = fma(ar[c], sh.v13[c], nx);
       #pragma unroll
-      for (int r = 0; r < U4; ++r) nx = fma((double)Br[r], sh.v24[r], nx);
+      for (int r = 0; r < U4; ++r) nx = fma(br[r], sh.v24[r], nx);
       C.dx[(size_t)(k + 1) * NX + lane] = nx;
     }
-    __syncthreads();
+    wsync();
     if (lane < NX) sh.v13[lane] = nx;
   }
   __syncthreads();
