@@ -98,12 +98,26 @@ __device__ void carve(WCtx& C, double* blk) {
 }
 
 // LDS of the stage recursion.
+// Matrices with 13 columns keep rows of 14 (XP), so that an entry with an even
+// column and its right neighbour are one aligned 16-byte pair; the stage
+// products read such pairs.
+constexpr int XP = NX + 1;
 struct WSh {
-  double A[NX * NX], B[NX * U4], W[NX * NX], WA[NX * NX], WB[NX * U4], Hwx[U4 * NX], K[U4 * NX];
-  double Aug[(L4 + 1) * U4];   // [H | Hwx | hw], column by column
-  double S[NX * NX], sv[NX], w[NX], kap[U4], T[C4 * TB], Sn[NSN];
+  alignas(16) double A[NX * XP];
+  alignas(16) double B[NX * U4];
+  alignas(16) double WA[NX * XP];
+  alignas(16) double WB[NX * U4];
+  alignas(16) double Hwx[U4 * XP];
+  alignas(16) double Kc[(NX + 1) * U4];    // the gains by column, then the feedforward
+  alignas(16) double Aug[(L4 + 1) * U4];   // [H | Hwx | hw], column by column
+  double W[NX * NX], S[NX * NX], sv[NX], w[NX], kap[U4], T[C4 * TB], Sn[NSN];
   double v13[NX], v24[U4], Q[NX], R[U4];
 };
+
+__device__ inline double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ inline void st2(double* p, double a, double b) {
+  *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
 
 __device__ inline bool stance(const WCtx& C, int k, int i) { return C.contact[k * C4 + i] != 0; }
 
@@ -329,8 +343,8 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
     for (int i = 0; i < 3; ++i) {
       const int e = lane + 64 * i;
       if (e < NX * NX) {
-        sh.A[e] = (double)fa[i];
         const int r = e / NX, c = e % NX;
+        sh.A[r * XP + c] = (double)fa[i];
         sh.W[e] = sh.S[e] + (r == c ? sh.Q[r] : 0.0);
       }
       if (e < C4 * TB) sh.T[e] = ft[i];
@@ -343,44 +357,89 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
     if (lane < NX) sh.w[lane] = sh.sv[lane] + sh.Q[lane] * (fx - fr);
     fetch(k > 0 ? k - 1 : 0);   // in flight during this stage
     wsync();
-    // W B and W A, element parallel
-    for (int e = lane; e < NX * U4 + NX * NX; e += 64) {
-      double a = 0.0;
-      if (e < NX * U4) {
-        const int i = e / U4, c = e % U4;
+    // W B and W A in blocks of two neighbouring entries of a row (each entry
+    // summed in the order of its own dot product)
+    for (int e = lane; e < NX * (U4 / 2) + NX * 7; e += 64) {
+      double a0 = 0.0, a1 = 0.0;
+      if (e < NX * (U4 / 2)) {
+        const int i = e / (U4 / 2), c = 2 * (e % (U4 / 2));
 #pragma unroll
-        for (int j = 0; j < NX; ++j) a = fma(sh.W[i * NX + j], sh.B[j * U4 + c], a);
-        sh.WB[e] = a;
+        for (int j = 0; j < NX; ++j) {
+          const double w = sh.W[i * NX + j];
+          const double2 b = ld2(&sh.B[j * U4 + c]);
+          a0 = fma(w, b.x, a0);
+          a1 = fma(w, b.y, a1);
+        }
+        st2(&sh.WB[i * U4 + c], a0, a1);
       } else {
-        const int f = e - NX * U4, i = f / NX, j = f % NX;
+        const int f = e - NX * (U4 / 2), i = f / 7, j = 2 * (f % 7);
 #pragma unroll
-        for (int l = 0; l < NX; ++l) a = fma(sh.W[i * NX + l], sh.A[l * NX + j], a);
-        sh.WA[f] = a;
+        for (int l = 0; l < NX; ++l) {
+          const double w = sh.W[i * NX + l];
+          const double2 b = ld2(&sh.A[l * XP + j]);
+          a0 = fma(w, b.x, a0);
+          a1 = fma(w, b.y, a1);
+        }
+        st2(&sh.WA[i * XP + j], a0, a1);   // column 13 of the pair is padding
       }
     }
     wsync();
-    // the columns of [H | Hwx | hw] (column c at Aug[c][0..23]):
-    // H = R' + B^T (W B), Hwx = B^T (W A), hw = rho + B^T w
-    for (int e = lane; e < (L4 + 1) * U4; e += 64) {
-      const int c = e / U4, r = e % U4;
-      double a;
-      if (c < U4) {
-        a = (r / 6 == c / 6) ? sh.T[(c / 6) * TB + (r % 6) * 6 + c % 6] : 0.0;
+    // the columns of [H | Hwx | hw] (column c at Aug[c][0..23]) in blocks of
+    // two rows r, r + 1: H = R' + B^T (W B) two columns at a time,
+    // Hwx = B^T (W A) and hw = rho + B^T w one column at a time
+    for (int e = lane; e < 12 * 12 + 12 * NX + 12; e += 64) {
+      if (e < 144) {
+        const int r = 2 * (e / 12), c = 2 * (e % 12);
+        double a00, a01, a10, a11;   // (r, c), (r, c+1), (r+1, c), (r+1, c+1)
+        if (r / 6 == c / 6) {
+          const double* Tb = sh.T + (c / 6) * TB;
+          const int rr = r % 6, cc = c % 6;
+          a00 = Tb[rr * 6 + cc];
+          a01 = Tb[rr * 6 + cc + 1];
+          a10 = Tb[(rr + 1) * 6 + cc];
+          a11 = Tb[(rr + 1) * 6 + cc + 1];
+        } else {
+          a00 = a01 = a10 = a11 = 0.0;
+        }
 #pragma unroll
-        for (int i = 0; i < NX; ++i) a = fma(sh.B[i * U4 + r], sh.WB[i * U4 + c], a);
-      } else if (c < L4) {
-        const int j = c - U4;
-        a = 0.0;
+        for (int i = 0; i < NX; ++i) {
+          const double2 b = ld2(&sh.B[i * U4 + r]);
+          const double2 g = ld2(&sh.WB[i * U4 + c]);
+          a00 = fma(b.x, g.x, a00);
+          a01 = fma(b.x, g.y, a01);
+          a10 = fma(b.y, g.x, a10);
+          a11 = fma(b.y, g.y, a11);
+        }
+        st2(&sh.Aug[c * U4 + r], a00, a10);
+        st2(&sh.Aug[(c + 1) * U4 + r], a01, a11);
+      } else if (e < 144 + 12 * NX) {
+        const int f = e - 144, r = 2 * (f / NX), j = f % NX;
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < NX; ++i) a = fma(sh.B[i * U4 + r], sh.WA[i * NX + j], a);
-        sh.Hwx[r * NX + j] = a;
-        C.Hx[(size_t)k * U4 * NX + r * NX + j] = a;
+        for (int i = 0; i < NX; ++i) {
+          const double2 b = ld2(&sh.B[i * U4 + r]);
+          const double g = sh.WA[i * XP + j];
+          a0 = fma(b.x, g, a0);
+          a1 = fma(b.y, g, a1);
+        }
+        sh.Hwx[r * XP + j] = a0;
+        sh.Hwx[(r + 1) * XP + j] = a1;
+        C.Hx[(size_t)k * U4 * NX + r * NX + j] = a0;
+        C.Hx[(size_t)k * U4 * NX + (r + 1) * NX + j] = a1;
+        st2(&sh.Aug[(U4 + j) * U4 + r], a0, a1);
       } else {
-        a = sh.T[(r / 6) * TB + 36 + r % 6];
+        const int r = 2 * (e - 144 - 12 * NX);
+        double a0 = sh.T[(r / 6) * TB + 36 + r % 6];
+        double a1 = sh.T[((r + 1) / 6) * TB + 36 + (r + 1) % 6];
 #pragma unroll
-        for (int i = 0; i < NX; ++i) a = fma(sh.B[i * U4 + r], sh.w[i], a);
+        for (int i = 0; i < NX; ++i) {
+          const double2 b = ld2(&sh.B[i * U4 + r]);
+          const double g = sh.w[i];
+          a0 = fma(b.x, g, a0);
+          a1 = fma(b.y, g, a1);
+        }
+        st2(&sh.Aug[L4 * U4 + r], a0, a1);
       }
-      sh.Aug[e] = a;
     }
     wsync();
     double col[U4];
@@ -388,44 +447,49 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
     for (int r = 0; r < U4; ++r)
       col[r] = lane <= L4 ? sh.Aug[lane * U4 + r] : (lane - L4 - 1 == r ? 1.0 : 0.0);
     gj_columns<U4>(col, unit);
-    if (lane >= U4 && lane < L4) {
-      const int j = lane - U4;
-      #pragma unroll
-      for (int r = 0; r < U4; ++r) {
-        const double v = -col[r];
-        sh.K[r * NX + j] = v;
-        C.K[(size_t)k * U4 * NX + r * NX + j] = v;
+    // lanes 24..36: the gain columns -H^{-1} Hwx; lane 37: the feedforward
+    // -H^{-1} hw; lanes 38..61: the columns of H^{-1}; each a contiguous
+    // column of 24 in the scratch (and the gains with the feedforward in LDS)
+    if (lane >= U4 && lane < L4 + 1 + U4) {
+      const double sg = lane <= L4 ? -1.0 : 1.0;
+      double* dst = lane < L4 ? C.K + (size_t)k * U4 * NX + (lane - U4) * U4
+                  : lane == L4 ? C.kap + (size_t)k * U4
+                               : C.Hi + (size_t)k * U4 * U4 + (lane - L4 - 1) * U4;
+#pragma unroll
+      for (int r = 0; r < U4; r += 2) st2(dst + r, sg * col[r], sg * col[r + 1]);
+      if (lane <= L4) {
+#pragma unroll
+        for (int r = 0; r < U4; r += 2) st2(&sh.Kc[(lane - U4) * U4 + r], -col[r], -col[r + 1]);
       }
-    } else if (lane == L4) {
-      #pragma unroll
-      for (int r = 0; r < U4; ++r) {
-        sh.kap[r] = -col[r];
-        C.kap[(size_t)k * U4 + r] = -col[r];
-      }
-    } else if (lane > L4 && lane < L4 + 1 + U4) {
-      // column lane - 38 of H^{-1}
-      const int j = lane - L4 - 1;
-      #pragma unroll
-      for (int r = 0; r < U4; ++r) C.Hi[(size_t)k * U4 * U4 + j * U4 + r] = col[r];
     }
     if (k == 0) break;   // x_0 is fixed: its value function is not needed
     wsync();
-    for (int e = lane; e < NSN; e += 64) {
-      double a = 0.0;
-      if (e < NX * NX) {
-        const int i = e / NX, j = e % NX;
-        #pragma unroll
-        for (int l = 0; l < NX; ++l) a = fma(sh.A[l * NX + i], sh.WA[l * NX + j], a);
-        #pragma unroll
-        for (int r = 0; r < U4; ++r) a = fma(sh.Hwx[r * NX + i], sh.K[r * NX + j], a);
-      } else {
-        const int i = e - NX * NX;
-        #pragma unroll
-        for (int l = 0; l < NX; ++l) a = fma(sh.A[l * NX + i], sh.w[l], a);
-        #pragma unroll
-        for (int r = 0; r < U4; ++r) a = fma(sh.Hwx[r * NX + i], sh.kap[r], a);
+    // S = A^T W A + Hwx^T K and s = A^T w + Hwx^T kap in blocks of two rows
+    // i, i + 1 (row 13 of the last block is padding)
+    for (int e = lane; e < 7 * (NX + 1); e += 64) {
+      const int i = 2 * (e / (NX + 1)), j = e % (NX + 1);   // j = 13: s
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int l = 0; l < NX; ++l) {
+        const double2 av = ld2(&sh.A[l * XP + i]);
+        const double g = j < NX ? sh.WA[l * XP + j] : sh.w[l];
+        a0 = fma(av.x, g, a0);
+        a1 = fma(av.y, g, a1);
       }
-      sh.Sn[e] = a;
+#pragma unroll
+      for (int r = 0; r < U4; ++r) {
+        const double2 hv = ld2(&sh.Hwx[r * XP + i]);
+        const double g = sh.Kc[j * U4 + r];
+        a0 = fma(hv.x, g, a0);
+        a1 = fma(hv.y, g, a1);
+      }
+      if (j < NX) {
+        sh.Sn[i * NX + j] = a0;
+        if (i + 1 < NX) sh.Sn[(i + 1) * NX + j] = a1;
+      } else {
+        sh.Sn[NX * NX + i] = a0;
+        if (i + 1 < NX) sh.Sn[NX * NX + i + 1] = a1;
+      }
     }
     wsync();
     for (int e = lane; e < NX * NX; e += 64) {
@@ -452,9 +516,9 @@ __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
   double fk[NX], fp;
   float fa[NX], fb[U4];
   auto fetch = [&](int k) {
-    const double* Kr = C.K + (size_t)k * U4 * NX + lk * NX;
+    const double* Kr = C.K + (size_t)k * U4 * NX + lk;   // row lk of K (stored by column)
 #pragma unroll
-    for (int c = 0; c < NX; ++c) fk[c] = Kr[c];
+    for (int c = 0; c < NX; ++c) fk[c] = Kr[c * U4];
     fp = C.kap[(size_t)k * U4 + lk];
     const float* Ar = C.A + (size_t)k * NX * NX + lx * NX;
     const float* Br = C.B + (size_t)k * NX * U4 + lx * U4;
