@@ -64,13 +64,22 @@ __device__ inline void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Global pointers with their address space spelled out: the context is
+// passed by reference into the phase functions, where a generic (flat)
+// access would count against the LDS counter too, so that every wait for an
+// LDS hand-off would also wait for the loads of the next stage in flight.
+#define GMEM __attribute__((address_space(1)))
+typedef const GMEM float* gcf;
+typedef const GMEM double* gcd;
+typedef GMEM double* gd;
+
 // The problem's FP64 scratch (refine_wide_block_doubles(n) doubles).
 struct WCtx {
   int b, n, N;
   double mu, fz, tm, mg, scf, scm;   // bounds, force scale, row scales
-  const float *A, *B, *e, *x_ref, *u_ref, *x0;
-  const uint8_t* contact;            // [n][4]
-  double *K, *kap, *u, *du, *x, *dx, *lam, *T, *s, *z, *ds, *dz, *rc, *Hi, *Hx;
+  gcf A, B, e, x_ref, u_ref, x0;
+  const GMEM uint8_t* contact;       // [n][4]
+  gd K, kap, u, du, x, dx, lam, T, s, z, ds, dz, rc, Hi, Hx;
 };
 
 static_assert(refine_wide_block_doubles(1) >=
@@ -78,7 +87,7 @@ static_assert(refine_wide_block_doubles(1) >=
                       2 * 2 * NX,
               "the carve below fits the scratch block");
 
-__device__ void carve(WCtx& C, double* blk) {
+__device__ void carve(WCtx& C, gd blk) {
   const int n = C.n;
   C.K = blk;    blk += (size_t)n * U4 * NX;
   C.kap = blk;  blk += (size_t)n * U4;
@@ -114,9 +123,13 @@ struct WSh {
   double v13[NX], v24[U4], Q[NX], R[U4];
 };
 
-__device__ inline double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+typedef double dpair __attribute__((ext_vector_type(2)));
+__device__ inline dpair ld2(const double* p) { return *reinterpret_cast<const dpair*>(p); }
 __device__ inline void st2(double* p, double a, double b) {
-  *reinterpret_cast<double2*>(p) = make_double2(a, b);
+  *reinterpret_cast<dpair*>(p) = dpair{a, b};
+}
+__device__ inline void st2(gd p, double a, double b) {
+  *reinterpret_cast<GMEM dpair*>(p) = dpair{a, b};
 }
 
 __device__ inline bool stance(const WCtx& C, int k, int i) { return C.contact[k * C4 + i] != 0; }
@@ -151,15 +164,15 @@ __device__ inline void rows_T(const WCtx& C, const double v[NROW], double o[6]) 
   for (int a = 0; a < 3; ++a) o[3 + a] = v[5 + a] - v[8 + a];
 }
 
-__device__ inline void ld6(const double* p, double v[6]) {
+__device__ inline void ld6(gcd p, double v[6]) {
   #pragma unroll
   for (int t = 0; t < 6; ++t) v[t] = p[t];
 }
-__device__ inline void ldr(const double* p, double v[NROW]) {
+__device__ inline void ldr(gcd p, double v[NROW]) {
   #pragma unroll
   for (int r = 0; r < NROW; ++r) v[r] = p[r];
 }
-__device__ inline void str(double* p, const double v[NROW]) {
+__device__ inline void str(gd p, const double v[NROW]) {
   #pragma unroll
   for (int r = 0; r < NROW; ++r) p[r] = v[r];
 }
@@ -171,7 +184,7 @@ __device__ __attribute__((noinline)) void build_terms(const WCtx& C, const WSh& 
   __syncthreads();
   for (int e = threadIdx.x; e < C.N * C4; e += 64) {
     const int k = e / C4, i = e % C4;
-    double* T = C.T + (size_t)e * TB;
+    gd T = C.T + (size_t)e * TB;
     if (!stance(C, k, i)) {
       #pragma unroll
       for (int t = 0; t < 36; ++t) T[t] = (t % 7 == 0) ? 1.0 : 0.0;
@@ -240,8 +253,8 @@ __device__ __attribute__((noinline)) void backward_rhs(const WCtx& C, WSh& sh) {
     float fbc[NX], fac[NX];
     auto fetch = [&](int k) {
       frho = C.T[(size_t)k * C4 * TB + (lu / 6) * TB + 36 + lu % 6];
-      const float* Bk = C.B + (size_t)k * NX * U4;
-      const float* Ak = C.A + (size_t)k * NX * NX;
+      const auto Bk = C.B + (size_t)k * NX * U4;
+      const auto Ak = C.A + (size_t)k * NX * NX;
 #pragma unroll
       for (int i = 0; i < NX; ++i) {
         fbc[i] = Bk[i * U4 + lu];
@@ -253,8 +266,8 @@ __device__ __attribute__((noinline)) void backward_rhs(const WCtx& C, WSh& sh) {
     fetch(C.N - 1);
     for (int k = C.N - 1; k >= 0; --k) {
       double h[U4], hw[U4], rho = frho, bc[NX], ac[NX];
-      const double* Hc = C.Hi + (size_t)k * U4 * U4 + lu;
-      const double* Hx = C.Hx + (size_t)k * U4 * NX + lx;
+      const auto Hc = C.Hi + (size_t)k * U4 * U4 + lu;
+      const auto Hx = C.Hx + (size_t)k * U4 * NX + lx;
 #pragma unroll
       for (int j = 0; j < U4; ++j) {
         h[j] = Hc[j * U4];
@@ -319,9 +332,9 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
   float fa[3], fb[5];
   double ft[3], fx, fr;
   auto fetch = [&](int k) {
-    const float* Ak = C.A + (size_t)k * NX * NX;
-    const float* Bk = C.B + (size_t)k * NX * U4;
-    const double* Tk = C.T + (size_t)k * C4 * TB;
+    const auto Ak = C.A + (size_t)k * NX * NX;
+    const auto Bk = C.B + (size_t)k * NX * U4;
+    const auto Tk = C.T + (size_t)k * C4 * TB;
 #pragma unroll
     for (int i = 0; i < 3; ++i) fa[i] = Ak[min(lane + 64 * i, NX * NX - 1)];
 #pragma unroll
@@ -366,7 +379,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
           const double w = sh.W[i * NX + j];
-          const double2 b = ld2(&sh.B[j * U4 + c]);
+          const dpair b = ld2(&sh.B[j * U4 + c]);
           a0 = fma(w, b.x, a0);
           a1 = fma(w, b.y, a1);
         }
@@ -376,7 +389,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
 #pragma unroll
         for (int l = 0; l < NX; ++l) {
           const double w = sh.W[i * NX + l];
-          const double2 b = ld2(&sh.A[l * XP + j]);
+          const dpair b = ld2(&sh.A[l * XP + j]);
           a0 = fma(w, b.x, a0);
           a1 = fma(w, b.y, a1);
         }
@@ -403,8 +416,8 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
         }
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          const double2 b = ld2(&sh.B[i * U4 + r]);
-          const double2 g = ld2(&sh.WB[i * U4 + c]);
+          const dpair b = ld2(&sh.B[i * U4 + r]);
+          const dpair g = ld2(&sh.WB[i * U4 + c]);
           a00 = fma(b.x, g.x, a00);
           a01 = fma(b.x, g.y, a01);
           a10 = fma(b.y, g.x, a10);
@@ -417,7 +430,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          const double2 b = ld2(&sh.B[i * U4 + r]);
+          const dpair b = ld2(&sh.B[i * U4 + r]);
           const double g = sh.WA[i * XP + j];
           a0 = fma(b.x, g, a0);
           a1 = fma(b.y, g, a1);
@@ -433,7 +446,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
         double a1 = sh.T[((r + 1) / 6) * TB + 36 + (r + 1) % 6];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          const double2 b = ld2(&sh.B[i * U4 + r]);
+          const dpair b = ld2(&sh.B[i * U4 + r]);
           const double g = sh.w[i];
           a0 = fma(b.x, g, a0);
           a1 = fma(b.y, g, a1);
@@ -452,7 +465,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
     // column of 24 in the scratch (and the gains with the feedforward in LDS)
     if (lane >= U4 && lane < L4 + 1 + U4) {
       const double sg = lane <= L4 ? -1.0 : 1.0;
-      double* dst = lane < L4 ? C.K + (size_t)k * U4 * NX + (lane - U4) * U4
+      gd dst = lane < L4 ? C.K + (size_t)k * U4 * NX + (lane - U4) * U4
                   : lane == L4 ? C.kap + (size_t)k * U4
                                : C.Hi + (size_t)k * U4 * U4 + (lane - L4 - 1) * U4;
 #pragma unroll
@@ -471,14 +484,14 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
       double a0 = 0.0, a1 = 0.0;
 #pragma unroll
       for (int l = 0; l < NX; ++l) {
-        const double2 av = ld2(&sh.A[l * XP + i]);
+        const dpair av = ld2(&sh.A[l * XP + i]);
         const double g = j < NX ? sh.WA[l * XP + j] : sh.w[l];
         a0 = fma(av.x, g, a0);
         a1 = fma(av.y, g, a1);
       }
 #pragma unroll
       for (int r = 0; r < U4; ++r) {
-        const double2 hv = ld2(&sh.Hwx[r * XP + i]);
+        const dpair hv = ld2(&sh.Hwx[r * XP + i]);
         const double g = sh.Kc[j * U4 + r];
         a0 = fma(hv.x, g, a0);
         a1 = fma(hv.y, g, a1);
@@ -516,12 +529,12 @@ __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
   double fk[NX], fp;
   float fa[NX], fb[U4];
   auto fetch = [&](int k) {
-    const double* Kr = C.K + (size_t)k * U4 * NX + lk;   // row lk of K (stored by column)
+    const auto Kr = C.K + (size_t)k * U4 * NX + lk;   // row lk of K (stored by column)
 #pragma unroll
     for (int c = 0; c < NX; ++c) fk[c] = Kr[c * U4];
     fp = C.kap[(size_t)k * U4 + lk];
-    const float* Ar = C.A + (size_t)k * NX * NX + lx * NX;
-    const float* Br = C.B + (size_t)k * NX * U4 + lx * U4;
+    const auto Ar = C.A + (size_t)k * NX * NX + lx * NX;
+    const auto Br = C.B + (size_t)k * NX * U4 + lx * U4;
 #pragma unroll
     for (int c = 0; c < NX; ++c) fa[c] = Ar[c];
 #pragma unroll
@@ -576,9 +589,9 @@ __device__ __attribute__((noinline)) double rollout(const WCtx& C, WSh& sh) {
     __syncthreads();
     double nx = 0.0, ax = 0.0, bu = 0.0;
     if (lane < NX) {
-      const float* Ar = C.A + (size_t)k * NX * NX + lane * NX;
-      const float* Br = C.B + (size_t)k * NX * U4 + lane * U4;
-      const double* uk = C.u + (size_t)k * U4;
+      const auto Ar = C.A + (size_t)k * NX * NX + lane * NX;
+      const auto Br = C.B + (size_t)k * NX * U4 + lane * U4;
+      const auto uk = C.u + (size_t)k * U4;
       #pragma unroll
       for (int c = 0; c < NX; ++c) ax = fma((double)Ar[c], sh.v13[c], ax);
       #pragma unroll
@@ -700,7 +713,7 @@ __device__ __attribute__((noinline)) double certificate(const WCtx& C, WSh& sh, 
       const double q =
           sh.Q[lane] * (C.x[(size_t)(k + 1) * NX + lane] - (double)C.x_ref[(size_t)k * NX + lane]);
       if (k + 1 < C.N) {
-        const float* A1 = C.A + (size_t)(k + 1) * NX * NX;
+        const auto A1 = C.A + (size_t)(k + 1) * NX * NX;
         #pragma unroll
         for (int i = 0; i < NX; ++i) al = fma((double)A1[i * NX + lane], sh.v13[i], al);
       }
@@ -727,8 +740,8 @@ __device__ __attribute__((noinline)) double certificate(const WCtx& C, WSh& sh, 
     }
     double gu[NROW], h[NROW], sc[NROW], mv[NROW], gr[6];
     rows_of(C, u, gu, h, sc);
-    const float* Bk = C.B + (size_t)k * NX * U4;
-    const double* lk = C.lam + (size_t)k * U4;
+    const auto Bk = C.B + (size_t)k * NX * U4;
+    const auto lk = C.lam + (size_t)k * U4;
     double tr = 0.0, tb = 0.0;
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
@@ -887,7 +900,7 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       for (int e = lane; e < C.N * C4; e += 64) {
         const int k = e / C4, i = e % C4;
         if (!stance(C, k, i)) continue;
-        double* cv = C.rc + (size_t)e * NROW;
+        gd cv = C.rc + (size_t)e * NROW;
         #pragma unroll
         for (int r = 0; r < NROW; ++r) cv[r] -= sigma * muv;
       }
@@ -943,25 +956,30 @@ __global__ void __launch_bounds__(64) refine_wide_kernel(Problem p, Workspace ws
                                                          double tol) {
   __shared__ WSh sh;
   const int lane = threadIdx.x;
-  WCtx C;
-  C.b = blockIdx.x;
-  C.n = p.n_max;
-  C.N = horizon(p, C.b);
-  const size_t s0 = (size_t)C.b * C.n;
-  C.mu = p.mu[C.b];
-  C.fz = p.fz_max[C.b];
-  C.tm = p.tau_max[C.b];
-  C.mg = weight_of(p, C.b);
-  C.scf = C.mg;
-  C.scm = C.tm > 0.0 ? C.tm : 1.0;
-  C.A = p.A + s0 * NX * NX;
-  C.B = p.B + s0 * NX * U4;
-  C.e = p.e ? p.e + s0 * NX : nullptr;
-  C.x_ref = p.x_ref + s0 * NX;
-  C.u_ref = p.u_ref ? p.u_ref + s0 * U4 : nullptr;
-  C.x0 = p.x0 + (size_t)C.b * NX;
-  C.contact = p.contact + s0 * C4;
-  carve(C, ws.rblk + (size_t)C.b * refine_wide_block_doubles(C.n));
+  // the problem's context lives in LDS (the phase functions read its fields
+  // with LDS loads, which no wait for a global load in flight holds up)
+  __shared__ WCtx C;
+  const size_t s0 = (size_t)blockIdx.x * p.n_max;
+  if (lane == 0) {
+    C.b = blockIdx.x;
+    C.n = p.n_max;
+    C.N = horizon(p, C.b);
+    C.mu = p.mu[C.b];
+    C.fz = p.fz_max[C.b];
+    C.tm = p.tau_max[C.b];
+    C.mg = weight_of(p, C.b);
+    C.scf = C.mg;
+    C.scm = C.tm > 0.0 ? C.tm : 1.0;
+    C.A = (gcf)(p.A + s0 * NX * NX);
+    C.B = (gcf)(p.B + s0 * NX * U4);
+    C.e = p.e ? (gcf)(p.e + s0 * NX) : nullptr;
+    C.x_ref = (gcf)(p.x_ref + s0 * NX);
+    C.u_ref = p.u_ref ? (gcf)(p.u_ref + s0 * U4) : nullptr;
+    C.x0 = (gcf)(p.x0 + (size_t)C.b * NX);
+    C.contact = (const GMEM uint8_t*)(p.contact + s0 * C4);
+    carve(C, (gd)(ws.rblk + (size_t)C.b * refine_wide_block_doubles(C.n)));
+  }
+  __syncthreads();
   if (lane < NX) sh.Q[lane] = p.Q[(size_t)C.b * NX + lane];
   if (lane < U4) sh.R[lane] = p.R[(size_t)C.b * U4 + lane];
   __syncthreads();
