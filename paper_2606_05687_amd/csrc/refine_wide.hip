@@ -111,16 +111,23 @@ __device__ void carve(WCtx& C, gd blk) {
 // column and its right neighbour are one aligned 16-byte pair; the stage
 // products read such pairs.
 constexpr int XP = NX + 1;
+// Arrays whose lives within a stage do not overlap share storage, which keeps
+// a workgroup within 20 KB of LDS (eight per compute unit):
+//   X: B, W B and the stage terms, from the stage's start to the system;
+//   Y: the system [H | Hwx | hw] column by column until the elimination reads
+//      it; then the gains by column with the feedforward, and the unsymmetrised
+//      value function, over the H columns, while the Hwx columns stay for the
+//      value-function update.
+constexpr int OFF_WB = NX * U4, OFF_T = 2 * NX * U4;        // in X
+constexpr int OFF_HWX = U4 * U4, OFF_SN = (NX + 1) * U4;     // in Y
+static_assert(OFF_SN + NSN <= OFF_HWX, "gains and value function fit over the H columns");
 struct WSh {
   alignas(16) double A[NX * XP];
-  alignas(16) double B[NX * U4];
   alignas(16) double WA[NX * XP];
-  alignas(16) double WB[NX * U4];
-  alignas(16) double Hwx[U4 * XP];
-  alignas(16) double Kc[(NX + 1) * U4];    // the gains by column, then the feedforward
-  alignas(16) double Aug[(L4 + 1) * U4];   // [H | Hwx | hw], column by column
-  double W[NX * NX], S[NX * NX], sv[NX], w[NX], kap[U4], T[C4 * TB], Sn[NSN];
-  double v13[NX], v24[U4], Q[NX], R[U4];
+  alignas(16) double X[2 * NX * U4 + C4 * TB];
+  alignas(16) double Y[(L4 + 1) * U4];
+  double W[NX * NX];   // S + Q of x_{k+1}, formed when S is
+  double sv[NX], w[NX], kap[U4], v13[NX], v24[U4], Q[NX], R[U4];
 };
 
 typedef double dpair __attribute__((ext_vector_type(2)));
@@ -322,16 +329,24 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
     return;
   }
   const int lane = threadIdx.x;
+  double* const B = sh.X;
+  double* const WB = sh.X + OFF_WB;
+  double* const T = sh.X + OFF_T;
+  double* const Aug = sh.Y;
+  double* const Kc = sh.Y;
+  double* const Sn = sh.Y + OFF_SN;
   __syncthreads();
-  for (int e = lane; e < NX * NX; e += 64) sh.S[e] = 0.0;
+  for (int e = lane; e < NX * NX; e += 64) sh.W[e] = (e % (NX + 1) == 0) ? sh.Q[e / NX] : 0.0;
   if (lane < NX) sh.sv[lane] = 0.0;
   // the stage data a lane moves into LDS (A: 3, B: 5, stage terms: 3 items per
-  // lane; x_{k+1} and x_ref[k] in lanes 0..12), fetched a stage ahead; the
-  // addresses are clamped into the stage's arrays, so every lane issues the
-  // same loads on every path
+  // lane; x_{k+1} and x_ref[k] in lanes 0..12; the contact flags), fetched a
+  // stage ahead; the addresses are clamped into the stage's arrays, so every
+  // lane issues the same loads on every path
   float fa[3], fb[5];
   double ft[3], fx, fr;
+  uint32_t fc;
   auto fetch = [&](int k) {
+    fc = *reinterpret_cast<const GMEM uint32_t*>(C.contact + (size_t)k * C4);
     const auto Ak = C.A + (size_t)k * NX * NX;
     const auto Bk = C.B + (size_t)k * NX * U4;
     const auto Tk = C.T + (size_t)k * C4 * TB;
@@ -351,21 +366,17 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
     uint32_t unit = 0;
     #pragma unroll
     for (int i = 0; i < C4; ++i)
-      if (!stance(C, k, i)) unit |= 0x3Fu << (6 * i);
+      if (((fc >> (8 * i)) & 0xFFu) == 0) unit |= 0x3Fu << (6 * i);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int e = lane + 64 * i;
-      if (e < NX * NX) {
-        const int r = e / NX, c = e % NX;
-        sh.A[r * XP + c] = (double)fa[i];
-        sh.W[e] = sh.S[e] + (r == c ? sh.Q[r] : 0.0);
-      }
-      if (e < C4 * TB) sh.T[e] = ft[i];
+      if (e < NX * NX) sh.A[(e / NX) * XP + e % NX] = (double)fa[i];
+      if (e < C4 * TB) T[e] = ft[i];
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       const int e = lane + 64 * i;
-      if (e < NX * U4) sh.B[e] = ((unit >> (e % U4)) & 1u) ? 0.0 : (double)fb[i];
+      if (e < NX * U4) B[e] = ((unit >> (e % U4)) & 1u) ? 0.0 : (double)fb[i];
     }
     if (lane < NX) sh.w[lane] = sh.sv[lane] + sh.Q[lane] * (fx - fr);
     fetch(k > 0 ? k - 1 : 0);   // in flight during this stage
@@ -379,11 +390,11 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
           const double w = sh.W[i * NX + j];
-          const dpair b = ld2(&sh.B[j * U4 + c]);
+          const dpair b = ld2(&B[j * U4 + c]);
           a0 = fma(w, b.x, a0);
           a1 = fma(w, b.y, a1);
         }
-        st2(&sh.WB[i * U4 + c], a0, a1);
+        st2(&WB[i * U4 + c], a0, a1);
       } else {
         const int f = e - NX * (U4 / 2), i = f / 7, j = 2 * (f % 7);
 #pragma unroll
@@ -405,7 +416,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
         const int r = 2 * (e / 12), c = 2 * (e % 12);
         double a00, a01, a10, a11;   // (r, c), (r, c+1), (r+1, c), (r+1, c+1)
         if (r / 6 == c / 6) {
-          const double* Tb = sh.T + (c / 6) * TB;
+          const double* Tb = T + (c / 6) * TB;
           const int rr = r % 6, cc = c % 6;
           a00 = Tb[rr * 6 + cc];
           a01 = Tb[rr * 6 + cc + 1];
@@ -416,49 +427,47 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
         }
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          const dpair b = ld2(&sh.B[i * U4 + r]);
-          const dpair g = ld2(&sh.WB[i * U4 + c]);
+          const dpair b = ld2(&B[i * U4 + r]);
+          const dpair g = ld2(&WB[i * U4 + c]);
           a00 = fma(b.x, g.x, a00);
           a01 = fma(b.x, g.y, a01);
           a10 = fma(b.y, g.x, a10);
           a11 = fma(b.y, g.y, a11);
         }
-        st2(&sh.Aug[c * U4 + r], a00, a10);
-        st2(&sh.Aug[(c + 1) * U4 + r], a01, a11);
+        st2(&Aug[c * U4 + r], a00, a10);
+        st2(&Aug[(c + 1) * U4 + r], a01, a11);
       } else if (e < 144 + 12 * NX) {
         const int f = e - 144, r = 2 * (f / NX), j = f % NX;
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          const dpair b = ld2(&sh.B[i * U4 + r]);
+          const dpair b = ld2(&B[i * U4 + r]);
           const double g = sh.WA[i * XP + j];
           a0 = fma(b.x, g, a0);
           a1 = fma(b.y, g, a1);
         }
-        sh.Hwx[r * XP + j] = a0;
-        sh.Hwx[(r + 1) * XP + j] = a1;
         C.Hx[(size_t)k * U4 * NX + r * NX + j] = a0;
         C.Hx[(size_t)k * U4 * NX + (r + 1) * NX + j] = a1;
-        st2(&sh.Aug[(U4 + j) * U4 + r], a0, a1);
+        st2(&Aug[(U4 + j) * U4 + r], a0, a1);
       } else {
         const int r = 2 * (e - 144 - 12 * NX);
-        double a0 = sh.T[(r / 6) * TB + 36 + r % 6];
-        double a1 = sh.T[((r + 1) / 6) * TB + 36 + (r + 1) % 6];
+        double a0 = T[(r / 6) * TB + 36 + r % 6];
+        double a1 = T[((r + 1) / 6) * TB + 36 + (r + 1) % 6];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          const dpair b = ld2(&sh.B[i * U4 + r]);
+          const dpair b = ld2(&B[i * U4 + r]);
           const double g = sh.w[i];
           a0 = fma(b.x, g, a0);
           a1 = fma(b.y, g, a1);
         }
-        st2(&sh.Aug[L4 * U4 + r], a0, a1);
+        st2(&Aug[L4 * U4 + r], a0, a1);
       }
     }
     wsync();
     double col[U4];
 #pragma unroll
     for (int r = 0; r < U4; ++r)
-      col[r] = lane <= L4 ? sh.Aug[lane * U4 + r] : (lane - L4 - 1 == r ? 1.0 : 0.0);
+      col[r] = lane <= L4 ? Aug[lane * U4 + r] : (lane - L4 - 1 == r ? 1.0 : 0.0);
     gj_columns<U4>(col, unit);
     // lanes 24..36: the gain columns -H^{-1} Hwx; lane 37: the feedforward
     // -H^{-1} hw; lanes 38..61: the columns of H^{-1}; each a contiguous
@@ -472,7 +481,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
       for (int r = 0; r < U4; r += 2) st2(dst + r, sg * col[r], sg * col[r + 1]);
       if (lane <= L4) {
 #pragma unroll
-        for (int r = 0; r < U4; r += 2) st2(&sh.Kc[(lane - U4) * U4 + r], -col[r], -col[r + 1]);
+        for (int r = 0; r < U4; r += 2) st2(&Kc[(lane - U4) * U4 + r], -col[r], -col[r + 1]);
       }
     }
     if (k == 0) break;   // x_0 is fixed: its value function is not needed
@@ -491,25 +500,28 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
       }
 #pragma unroll
       for (int r = 0; r < U4; ++r) {
-        const dpair hv = ld2(&sh.Hwx[r * XP + i]);
-        const double g = sh.Kc[j * U4 + r];
-        a0 = fma(hv.x, g, a0);
-        a1 = fma(hv.y, g, a1);
+        // Hwx (r, i) and (r, i + 1): rows r of the system's columns 24 + i, 25 + i
+        const double h0 = Aug[OFF_HWX + i * U4 + r];
+        const double h1 = i + 1 < NX ? Aug[OFF_HWX + (i + 1) * U4 + r] : 0.0;
+        const double g = Kc[j * U4 + r];
+        a0 = fma(h0, g, a0);
+        a1 = fma(h1, g, a1);
       }
       if (j < NX) {
-        sh.Sn[i * NX + j] = a0;
-        if (i + 1 < NX) sh.Sn[(i + 1) * NX + j] = a1;
+        Sn[i * NX + j] = a0;
+        if (i + 1 < NX) Sn[(i + 1) * NX + j] = a1;
       } else {
-        sh.Sn[NX * NX + i] = a0;
-        if (i + 1 < NX) sh.Sn[NX * NX + i + 1] = a1;
+        Sn[NX * NX + i] = a0;
+        if (i + 1 < NX) Sn[NX * NX + i + 1] = a1;
       }
     }
     wsync();
     for (int e = lane; e < NX * NX; e += 64) {
       const int i = e / NX, j = e % NX;
-      sh.S[e] = 0.5 * (sh.Sn[i * NX + j] + sh.Sn[j * NX + i]);
+      const double s = 0.5 * (Sn[i * NX + j] + Sn[j * NX + i]);
+      sh.W[e] = s + (i == j ? sh.Q[i] : 0.0);
     }
-    if (lane < NX) sh.sv[lane] = sh.Sn[NX * NX + lane];
+    if (lane < NX) sh.sv[lane] = Sn[NX * NX + lane];
   }
   __syncthreads();
 }
