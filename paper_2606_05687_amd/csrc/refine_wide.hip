@@ -554,14 +554,15 @@ __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
   };
   fetch(0);
   for (int k = 0; k < C.N; ++k) {
-    double kr[NX], kp = fp, ar[NX], br[U4];
+    double kr[NX], kp = fp;
+    float ar[NX], br[U4];
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       kr[c] = fk[c];
-      ar[c] = (double)fa[c];
+      ar[c] = fa[c];
     }
 #pragma unroll
-    for (int r = 0; r < U4; ++r) br[r] = (double)fb[r];
+    for (int r = 0; r < U4; ++r) br[r] = fb[r];
     fetch(k + 1 < C.N ? k + 1 : k);   // in flight during this stage
     wsync();
     if (lane < U4) {
@@ -575,9 +576,9 @@ __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
     double nx = 0.0;
     if (lane < NX) {
       #pragma unroll
-      for (int c = 0; c < NX; ++c) nx = fma(ar[c], sh.v13[c], nx);
+      for (int c = 0; c < NX; ++c) nx = fma((double)ar[c], sh.v13[c], nx);
       #pragma unroll
-      for (int r = 0; r < U4; ++r) nx = fma(br[r], sh.v24[r], nx);
+      for (int r = 0; r < U4; ++r) nx = fma((double)br[r], sh.v24[r], nx);
       C.dx[(size_t)(k + 1) * NX + lane] = nx;
     }
     wsync();
