@@ -90,26 +90,32 @@ __global__ void __launch_bounds__(64 * (NC / 2)) setup_kernel(Problem p, Workspa
     if (tid == 0) ws.sf[s] = 1.f;
     return;
   }
+  // the stage's force and moment scales, and the next stage's (read once:
+  // each needs the stage's contact flags and the problem's bounds)
+  const float sfk = scale_of<NC>(p, b, k, 0, sc), smk = scale_of<NC>(p, b, k, 3, sc);
+  const bool has_next = (k + 1 < N);
+  const float sf1 = has_next ? scale_of<NC>(p, b, k + 1, 0, sc) : 1.f;
+  const float sm1 = has_next ? scale_of<NC>(p, b, k + 1, 3, sc) : 1.f;
+  auto scale_k = [&](int j) { return (j % 6) < 3 ? sfk : smk; };
   const float* Bk = p.B + (size_t)s * NX * U;
   for (int i = tid; i < NX * U; i += blockDim.x) {
     const int j = i % U;
-    const float v = Bk[i] * scale_of<NC>(p, b, k, j, sc);
+    const float v = Bk[i] * scale_k(j);
     sBt[i] = v;
     ws.Bt[(size_t)s * NX * U + i] = v;
     if (bf16) ws.Btbf[(size_t)s * NX * U + i] = to_bf16(v);
   }
-  const bool has_next = (k + 1 < N);
   if (has_next) {
     const float* A1 = p.A + (size_t)(s + 1) * NX * NX;
     const float* B1 = p.B + (size_t)(s + 1) * NX * U;
     for (int e = tid; e < NX * L; e += blockDim.x) {
       const int i = e / L, c = e % L;
       sTop[e] = (c < NX) ? A1[i * NX + c]
-                         : B1[i * U + c - NX] * scale_of<NC>(p, b, k + 1, c - NX, sc);
+                         : B1[i * U + c - NX] * ((c - NX) % 6 < 3 ? sf1 : sm1);
     }
   }
   if (tid == 0) {
-    ws.sf[s] = scale_of<NC>(p, b, k, 0, sc);
+    ws.sf[s] = sfk;
     if (k == 0) ws.tsc[b] = sc ? p.tau_max[b] : 1.f;
   }
   if (bf16) {
@@ -133,7 +139,7 @@ __global__ void __launch_bounds__(64 * (NC / 2)) setup_kernel(Problem p, Workspa
       if (lane < NX) {
         dg = p.Q[(size_t)b * NX + lane];
       } else {
-        const float sj = scale_of<NC>(p, b, k, lane - NX, sc);
+        const float sj = scale_k(lane - NX);
         dg = p.R[(size_t)b * U + lane - NX] * sj * sj;
       }
 #pragma unroll
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(64 * (NC / 2)) setup_kernel(Problem p, Workspa
     } else {
       const int j = lane - NX;
       const float ur = p.u_ref ? p.u_ref[(size_t)s * U + j] : 0.f;
-      q = p.R[(size_t)b * U + j] * scale_of<NC>(p, b, k, j, sc) * ur;
+      q = p.R[(size_t)b * U + j] * scale_k(j) * ur;
     }
     ws.qb[(size_t)s * L + lane] = q;
   }
