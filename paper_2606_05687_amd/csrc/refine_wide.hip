@@ -921,7 +921,7 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       // kept inverse carries the Hessian's conditioning into the step, which
       // then limits how closely u meets stationarity)
       build_terms(C, sh);
-      backward(C, sh, muv <= 1e-6);
+      backward(C, sh, muv <= 1e-8);
       forward(C, sh);
     }
     const double a = m > 0.0 ? fmin(1.0, 0.99 * row_steps(C)) : 1.0;
