@@ -53,17 +53,23 @@ REFINE_BYTES_PER_PASS_STAGE = 4_500
 REFINE_DENSE_BACKWARD = 3744 + 312 + 4394 + 338 + 4056 + 3744 + 4368 + 3744 + 5904 + 9100
 REFINE_DENSE_FORWARD = 1250 + 650 + 500
 # The four-contact refinement (feet and hands, 24 inputs) per stage of one
-# interior-point iteration: two factorisations of the stage system (W B 8112,
-# W A 4394, B^T W B 14976, B^T W A 8112, B^T w 624, Gauss-Jordan on the 24 x 38
-# system 41952, S and s 13468: 91 638 each) and two rollouts of the gains
-# (1586 each).  Bytes: the iteration's data flow, each array crossing HBM once
+# interior-point iteration: two backward recursions, the predictor's a
+# factorisation of the stage system (W B 8112, W A 4394, B^T W B 14976, B^T W A
+# 8112, B^T w 624, Gauss-Jordan on the 24 x 38 system 41952, S and s 13468:
+# 91 638), the corrector's the vector part with the kept inverse (B^T w 624,
+# H^-1 hw 1152, A^T w 338, Hwx^T kappa 624: 2738) except near the optimum, where
+# it factors again; and two rollouts of the gains (1586 each).  The kernel
+# reports the stages its factoring recursions covered, so the flops of a solve
+# are counted from that mix.  Bytes: the iteration's data flow, each array crossing HBM once
 # per phase that uses it: the factorisation reads A, B (FP32), the stage terms
 # and x, and writes K, kappa, H^-1 and Hwx (13 216 B); the corrector's vector
 # pass reads B, A, rho, x, H^-1 and Hwx and writes kappa (9568 B); two rollouts
 # of the gains (4908 B each); two builds of the stage terms (2592 B each); two
 # slack and multiplier steps (2144 B each); the step and the next residuals
 # (3736 B); the corrector's target (1760 B)
-WIDE_FLOPS_PER_IPM_STAGE = 2 * (8112 + 4394 + 14976 + 8112 + 624 + 41952 + 13468) + 2 * 1586
+WIDE_FACTOR_FLOPS = 8112 + 4394 + 14976 + 8112 + 624 + 41952 + 13468
+WIDE_VECTOR_FLOPS = 624 + 1152 + 338 + 624
+WIDE_ROLLOUT_FLOPS = 1586
 WIDE_BYTES_PER_IPM_STAGE = 13216 + 9568 + 2 * 4908 + 2 * 2592 + 2 * 2144 + 3736 + 1760
 # its sweep per stage: operators A 676 + Bt 1248 + H packed 2812 + M packed
 # 1200 + qbar 148 + e 52 + contact 4 + force scale 4 = 6144 B read, iterates
@@ -674,8 +680,11 @@ def main():
     dense_flops = float(stf.sum() * REFINE_DENSE_BACKWARD +
                         (N_b * eq_p).sum() * REFINE_DENSE_FORWARD +
                         (N_b * ipm_p).sum() * (REFINE_DENSE_BACKWARD + 2 * REFINE_DENSE_FORWARD))
-    if wide:   # already a dense count
-        dense_flops = float(pass_stages) * WIDE_FLOPS_PER_IPM_STAGE
+    if wide:   # two recursions and two rollouts per iteration-stage
+        factored = int(stf.sum())
+        dense_flops = float(factored * WIDE_FACTOR_FLOPS +
+                            (2 * pass_stages - factored) * WIDE_VECTOR_FLOPS +
+                            2 * pass_stages * WIDE_ROLLOUT_FLOPS)
     sweep_b = WIDE_SWEEP_BYTES_PER_STAGE if wide else SWEEP_BYTES_PER_STAGE
     setup_b = WIDE_SETUP_BYTES_PER_STAGE if wide else SETUP_BYTES_PER_STAGE
     work = {"pass_stages": pass_stages,
@@ -695,7 +704,7 @@ def main():
         "refine_kernel": {"ms": refine_ms},
     }
     # algorithmic work of each phase per launch
-    flops_ps = WIDE_FLOPS_PER_IPM_STAGE if wide else REFINE_FLOPS_PER_PASS_STAGE
+    flops_ps = (dense_flops / max(1, pass_stages)) if wide else REFINE_FLOPS_PER_PASS_STAGE
     bytes_ps = WIDE_BYTES_PER_IPM_STAGE if wide else REFINE_BYTES_PER_PASS_STAGE
     refine_flops = float(pass_stages) * flops_ps
     refine_bytes = float(pass_stages) * bytes_ps

@@ -192,9 +192,13 @@ typedef struct {
                               crossover and polish), interior-point
                               iterations, stages whose backward recursion the
                               equality passes factored (a pass restarted at
-                              stage k factors k stages), and the refinement
-                              launch (1 or 2) that finished the problem;
-                              0 0 0 0 for a problem with bad input */
+                              stage k factors k stages; with four contacts:
+                              the stages of the interior point's factoring
+                              recursions, every predictor and the correctors
+                              near the optimum, the other correctors running
+                              the recursion's vector part only), and the
+                              refinement launch (1 or 2) that finished the
+                              problem; 0 0 0 0 for a problem with bad input */
 } pinmpc_out;
 
 /* Fill *s with the defaults listed above (host memory, caller-owned; a null

@@ -845,9 +845,10 @@ __device__ __attribute__((noinline)) double row_steps(const WCtx& C) {
 // Interior point from the current u (its rollout in x).  Returns the
 // iterations; *ok tells whether the certificate was met (then res is it).
 __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, double tol, double res[PINMPC_NRES],
-                   bool* ok) {
+                   bool* ok, int* nfact) {
   const int lane = threadIdx.x;
   *ok = false;
+  *nfact = 0;   // backward recursions that factored (the others: vector part only)
   // rows of stance contacts, starting slacks (at least 1) and multipliers 1
   double mloc = 0.0, smz = 0.0, rpn = 0.0;
   __syncthreads();
@@ -886,6 +887,7 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
     // predictor: affine target rc = s z (in C.rc)
     build_terms(C, sh);
     backward(C, sh, true);
+    ++*nfact;
     forward(C, sh);
     double sigma = 0.0;
     if (m > 0.0) {
@@ -921,7 +923,9 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       // kept inverse carries the Hessian's conditioning into the step, which
       // then limits how closely u meets stationarity)
       build_terms(C, sh);
-      backward(C, sh, muv <= 1e-8);
+      const bool refactor = muv <= 1e-8;
+      backward(C, sh, refactor);
+      *nfact += refactor;
       forward(C, sh);
     }
     const double a = m > 0.0 ? fmin(1.0, 0.99 * row_steps(C)) : 1.0;
@@ -1052,11 +1056,11 @@ __global__ void __launch_bounds__(64) refine_wide_kernel(Problem p, Workspace ws
     C.u[e] = stance(C, k, j / 6) ? v : 0.0;
   }
   double res[PINMPC_NRES] = {0, 0, 0, 0, 0};
-  int its = 0;
+  int its = 0, nfact = 0;
   bool ok = false;
   (void)rollout(C, sh);
   if (refine) {
-    its = ipm(C, sh, ipm_max, tol, res, &ok);   // res: the returned point's
+    its = ipm(C, sh, ipm_max, tol, res, &ok, &nfact);   // res: the returned point's
   } else {
     // the ADMM point as it is
     (void)certificate(C, sh, res, tol);
@@ -1074,7 +1078,7 @@ __global__ void __launch_bounds__(64) refine_wide_kernel(Problem p, Workspace ws
     if (out_iters) out_iters[C.b] = admm_iters + its;
   }
   if (out_detail && lane < 4) {
-    const int v = lane == 1 ? its : lane == 3 ? 1 : 0;
+    const int v = lane == 1 ? its : lane == 2 ? nfact * N : lane == 3 ? 1 : 0;
     out_detail[(size_t)C.b * 4 + lane] = v;
   }
   if (out_res && lane < PINMPC_NRES) out_res[(size_t)C.b * PINMPC_NRES + lane] = (float)res[lane];

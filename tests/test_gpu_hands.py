@@ -53,8 +53,15 @@ def test_hands_parity(solver):
     assert out["u"].shape[-1] == 24
     _check_invariants(batch, out, range(64))
     _compare(batch, out, range(64))
-    assert np.all(out["detail"][:, 1] > 0)     # interior-point iterations
-    print("interior-point iterations", np.bincount(out["detail"][:, 1]))
+    det = out["detail"].astype(np.int64)
+    its, fact, n = det[:, 1], det[:, 2], np.asarray(batch["N"], dtype=np.int64)
+    assert np.all(its > 0)                      # interior-point iterations
+    assert np.all(det[:, 0] == 0) and np.all(det[:, 3] == 1)
+    # stages of the factoring recursions: every predictor, some correctors
+    assert np.all(fact % n == 0)
+    assert np.all(fact >= its * n) and np.all(fact < 2 * its * n)
+    print("interior-point iterations", np.bincount(its),
+          "factorisations per iteration", (fact / n).sum() / its.sum())
 
 
 def test_hands_parity_offsets_ragged(solver):
