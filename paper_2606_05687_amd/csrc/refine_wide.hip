@@ -187,6 +187,7 @@ __device__ inline void str(gd p, const double v[NROW]) {
 // Stage input terms of the Newton step, in parallel over (stage, contact):
 // the R' block and rho of every contact (identity and zero on a swing
 // contact), from the iterate (u, s, z) and the complementarity target rc.
+template <int OCC>
 __device__ __attribute__((noinline)) void build_terms(const WCtx& C, const WSh& sh) {
   __syncthreads();
   for (int e = threadIdx.x; e < C.N * C4; e += 64) {
@@ -246,6 +247,7 @@ __device__ __attribute__((noinline)) void build_terms(const WCtx& C, const WSh& 
 // right-hand side of the same Newton matrix (factor = false: the corrector of
 // an interior-point iteration), whose recursion is the vector part alone:
 // hw = rho + B^T w, kap = -H^{-1} hw, s = A^T w + Hwx^T kap.
+template <int OCC>
 __device__ __attribute__((noinline)) void backward_rhs(const WCtx& C, WSh& sh) {
   const int lane = threadIdx.x;
   __syncthreads();
@@ -323,9 +325,10 @@ __device__ __attribute__((noinline)) void backward_rhs(const WCtx& C, WSh& sh) {
   }
 }
 
+template <int OCC>
 __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool factor) {
   if (!factor) {
-    backward_rhs(C, sh);
+    backward_rhs<OCC>(C, sh);
     return;
   }
   const int lane = threadIdx.x;
@@ -362,6 +365,13 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
   };
   fetch(C.N - 1);
   for (int k = C.N - 1; k >= 0; --k) {
+    // with two waves per SIMD the lane index is opaque to the compiler once
+    // per stage: the per-lane LDS addresses below are then formed anew each
+    // stage (a few integer operations) instead of held in registers across
+    // it, which lets the two waves share a SIMD without spilling inside it
+    int lane_k = threadIdx.x;
+    if constexpr (OCC > 1) asm volatile("" : "+v"(lane_k));
+    const int lane = lane_k;
     wsync();
     uint32_t unit = 0;
     #pragma unroll
@@ -528,6 +538,7 @@ __device__ __attribute__((noinline)) void backward(const WCtx& C, WSh& sh, bool 
 
 // Forward rollout of the gains from dx_0 = 0: du_k = K_k dx_k + kap_k,
 // dx_{k+1} = A_k dx_k + B_k du_k.
+template <int OCC>
 __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
   const int lane = threadIdx.x;
   __syncthreads();
@@ -589,6 +600,7 @@ __device__ __attribute__((noinline)) void forward(const WCtx& C, WSh& sh) {
 
 // FP64 rollout of u from x0 into x, and the dynamics residual of that
 // trajectory (normalised as the certificate's r_dyn).
+template <int OCC>
 __device__ __attribute__((noinline)) double rollout(const WCtx& C, WSh& sh) {
   const int lane = threadIdx.x;
   __syncthreads();
@@ -712,10 +724,11 @@ __device__ void force_refit(int am, double mu, const double gf[3], double m[5]) 
 // construction and stationarity measures how well u meets it.  (The interior
 // point's own multipliers lose their accuracy as the slacks of active rows
 // approach zero: their step divides by the slack.)  Returns max(res).
+template <int OCC>
 __device__ __attribute__((noinline)) double certificate(const WCtx& C, WSh& sh, double res[PINMPC_NRES],
                                                       double tol) {
   const int lane = threadIdx.x;
-  res[0] = rollout(C, sh);
+  res[0] = rollout<OCC>(C, sh);
   // costates, backwards: lam_k = Q (x_{k+1} - r_k) + A_{k+1}^T lam_{k+1}
   double tq = 0.0, tl = 0.0, ta = 0.0;
   if (lane < NX) sh.v13[lane] = 0.0;
@@ -814,6 +827,7 @@ __device__ __attribute__((noinline)) double certificate(const WCtx& C, WSh& sh, 
 
 // Slack and multiplier steps of the direction (du) for complementarity
 // target rc; returns the largest step keeping s, z >= 0 (at most 1).
+template <int OCC>
 __device__ __attribute__((noinline)) double row_steps(const WCtx& C) {
   double amax = 1.0;
   for (int e = threadIdx.x; e < C.N * C4; e += 64) {
@@ -844,6 +858,7 @@ __device__ __attribute__((noinline)) double row_steps(const WCtx& C) {
 
 // Interior point from the current u (its rollout in x).  Returns the
 // iterations; *ok tells whether the certificate was met (then res is it).
+template <int OCC>
 __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, double tol, double res[PINMPC_NRES],
                    bool* ok, int* nfact) {
   const int lane = threadIdx.x;
@@ -876,7 +891,7 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
     const double muv = m > 0.0 ? wsum(smz) / m : 0.0;
     rpn = wmax(rpn);
     if (muv <= 1e-8 && rpn <= 1e-8) {
-      if (certificate(C, sh, res, tol) <= tol) {
+      if (certificate<OCC>(C, sh, res, tol) <= tol) {
         *ok = true;
         return it;
       }
@@ -885,13 +900,13 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       if (muv <= 1e-20) break;
     }
     // predictor: affine target rc = s z (in C.rc)
-    build_terms(C, sh);
-    backward(C, sh, true);
+    build_terms<OCC>(C, sh);
+    backward<OCC>(C, sh, true);
     ++*nfact;
-    forward(C, sh);
+    forward<OCC>(C, sh);
     double sigma = 0.0;
     if (m > 0.0) {
-      const double aa = row_steps(C);
+      const double aa = row_steps<OCC>(C);
       double sm = 0.0;
       for (int e = lane; e < C.N * C4; e += 64) {
         const int k = e / C4, i = e % C4;
@@ -922,13 +937,13 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       // (near the optimum the corrector factors again: the product with the
       // kept inverse carries the Hessian's conditioning into the step, which
       // then limits how closely u meets stationarity)
-      build_terms(C, sh);
+      build_terms<OCC>(C, sh);
       const bool refactor = muv <= 1e-8;
-      backward(C, sh, refactor);
+      backward<OCC>(C, sh, refactor);
       *nfact += refactor;
-      forward(C, sh);
+      forward<OCC>(C, sh);
     }
-    const double a = m > 0.0 ? fmin(1.0, 0.99 * row_steps(C)) : 1.0;
+    const double a = m > 0.0 ? fmin(1.0, 0.99 * row_steps<OCC>(C)) : 1.0;
     // step; residuals and affine target of the new point
     __syncthreads();
     smz = 0.0;
@@ -961,11 +976,12 @@ __device__ __attribute__((noinline)) int ipm(const WCtx& C, WSh& sh, int maxit, 
       str(C.rc + (size_t)e * NROW, cv);
     }
   }
-  *ok = certificate(C, sh, res, tol) <= tol;
+  *ok = certificate<OCC>(C, sh, res, tol) <= tol;
   return it;
 }
 
-__global__ void __launch_bounds__(64) refine_wide_kernel(Problem p, Workspace ws, float* out_u,
+template <int OCC>
+__global__ void __launch_bounds__(64, OCC) refine_wide_kernel(Problem p, Workspace ws, float* out_u,
                                                          float* out_x, float* out_res,
                                                          int32_t* out_iters, int32_t* out_status,
                                                          int32_t* out_detail, int admm_iters,
@@ -1058,12 +1074,12 @@ __global__ void __launch_bounds__(64) refine_wide_kernel(Problem p, Workspace ws
   double res[PINMPC_NRES] = {0, 0, 0, 0, 0};
   int its = 0, nfact = 0;
   bool ok = false;
-  (void)rollout(C, sh);
+  (void)rollout<OCC>(C, sh);
   if (refine) {
-    its = ipm(C, sh, ipm_max, tol, res, &ok, &nfact);   // res: the returned point's
+    its = ipm<OCC>(C, sh, ipm_max, tol, res, &ok, &nfact);   // res: the returned point's
   } else {
     // the ADMM point as it is
-    (void)certificate(C, sh, res, tol);
+    (void)certificate<OCC>(C, sh, res, tol);
   }
 
   // outputs
@@ -1090,9 +1106,22 @@ hipError_t launch_refine_wide(const Problem& p, const Workspace& w, const pinmpc
                               const pinmpc_out& out, hipStream_t st) {
   if (p.batch == 0) return hipSuccess;
   if (p.nc != C4 || p.n_max > PINMPC_NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(refine_wide_kernel, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
-                     out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
-                     s.ipm_iters, s.kkt_tol);
+  // two waves per SIMD once the batch has more problems than the chip has
+  // SIMDs; below that every problem has a SIMD of its own and the one-wave
+  // build, with all registers for its stage, is faster (both builds do the
+  // same arithmetic in the same order: bitwise the same results)
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (p.batch > 4 * cus)
+    hipLaunchKernelGGL(refine_wide_kernel<2>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
+                       out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
+                       s.ipm_iters, s.kkt_tol);
+  else
+    hipLaunchKernelGGL(refine_wide_kernel<1>, dim3(p.batch), dim3(64), 0, st, p, w, out.u, out.x,
+                       out.res, out.iters, out.status, out.detail, s.iters, s.accel, s.refine,
+                       s.ipm_iters, s.kkt_tol);
   return hipGetLastError();
 }
 
